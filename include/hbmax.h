@@ -1,0 +1,247 @@
+/*
+ * hbmax.h -- C ABI of the MI355X (gfx950) memory-efficient IMM hot path.
+ *
+ * The library samples random reverse-reachable (RR) sets on the transposed
+ * graph under the IC or LT diffusion model, stores them plain, Huffman-coded
+ * (a codebook learned from a warm-up block) or with hot vertices in bitmap
+ * rows, and runs greedy max-coverage seed selection directly on that store.
+ * The operations follow the paper's problem statement (Introduction and
+ * Background: G = (V, E, w), a diffusion model and a budget k), the RR-set
+ * definitions of the Background section, Alg. 1 (sampling-and-encoding),
+ * Alg. 2 and Alg. 3 with Eq. 3 (selection on the coded sets) and Eq. 1
+ * (the IMM sampling schedule of Tang et al.).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an hbm_status; nothing else crosses the ABI on error,
+ *    and host outputs are left untouched when the status is not HBM_OK.
+ *    hbm_last_error() gives a human-readable reason for the last failure.
+ *  - A context owns all device memory it allocates.  Device memory comes from
+ *    the optional allocator callback, else hipMalloc.  Calls on one context
+ *    are not thread-safe; distinct contexts are independent.
+ *  - All work is issued on the stream given to hbm_create.  Calls that return
+ *    host outputs synchronise that stream before returning.
+ *  - Vertex ids are int32 in [0, n); edge counts are below 2^32; the number of
+ *    RR sets held by a store is below 2^31.
+ *  - RR set j under seed s is a pure function of (graph, model, s, j): the
+ *    Philox4x32-10 stream is keyed by s and counted by (j, edge group or
+ *    vertex, tag), so any prefix of a store equals the sets a larger request
+ *    would produce, independent of launch shape or block size.
+ */
+#ifndef HBMAX_H
+#define HBMAX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hbm_status {
+    HBM_OK = 0,
+    HBM_EINVAL = 1,  /* bad argument or malformed graph */
+    HBM_ENOMEM = 2,  /* device allocation failed (state unchanged) */
+    HBM_EBUDGET = 3, /* request exceeds the context's store budget (state unchanged) */
+    HBM_EDEVICE = 4, /* a HIP call failed */
+    HBM_ESTATE = 5   /* call made in the wrong order (e.g. sampling before a graph) */
+} hbm_status;
+
+/* Diffusion models of the Background section. */
+typedef enum hbm_model { HBM_IC = 0, HBM_LT = 1 } hbm_model;
+
+/* Edge probabilities: EDGE uses the given weight w(u,v); WC (weighted cascade)
+   uses 1/indeg(v), rounded to float32, and ignores w. */
+typedef enum hbm_prob { HBM_PROB_EDGE = 0, HBM_PROB_WC = 1 } hbm_prob;
+
+/* Store encodings (Alg. 1).  HUFFMAN: Huffmax byte strings with verbatim
+   copies of codeless vertices.  HOT_BITMAP: the top fraction of vertices by
+   warm-up frequency go to bitmap rows (Bitmax restricted to hot vertices),
+   the rest are kept as plain ids.  HUFFMAN_HOT_BITMAP: hot rows plus Huffman
+   coding of the remaining vertices. */
+typedef enum hbm_enc {
+    HBM_ENC_NONE = 0,
+    HBM_ENC_HUFFMAN = 1,
+    HBM_ENC_HOT_BITMAP = 2,
+    HBM_ENC_HUFFMAN_HOT_BITMAP = 3
+} hbm_enc;
+
+typedef struct hbm_ctx hbm_ctx;
+
+/* Device allocator callback (e.g. a framework's caching allocator).  alloc
+   returns device memory or NULL; release frees it.  Both run on the calling
+   thread.  Pass NULL to hbm_create to use hipMalloc / hipFree. */
+typedef struct hbm_allocator {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*release)(void *ptr, void *user);
+    void *user;
+} hbm_allocator;
+
+/* Sizes of the current store.  Bytes counted per part; B/RR = store_bytes / nsets. */
+typedef struct hbm_store_stats {
+    int64_t nsets;          /* RR sets held (theta) */
+    int64_t members;        /* total vertex occurrences */
+    int64_t warmup_sets;    /* W: sets in the warm-up block */
+    int32_t encoding;       /* hbm_enc */
+    int32_t nhot;           /* hot vertices with bitmap rows */
+    int32_t alphabet;       /* vertices with a Huffman code */
+    int32_t max_code_len;   /* longest code, bits */
+    int32_t ustar_enc;      /* warm-up top coded vertex (-1 if none) */
+    int32_t escape_bits;    /* width of a verbatim id */
+    int64_t escapes;        /* codeless occurrences copied verbatim */
+    uint64_t payload_bits;  /* Huffman stream bits */
+    int64_t index_bytes;    /* per-set offsets */
+    int64_t bitmap_bytes;   /* hot rows */
+    int64_t raw_bytes;      /* plain ids (NONE / cold part of HOT_BITMAP) */
+    int64_t codebook_bytes; /* lengths + symbol table + hot list */
+    int64_t store_bytes;    /* index + payload + bitmap + raw (codebook excluded) */
+    double skewness;        /* Eq. 2 over the warm-up block */
+    double density;         /* Eq. 2 over the warm-up block */
+} hbm_store_stats;
+
+/* Result details of hbm_imm. */
+typedef struct hbm_imm_stats {
+    int32_t rounds;             /* estimation rounds run */
+    int64_t theta_round[64];    /* theta_i per round */
+    uint64_t cov_round[64];     /* coverage of the round's k seeds */
+    double lb;                  /* lower bound of OPT (1 if no round passed) */
+    int64_t theta_final;        /* ceil(lambda* / LB) */
+    int64_t nsets_final;        /* sets in the final store: max(theta_final, last theta_i) */
+    uint64_t coverage;          /* sets covered by the final seeds */
+    double influence;           /* n * coverage / nsets_final */
+    double lambda_prime, lambda_star;
+    double t_sample_ms, t_encode_ms, t_select_ms, t_total_ms;
+    hbm_store_stats store;
+} hbm_imm_stats;
+
+/* ---------------------------------------------------------------- lifetime */
+
+/* Create a context on HIP device `device`, issuing work on `stream`
+   (a hipStream_t; NULL = the null stream).  `alloc` may be NULL. */
+hbm_status hbm_create(hbm_ctx **out, int device, void *stream, const hbm_allocator *alloc);
+
+/* Free every device buffer owned by the context.  NULL is a no-op. */
+void hbm_destroy(hbm_ctx *ctx);
+
+/* Reason for the last non-OK status on this context ("" if none). */
+const char *hbm_last_error(const hbm_ctx *ctx);
+
+/* Cap, in bytes, on device memory held by the RR store (0 = no cap).
+   Sampling that would exceed it returns HBM_EBUDGET and leaves the store as it was. */
+hbm_status hbm_set_budget(hbm_ctx *ctx, int64_t store_bytes);
+
+/* ---------------------------------------------------------------- graph */
+
+/* Load G = (V, E, w) given as a FORWARD CSR in device memory:
+ *   row_ptr  int64[n+1]  out-edge offsets, row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
+ *   dst      int32[m]    target of each out-edge
+ *   w        float32[m]  weight of each out-edge, or NULL when prob == HBM_PROB_WC
+ * The buffers are only read during the call.  The library builds the
+ * transposed graph (in-edges of v ordered by ascending source; edge id =
+ * position in that order), then the per-edge (IC-EDGE) or per-vertex (WC)
+ * live thresholds, or for LT the running float32 sum of in-weights along each
+ * in-row (added left to right).
+ * HBM_EINVAL when: n <= 0, m < 0 or m >= 2^32, row_ptr malformed, a target
+ * out of range, a self-loop, a duplicate (u,v), a weight that is NaN or
+ * negative, an IC weight above 1, or an LT in-weight sum (float32, added
+ * left to right) above 1 + 2^-20 + indeg(v) * 2^-23 (the second term covers
+ * float32 accumulation of rows already normalised to sum 1).
+ * Loading a graph resets the RR store. */
+hbm_status hbm_load_graph(hbm_ctx *ctx, int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *dst,
+                          const float *w, hbm_model model, hbm_prob prob);
+
+/* ---------------------------------------------------------------- store */
+
+/* Choose the store encoding.  warmup_frac: the warm-up block is the first
+ * W = min(theta, max(1, ceil(warmup_frac * theta))) sets of the first
+ * sampling request after a reset (Alg. 1's first block); the codebook and the
+ * hot set come from its vertex frequencies and are never rebuilt.  hot_frac:
+ * the hot set is the ceil(hot_frac * n) vertices with the highest warm-up
+ * frequency (ties to the lower id; vertices never seen are excluded).
+ * Resets the store.  HBM_EINVAL for fractions outside (0, 1] where used. */
+hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, double hot_frac);
+
+/* Make the store hold RR sets j = 0 .. theta-1 under `seed`.  Appends when the
+ * seed matches and theta grows; a different seed, or a smaller theta, resets
+ * the store first.  HBM_ESTATE without a graph; HBM_EINVAL if theta < 0 or
+ * theta >= 2^31; HBM_EBUDGET / HBM_ENOMEM leave the store unchanged. */
+hbm_status hbm_sample_rr(hbm_ctx *ctx, int64_t theta, uint64_t seed);
+
+/* Greedy max coverage over the store (the Seed Selection paragraph; Alg. 2 /
+ * Alg. 3 picking exactly k seeds): each pick is the unselected vertex in the
+ * most uncovered sets, the lowest id winning ties.  Host outputs:
+ *   seeds int32[k], gains uint64[k] (uncovered sets each pick covered),
+ *   coverage = sum of gains.
+ * The store is not modified.  HBM_EINVAL if k < 1 or k > n. */
+hbm_status hbm_select_seeds(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
+
+/* Full IMM (Eq. 1 read as Tang et al.'s lambda'; their lower bound and final
+ * theta): l is adjusted to l (1 + ln 2 / ln n); estimation round i samples
+ * theta_i = ceil(lambda' / (n / 2^i)) sets and selects k seeds; the first
+ * round with n cov_i / theta_i >= (1 + sqrt(2) eps) n / 2^i fixes
+ * LB = n cov_i / (theta_i (1 + sqrt(2) eps)); then theta = ceil(lambda* / LB)
+ * and the final k seeds come from max(theta, theta_last) sets.  RR sets are
+ * reused across rounds.  The store is reset first.  Host outputs: seeds
+ * int32[k], gains uint64[k] (may be NULL), stats (may be NULL). */
+hbm_status hbm_imm(hbm_ctx *ctx, int32_t k, double eps, double l, uint64_t seed, int32_t *seeds, uint64_t *gains,
+                   hbm_imm_stats *stats);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Launch-shape parameters.  They change speed only, never results (RR sets are
+ * pure functions of their index, selection is exact).  Unknown keys or values out
+ * of range return HBM_EINVAL. */
+typedef enum hbm_tune_key {
+    HBM_TUNE_IC_TIER1 = 0,        /* 1: light IC sets on one wave each (default); 0: every set on a
+                                     workgroup of its own */
+    HBM_TUNE_IC_T1_BUDGET = 1,    /* edge groups (4 in-edges) one wave may expand before the set moves
+                                     to a workgroup of its own; 0 = no limit.  Default 4096 */
+    HBM_TUNE_BLOCK_SETS = 2       /* RR sets sampled per block (scratch index size), >= 1024.
+                                     Default 2^21 */
+} hbm_tune_key;
+
+hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);
+
+/* ---------------------------------------------------------------- inspection */
+
+/* Decode RR set j to ascending ids in host `buf` (capacity `cap`); *len gets
+ * its size.  HBM_EINVAL if j is out of range or cap is too small (then *len
+ * still gets the size). */
+hbm_status hbm_get_rr(hbm_ctx *ctx, int64_t j, int32_t *buf, int64_t cap, int64_t *len);
+
+/* Decode sets [j0, j1) into host arrays: off int64[j1-j0+1] (relative offsets)
+ * and mem int32[cap].  *total gets the member count; HBM_EINVAL if cap is too small. */
+hbm_status hbm_dump_sets(hbm_ctx *ctx, int64_t j0, int64_t j1, int64_t *off, int32_t *mem, int64_t cap,
+                         int64_t *total);
+
+/* Sizes and coding statistics of the store. */
+hbm_status hbm_get_store_stats(hbm_ctx *ctx, hbm_store_stats *out);
+
+/* Raw arrays of the store and the graph, copied to host, for bit-level checks.
+ * `what` selects the array; *bytes gets its size; HBM_EINVAL if cap is too
+ * small or the array does not exist for the current encoding. */
+typedef enum hbm_array {
+    HBM_A_IN_PTR = 0,    /* int64[n+1]  transposed-graph offsets */
+    HBM_A_IN_SRC = 1,    /* int32[m]    in-edge sources */
+    HBM_A_THRESH = 2,    /* uint32[m or n]  live thresholds: edge live iff (philox word >> 8) < thr */
+    HBM_A_COUNTS = 3,    /* uint32[n]   vertex frequencies over the whole store */
+    HBM_A_WARM = 4,      /* uint32[n]   vertex frequencies over the warm-up block */
+    HBM_A_HOT = 5,       /* int32[nhot] hot vertices by rank */
+    HBM_A_BITMAP = 6,    /* uint64[ceil(nsets/64) * nhot], word-major: word w, rank r at w*nhot + r */
+    HBM_A_RAW_OFF = 7,   /* int64[nsets+1] offsets of the plain ids */
+    HBM_A_RAW_MEM = 8,   /* int32[]     plain ids, ascending per set */
+    HBM_A_LENS = 9,      /* uint8[n]    Huffman code lengths (0 = codeless) */
+    HBM_A_CODES = 10,    /* uint32[n]   canonical codes, right-aligned */
+    HBM_A_BITOFF = 11,   /* int64[nsets+1] start bit of each set's string */
+    HBM_A_PAYLOAD = 12   /* uint32[]    bit stream, MSB first within each word */
+} hbm_array;
+
+hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_bytes, int64_t *bytes);
+
+/* Library version string. */
+const char *hbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBMAX_H */

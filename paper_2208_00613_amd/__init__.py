@@ -1,0 +1,234 @@
+"""Python binding of the gfx950 memory-efficient IMM library (``include/hbmax.h``).
+
+Argument marshalling only: every step of sampling, encoding and selection runs
+in the HIP kernels of ``libhbmax.so``.  PyTorch provides device memory (graph
+upload) and the stream.  Importing the package fails loudly if the library has
+not been built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libhbmax.so")
+
+HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EBUDGET, HBM_EDEVICE, HBM_ESTATE = range(6)
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBUDGET", 4: "EDEVICE", 5: "ESTATE"}
+HBM_IC, HBM_LT = 0, 1
+HBM_PROB_EDGE, HBM_PROB_WC = 0, 1
+ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3}
+ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uint32), "COUNTS": (3, np.uint32),
+          "WARM": (4, np.uint32), "HOT": (5, np.int32), "BITMAP": (6, np.uint64), "RAW_OFF": (7, np.int64),
+          "RAW_MEM": (8, np.int32), "LENS": (9, np.uint8), "CODES": (10, np.uint32), "BITOFF": (11, np.int64),
+          "PAYLOAD": (12, np.uint32)}
+EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
+            "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
+            "hbm_export", "hbm_version", "hbm_set_tuning"]
+TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2}
+
+
+class HbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class StoreStats(C.Structure):
+    _fields_ = [("nsets", C.c_int64), ("members", C.c_int64), ("warmup_sets", C.c_int64), ("encoding", C.c_int32),
+                ("nhot", C.c_int32), ("alphabet", C.c_int32), ("max_code_len", C.c_int32),
+                ("ustar_enc", C.c_int32), ("escape_bits", C.c_int32), ("escapes", C.c_int64),
+                ("payload_bits", C.c_uint64), ("index_bytes", C.c_int64), ("bitmap_bytes", C.c_int64),
+                ("raw_bytes", C.c_int64), ("codebook_bytes", C.c_int64), ("store_bytes", C.c_int64),
+                ("skewness", C.c_double), ("density", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ImmStats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("theta_round", C.c_int64 * 64), ("cov_round", C.c_uint64 * 64),
+                ("lb", C.c_double), ("theta_final", C.c_int64), ("nsets_final", C.c_int64),
+                ("coverage", C.c_uint64), ("influence", C.c_double), ("lambda_prime", C.c_double),
+                ("lambda_star", C.c_double), ("t_sample_ms", C.c_double), ("t_encode_ms", C.c_double),
+                ("t_select_ms", C.c_double), ("t_total_ms", C.c_double), ("store", StoreStats)]
+
+    def as_dict(self):
+        r = self.rounds
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("theta_round", "cov_round", "store")}
+        d["theta_round"] = list(self.theta_round[:r])
+        d["cov_round"] = list(self.cov_round[:r])
+        d["store"] = self.store.as_dict()
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load libhbmax.so (built by ``_build.build()``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    sig = {
+        "hbm_create": ([C.POINTER(P), C.c_int, P, P], C.c_int),
+        "hbm_destroy": ([P], None),
+        "hbm_last_error": ([P], C.c_char_p),
+        "hbm_set_budget": ([P, I64], C.c_int),
+        "hbm_load_graph": ([P, I32, I64, P, P, P, C.c_int, C.c_int], C.c_int),
+        "hbm_set_encoding": ([P, C.c_int, D, D], C.c_int),
+        "hbm_sample_rr": ([P, I64, U64], C.c_int),
+        "hbm_select_seeds": ([P, I32, P, P, P], C.c_int),
+        "hbm_imm": ([P, I32, D, D, U64, P, P, C.POINTER(ImmStats)], C.c_int),
+        "hbm_get_rr": ([P, I64, P, I64, C.POINTER(I64)], C.c_int),
+        "hbm_dump_sets": ([P, I64, I64, P, P, I64, C.POINTER(I64)], C.c_int),
+        "hbm_get_store_stats": ([P, C.POINTER(StoreStats)], C.c_int),
+        "hbm_export": ([P, C.c_int, P, I64, C.POINTER(I64)], C.c_int),
+        "hbm_version": ([], C.c_char_p),
+        "hbm_set_tuning": ([P, C.c_int, I64], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """One hbm_ctx on a HIP device, issuing work on a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self._torch = torch
+        L = lib()
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = C.c_void_p()
+        st = L.hbm_create(C.byref(h), device, C.c_void_p(stream.cuda_stream), None)
+        if st != HBM_OK:
+            raise HbmError(st, "hbm_create failed")
+        self.h = h
+        self.n = 0
+        self._graph_dev = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != HBM_OK:
+            msg = lib().hbm_last_error(self.h)
+            raise HbmError(st, msg.decode() if msg else "")
+
+    # ---------------------------------------------------------------- API (same names as the C ABI)
+    def hbm_set_budget(self, nbytes: int):
+        self._check(lib().hbm_set_budget(self.h, int(nbytes)))
+
+    def hbm_set_tuning(self, key: str, value: int):
+        self._check(lib().hbm_set_tuning(self.h, TUNE[key], int(value)))
+
+    def hbm_load_graph(self, n, row_ptr, dst, w=None, model="IC", prob="EDGE"):
+        """Upload a forward CSR (numpy or torch) and load it; device copies live only for the call."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        with torch.cuda.stream(self.stream):
+            rp = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(dev)
+            ds = torch.as_tensor(np.ascontiguousarray(dst, dtype=np.int32)).to(dev)
+            ww = None if w is None else torch.as_tensor(np.ascontiguousarray(w, dtype=np.float32)).to(dev)
+        self.stream.synchronize()
+        m = int(ds.numel())
+        mod = HBM_IC if model in ("IC", HBM_IC) else HBM_LT
+        pr = HBM_PROB_WC if prob in ("WC", HBM_PROB_WC) else HBM_PROB_EDGE
+        st = lib().hbm_load_graph(self.h, int(n), m, C.c_void_p(rp.data_ptr()),
+                                  C.c_void_p(ds.data_ptr() if m else 0),
+                                  C.c_void_p(ww.data_ptr()) if ww is not None else None, mod, pr)
+        self.stream.synchronize()
+        del rp, ds, ww
+        self._check(st)
+        self.n = int(n)
+
+    def load_synth(self, g, model="IC", prob="EDGE"):
+        self.hbm_load_graph(g.n, g.row_ptr, g.dst, g.w if prob == "EDGE" else None, model=model, prob=prob)
+
+    def hbm_set_encoding(self, enc="NONE", warmup_frac=0.1, hot_frac=0.01):
+        self._check(lib().hbm_set_encoding(self.h, ENC[enc] if isinstance(enc, str) else int(enc),
+                                           float(warmup_frac), float(hot_frac)))
+
+    def hbm_sample_rr(self, theta: int, seed: int):
+        self._check(lib().hbm_sample_rr(self.h, int(theta), int(seed)))
+
+    def hbm_select_seeds(self, k: int):
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        cov = np.zeros(1, dtype=np.uint64)
+        self._check(lib().hbm_select_seeds(self.h, int(k), _ptr(seeds), _ptr(gains), _ptr(cov)))
+        return seeds, gains, int(cov[0])
+
+    def hbm_imm(self, k: int, eps: float, l: float, seed: int):
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        st = ImmStats()
+        self._check(lib().hbm_imm(self.h, int(k), float(eps), float(l), int(seed), _ptr(seeds), _ptr(gains),
+                                  C.byref(st)))
+        return seeds, gains, st.as_dict()
+
+    def hbm_get_rr(self, j: int) -> np.ndarray:
+        ln = C.c_int64()
+        st = lib().hbm_get_rr(self.h, int(j), None, 0, C.byref(ln))
+        if st not in (HBM_OK, HBM_EINVAL):
+            self._check(st)
+        buf = np.zeros(max(ln.value, 1), dtype=np.int32)
+        self._check(lib().hbm_get_rr(self.h, int(j), _ptr(buf), buf.size, C.byref(ln)))
+        return buf[:ln.value]
+
+    def hbm_dump_sets(self, j0: int, j1: int):
+        off = np.zeros(j1 - j0 + 1, dtype=np.int64)
+        tot = C.c_int64()
+        st = lib().hbm_dump_sets(self.h, int(j0), int(j1), _ptr(off), None, 0, C.byref(tot))
+        if st not in (HBM_OK, HBM_EINVAL):
+            self._check(st)
+        mem = np.zeros(max(tot.value, 1), dtype=np.int32)
+        self._check(lib().hbm_dump_sets(self.h, int(j0), int(j1), _ptr(off), _ptr(mem), mem.size, C.byref(tot)))
+        return off, mem[:tot.value]
+
+    def hbm_get_store_stats(self) -> dict:
+        s = StoreStats()
+        self._check(lib().hbm_get_store_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def hbm_export(self, name: str) -> np.ndarray:
+        code, dt = ARRAYS[name]
+        nb = C.c_int64()
+        st = lib().hbm_export(self.h, code, None, 0, C.byref(nb))
+        if st not in (HBM_OK, HBM_EINVAL):
+            self._check(st)
+        buf = np.zeros(max(nb.value // np.dtype(dt).itemsize, 1), dtype=dt)
+        self._check(lib().hbm_export(self.h, code, _ptr(buf), buf.nbytes, C.byref(nb)))
+        return buf[:nb.value // np.dtype(dt).itemsize]
+
+
+def version() -> str:
+    return lib().hbm_version().decode()

@@ -1,0 +1,304 @@
+// api.hip -- the C ABI (include/hbmax.h) and the IMM driver.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "hbm_internal.h"
+
+struct hbm_ctx {
+    hbm::Ctx c;
+};
+
+using hbm::Ctx;
+using hbm::Error;
+
+namespace {
+
+template <class F>
+hbm_status guard(hbm_ctx *ctx, F &&f) {
+    if (!ctx) return HBM_EINVAL;
+    ctx->c.last_error.clear();
+    try {
+        hipError_t e = hipSetDevice(ctx->c.device);
+        if (e != hipSuccess) throw Error{HBM_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e)};
+        f(ctx->c);
+        return HBM_OK;
+    } catch (const Error &e) {
+        ctx->c.last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        ctx->c.last_error = "host allocation failed";
+        return HBM_ENOMEM;
+    } catch (const std::exception &e) {
+        ctx->c.last_error = e.what();
+        return HBM_EDEVICE;
+    }
+}
+
+// IMM parameters (Tang, Shi, Xiao 2015), evaluated in double in this order.
+struct ImmParams {
+    double l_adj, eps_prime, lnC, lambda_prime, lambda_star;
+};
+
+ImmParams imm_params(int32_t n, int32_t k, double eps, double l) {
+    ImmParams p;
+    const double dn = (double)n;
+    p.l_adj = l * (1.0 + log(2.0) / log(dn));
+    p.eps_prime = sqrt(2.0) * eps;
+    double lc = 0.0;
+    for (int32_t i = 1; i <= k; i++) lc += log((double)(n - k + i)) - log((double)i);
+    p.lnC = lc;
+    const double ep = p.eps_prime, la = p.l_adj;
+    p.lambda_prime = (2.0 + 2.0 * ep / 3.0) * (lc + la * log(dn) + log(log2(dn))) * dn / (ep * ep);
+    const double e1 = 1.0 - 1.0 / exp(1.0);
+    const double alpha = sqrt(la * log(dn) + log(2.0));
+    const double beta = sqrt(e1 * (lc + la * log(dn) + log(2.0)));
+    p.lambda_star = 2.0 * dn * (e1 * alpha + beta) * (e1 * alpha + beta) / (eps * eps);
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hbm_version(void) { return "hbmax-gfx950 0.1"; }
+
+hbm_status hbm_create(hbm_ctx **out, int device, void *stream, const hbm_allocator *alloc) {
+    if (!out) return HBM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return HBM_EDEVICE;
+    if (device < 0 || device >= ndev) return HBM_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->release)) return HBM_EINVAL;
+    hbm_ctx *ctx = new (std::nothrow) hbm_ctx;
+    if (!ctx) return HBM_ENOMEM;
+    ctx->c.device = device;
+    ctx->c.stream = (hipStream_t)stream;
+    if (alloc) {
+        ctx->c.alloc = *alloc;
+        ctx->c.has_alloc = true;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return HBM_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->c.num_cus = prop.multiProcessorCount;
+    *out = ctx;
+    return HBM_OK;
+}
+
+void hbm_destroy(hbm_ctx *ctx) {
+    if (!ctx) return;
+    try {
+        (void)hipSetDevice(ctx->c.device);
+        (void)hipStreamSynchronize(ctx->c.stream);
+        hbm::select_free(ctx->c);
+        hbm::store_free(ctx->c);
+        hbm::graph_free(ctx->c);
+        hbm::buf_free(ctx->c, ctx->c.scan_tmp);
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+const char *hbm_last_error(const hbm_ctx *ctx) { return ctx ? ctx->c.last_error.c_str() : "null context"; }
+
+hbm_status hbm_set_budget(hbm_ctx *ctx, int64_t bytes) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(bytes >= 0, HBM_EINVAL, "budget must be >= 0");
+        c.budget = bytes;
+    });
+}
+
+hbm_status hbm_load_graph(hbm_ctx *ctx, int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *dst,
+                          const float *w, hbm_model model, hbm_prob prob) {
+    return guard(ctx, [&](Ctx &c) { hbm::graph_load(c, n, m, row_ptr, dst, w, (int)model, (int)prob); });
+}
+
+hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, double hot_frac) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(enc >= HBM_ENC_NONE && enc <= HBM_ENC_HUFFMAN_HOT_BITMAP, HBM_EINVAL, "unknown encoding");
+        if (enc != HBM_ENC_NONE)
+            HBM_REQUIRE(warmup_frac > 0.0 && warmup_frac <= 1.0, HBM_EINVAL, "warmup_frac must be in (0, 1]");
+        if (enc == HBM_ENC_HOT_BITMAP || enc == HBM_ENC_HUFFMAN_HOT_BITMAP)
+            HBM_REQUIRE(hot_frac > 0.0 && hot_frac <= 1.0, HBM_EINVAL, "hot_frac must be in (0, 1]");
+        hbm::store_reset(c);
+        c.s.enc = (int)enc;
+        c.s.warmup_frac = warmup_frac > 0.0 ? warmup_frac : 0.1;
+        c.s.hot_frac = hot_frac;
+    });
+}
+
+hbm_status hbm_sample_rr(hbm_ctx *ctx, int64_t theta, uint64_t seed) {
+    return guard(ctx, [&](Ctx &c) { hbm::store_extend(c, theta, seed); });
+}
+
+hbm_status hbm_select_seeds(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(seeds && gains && coverage, HBM_EINVAL, "null output");
+        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+        HBM_REQUIRE(k >= 1 && k <= c.g.n, HBM_EINVAL, "k must be in [1, n]");
+        std::vector<int32_t> s((size_t)k);
+        std::vector<uint64_t> g((size_t)k);
+        uint64_t cov = 0;
+        hbm::select_seeds(c, k, s.data(), g.data(), &cov);
+        std::memcpy(seeds, s.data(), (size_t)k * 4);
+        std::memcpy(gains, g.data(), (size_t)k * 8);
+        *coverage = cov;
+    });
+}
+
+hbm_status hbm_imm(hbm_ctx *ctx, int32_t k, double eps, double l, uint64_t seed, int32_t *seeds, uint64_t *gains,
+                   hbm_imm_stats *stats) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(seeds, HBM_EINVAL, "null seeds");
+        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+        const int32_t n = c.g.n;
+        HBM_REQUIRE(n >= 2, HBM_EINVAL, "IMM needs n >= 2");
+        HBM_REQUIRE(k >= 1 && k <= n, HBM_EINVAL, "k must be in [1, n]");
+        HBM_REQUIRE(eps > 0.0 && std::isfinite(eps), HBM_EINVAL, "eps must be positive");
+        HBM_REQUIRE(l > 0.0 && std::isfinite(l), HBM_EINVAL, "l must be positive");
+        const auto t0 = std::chrono::steady_clock::now();
+        c.t_sample = c.t_select = c.t_encode = 0;
+        hbm::store_reset(c);
+        const ImmParams P = imm_params(n, k, eps, l);
+        const double dn = (double)n;
+        hbm_imm_stats st{};
+        st.lambda_prime = P.lambda_prime;
+        st.lambda_star = P.lambda_star;
+        std::vector<int32_t> s((size_t)k);
+        std::vector<uint64_t> g((size_t)k);
+        uint64_t cov = 0;
+        double lb = 1.0;
+        for (int32_t i = 1; (double)i <= log2(dn) - 1.0; i++) {
+            const double x = dn / pow(2.0, (double)i);
+            const int64_t th = (int64_t)ceil(P.lambda_prime / x);
+            hbm::store_extend(c, th, seed);
+            hbm::select_seeds(c, k, s.data(), g.data(), &cov);
+            if (st.rounds < 64) {
+                st.theta_round[st.rounds] = th;
+                st.cov_round[st.rounds] = cov;
+            }
+            st.rounds++;
+            if (dn * (double)cov / (double)th >= (1.0 + P.eps_prime) * x) {
+                lb = dn * (double)cov / ((double)th * (1.0 + P.eps_prime));
+                break;
+            }
+        }
+        const double thf = ceil(P.lambda_star / lb);
+        HBM_REQUIRE(thf < 2147483648.0, HBM_EBUDGET, "final theta exceeds 2^31 sets");
+        const int64_t theta = (int64_t)thf;
+        st.lb = lb;
+        st.theta_final = theta;
+        hbm::store_extend(c, std::max<int64_t>(theta, c.s.nsets), seed);
+        hbm::select_seeds(c, k, s.data(), g.data(), &cov);
+        st.nsets_final = c.s.nsets;
+        st.coverage = cov;
+        st.influence = dn * (double)cov / (double)c.s.nsets;
+        st.t_sample_ms = c.t_sample;
+        st.t_encode_ms = c.t_encode;
+        st.t_select_ms = c.t_select;
+        st.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        hbm::store_stats(c, &st.store);
+        std::memcpy(seeds, s.data(), (size_t)k * 4);
+        if (gains) std::memcpy(gains, g.data(), (size_t)k * 8);
+        if (stats) *stats = st;
+    });
+}
+
+hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
+    return guard(ctx, [&](Ctx &c) {
+        switch (key) {
+            case HBM_TUNE_IC_TIER1:
+                HBM_REQUIRE(value == 0 || value == 1, HBM_EINVAL, "IC_TIER1 must be 0 or 1");
+                c.ic_tier1 = (int)value;
+                break;
+            case HBM_TUNE_IC_T1_BUDGET:
+                HBM_REQUIRE(value >= 0, HBM_EINVAL, "IC_T1_BUDGET must be >= 0");
+                c.ic_t1_budget = value;
+                break;
+            case HBM_TUNE_BLOCK_SETS:
+                HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
+                c.block_sets = value;
+                break;
+            default:
+                throw Error{HBM_EINVAL, "unknown tuning key"};
+        }
+    });
+}
+
+hbm_status hbm_get_rr(hbm_ctx *ctx, int64_t j, int32_t *buf, int64_t cap, int64_t *len) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(len, HBM_EINVAL, "null len");
+        HBM_REQUIRE(j >= 0 && j < c.s.nsets, HBM_EINVAL, "set index out of range");
+        std::vector<int64_t> off;
+        std::vector<int32_t> mem;
+        hbm::store_dump(c, j, j + 1, off, mem);
+        *len = (int64_t)mem.size();
+        HBM_REQUIRE((int64_t)mem.size() <= cap && (buf || mem.empty()), HBM_EINVAL, "buffer too small");
+        if (!mem.empty()) std::memcpy(buf, mem.data(), mem.size() * 4);
+    });
+}
+
+hbm_status hbm_dump_sets(hbm_ctx *ctx, int64_t j0, int64_t j1, int64_t *off, int32_t *mem, int64_t cap,
+                         int64_t *total) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(off && total, HBM_EINVAL, "null output");
+        HBM_REQUIRE(0 <= j0 && j0 <= j1 && j1 <= c.s.nsets, HBM_EINVAL, "range out of bounds");
+        std::vector<int64_t> o;
+        std::vector<int32_t> m;
+        hbm::store_dump(c, j0, j1, o, m);
+        *total = (int64_t)m.size();
+        HBM_REQUIRE((int64_t)m.size() <= cap && (mem || m.empty()), HBM_EINVAL, "buffer too small");
+        std::memcpy(off, o.data(), o.size() * 8);
+        if (!m.empty()) std::memcpy(mem, m.data(), m.size() * 4);
+    });
+}
+
+hbm_status hbm_get_store_stats(hbm_ctx *ctx, hbm_store_stats *out) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(out, HBM_EINVAL, "null output");
+        hbm::store_stats(c, out);
+    });
+}
+
+hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_bytes, int64_t *bytes) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(bytes, HBM_EINVAL, "null bytes");
+        const hbm::Store &s = c.s;
+        const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+        const void *src = nullptr;
+        int64_t nb = 0;
+        const int64_t n = c.g.n, T = s.nsets;
+        switch (what) {
+            case HBM_A_IN_PTR: src = c.g.in_ptr.p; nb = c.g.loaded ? (n + 1) * 8 : 0; break;
+            case HBM_A_IN_SRC: src = c.g.in_src.p; nb = c.g.m * 4; break;
+            case HBM_A_THRESH:
+                src = c.g.thr.p;
+                nb = (c.g.model == HBM_IC && c.g.prob == HBM_PROB_WC) ? n * 4 : c.g.m * 4;
+                break;
+            case HBM_A_COUNTS: src = s.hist.p; nb = s.hist.p ? n * 4 : 0; break;
+            case HBM_A_WARM: src = s.warm.p; nb = (s.warm.p && s.model_ready) ? n * 4 : 0; break;
+            case HBM_A_HOT: src = s.hot.p; nb = (int64_t)s.nhot * 4; break;
+            case HBM_A_BITMAP: src = s.bitmap.p; nb = s.nhot ? ((T + 63) / 64) * s.nhot * 8 : 0; break;
+            case HBM_A_RAW_OFF: src = s.raw_off.p; nb = (!huff && T) ? (T + 1) * 8 : 0; break;
+            case HBM_A_RAW_MEM: src = s.raw_mem.p; nb = (!huff && T) ? s.raw_count * 4 : 0; break;
+            case HBM_A_LENS: src = s.lens.p; nb = (huff && s.model_ready) ? n : 0; break;
+            case HBM_A_CODES: src = s.codes.p; nb = (huff && s.model_ready) ? n * 4 : 0; break;
+            case HBM_A_BITOFF: src = s.bitoff.p; nb = (huff && T) ? (T + 1) * 8 : 0; break;
+            case HBM_A_PAYLOAD: src = s.payload.p; nb = (huff && T) ? (int64_t)((s.nbits + 31) / 32) * 4 : 0; break;
+            default: throw Error{HBM_EINVAL, "unknown array"};
+        }
+        *bytes = nb;
+        HBM_REQUIRE(nb <= cap_bytes, HBM_EINVAL, "buffer too small");
+        if (nb > 0) {
+            HBM_REQUIRE(src && host_out, HBM_EINVAL, "array not present");
+            HBM_HIP(hipMemcpyAsync(host_out, src, (size_t)nb, hipMemcpyDeviceToHost, c.stream));
+            HBM_HIP(hipStreamSynchronize(c.stream));
+        }
+    });
+}
+
+}  // extern "C"

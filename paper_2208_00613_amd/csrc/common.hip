@@ -1,0 +1,94 @@
+// common.hip -- device memory through the context's allocator, and prefix sums.
+#include <rocprim/device/device_scan.hpp>
+
+#include "hbm_internal.h"
+
+namespace hbm {
+
+static void *raw_alloc(Ctx &c, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (c.has_alloc) {
+        p = c.alloc.alloc(bytes, c.alloc.user);
+        if (!p) throw Error{HBM_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{HBM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+        }
+    }
+    return p;
+}
+
+static void raw_free(Ctx &c, void *p) {
+    if (!p) return;
+    if (c.has_alloc) {
+        // the caller's allocator may recycle the block on another stream: finish our work first
+        (void)hipStreamSynchronize(c.stream);
+        c.alloc.release(p, c.alloc.user);
+    } else {
+        (void)hipStreamSynchronize(c.stream);
+        (void)hipFree(p);
+    }
+}
+
+void buf_free(Ctx &c, Buf &b) {
+    raw_free(c, b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+void buf_alloc(Ctx &c, Buf &b, size_t bytes) {
+    buf_free(c, b);
+    b.p = raw_alloc(c, bytes);
+    b.bytes = bytes;
+}
+
+void buf_grow(Ctx &c, Buf &b, size_t bytes, bool keep) {
+    if (b.p && b.bytes >= bytes) return;
+    size_t cap = b.bytes ? b.bytes : 256;
+    while (cap < bytes) cap = cap < (size_t(1) << 30) ? cap * 2 : cap + (cap >> 1);
+    void *np = raw_alloc(c, cap);
+    if (keep && b.p && b.bytes) {
+        hipError_t e = hipMemcpyAsync(np, b.p, b.bytes, hipMemcpyDeviceToDevice, c.stream);
+        if (e != hipSuccess) {
+            raw_free(c, np);
+            throw Error{HBM_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)};
+        }
+        // new tail must read as zero for buffers that are OR-ed into
+        HBM_HIP(hipMemsetAsync((char *)np + b.bytes, 0, cap - b.bytes, c.stream));
+    } else {
+        HBM_HIP(hipMemsetAsync(np, 0, cap, c.stream));
+    }
+    raw_free(c, b.p);
+    b.p = np;
+    b.bytes = cap;
+}
+
+void buf_zero(Ctx &c, Buf &b, size_t off, size_t bytes) {
+    if (bytes) HBM_HIP(hipMemsetAsync((char *)b.p + off, 0, bytes, c.stream));
+}
+
+// exclusive prefix sum with a 64-bit accumulator: out[i] = init + sum(in[0..i))
+
+template <class In>
+static void scan_impl(Ctx &c, const In *in, int64_t *out, int64_t count, int64_t init) {
+    if (count <= 0) return;
+    size_t bytes = 0;
+    HBM_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, (int64_t)init, (size_t)count,
+                                    rocprim::plus<int64_t>(), c.stream));
+    buf_grow(c, c.scan_tmp, bytes, false);
+    hipError_t e = rocprim::exclusive_scan(c.scan_tmp.p, bytes, in, out, (int64_t)init, (size_t)count,
+                                           rocprim::plus<int64_t>(), c.stream);
+    if (e != hipSuccess) throw Error{HBM_EDEVICE, std::string("exclusive_scan: ") + hipGetErrorString(e)};
+}
+
+void scan_u32_to_i64(Ctx &c, const uint32_t *in, int64_t *out, int64_t count, int64_t init) {
+    scan_impl(c, in, out, count, init);
+}
+void scan_u64_to_i64(Ctx &c, const uint64_t *in, int64_t *out, int64_t count, int64_t init) {
+    scan_impl(c, in, out, count, init);
+}
+
+}  // namespace hbm

@@ -1,0 +1,101 @@
+// hbm_device.h -- device-side helpers for gfx950 kernels (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hbm {
+
+constexpr int WAVE = 64;
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products,
+// key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t pick4(const uint4 &y, uint32_t q) {
+    return q == 0 ? y.x : q == 1 ? y.y : q == 2 ? y.z : y.w;
+}
+
+// Uniform root of RR set j: floor(x * n / 2^64), x the first 64 bits of the tag-0 draw.
+__device__ __forceinline__ uint32_t rr_root(uint64_t seed, uint64_t j, uint32_t n) {
+    const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), 0u, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t x = (uint64_t)y.x | ((uint64_t)y.y << 32);
+    return (uint32_t)__umul64hi(x, (uint64_t)n);
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Order LDS traffic between the lanes of one wave (single-wave workgroups need no s_barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const unsigned l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T o = __shfl_up(v, d, WAVE);
+        if (l >= (unsigned)d) v += o;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        uint64_t o = __shfl_xor(v, d, WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Read 32 bits of an MSB-first bit stream starting at bit `pos` (buffer padded by one word).
+__device__ __forceinline__ uint32_t peek32(const uint32_t *__restrict__ buf, uint64_t pos) {
+    const uint64_t w = pos >> 5;
+    const uint32_t sh = (uint32_t)(pos & 31);
+    const uint64_t two = ((uint64_t)buf[w] << 32) | (uint64_t)buf[w + 1];
+    return (uint32_t)((two << sh) >> 32);
+}
+
+// Binary search: first index in [lo, hi) with a[i] > key (a non-decreasing).
+template <class T, class I>
+__device__ __forceinline__ I upper_bound_dev(const T *__restrict__ a, I lo, I hi, T key) {
+    while (lo < hi) {
+        I mid = lo + (hi - lo) / 2;
+        if (a[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace hbm

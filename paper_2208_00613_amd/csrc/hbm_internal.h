@@ -1,0 +1,202 @@
+// hbm_internal.h -- shared internals of the gfx950 IMM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/hbmax.h"
+
+namespace hbm {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    hbm_status st;
+    std::string msg;
+};
+
+#define HBM_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::hbm::Error{HBM_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define HBM_REQUIRE(cond, code, text)                           \
+    do {                                                        \
+        if (!(cond)) throw ::hbm::Error{code, std::string(text)}; \
+    } while (0)
+
+// ------------------------------------------------------------------ device memory
+struct Ctx;
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+void buf_alloc(Ctx &c, Buf &b, size_t bytes);            // frees old contents
+void buf_grow(Ctx &c, Buf &b, size_t bytes, bool keep);  // capacity >= bytes, optionally keeping contents
+void buf_free(Ctx &c, Buf &b);
+void buf_zero(Ctx &c, Buf &b, size_t off, size_t bytes);
+
+// ------------------------------------------------------------------ graph
+struct DGraph {
+    int32_t n = 0;
+    int64_t m = 0;
+    int model = HBM_IC, prob = HBM_PROB_EDGE;
+    Buf in_ptr;  // int64[n+1]
+    Buf in_src;  // int32[m]
+    Buf thr;     // uint32[m] (IC-EDGE, LT) or uint32[n] (IC-WC)
+    bool loaded = false;
+};
+
+// ------------------------------------------------------------------ store
+struct Codebook {
+    int32_t nsym = 0;       // coded vertices
+    int32_t maxlen = 0;
+    int32_t ustar_enc = -1;
+    int32_t wbits = 1;      // verbatim id width
+    uint64_t lim[34] = {};  // left-justified limit of codes of length <= L (index L), 33 bits
+    int32_t base[34] = {};  // symbol index of a code c of length L: base[L] + c
+    int32_t minlen = 0;
+};
+
+struct Store {
+    int enc = HBM_ENC_NONE;
+    double warmup_frac = 0.1, hot_frac = 0.01;
+    bool has_seed = false;
+    uint64_t seed = 0;
+    int64_t nsets = 0;
+    int64_t W = 0;          // warm-up sets (0 until the first request)
+    bool model_ready = false;
+    int64_t members = 0;
+
+    Buf hist;      // uint32[n] frequencies over all sets
+    Buf warm;      // uint32[n] frequencies over the warm-up block
+    // hot bitmap
+    int32_t nhot = 0;
+    Buf hot;       // int32[nhot]
+    Buf hot_rank;  // int32[n], -1 if cold
+    Buf bitmap;    // uint64[words * nhot]
+    int64_t bm_words = 0;
+    // raw (cold) ids
+    Buf raw_off;   // int64[nsets+1]
+    Buf raw_mem;   // int32[]
+    int64_t raw_count = 0;
+    // Huffman
+    Codebook cb;
+    Buf lens;      // uint8[n]
+    Buf codes;     // uint32[n]
+    Buf symtab;    // int32[nsym] ids ordered by (length, id)
+    Buf cbtab;     // uint64 lim[34], int64 base[34] decode tables
+    Buf bitoff;    // int64[nsets+1]
+    Buf payload;   // uint32[]
+    uint64_t nbits = 0;
+    int64_t escapes = 0;
+    double skew = 0.0, density = 0.0;
+    std::vector<uint32_t> warm_sizes;  // set sizes of the warm-up block (Eq. 2)
+};
+
+// ------------------------------------------------------------------ sampling scratch
+struct Scratch {
+    Buf mem;        // uint32 members of the current block
+    size_t cap = 0; // entries
+    Buf pos;        // uint32 per set: start in mem, or a status code
+    Buf size;       // uint32 per set
+    Buf ctrl;       // uint64 control words (cursor, counters, ...)
+    Buf defer;      // uint32 deferred set offsets within the block
+    int64_t bcap = 0;
+    // big-set slots
+    Buf t2_bitmap;  // uint32 words: slots * ceil(n/32)
+    Buf t2_queue;   // uint32: slots * n
+    int t2_slots = 0;
+    Buf lt2_hash;   // uint32: lanes * 4096, kept empty between walks
+    Buf lt2_path;   // uint32: lanes * 2 * 2048 (path, slots)
+    uint64_t lt2_lanes = 0;
+    Buf aux;        // uint64 per set (+1): bit lengths
+    Buf cnt;        // uint32 per set (+1): plain-id counts
+};
+
+// control word indices
+enum : int {
+    CW_CURSOR = 0,     // next free scratch entry
+    CW_NEXT = 1,       // next set (work distribution)
+    CW_NDEFER = 2,     // deferred count
+    CW_FIRST_OVF = 3,  // lowest block offset that ran out of scratch
+    CW_NEXT2 = 4,      // tier-2 work counter
+    CW_SUM = 5,        // generic accumulator
+    CW_COUNT = 8
+};
+constexpr uint32_t POS_DEFER = 0xFFFFFFFFu;
+constexpr uint32_t POS_OVF = 0xFFFFFFFEu;
+
+// ------------------------------------------------------------------ selection state
+struct SelState {
+    Buf counts;   // uint32[n]
+    Buf selmask;  // uint32[ceil(n/32)]
+    Buf covered;  // uint64[words]
+    Buf newly;    // uint64[words]
+    Buf keys;     // uint64[k]
+    Buf partial;  // uint64 per argmax block + a ticket counter
+    int64_t words_cap = 0;
+};
+
+// ------------------------------------------------------------------ context
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hbm_allocator alloc{};
+    bool has_alloc = false;
+    std::string last_error;
+    int64_t budget = 0;
+    int num_cus = 256;
+    // tuning (speed only)
+    int ic_tier1 = 1;
+    int64_t ic_t1_budget = 4096;
+    int64_t block_sets = int64_t(1) << 21;
+    DGraph g;
+    Store s;
+    Scratch sc;
+    SelState sel;
+    Buf scan_tmp;  // rocPRIM temporary storage
+    // timing of the last operations (ms)
+    double t_sample = 0, t_encode = 0, t_select = 0;
+};
+
+// ------------------------------------------------------------------ host entry points of each part
+void graph_load(Ctx &c, int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *dst, const float *w, int model,
+                int prob);
+void graph_free(Ctx &c);
+
+void store_reset(Ctx &c);
+void store_free(Ctx &c);
+void store_extend(Ctx &c, int64_t theta, uint64_t seed);
+int64_t store_bytes(const Ctx &c);
+void store_stats(Ctx &c, hbm_store_stats *out);
+void store_dump(Ctx &c, int64_t j0, int64_t j1, std::vector<int64_t> &off, std::vector<int32_t> &mem);
+
+// sample sets [j0, j1) into scratch; returns the number of sets completed (a prefix)
+int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed);
+
+void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
+void select_free(Ctx &c);
+
+// launch helpers
+inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// exclusive scan helpers (device), implemented with rocPRIM
+void scan_u32_to_i64(Ctx &c, const uint32_t *in, int64_t *out, int64_t count, int64_t init);
+void scan_u64_to_i64(Ctx &c, const uint64_t *in, int64_t *out, int64_t count, int64_t init);
+
+}  // namespace hbm

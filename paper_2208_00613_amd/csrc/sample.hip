@@ -1,0 +1,821 @@
+// sample.hip -- RR-set sampling on the transposed graph (the sampling step of IMM:
+// a randomized BFS in which only live in-edges enter the next frontier).
+//
+// IC (Background, IC model): in-edge e of v is live iff (word >> 8) < thr, with
+// word = component e%4 of Philox(seed; j, e/4, tag 1).  The RR set is every
+// vertex that reaches the root over live edges; because each coin is keyed by
+// (j, e) alone, the set is independent of visit order, thread mapping or tier.
+// LT (live-edge form of the LT model): vertex cur keeps in-edge e, the first
+// whose running in-weight exceeds (word0 >> 8) / 2^24 of Philox(seed; j, cur,
+// tag 2), or none; the reverse walk stops at none or at a repeated vertex.
+//
+// Tiers.  IC tier 1: one wave per set, visited set in an LDS hash table and the
+// BFS queue in LDS; a frontier batch of up to 64 vertices is flattened into
+// groups of four in-edges (one Philox call each) spread over the lanes.  Sets
+// that outgrow the LDS queue, or whose expansion work passes a budget (sets that
+// reach in-degree hubs), are redone by tier 2: one 512-thread workgroup per set,
+// a visited bitmap over V and a queue in device memory, each level's edge groups
+// spread over all eight waves.  LT tier 1: one lane per
+// walk with the path in an LDS column; lanes refill from a shared counter as
+// their walks end.  Longer walks go to tier 2 (lane per walk, device-memory hash
+// and path), and walks longer still to tier 3 (bitmap over V).
+//
+// Every finished set is sorted ascending (its canonical form) and written to a
+// scratch arena; pos[b] / size[b] record where.  Block offsets that found no
+// arena space are marked POS_OVF and the lowest such offset is reported: the
+// caller keeps the completed prefix of the block and resamples the rest.
+#include "hbm_device.h"
+#include "hbm_internal.h"
+
+namespace hbm {
+
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+
+struct SampleArgs {
+    const int64_t *in_ptr;
+    const int32_t *in_src;
+    const uint32_t *thr;
+    int32_t n;
+    int wc;          // thresholds per vertex (IC-WC)
+    uint64_t seed;
+    int64_t j0;      // first set index of the block
+    int64_t nb;      // sets in the block
+    uint32_t *mem;   // scratch arena
+    uint64_t cap;    // arena entries
+    uint32_t *pos;
+    uint32_t *size;
+    unsigned long long *ctrl;
+    uint32_t *defer;   // deferred block offsets (tier 1 -> tier 2)
+    uint64_t gbudget;  // edge groups a tier-1 wave may expand per set (0 = no limit)
+    uint32_t *defer2;  // deferred block offsets (tier 2 -> tier 3)
+};
+
+__device__ __forceinline__ uint32_t hash32(uint32_t v, int bits) { return (v * 0x9E3779B1u) >> (32 - bits); }
+
+// Wave-wide bitonic sort of a[0..P) in LDS (P a power of two, pads hold EMPTY).
+__device__ void wave_bitonic(uint32_t *a, int P, unsigned lane) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = lane; i < P; i += WAVE) {
+                int ixj = i ^ jj;
+                if (ixj > i) {
+                    uint32_t x = a[i], y = a[ixj];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[ixj] = x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Block-wide bitonic sort (blockDim threads, __syncthreads between stages).
+__device__ void block_bitonic(uint32_t *a, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                int ixj = i ^ jj;
+                if (ixj > i) {
+                    uint32_t x = a[i], y = a[ixj];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ int pow2_at_least(int s) {
+    int P = 1;
+    while (P < s) P <<= 1;
+    return P;
+}
+
+// Per-wave arena cursor: chunks of the arena are claimed with one atomic each.
+struct WaveArena {
+    uint64_t cur = 0, end = 0;
+};
+constexpr uint64_t ARENA_CHUNK = 4096;
+
+// Claim `s` entries for the calling wave (wave-uniform s).  Returns false when the arena is full.
+__device__ __forceinline__ bool arena_claim(WaveArena &A, uint64_t s, const SampleArgs &a, uint64_t &at) {
+    if (A.cur + s > A.end) {
+        uint64_t want = s > ARENA_CHUNK ? s : ARENA_CHUNK;
+        uint64_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(&a.ctrl[CW_CURSOR], (unsigned long long)want);
+        base = __shfl(base, 0, WAVE);
+        if (base + want > a.cap) return false;
+        A.cur = base;
+        A.end = base + want;
+    }
+    at = A.cur;
+    A.cur += s;
+    return true;
+}
+
+__device__ __forceinline__ void mark_ovf(const SampleArgs &a, uint32_t b) {
+    a.pos[b] = POS_OVF;
+    a.size[b] = 0;
+    atomicMin(&a.ctrl[CW_FIRST_OVF], (unsigned long long)b);
+}
+
+// ---------------------------------------------------------------------------- IC tier 1
+template <int HB>
+struct IcT1Lds {
+    static constexpr int HC = 1 << HB;
+    static constexpr int QC = HC / 2;
+    uint32_t h[HC];
+    uint32_t q[QC];
+    uint16_t qs[QC];
+    uint32_t sP[WAVE];
+    uint32_t sE0[WAVE];
+    uint32_t sE1[WAVE];
+    uint32_t sT[WAVE];
+    uint32_t cnt;
+    uint32_t ovf;
+};
+
+template <int HB, int WPB>
+__global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
+    using L = IcT1Lds<HB>;
+    __shared__ L lds_all[WPB];
+    const unsigned lane = lane_id();
+    L &S = lds_all[threadIdx.x / WAVE];
+    for (int i = lane; i < L::HC; i += WAVE) S.h[i] = EMPTY;
+    wave_sync();
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const int step = a.nb >= 65536 ? 8 : 1;
+    WaveArena A;
+    for (;;) {
+        uint64_t jb = 0;
+        if (lane == 0) jb = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)step);
+        jb = __shfl(jb, 0, WAVE);
+        if (jb >= (uint64_t)a.nb) break;
+        const uint64_t je = jb + step < (uint64_t)a.nb ? jb + step : (uint64_t)a.nb;
+        for (uint64_t b = jb; b < je; b++) {
+            const uint64_t j = (uint64_t)a.j0 + b;
+            const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
+            const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
+            if (lane == 0) {
+                uint32_t hs = hash32(root, HB);
+                S.h[hs] = root;
+                S.q[0] = root;
+                S.qs[0] = (uint16_t)hs;
+                S.cnt = 1;
+                S.ovf = 0;
+            }
+            wave_sync();
+            uint32_t head = 0, qsize = 1;
+            uint64_t work = 0;
+            bool ovf = false;
+            while (head < qsize) {
+                const uint32_t nbat = qsize - head < (uint32_t)WAVE ? qsize - head : (uint32_t)WAVE;
+                uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
+                if (lane < nbat) {
+                    const uint32_t v = S.q[head + lane];
+                    e0 = (uint32_t)a.in_ptr[v];
+                    e1 = (uint32_t)a.in_ptr[v + 1];
+                    ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
+                    if (a.wc) tv = a.thr[v];
+                }
+                const uint32_t P = wave_incl_scan(ng);
+                const uint32_t G = __shfl(P, WAVE - 1, WAVE);
+                work += G;
+                if (a.gbudget && work > a.gbudget) {  // heavy set: tier 2 spreads it over a whole workgroup
+                    ovf = true;
+                    break;
+                }
+                S.sP[lane] = P;
+                S.sE0[lane] = e0;
+                S.sE1[lane] = e1;
+                S.sT[lane] = tv;
+                wave_sync();
+                head += nbat;
+                for (uint32_t base = 0; base < G; base += WAVE) {
+                    const uint32_t g = base + lane;
+                    if (g < G) {
+                        const uint32_t i = upper_bound_dev<uint32_t, uint32_t>(S.sP, 0u, (uint32_t)WAVE, g);
+                        const uint32_t excl = i ? S.sP[i - 1] : 0u;
+                        const uint32_t E0 = S.sE0[i], E1 = S.sE1[i];
+                        const uint32_t grp = (E0 >> 2) + (g - excl);
+                        const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
+                        uint4 t4;
+                        if (a.wc) {
+                            const uint32_t T = S.sT[i];
+                            t4 = make_uint4(T, T, T, T);
+                        } else {
+                            t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
+                        }
+                        const uint32_t eb = grp * 4;
+#pragma unroll
+                        for (uint32_t qq = 0; qq < 4; qq++) {
+                            const uint32_t e = eb + qq;
+                            if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
+                                // Once the queue is full the set is redone by tier 2; stop inserting so
+                                // the table never holds more than QC + 64 keys (always has free slots).
+                                if (S.cnt >= (uint32_t)L::QC) {
+                                    S.ovf = 1;
+                                    continue;
+                                }
+                                const uint32_t u = (uint32_t)a.in_src[e];
+                                uint32_t hs = hash32(u, HB);
+                                for (;;) {
+                                    const uint32_t old = atomicCAS(&S.h[hs], EMPTY, u);
+                                    if (old == EMPTY) {
+                                        const uint32_t p = atomicAdd(&S.cnt, 1u);
+                                        if (p < (uint32_t)L::QC) {
+                                            S.q[p] = u;
+                                            S.qs[p] = (uint16_t)hs;
+                                        } else {
+                                            S.ovf = 1;
+                                        }
+                                        break;
+                                    }
+                                    if (old == u) break;
+                                    hs = (hs + 1) & (L::HC - 1);
+                                }
+                            }
+                        }
+                    }
+                }
+                wave_sync();
+                qsize = S.cnt;
+                if (S.ovf || qsize > (uint32_t)L::QC) {
+                    ovf = true;
+                    break;
+                }
+            }
+            if (ovf) {
+                for (int i = lane; i < L::HC; i += WAVE) S.h[i] = EMPTY;
+                if (lane == 0) {
+                    a.pos[b] = POS_DEFER;
+                    a.size[b] = 0;
+                    const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
+                    a.defer[d] = (uint32_t)b;
+                }
+                wave_sync();
+                continue;
+            }
+            // canonical order, then release the hash slots
+            const int s = (int)qsize;
+            for (int i = lane; i < s; i += WAVE) S.h[S.qs[i]] = EMPTY;
+            if (s > 1) {
+                const int P2 = pow2_at_least(s);
+                for (int i = s + lane; i < P2; i += WAVE) S.q[i] = EMPTY;
+                wave_sync();
+                wave_bitonic(S.q, P2, lane);
+            }
+            uint64_t at = 0;
+            if (!arena_claim(A, (uint64_t)s, a, at)) {
+                if (lane == 0) mark_ovf(a, (uint32_t)b);
+                wave_sync();
+                continue;
+            }
+            for (int i = lane; i < s; i += WAVE) a.mem[at + i] = S.q[i];
+            if (lane == 0) {
+                a.pos[b] = (uint32_t)at;
+                a.size[b] = (uint32_t)s;
+            }
+            wave_sync();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- IC tier 2
+constexpr int T2_THREADS = 512;
+constexpr int T2_WAVES = T2_THREADS / WAVE;
+constexpr int T2_SORT_CAP = 8192;
+
+struct T2Args {
+    SampleArgs a;
+    uint32_t *bitmap;  // slots * words
+    uint32_t *queue;   // slots * n
+    uint64_t words;    // ceil(n / 32)
+    const uint32_t *list;
+    uint32_t nlist;
+    int model;         // HBM_IC or HBM_LT
+};
+
+// Block-wide inclusive scan of one value per thread (wave shuffles + one LDS pass).
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t *wsum) {
+    const uint32_t inc = wave_incl_scan(v);
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wv; w++) before += wsum[w];
+    return inc + before;
+}
+
+// Emit the set held in `bm` ascending by scanning the bitmap (sets too large for an LDS sort).
+__device__ void emit_from_bitmap(const uint32_t *bm, uint64_t words, uint32_t *out, uint32_t *wsum) {
+    __shared__ uint32_t running;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    for (uint64_t w0 = 0; w0 < words; w0 += blockDim.x) {
+        const uint64_t w = w0 + threadIdx.x;
+        const uint32_t word = w < words ? bm[w] : 0u;
+        const uint32_t c = __popc(word);
+        const uint32_t inc = block_incl_scan(c, wsum);
+        uint32_t o = running + inc - c;
+        uint32_t x = word;
+        while (x) {
+            const int bit = __ffs(x) - 1;
+            out[o++] = (uint32_t)(w * 32 + bit);
+            x &= x - 1;
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) running += inc;
+        __syncthreads();
+    }
+}
+
+// One workgroup per big set: a visited bitmap over V and a queue in device memory.
+// IC: each level's frontier is taken 512 vertices at a time; their edge groups are
+// spread over all threads of the block.  LT: one thread walks with the exact bitmap.
+__global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
+    const SampleArgs &a = t.a;
+    __shared__ uint32_t sP[T2_THREADS];
+    __shared__ uint32_t sE0[T2_THREADS];
+    __shared__ uint32_t sE1[T2_THREADS];
+    __shared__ uint32_t sT[T2_THREADS];
+    __shared__ uint32_t wsum[T2_WAVES];
+    __shared__ uint32_t sort_buf[T2_SORT_CAP];
+    __shared__ uint32_t qn;
+    __shared__ uint32_t item;
+    __shared__ unsigned long long s_at;
+    __shared__ int s_ok;
+    uint32_t *bm = t.bitmap + (uint64_t)blockIdx.x * t.words;
+    uint32_t *queue = t.queue + (uint64_t)blockIdx.x * (uint64_t)a.n;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    for (;;) {
+        if (threadIdx.x == 0) item = (uint32_t)atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
+        __syncthreads();
+        const uint32_t it = item;
+        __syncthreads();
+        if (it >= t.nlist) break;
+        const uint32_t b = t.list[it];
+        const uint64_t j = (uint64_t)a.j0 + b;
+        const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
+        const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
+        if (threadIdx.x == 0) {
+            bm[root >> 5] |= 1u << (root & 31);
+            queue[0] = root;
+            qn = 1;
+        }
+        __syncthreads();
+        if (t.model == HBM_IC) {
+            uint32_t head = 0;
+            uint32_t tail = qn;
+            while (head < tail) {
+                for (uint32_t c0 = head; c0 < tail; c0 += T2_THREADS) {
+                    const uint32_t cn = tail - c0 < (uint32_t)T2_THREADS ? tail - c0 : (uint32_t)T2_THREADS;
+                    uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
+                    if (threadIdx.x < cn) {
+                        const uint32_t v = queue[c0 + threadIdx.x];
+                        e0 = (uint32_t)a.in_ptr[v];
+                        e1 = (uint32_t)a.in_ptr[v + 1];
+                        ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
+                        if (a.wc) tv = a.thr[v];
+                    }
+                    const uint32_t P = block_incl_scan(ng, wsum);
+                    sP[threadIdx.x] = P;
+                    sE0[threadIdx.x] = e0;
+                    sE1[threadIdx.x] = e1;
+                    sT[threadIdx.x] = tv;
+                    __syncthreads();
+                    const uint32_t G = sP[T2_THREADS - 1];
+                    for (uint32_t g = threadIdx.x; g < G; g += T2_THREADS) {
+                        const uint32_t i = upper_bound_dev<uint32_t, uint32_t>(sP, 0u, cn, g);
+                        const uint32_t excl = i ? sP[i - 1] : 0u;
+                        const uint32_t E0 = sE0[i], E1 = sE1[i];
+                        const uint32_t grp = (E0 >> 2) + (g - excl);
+                        const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
+                        uint4 t4;
+                        if (a.wc) {
+                            const uint32_t T = sT[i];
+                            t4 = make_uint4(T, T, T, T);
+                        } else {
+                            t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
+                        }
+                        const uint32_t eb = grp * 4;
+#pragma unroll
+                        for (uint32_t qq = 0; qq < 4; qq++) {
+                            const uint32_t e = eb + qq;
+                            if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
+                                const uint32_t u = (uint32_t)a.in_src[e];
+                                const uint32_t bit = 1u << (u & 31);
+                                const uint32_t old = atomicOr(&bm[u >> 5], bit);
+                                if (!(old & bit)) {
+                                    const uint32_t p = atomicAdd(&qn, 1u);
+                                    queue[p] = u;
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                head = tail;
+                tail = qn;
+                __syncthreads();
+            }
+        } else if (threadIdx.x == 0) {
+            // LT walk with an exact visited bitmap
+            uint32_t cur = root, len = 1;
+            for (;;) {
+                const uint4 y = philox10(jlo, jhi, cur, 2u, k0, k1);
+                const uint32_t r = y.x >> 8;
+                const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
+                const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                if (e == e1) break;
+                const uint32_t s = (uint32_t)a.in_src[e];
+                const uint32_t bit = 1u << (s & 31);
+                if (bm[s >> 5] & bit) break;
+                bm[s >> 5] |= bit;
+                queue[len++] = s;
+                cur = s;
+            }
+            qn = len;
+        }
+        __syncthreads();
+        const uint32_t s = qn;
+        if (threadIdx.x == 0) {
+            const unsigned long long at = atomicAdd(&a.ctrl[CW_CURSOR], (unsigned long long)s);
+            s_at = at;
+            s_ok = at + s <= a.cap;
+        }
+        __syncthreads();
+        const uint64_t at = s_at;
+        if (s_ok) {
+            if ((int)s <= T2_SORT_CAP) {
+                const int P2 = pow2_at_least((int)s);
+                for (int i = threadIdx.x; i < P2; i += T2_THREADS) sort_buf[i] = i < (int)s ? queue[i] : EMPTY;
+                __syncthreads();
+                block_bitonic(sort_buf, P2);
+                for (int i = threadIdx.x; i < (int)s; i += T2_THREADS) a.mem[at + i] = sort_buf[i];
+            } else {
+                emit_from_bitmap(bm, t.words, a.mem + at, wsum);
+            }
+            if (threadIdx.x == 0) {
+                a.pos[b] = (uint32_t)at;
+                a.size[b] = s;
+            }
+        } else if (threadIdx.x == 0) {
+            mark_ovf(a, b);
+        }
+        __syncthreads();
+        // release the visited bits
+        for (uint32_t i = threadIdx.x; i < s; i += T2_THREADS) bm[queue[i] >> 5] = 0u;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------- LT tier 1
+constexpr int LT_LW = 128;  // path capacity per lane in LDS
+
+__global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
+    __shared__ uint32_t path[LT_LW * WAVE];  // path[k * WAVE + lane]
+    const unsigned lane = lane_id();
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    WaveArena A;
+    bool active = false, exhausted = false;
+    uint32_t b = 0, cur = 0, len = 0;
+    uint64_t j = 0;
+    for (;;) {
+        // refill idle lanes with one atomic per wave
+        const uint64_t idle = __ballot(!active && !exhausted);
+        if (idle) {
+            const uint32_t want = __popcll(idle);
+            uint64_t base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)want);
+            base = __shfl(base, 0, WAVE);
+            if (!active && !exhausted) {
+                const uint32_t rank = __popcll(idle & ((1ull << lane) - 1));
+                const uint64_t bb = base + rank;
+                if (bb < (uint64_t)a.nb) {
+                    b = (uint32_t)bb;
+                    j = (uint64_t)a.j0 + bb;
+                    cur = rr_root(a.seed, j, (uint32_t)a.n);
+                    path[lane] = cur;
+                    len = 1;
+                    active = true;
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        if (!__ballot(active)) break;
+        bool finished = false, deferred = false;
+        if (active) {
+            const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
+            const uint32_t r = y.x >> 8;
+            const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
+            const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+            if (e == e1) {
+                finished = true;
+            } else {
+                const uint32_t s = (uint32_t)a.in_src[e];
+                bool seen = false;
+                for (uint32_t k = 0; k < len; k++) seen |= path[k * WAVE + lane] == s;
+                if (seen) {
+                    finished = true;
+                } else if (len == (uint32_t)LT_LW) {
+                    deferred = true;
+                } else {
+                    path[len * WAVE + lane] = s;
+                    len++;
+                    cur = s;
+                }
+            }
+        }
+        if (deferred) {
+            a.pos[b] = POS_DEFER;
+            a.size[b] = 0;
+            const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
+            a.defer[d] = b;
+            active = false;
+        }
+        const uint64_t fin = __ballot(finished);
+        if (fin) {
+            if (finished) {
+                // insertion sort of this lane's column
+                for (uint32_t x = 1; x < len; x++) {
+                    const uint32_t v = path[x * WAVE + lane];
+                    int y2 = (int)x - 1;
+                    while (y2 >= 0 && path[y2 * WAVE + lane] > v) {
+                        path[(y2 + 1) * WAVE + lane] = path[y2 * WAVE + lane];
+                        y2--;
+                    }
+                    path[(y2 + 1) * WAVE + lane] = v;
+                }
+            }
+            const uint32_t mine = finished ? len : 0u;
+            const uint32_t incl = wave_incl_scan(mine);
+            const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+            uint64_t at = 0;
+            const bool ok = arena_claim(A, tot, a, at);
+            if (finished) {
+                if (ok) {
+                    const uint64_t o = at + incl - mine;
+                    for (uint32_t x = 0; x < len; x++) a.mem[o + x] = path[x * WAVE + lane];
+                    a.pos[b] = (uint32_t)o;
+                    a.size[b] = len;
+                } else {
+                    mark_ovf(a, b);
+                }
+                active = false;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- LT tier 2
+constexpr int LT2_HB = 12;                 // hash slots per lane: 4096
+constexpr int LT2_QC = (1 << LT2_HB) / 2;  // path capacity: 2048
+
+struct Lt2Args {
+    SampleArgs a;
+    uint32_t *hash;   // lanes * 4096
+    uint32_t *pathb;  // lanes * 2048
+    const uint32_t *list;
+    uint32_t nlist;
+};
+
+__global__ __launch_bounds__(WAVE) void k_lt_t2(Lt2Args t) {
+    const SampleArgs &a = t.a;
+    const unsigned lane = lane_id();
+    const uint64_t gl = (uint64_t)blockIdx.x * WAVE + lane;
+    uint32_t *H = t.hash + gl * (1u << LT2_HB);
+    uint32_t *Pp = t.pathb + gl * (2 * LT2_QC);
+    uint32_t *Sl = Pp + LT2_QC;  // hash slot of each path entry
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    WaveArena A;
+    for (;;) {
+        uint64_t it = 0;
+        if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], (unsigned long long)WAVE);
+        it = __shfl(it, 0, WAVE) + lane;
+        if (__ballot(it < t.nlist) == 0) break;
+        bool have = it < t.nlist;
+        uint32_t b = have ? t.list[it] : 0u, len = 0;
+        bool ok = true;
+        if (have) {
+            const uint64_t j = (uint64_t)a.j0 + b;
+            uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
+            Pp[0] = cur;
+            Sl[0] = hash32(cur, LT2_HB);
+            H[Sl[0]] = cur;
+            len = 1;
+            for (;;) {
+                const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
+                const uint32_t r = y.x >> 8;
+                const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
+                const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                if (e == e1) break;
+                const uint32_t s = (uint32_t)a.in_src[e];
+                uint32_t hs = hash32(s, LT2_HB);
+                bool seen = false;
+                for (;;) {
+                    const uint32_t x = H[hs];
+                    if (x == s) { seen = true; break; }
+                    if (x == EMPTY) break;
+                    hs = (hs + 1) & ((1u << LT2_HB) - 1);
+                }
+                if (seen) break;
+                if (len == (uint32_t)LT2_QC) { ok = false; break; }
+                H[hs] = s;
+                Sl[len] = hs;
+                Pp[len++] = s;
+                cur = s;
+            }
+            // release exactly the slots this walk filled
+            for (uint32_t x = 0; x < len; x++) H[Sl[x]] = EMPTY;
+            if (ok) {
+                // insertion sort of the path in device memory (short: tier-2 walks)
+                for (uint32_t x = 1; x < len; x++) {
+                    const uint32_t v = Pp[x];
+                    int y2 = (int)x - 1;
+                    while (y2 >= 0 && Pp[y2] > v) {
+                        Pp[y2 + 1] = Pp[y2];
+                        y2--;
+                    }
+                    Pp[y2 + 1] = v;
+                }
+            }
+        }
+        if (have && !ok) {
+            a.pos[b] = POS_DEFER;
+            a.size[b] = 0;
+            const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
+            a.defer2[d] = b;
+        }
+        const bool out = have && ok;
+        const uint32_t mine = out ? len : 0u;
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+        uint64_t at = 0;
+        const bool got = tot ? arena_claim(A, tot, a, at) : true;
+        if (out) {
+            if (got) {
+                const uint64_t o = at + incl - mine;
+                for (uint32_t x = 0; x < len; x++) a.mem[o + x] = Pp[x];
+                a.pos[b] = (uint32_t)o;
+                a.size[b] = len;
+            } else {
+                mark_ovf(a, b);
+            }
+        }
+    }
+}
+
+__global__ void k_iota_u32(uint32_t *p, uint64_t count) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------- host
+struct Ctrl {
+    unsigned long long w[CW_COUNT];
+};
+
+static Ctrl read_ctrl(Ctx &c) {
+    Ctrl r;
+    HBM_HIP(hipMemcpyAsync(r.w, c.sc.ctrl.p, sizeof(r.w), hipMemcpyDeviceToHost, c.stream));
+    HBM_HIP(hipStreamSynchronize(c.stream));
+    return r;
+}
+
+static void set_ctrl(Ctx &c, unsigned long long first_ovf) {
+    Ctrl r{};
+    r.w[CW_FIRST_OVF] = first_ovf;
+    HBM_HIP(hipMemcpyAsync(c.sc.ctrl.p, r.w, sizeof(r.w), hipMemcpyHostToDevice, c.stream));
+}
+
+static void reset_counter(Ctx &c, int which) {
+    HBM_HIP(hipMemsetAsync((char *)c.sc.ctrl.p + which * 8, 0, 8, c.stream));
+}
+
+static void ensure_t2(Ctx &c) {
+    Scratch &sc = c.sc;
+    if (sc.t2_slots) return;
+    const uint64_t n = (uint64_t)c.g.n;
+    const uint64_t words = (n + 31) / 32;
+    int slots = 2 * c.num_cus;
+    const uint64_t per = words * 4 + n * 4;
+    const uint64_t cap_bytes = uint64_t(8) << 30;  // at most 8 GiB for big-set slots
+    while (slots > 8 && per * slots > cap_bytes) slots /= 2;
+    buf_alloc(c, sc.t2_bitmap, words * 4 * slots);
+    buf_zero(c, sc.t2_bitmap, 0, words * 4 * slots);
+    buf_alloc(c, sc.t2_queue, n * 4 * slots);
+    sc.t2_slots = slots;
+}
+
+int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
+    Scratch &sc = c.sc;
+    const int64_t nb = j1 - j0;
+    HBM_REQUIRE(nb <= sc.bcap, HBM_EDEVICE, "internal: block larger than scratch index");
+    set_ctrl(c, (unsigned long long)nb);
+    SampleArgs a;
+    a.in_ptr = c.g.in_ptr.as<int64_t>();
+    a.in_src = c.g.in_src.as<int32_t>();
+    a.thr = c.g.thr.as<uint32_t>();
+    a.n = c.g.n;
+    a.wc = c.g.model == HBM_IC && c.g.prob == HBM_PROB_WC;
+    a.seed = seed;
+    a.j0 = j0;
+    a.nb = nb;
+    a.mem = sc.mem.as<uint32_t>();
+    a.cap = sc.cap;
+    a.pos = sc.pos.as<uint32_t>();
+    a.size = sc.size.as<uint32_t>();
+    a.ctrl = sc.ctrl.as<unsigned long long>();
+    a.defer = sc.defer.as<uint32_t>();
+    a.defer2 = sc.defer.as<uint32_t>() + sc.bcap;
+
+    a.gbudget = (uint64_t)c.ic_t1_budget;
+    if (c.g.model == HBM_IC && !c.ic_tier1) {
+        // every set goes to tier 2 (one workgroup per set)
+        k_iota_u32<<<grid_for(nb, 256, 65536), 256, 0, c.stream>>>(a.defer, (uint64_t)nb);
+        const unsigned long long nbv = (unsigned long long)nb;
+        HBM_HIP(hipMemcpyAsync(a.ctrl + CW_NDEFER, &nbv, 8, hipMemcpyHostToDevice, c.stream));
+    } else if (c.g.model == HBM_IC) {
+        constexpr int WPB = 4;
+        const unsigned grid = (unsigned)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)c.num_cus * 8);
+        k_ic_t1<9, WPB><<<grid, WPB * WAVE, 0, c.stream>>>(a);
+    } else {
+        const unsigned grid = (unsigned)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)c.num_cus * 5);
+        k_lt_t1<<<grid, WAVE, 0, c.stream>>>(a);
+    }
+    HBM_HIP(hipGetLastError());
+    Ctrl r = read_ctrl(c);
+    const uint64_t nd = r.w[CW_NDEFER];
+    if (nd > 0) {
+        if (c.g.model == HBM_IC) {
+            ensure_t2(c);
+            T2Args t;
+            t.a = a;
+            t.bitmap = sc.t2_bitmap.as<uint32_t>();
+            t.queue = sc.t2_queue.as<uint32_t>();
+            t.words = ((uint64_t)c.g.n + 31) / 32;
+            t.list = a.defer;
+            t.nlist = (uint32_t)nd;
+            t.model = HBM_IC;
+            const unsigned grid = (unsigned)std::min<uint64_t>(nd, (uint64_t)sc.t2_slots);
+            k_big<<<grid, T2_THREADS, 0, c.stream>>>(t);
+            HBM_HIP(hipGetLastError());
+        } else {
+            // tier 2: lane per walk with device-memory hash and path
+            if (!sc.lt2_lanes) {
+                const uint64_t L = (uint64_t)c.num_cus * 2 * WAVE;
+                buf_alloc(c, sc.lt2_hash, L * (1u << LT2_HB) * 4);
+                buf_alloc(c, sc.lt2_path, L * 2 * LT2_QC * 4);
+                k_fill_u32<<<grid_for(L << LT2_HB, 256, 65536), 256, 0, c.stream>>>(sc.lt2_hash.as<uint32_t>(),
+                                                                                   L << LT2_HB, EMPTY);
+                HBM_HIP(hipGetLastError());
+                sc.lt2_lanes = L;
+            }
+            const uint64_t lanes = std::min<uint64_t>(((nd + WAVE - 1) / WAVE) * WAVE, sc.lt2_lanes);
+            reset_counter(c, CW_NDEFER);
+            Lt2Args t;
+            t.a = a;
+            t.hash = sc.lt2_hash.as<uint32_t>();
+            t.pathb = sc.lt2_path.as<uint32_t>();
+            t.list = a.defer;
+            t.nlist = (uint32_t)nd;
+            k_lt_t2<<<(unsigned)(lanes / WAVE), WAVE, 0, c.stream>>>(t);
+            HBM_HIP(hipGetLastError());
+            Ctrl r2 = read_ctrl(c);
+            const uint64_t nd3 = r2.w[CW_NDEFER];
+            if (nd3 > 0) {
+                ensure_t2(c);
+                reset_counter(c, CW_NEXT2);
+                T2Args t3;
+                t3.a = a;
+                t3.bitmap = sc.t2_bitmap.as<uint32_t>();
+                t3.queue = sc.t2_queue.as<uint32_t>();
+                t3.words = ((uint64_t)c.g.n + 31) / 32;
+                t3.list = a.defer2;
+                t3.nlist = (uint32_t)nd3;
+                t3.model = HBM_LT;
+                const unsigned grid = (unsigned)std::min<uint64_t>(nd3, (uint64_t)sc.t2_slots);
+                k_big<<<grid, T2_THREADS, 0, c.stream>>>(t3);
+                HBM_HIP(hipGetLastError());
+            }
+        }
+        r = read_ctrl(c);
+    }
+    return (int64_t)std::min<unsigned long long>(r.w[CW_FIRST_OVF], (unsigned long long)nb);
+}
+
+}  // namespace hbm

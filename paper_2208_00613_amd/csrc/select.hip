@@ -1,0 +1,391 @@
+// select.hip -- greedy max coverage on the (encoded) RR store.
+//
+// k iterations (the Seed Selection paragraph; Alg. 2 / Alg. 3 read as picking
+// exactly k seeds).  Each iteration t runs three kernels on the stream:
+//   argmax : u* = the unselected vertex with the highest count, lowest id on
+//            ties; the 64-bit key (count+1) << 32 | ~id is reduced with atomicMax
+//            into keys[t] (an exact argmax, not the paper's parallel-merge
+//            heuristic, which can miss the true maximum);
+//   mark   : one wave per 64 consecutive sets (one word of the covered mask).
+//            If u* is hot its bitmap row gives the newly covered sets directly
+//            (Eq. 3: row AND NOT covered).  Otherwise every uncovered set is
+//            searched for u*: binary search in plain ids, or a partial decode
+//            of the Huffman string that stops at u* or at the first larger id
+//            (Alg. 2's DecodeFind; ids after the front element are ascending).
+//            The plain / coded members of newly covered sets are decremented.
+//   hot    : counts of hot vertices drop by popcount(row AND newly), word by
+//            word (Alg. 3's SUBTRACT and POPCOUNT, applied to the change only).
+// Counts are exact 32-bit integers (the paper's float frequencies are not exact
+// beyond 2^24).  The store itself is never modified.
+#include "hbm_device.h"
+#include "hbm_internal.h"
+
+namespace hbm {
+
+struct SelArgs {
+    int64_t T;       // sets
+    int64_t words;   // ceil(T / 64)
+    int32_t n;
+    uint32_t *counts;
+    uint32_t *selmask;
+    unsigned long long *covered;
+    unsigned long long *newly;
+    unsigned long long *keys;
+    int32_t nhot;
+    const int32_t *hot;
+    const int32_t *hot_rank;
+    const unsigned long long *bitmap;
+    const int64_t *raw_off;
+    const int32_t *raw_mem;
+    int huff;
+    const int64_t *bitoff;
+    const uint32_t *payload;
+    const uint64_t *lim;
+    const int64_t *base;
+    const int32_t *symtab;
+    const uint8_t *lens;
+    int32_t minlen;
+    int32_t wbits;
+    int32_t ustar_enc;
+    int64_t nraw;                 // plain ids in the store
+    unsigned long long *partial;  // per-block argmax partials
+    unsigned *ticket;             // blocks finished (reset by the last one)
+};
+
+// Exact argmax over counts; also clears the `newly` words for this iteration's find step.
+// Each block reduces its slice, writes a partial, and the last block to finish reduces the partials.
+__global__ __launch_bounds__(256) void k_argmax(SelArgs A, int t) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = tid; w < A.words; w += nthr) A.newly[w] = 0ull;
+    unsigned long long best = 0;
+    const int64_t n4 = A.n >> 2;
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
+    for (int64_t q = tid; q < n4; q += nthr) {
+        const uint4 c = c4[q];
+        const uint32_t sm = A.selmask[q >> 3] >> ((q & 7) * 4);
+        const uint32_t v0 = (uint32_t)(q * 4);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const uint32_t cr = r == 0 ? c.x : r == 1 ? c.y : r == 2 ? c.z : c.w;
+            const unsigned long long key =
+                ((sm >> r) & 1u) ? 0ull : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~(v0 + r));
+            best = key > best ? key : best;
+        }
+    }
+    for (int64_t v = n4 * 4 + tid; v < A.n; v += nthr) {
+        const bool sel = (A.selmask[v >> 5] >> (v & 31)) & 1u;
+        const unsigned long long key =
+            sel ? 0ull : (((unsigned long long)A.counts[v] + 1ull) << 32) | (unsigned long long)(~(uint32_t)v);
+        best = key > best ? key : best;
+    }
+    best = wave_max_u64(best);
+    __shared__ unsigned long long part[256 / WAVE];
+    __shared__ bool last;
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = part[0];
+        for (int i = 1; i < (int)(blockDim.x / WAVE); i++) b = part[i] > b ? part[i] : b;
+        A.partial[blockIdx.x] = b;
+        __threadfence();
+        const unsigned ticket = atomicAdd(A.ticket, 1u);
+        last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        unsigned long long b = 0;
+        for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
+            const unsigned long long x = __hip_atomic_load(&A.partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            b = x > b ? x : b;
+        }
+        b = wave_max_u64(b);
+        if (lane_id() == 0) part[threadIdx.x / WAVE] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = part[0];
+            for (int i = 1; i < (int)(blockDim.x / WAVE); i++) m = part[i] > m ? part[i] : m;
+            A.keys[t] = m;
+            *A.ticket = 0u;
+        }
+    }
+}
+
+struct Tabs {
+    uint64_t lim[34];
+    int64_t base[34];
+};
+
+__device__ __forceinline__ uint32_t dec_code(const SelArgs &A, const Tabs &tb, uint64_t &pos) {
+    const uint32_t w = peek32(A.payload, pos);
+    int L = A.minlen;
+    while ((uint64_t)w >= tb.lim[L]) L++;
+    pos += (uint64_t)L;
+    return (uint32_t)A.symtab[tb.base[L] + (int64_t)(w >> (32 - L))];
+}
+
+__device__ __forceinline__ uint32_t read_gamma(const uint32_t *payload, uint64_t &pos) {
+    const uint32_t L = __clz(peek32(payload, pos));
+    pos += L;
+    const uint32_t g = peek32(payload, pos) >> (31 - L);
+    pos += L + 1;
+    return g;
+}
+
+__device__ bool huff_contains(const SelArgs &A, const Tabs &tb, int64_t j, uint32_t u, bool u_coded) {
+    uint64_t pos = (uint64_t)A.bitoff[j];
+    const uint64_t end = (uint64_t)A.bitoff[j + 1];
+    const uint32_t nesc = read_gamma(A.payload, pos) - 1;
+    if (!u_coded) {
+        for (uint32_t q = 0; q < nesc; q++) {
+            const uint32_t v = peek32(A.payload, pos) >> (32 - A.wbits);
+            pos += A.wbits;
+            if (v == u) return true;
+            if (v > u) return false;
+        }
+        return false;
+    }
+    pos += (uint64_t)nesc * A.wbits;
+    bool first = true;
+    while (pos < end) {
+        const uint32_t v = dec_code(A, tb, pos);
+        if (v == u) return true;
+        if (v > u && !(first && (int32_t)v == A.ustar_enc)) return false;
+        first = false;
+    }
+    return false;
+}
+
+__device__ void huff_decrement(const SelArgs &A, const Tabs &tb, int64_t j) {
+    uint64_t pos = (uint64_t)A.bitoff[j];
+    const uint64_t end = (uint64_t)A.bitoff[j + 1];
+    const uint32_t nesc = read_gamma(A.payload, pos) - 1;
+    for (uint32_t q = 0; q < nesc; q++) {
+        const uint32_t v = peek32(A.payload, pos) >> (32 - A.wbits);
+        pos += A.wbits;
+        atomicSub(&A.counts[v], 1u);
+    }
+    while (pos < end) atomicSub(&A.counts[dec_code(A, tb, pos)], 1u);
+}
+
+__device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
+    key = A.keys[t];
+    return ~(uint32_t)key;
+}
+
+// Plain ids: one coalesced pass over every stored id; a match marks its set (if uncovered) in `newly`.
+__global__ __launch_bounds__(256) void k_find_raw(SelArgs A, int t) {
+    unsigned long long key;
+    const uint32_t u = ustar_of(A, t, key);
+    if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = A.nraw >> 2;
+    const uint4 *m4 = reinterpret_cast<const uint4 *>(A.raw_mem);
+    for (int64_t q = tid; q <= n4; q += nthr) {
+        uint32_t x[4];
+        int cnt = 4;
+        if (q < n4) {
+            const uint4 m = m4[q];
+            x[0] = m.x; x[1] = m.y; x[2] = m.z; x[3] = m.w;
+        } else {
+            cnt = (int)(A.nraw - n4 * 4);
+            for (int r = 0; r < cnt; r++) x[r] = (uint32_t)A.raw_mem[n4 * 4 + r];
+        }
+        for (int r = 0; r < cnt; r++) {
+            if (x[r] != u) continue;
+            const int64_t i = q * 4 + r;
+            // set containing position i: last j with raw_off[j] <= i
+            int64_t lo = 0, hi = A.T;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (A.raw_off[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            const unsigned long long bit = 1ull << (lo & 63);
+            if (!(A.covered[lo >> 6] & bit)) atomicOr(&A.newly[lo >> 6], bit);
+        }
+    }
+}
+
+// Huffman strings: one lane per uncovered set, partial decode that stops at u* or a larger id.
+__global__ __launch_bounds__(256) void k_find_huff(SelArgs A, int t) {
+    __shared__ Tabs tb;
+    for (int i = threadIdx.x; i < 34; i += blockDim.x) {
+        tb.lim[i] = A.lim[i];
+        tb.base[i] = A.base[i];
+    }
+    __syncthreads();
+    unsigned long long key;
+    const uint32_t u = ustar_of(A, t, key);
+    if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
+    const bool u_coded = A.lens[u] > 0;
+    const unsigned lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
+        const unsigned long long cov = A.covered[w];
+        const int64_t j = w * 64 + lane;
+        const bool found = j < A.T && !((cov >> lane) & 1ull) && huff_contains(A, tb, j, u, u_coded);
+        const unsigned long long nw = __ballot(found);
+        if (lane == 0 && nw) A.newly[w] = nw;
+    }
+}
+
+// Apply the pick: newly = (hot row or found sets) AND NOT covered; covered |= newly;
+// decrement the plain / coded members of newly covered sets.
+__global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
+    __shared__ Tabs tb;
+    if (A.huff) {
+        for (int i = threadIdx.x; i < 34; i += blockDim.x) {
+            tb.lim[i] = A.lim[i];
+            tb.base[i] = A.base[i];
+        }
+    }
+    __syncthreads();
+    unsigned long long key;
+    const uint32_t u = ustar_of(A, t, key);
+    if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
+    const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
+    const unsigned lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
+        const unsigned long long cov = A.covered[w];
+        const unsigned long long nw = (r >= 0 ? A.bitmap[w * (int64_t)A.nhot + r] : A.newly[w]) & ~cov;
+        if (lane == 0) {
+            A.newly[w] = nw;
+            if (nw) A.covered[w] = cov | nw;
+        }
+        if (!nw) continue;
+        if (A.huff) {
+            if ((nw >> lane) & 1ull) huff_decrement(A, tb, w * 64 + lane);
+        } else if (A.raw_off) {
+            unsigned long long rest = nw;
+            while (rest) {
+                const int b = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const int64_t j = w * 64 + b;
+                const int64_t e = A.raw_off[j + 1];
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) atomicSub(&A.counts[A.raw_mem[i]], 1u);
+            }
+        }
+    }
+}
+
+// hot counts -= popcount(row AND newly), over a segment of words per block row
+__global__ __launch_bounds__(256) void k_dec_hot(SelArgs A, int64_t seg) {
+    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t w0 = blockIdx.y * seg;
+    const int64_t w1 = w0 + seg < A.words ? w0 + seg : A.words;
+    uint32_t acc = 0;
+    for (int64_t w = w0; w < w1; w++) {
+        const unsigned long long nwv = A.newly[w];
+        if (nwv && h < A.nhot) acc += __popcll(A.bitmap[w * (int64_t)A.nhot + h] & nwv);
+    }
+    if (acc) atomicSub(&A.counts[A.hot[h]], acc);
+}
+
+void select_free(Ctx &c) {
+    SelState &S = c.sel;
+    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial}) buf_free(c, *b);
+    S.words_cap = 0;
+}
+
+void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
+    HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+    HBM_REQUIRE(k >= 1 && k <= c.g.n, HBM_EINVAL, "k must be in [1, n]");
+    Store &s = c.s;
+    SelState &S = c.sel;
+    const int32_t n = c.g.n;
+    const int64_t T = s.nsets;
+    const int64_t words = (T + 63) / 64;
+    hipEvent_t e0, e1;
+    HBM_HIP(hipEventCreate(&e0));
+    HBM_HIP(hipEventCreate(&e1));
+    HBM_HIP(hipEventRecord(e0, c.stream));
+    buf_grow(c, S.counts, (size_t)n * 4, false);
+    buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
+    buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
+    buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
+    buf_grow(c, S.keys, (size_t)k * 8, false);
+    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256, (int64_t)c.num_cus * 2);
+    if (S.partial.bytes < (size_t)g_arg * 8 + 8) {
+        buf_grow(c, S.partial, (size_t)g_arg * 8 + 8, false);
+        buf_zero(c, S.partial, 0, S.partial.bytes);
+    }
+    if (T > 0) HBM_HIP(hipMemcpyAsync(S.counts.p, s.hist.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c.stream));
+    else buf_zero(c, S.counts, 0, (size_t)n * 4);
+    buf_zero(c, S.selmask, 0, ((size_t)n + 31) / 32 * 4);
+    buf_zero(c, S.covered, 0, (size_t)std::max<int64_t>(words, 1) * 8);
+    buf_zero(c, S.keys, 0, (size_t)k * 8);
+
+    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+    SelArgs A{};
+    A.T = T;
+    A.words = words;
+    A.n = n;
+    A.counts = S.counts.as<uint32_t>();
+    A.selmask = S.selmask.as<uint32_t>();
+    A.covered = S.covered.as<unsigned long long>();
+    A.newly = S.newly.as<unsigned long long>();
+    A.keys = S.keys.as<unsigned long long>();
+    A.nhot = s.nhot;
+    A.hot = s.hot.as<int32_t>();
+    A.hot_rank = s.nhot ? s.hot_rank.as<int32_t>() : nullptr;
+    A.bitmap = s.bitmap.as<unsigned long long>();
+    A.raw_off = huff ? nullptr : s.raw_off.as<int64_t>();
+    A.raw_mem = huff ? nullptr : s.raw_mem.as<int32_t>();
+    A.huff = huff && T > 0;
+    A.bitoff = s.bitoff.as<int64_t>();
+    A.payload = s.payload.as<uint32_t>();
+    A.lim = s.cbtab.as<uint64_t>();
+    A.base = s.cbtab.as<int64_t>() + 34;
+    A.symtab = s.symtab.as<int32_t>();
+    A.lens = s.lens.as<uint8_t>();
+    A.minlen = s.cb.minlen;
+    A.wbits = s.cb.wbits;
+    A.ustar_enc = s.cb.ustar_enc;
+    A.nraw = huff ? 0 : s.raw_count;
+    A.partial = S.partial.as<unsigned long long>();
+    A.ticket = reinterpret_cast<unsigned *>(S.partial.as<unsigned long long>() + g_arg);
+
+    const unsigned g_mark = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
+    const unsigned g_find = grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)c.num_cus * 4);
+    const unsigned hx = (unsigned)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
+    int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / hx));
+    const int64_t seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
+    nseg = std::max<int64_t>(1, (words + seg - 1) / seg);
+    for (int t = 0; t < k; t++) {
+        k_argmax<<<g_arg, 256, 0, c.stream>>>(A, t);
+        if (T > 0) {
+            if (huff) k_find_huff<<<g_mark, 256, 0, c.stream>>>(A, t);
+            else if (A.nraw > 0) k_find_raw<<<g_find, 256, 0, c.stream>>>(A, t);
+            k_apply<<<g_mark, 256, 0, c.stream>>>(A, t);
+            if (s.nhot > 0) k_dec_hot<<<dim3(hx, (unsigned)nseg), 256, 0, c.stream>>>(A, seg);
+        } else {
+            k_apply<<<1, 64, 0, c.stream>>>(A, t);  // only records the selection
+        }
+    }
+    HBM_HIP(hipGetLastError());
+    std::vector<unsigned long long> keys((size_t)k);
+    HBM_HIP(hipMemcpyAsync(keys.data(), S.keys.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.stream));
+    HBM_HIP(hipEventRecord(e1, c.stream));
+    HBM_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    c.t_select += ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    uint64_t cov = 0;
+    for (int t = 0; t < k; t++) {
+        const unsigned long long key = keys[(size_t)t];
+        HBM_REQUIRE(key != 0, HBM_EDEVICE, "internal: empty argmax");
+        seeds[t] = (int32_t)(~(uint32_t)key);
+        gains[t] = (uint64_t)(key >> 32) - 1;
+        cov += gains[t];
+    }
+    *coverage = cov;
+}
+
+}  // namespace hbm

@@ -1,0 +1,315 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Integer results (RR sets, counts, codes, bit streams, seeds, gains, coverage)
+must be bit-exact.  Every case prints its name, sizes and seed before it runs.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from synth import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2208_00613_amd as P
+
+    P.lib()
+    return P
+
+
+@pytest.fixture()
+def ctx(P):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _ograph(orc, g, model, prob):
+    return orc.Graph(g.n, g.row_ptr, g.dst, g.w if prob == "EDGE" else None, model=model, prob=prob)
+
+
+def _check_sets(ctx, st, theta, chunk=200_000):
+    ooff, omem = st.arrays()
+    for j0 in range(0, theta, chunk):
+        j1 = min(theta, j0 + chunk)
+        off, mem = ctx.hbm_dump_sets(j0, j1)
+        ro = ooff[j0:j1 + 1] - ooff[j0]
+        assert np.array_equal(off, ro), f"set sizes differ in [{j0},{j1})"
+        assert np.array_equal(mem, omem[ooff[j0]:ooff[j1]]), f"set members differ in [{j0},{j1})"
+
+
+# ---------------------------------------------------------------- graph ingest
+@pytest.mark.parametrize("model,prob", [("IC", "EDGE"), ("IC", "WC"), ("LT", "EDGE"), ("LT", "WC")])
+def test_transpose_and_thresholds(orc, ctx, model, prob):
+    _say("transpose", model, prob)
+    g = G.rmat(12, seed=7)
+    w = G.lt_weights(g, 8) if model == "LT" else np.random.default_rng(3).random(g.m, dtype=np.float32)
+    g = G.with_weights(g, w)
+    ctx.load_synth(g, model=model, prob=prob)
+    og = _ograph(orc, g, model, prob)
+    ptr, src = og.in_csr()
+    assert np.array_equal(ctx.hbm_export("IN_PTR"), ptr)
+    assert np.array_equal(ctx.hbm_export("IN_SRC"), src)
+    thr = ctx.hbm_export("THRESH")
+    indeg = np.diff(ptr)
+    two24 = np.float32(16777216.0)
+    if model == "IC" and prob == "WC":
+        p = np.where(indeg > 0, np.float32(1.0) / np.maximum(indeg, 1).astype(np.float32), np.float32(0))
+        want = np.ceil(p.astype(np.float32) * two24).astype(np.uint32)
+    else:
+        # weights in in-edge order
+        order = np.lexsort((g.src(), g.dst))
+        w_in = g.w[order]
+        if prob == "WC":
+            w_in = (np.float32(1.0) / np.repeat(indeg, indeg).astype(np.float32)).astype(np.float32)
+        if model == "IC":
+            want = np.ceil(w_in * two24).astype(np.uint32)
+        else:
+            want = np.zeros(g.m, dtype=np.uint32)
+            for v in range(g.n):
+                acc = np.float32(0)
+                for e in range(ptr[v], ptr[v + 1]):
+                    acc = np.float32(acc + w_in[e])
+                    want[e] = np.uint32(np.ceil(np.float32(acc * two24)))
+    assert np.array_equal(thr, want)
+
+
+def test_wc_threshold_division_all_degrees(P, ctx):
+    """Per-vertex WC thresholds for every in-degree 1..2000 and one hub of 2^16: 1/d rounded to float32."""
+    _say("wc thresholds, all degrees")
+    K = 2000
+    u, v = [], []
+    for d in range(1, K + 1):
+        u.extend(range(K + 1, K + 1 + d))
+        v.extend([d] * d)
+    D = 1 << 16
+    u.extend(range(1, D + 1))
+    v.extend([0] * D)
+    n = max(D, 2 * K) + 1
+    g = G._csr_from_pairs(n, np.array(u), np.array(v))
+    ctx.hbm_load_graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
+    thr = ctx.hbm_export("THRESH")
+    deg = g.indeg()
+    p = np.where(deg > 0, np.float32(1.0) / np.maximum(deg, 1).astype(np.float32), np.float32(0.0))
+    want = np.ceil(p.astype(np.float32) * np.float32(16777216.0)).astype(np.uint32)
+    assert np.array_equal(thr, want)
+
+
+@pytest.mark.parametrize("bad", ["self_loop", "duplicate", "range", "nan", "negative", "lt_sum", "ic_above_1",
+                                 "rowptr"])
+def test_invalid_graph_rejected(P, ctx, bad):
+    _say("invalid graph", bad)
+    n = 6
+    rp = np.array([0, 2, 3, 4, 5, 6, 6], dtype=np.int64)
+    dst = np.array([1, 2, 3, 4, 5, 0], dtype=np.int32)
+    w = np.full(6, 0.5, dtype=np.float32)
+    model = "IC"
+    if bad == "self_loop":
+        dst[0] = 0
+    elif bad == "duplicate":
+        dst[1] = 1
+    elif bad == "range":
+        dst[2] = 9
+    elif bad == "nan":
+        w[3] = np.nan
+    elif bad == "negative":
+        w[3] = -0.1
+    elif bad == "ic_above_1":
+        w[3] = 1.5
+    elif bad == "lt_sum":
+        model = "LT"
+        dst[1] = 3  # vertex 3 gets in-edges from 0 and 2
+        rp = np.array([0, 2, 3, 4, 5, 6, 6], dtype=np.int64)
+        w[:] = 0.75
+    elif bad == "rowptr":
+        rp[3] = 1
+    with pytest.raises(P.HbmError) as ei:
+        ctx.hbm_load_graph(n, rp, dst, w, model=model, prob="EDGE")
+    assert ei.value.status == P.HBM_EINVAL
+    # the context stays usable
+    ctx.hbm_load_graph(n, np.array([0, 1, 2, 3, 4, 5, 6], dtype=np.int64), np.array([1, 2, 3, 4, 5, 0], np.int32),
+                       np.full(6, 0.5, np.float32), model="IC", prob="EDGE")
+
+
+def test_state_errors(P, ctx):
+    _say("state errors")
+    with pytest.raises(P.HbmError) as ei:
+        ctx.hbm_sample_rr(10, 1)
+    assert ei.value.status == P.HBM_ESTATE
+    g = G.erdos_renyi(64, 256, seed=2)
+    ctx.load_synth(g, "IC", "EDGE")
+    with pytest.raises(P.HbmError) as ei:
+        ctx.hbm_select_seeds(0)
+    assert ei.value.status == P.HBM_EINVAL
+    with pytest.raises(P.HbmError) as ei:
+        ctx.hbm_select_seeds(65)
+    assert ei.value.status == P.HBM_EINVAL
+    with pytest.raises(P.HbmError):
+        ctx.hbm_sample_rr(-1, 1)
+    with pytest.raises(P.HbmError):
+        ctx.hbm_set_encoding("HOT_BITMAP", 0.1, 0.0)
+
+
+# ---------------------------------------------------------------- RR sets and seeds
+def test_c1_tiny_ic_full(orc, ctx):
+    """Config C1: ER n=1024 m=8192, p~U[0,0.1], theta=10^4, seed 42, k=10, no compression."""
+    _say("c1 full parity")
+    g = G.config_graph("c1")
+    ctx.load_synth(g, "IC", "EDGE")
+    ctx.hbm_set_encoding("NONE")
+    ctx.hbm_sample_rr(10_000, 42)
+    og = _ograph(orc, g, "IC", "EDGE")
+    st = orc.sample_store(og, 42, 10_000)
+    _check_sets(ctx, st, 10_000)
+    assert np.array_equal(ctx.hbm_export("COUNTS").astype(np.uint64), st.counts(g.n))
+    seeds, gains, cov = ctx.hbm_select_seeds(10)
+    os_, og_, oc = orc.greedy(st, g.n, 10)
+    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
+
+
+@pytest.mark.parametrize("model,prob,scale,theta", [("IC", "WC", 14, 30_000), ("LT", "EDGE", 14, 30_000),
+                                                    ("IC", "EDGE", 11, 3_000)])
+def test_sets_and_seeds_rmat(orc, ctx, model, prob, scale, theta):
+    _say("rmat sets", model, prob, scale, theta)
+    g = G.rmat(scale, seed=scale)
+    if model == "LT":
+        g = G.with_weights(g, G.lt_weights(g, 5))
+    elif prob == "EDGE":
+        # large RR sets: constant p well above the critical value drives the big-set tier
+        g = G.with_weights(g, np.full(g.m, 0.25, dtype=np.float32))
+    ctx.load_synth(g, model, prob)
+    ctx.hbm_set_encoding("NONE")
+    ctx.hbm_sample_rr(theta, 42)
+    og = _ograph(orc, g, model, prob)
+    st = orc.sample_store(og, 42, theta)
+    _check_sets(ctx, st, theta)
+    seeds, gains, cov = ctx.hbm_select_seeds(20)
+    os_, og_, oc = orc.greedy(st, g.n, 20)
+    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
+
+
+def test_lt_long_walks_all_tiers(orc, ctx):
+    """A directed path with weight 1: walk length = root id + 1, crossing every LT tier."""
+    _say("lt long walks")
+    n = 5000
+    g = G._csr_from_pairs(n, np.arange(n - 1), np.arange(1, n))
+    g = G.with_weights(g, np.ones(g.m, dtype=np.float32))
+    ctx.load_synth(g, "LT", "EDGE")
+    ctx.hbm_set_encoding("NONE")
+    ctx.hbm_sample_rr(400, 9)
+    og = _ograph(orc, g, "LT", "EDGE")
+    st = orc.sample_store(og, 9, 400)
+    _check_sets(ctx, st, 400)
+
+
+def test_append_equals_direct(orc, ctx):
+    _say("append vs direct")
+    g = G.rmat(12, seed=3)
+    ctx.load_synth(g, "IC", "WC")
+    ctx.hbm_set_encoding("NONE")
+    ctx.hbm_sample_rr(1000, 5)
+    ctx.hbm_sample_rr(2500, 5)
+    ctx.hbm_sample_rr(7000, 5)
+    og = _ograph(orc, g, "IC", "WC")
+    st = orc.sample_store(og, 5, 7000)
+    _check_sets(ctx, st, 7000)
+    # a new seed resets
+    ctx.hbm_sample_rr(500, 6)
+    st6 = orc.sample_store(og, 6, 500)
+    _check_sets(ctx, st6, 500)
+
+
+# ---------------------------------------------------------------- encodings
+@pytest.mark.parametrize("enc", ["HUFFMAN", "HOT_BITMAP", "HUFFMAN_HOT_BITMAP"])
+@pytest.mark.parametrize("model", ["IC", "LT"])
+def test_encoding_bit_exact(orc, ctx, enc, model):
+    _say("encoding", enc, model)
+    g = G.rmat(13, seed=21)
+    prob = "WC" if model == "IC" else "EDGE"
+    if model == "LT":
+        g = G.with_weights(g, G.lt_weights(g, 4))
+    theta, wf, hf = 12_000, 0.1, 0.01
+    ctx.load_synth(g, model, prob)
+    ctx.hbm_set_encoding(enc, wf, hf)
+    ctx.hbm_sample_rr(theta, 42)
+    og = _ograph(orc, g, model, prob)
+    st = orc.sample_store(og, 42, theta)
+    W = orc.warmup_count(wf, theta)
+    e = orc.Encoded(st, g.n, enc, W, hot_frac=hf)
+    assert np.array_equal(ctx.hbm_export("WARM").astype(np.uint64), e.warm)
+    if e.nhot:
+        assert np.array_equal(ctx.hbm_export("HOT"), e.hot)
+        assert np.array_equal(ctx.hbm_export("BITMAP"), e.bitmap)
+    if e.cold_off is not None:
+        assert np.array_equal(ctx.hbm_export("RAW_OFF"), e.cold_off)
+        assert np.array_equal(ctx.hbm_export("RAW_MEM"), e.cold_mem)
+    if e.lens is not None:
+        assert np.array_equal(ctx.hbm_export("LENS"), e.lens)
+        assert np.array_equal(ctx.hbm_export("CODES"), e.codes)
+        assert np.array_equal(ctx.hbm_export("BITOFF"), e.bitoff)
+        pay = ctx.hbm_export("PAYLOAD")
+        nw = (e.payload_bits + 31) // 32
+        assert np.array_equal(pay[:nw], e.payload[:nw])
+    stats = ctx.hbm_get_store_stats()
+    assert stats["nsets"] == theta and stats["warmup_sets"] == W
+    if e.lens is not None:
+        assert stats["payload_bits"] == e.payload_bits and stats["escapes"] == e.n_escapes
+    _check_sets(ctx, st, theta)
+    seeds, gains, cov = ctx.hbm_select_seeds(25)
+    os_, og_, oc = orc.greedy(st, g.n, 25)
+    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
+
+
+# ---------------------------------------------------------------- IMM
+@pytest.mark.parametrize("model,enc", [("IC", "HOT_BITMAP"), ("LT", "HUFFMAN"), ("IC", "NONE")])
+def test_imm_small(orc, ctx, model, enc):
+    _say("imm", model, enc)
+    g = G.rmat(13, seed=31)
+    prob = "WC" if model == "IC" else "EDGE"
+    if model == "LT":
+        g = G.with_weights(g, G.lt_weights(g, 6))
+    k, eps = 10, 0.5
+    ctx.load_synth(g, model, prob)
+    ctx.hbm_set_encoding(enc, 0.1, 0.01)
+    seeds, gains, st = ctx.hbm_imm(k, eps, 1.0, 42)
+    og = _ograph(orc, g, model, prob)
+    os_, og_, ost, _ = orc.imm(og, k, eps, 1.0, 42)
+    assert st["theta_round"] == ost["theta_round"]
+    assert st["cov_round"] == ost["cov_round"]
+    assert st["lb"] == ost["lb"] and st["theta_final"] == ost["theta_final"]
+    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == ost["coverage"]
+
+
+# ---------------------------------------------------------------- launch-shape invariance
+@pytest.mark.parametrize("tier1,budget,block", [(0, 0, 1 << 21), (1, 0, 1 << 21), (1, 256, 1024), (1, 4096, 3000)])
+def test_tuning_invariance(orc, ctx, tier1, budget, block):
+    """Tier choice, tier-1 work budget and block size change speed only, never the sets."""
+    _say("tuning invariance", tier1, budget, block)
+    g = G.rmat(14, seed=14)
+    ctx.load_synth(g, "IC", "WC")
+    ctx.hbm_set_tuning("IC_TIER1", tier1)
+    ctx.hbm_set_tuning("IC_T1_BUDGET", budget)
+    ctx.hbm_set_tuning("BLOCK_SETS", block)
+    ctx.hbm_set_encoding("HOT_BITMAP", 0.1, 0.01)
+    theta = 20_000
+    ctx.hbm_sample_rr(theta, 42)
+    og = _ograph(orc, g, "IC", "WC")
+    st = orc.sample_store(og, 42, theta)
+    _check_sets(ctx, st, theta)
+    seeds, gains, cov = ctx.hbm_select_seeds(15)
+    os_, og_, oc = orc.greedy(st, g.n, 15)
+    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
