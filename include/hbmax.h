@@ -201,6 +201,27 @@ typedef enum hbm_tune_key {
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);
 
+/* ---------------------------------------------------------------- profiling */
+
+/* Per-kernel statistics gathered while profiling is on: every launch is timed
+ * with a pair of HIP events recorded on the context's stream.  alg_bytes and
+ * alg_ops are the algorithmic traffic and work of those launches (the bytes the
+ * method must move, excluding re-reads; ops = Philox calls for samplers), from
+ * device-side counters where the amount depends on the data. */
+typedef struct hbm_kernel_stat {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+    double alg_ops;
+} hbm_kernel_stat;
+
+/* enable != 0 starts profiling and clears the statistics; 0 stops it. */
+hbm_status hbm_profile(hbm_ctx *ctx, int32_t enable);
+
+/* Copy up to `cap` entries into host `out`; *count gets the number available. */
+hbm_status hbm_profile_read(hbm_ctx *ctx, hbm_kernel_stat *out, int32_t cap, int32_t *count);
+
 /* ---------------------------------------------------------------- inspection */
 
 /* Decode RR set j to ascending ids in host `buf` (capacity `cap`); *len gets

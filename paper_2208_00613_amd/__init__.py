@@ -27,7 +27,7 @@ ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uin
           "PAYLOAD": (12, np.uint32)}
 EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
-            "hbm_export", "hbm_version", "hbm_set_tuning"]
+            "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_profile", "hbm_profile_read"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2}
 
 
@@ -47,6 +47,11 @@ class StoreStats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("alg_bytes", C.c_double), ("alg_ops", C.c_double)]
 
 
 class ImmStats(C.Structure):
@@ -93,6 +98,8 @@ def lib():
         "hbm_export": ([P, C.c_int, P, I64, C.POINTER(I64)], C.c_int),
         "hbm_version": ([], C.c_char_p),
         "hbm_set_tuning": ([P, C.c_int, I64], C.c_int),
+        "hbm_profile": ([P, I32], C.c_int),
+        "hbm_profile_read": ([P, C.POINTER(KernelStat), I32, C.POINTER(I32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -146,6 +153,17 @@ class Context:
     # ---------------------------------------------------------------- API (same names as the C ABI)
     def hbm_set_budget(self, nbytes: int):
         self._check(lib().hbm_set_budget(self.h, int(nbytes)))
+
+    def hbm_profile(self, enable: bool):
+        self._check(lib().hbm_profile(self.h, 1 if enable else 0))
+
+    def hbm_profile_read(self) -> list:
+        cnt = C.c_int32()
+        self._check(lib().hbm_profile_read(self.h, None, 0, C.byref(cnt)))
+        arr = (KernelStat * max(cnt.value, 1))()
+        self._check(lib().hbm_profile_read(self.h, arr, cnt.value, C.byref(cnt)))
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                     alg_bytes=arr[i].alg_bytes, alg_ops=arr[i].alg_ops) for i in range(cnt.value)]
 
     def hbm_set_tuning(self, key: str, value: int):
         self._check(lib().hbm_set_tuning(self.h, TUNE[key], int(value)))

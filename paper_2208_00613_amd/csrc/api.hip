@@ -229,6 +229,33 @@ hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
     });
 }
 
+hbm_status hbm_profile(hbm_ctx *ctx, int32_t enable) {
+    return guard(ctx, [&](Ctx &c) {
+        hbm::prof_flush(c);
+        c.prof.on = enable != 0;
+        if (enable) c.prof.stats.clear();
+        if (c.dctr.p) hbm::buf_zero(c, c.dctr, 0, hbm::DC_COUNT * 8);
+    });
+}
+
+hbm_status hbm_profile_read(hbm_ctx *ctx, hbm_kernel_stat *out, int32_t cap, int32_t *count) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(count, HBM_EINVAL, "null count");
+        hbm::prof_flush(c);
+        const auto &S = c.prof.stats;
+        *count = (int32_t)S.size();
+        for (int32_t i = 0; i < cap && i < (int32_t)S.size(); i++) {
+            hbm_kernel_stat &o = out[i];
+            std::memset(o.name, 0, sizeof(o.name));
+            std::strncpy(o.name, S[(size_t)i].name.c_str(), sizeof(o.name) - 1);
+            o.launches = S[(size_t)i].launches;
+            o.total_ms = S[(size_t)i].ms;
+            o.alg_bytes = S[(size_t)i].bytes;
+            o.alg_ops = S[(size_t)i].ops;
+        }
+    });
+}
+
 hbm_status hbm_get_rr(hbm_ctx *ctx, int64_t j, int32_t *buf, int64_t cap, int64_t *len) {
     return guard(ctx, [&](Ctx &c) {
         HBM_REQUIRE(len, HBM_EINVAL, "null len");

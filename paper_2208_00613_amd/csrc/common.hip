@@ -91,4 +91,78 @@ void scan_u64_to_i64(Ctx &c, const uint64_t *in, int64_t *out, int64_t count, in
     scan_impl(c, in, out, count, init);
 }
 
+// ------------------------------------------------------------------ profiler
+int prof_begin(Ctx &c, const char *name) {
+    if (!c.prof.on) return -1;
+    Prof &P = c.prof;
+    int k = -1;
+    for (size_t i = 0; i < P.stats.size(); i++)
+        if (P.stats[i].name == name) k = (int)i;
+    if (k < 0) {
+        P.stats.push_back(KStat{name});
+        k = (int)P.stats.size() - 1;
+    }
+    ProfPending e{k, nullptr, nullptr, 0, 0};
+    for (hipEvent_t *ev : {&e.a, &e.b}) {
+        if (!P.pool.empty()) {
+            *ev = P.pool.back();
+            P.pool.pop_back();
+        } else {
+            HBM_HIP(hipEventCreate(ev));
+        }
+    }
+    HBM_HIP(hipEventRecord(e.a, c.stream));
+    P.pending.push_back(e);
+    return (int)P.pending.size() - 1;
+}
+
+void prof_end(Ctx &c, int slot, double bytes, double ops) {
+    if (slot < 0) return;
+    ProfPending &e = c.prof.pending[(size_t)slot];
+    HBM_HIP(hipEventRecord(e.b, c.stream));
+    e.bytes += bytes;
+    e.ops += ops;
+}
+
+void prof_add(Ctx &c, int slot, double bytes, double ops) {
+    if (slot < 0) return;
+    c.prof.pending[(size_t)slot].bytes += bytes;
+    c.prof.pending[(size_t)slot].ops += ops;
+}
+
+void prof_flush(Ctx &c) {
+    Prof &P = c.prof;
+    if (P.pending.empty()) return;
+    HBM_HIP(hipEventSynchronize(P.pending.back().b));
+    for (ProfPending &e : P.pending) {
+        float ms = 0;
+        HBM_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+        KStat &k = P.stats[(size_t)e.kernel];
+        k.launches++;
+        k.ms += ms;
+        k.bytes += e.bytes;
+        k.ops += e.ops;
+        P.pool.push_back(e.a);
+        P.pool.push_back(e.b);
+    }
+    P.pending.clear();
+}
+
+unsigned long long *prof_counters(Ctx &c) {
+    if (!c.prof.on) return nullptr;
+    if (!c.dctr.p) {
+        buf_alloc(c, c.dctr, DC_COUNT * 8);
+        buf_zero(c, c.dctr, 0, DC_COUNT * 8);
+    }
+    return c.dctr.as<unsigned long long>();
+}
+
+void prof_read_counters(Ctx &c, unsigned long long *host) {
+    for (int i = 0; i < DC_COUNT; i++) host[i] = 0;
+    if (!c.prof.on || !c.dctr.p) return;
+    HBM_HIP(hipMemcpyAsync(host, c.dctr.p, DC_COUNT * 8, hipMemcpyDeviceToHost, c.stream));
+    HBM_HIP(hipStreamSynchronize(c.stream));
+    buf_zero(c, c.dctr, 0, DC_COUNT * 8);
+}
+
 }  // namespace hbm

@@ -147,6 +147,27 @@ struct SelState {
     int64_t words_cap = 0;
 };
 
+// ------------------------------------------------------------------ profiler
+struct KStat {
+    std::string name;
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, ops = 0;
+};
+struct ProfPending {
+    int kernel;
+    hipEvent_t a, b;
+    double bytes, ops;
+};
+struct Prof {
+    bool on = false;
+    std::vector<KStat> stats;
+    std::vector<ProfPending> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+// device counters of the samplers (indices into Ctx::dctr)
+enum : int { DC_PHILOX = 0, DC_EXPANDED = 1, DC_LIVE = 2, DC_EDGES = 3, DC_MEMBERS = 4, DC_PROBES = 5, DC_COUNT = 8 };
+
 // ------------------------------------------------------------------ context
 struct Ctx {
     int device = 0;
@@ -165,6 +186,8 @@ struct Ctx {
     Scratch sc;
     SelState sel;
     Buf scan_tmp;  // rocPRIM temporary storage
+    Prof prof;
+    Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)
     // timing of the last operations (ms)
     double t_sample = 0, t_encode = 0, t_select = 0;
 };
@@ -186,6 +209,15 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed);
 
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
 void select_free(Ctx &c);
+
+// profiler: prof_begin records the start event of a launch (returns -1 when off),
+// prof_end the stop event; prof_set fills in work that is known only later.
+int prof_begin(Ctx &c, const char *name);
+void prof_end(Ctx &c, int slot, double bytes = 0, double ops = 0);
+void prof_add(Ctx &c, int slot, double bytes, double ops);
+void prof_flush(Ctx &c);
+unsigned long long *prof_counters(Ctx &c);  // device counters, or null when profiling is off
+void prof_read_counters(Ctx &c, unsigned long long *host);  // and clear them
 
 // launch helpers
 inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {

@@ -47,6 +47,7 @@ struct SampleArgs {
     unsigned long long *ctrl;
     uint32_t *defer;   // deferred block offsets (tier 1 -> tier 2)
     uint64_t gbudget;  // edge groups a tier-1 wave may expand per set (0 = no limit)
+    unsigned long long *dctr;  // work counters (DC_*), or null
     uint32_t *defer2;  // deferred block offsets (tier 2 -> tier 3)
 };
 
@@ -153,6 +154,8 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     const int step = a.nb >= 65536 ? 8 : 1;
     WaveArena A;
+    // work of completed sets (profiling): Philox calls, expanded vertices, in-edges, live edges, members
+    uint64_t c_ph = 0, c_exp = 0, c_edges = 0, c_live = 0, c_mem = 0;
     for (;;) {
         uint64_t jb = 0;
         if (lane == 0) jb = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)step);
@@ -173,7 +176,8 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
             }
             wave_sync();
             uint32_t head = 0, qsize = 1;
-            uint64_t work = 0;
+            uint64_t work = 0, s_exp = 0, s_edges = 0;
+            uint32_t s_live = 0;
             bool ovf = false;
             while (head < qsize) {
                 const uint32_t nbat = qsize - head < (uint32_t)WAVE ? qsize - head : (uint32_t)WAVE;
@@ -191,6 +195,10 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
                 if (a.gbudget && work > a.gbudget) {  // heavy set: tier 2 spreads it over a whole workgroup
                     ovf = true;
                     break;
+                }
+                if (a.dctr) {
+                    s_exp += nbat;
+                    s_edges += wave_sum(e1 - e0);
                 }
                 S.sP[lane] = P;
                 S.sE0[lane] = e0;
@@ -218,6 +226,7 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
                         for (uint32_t qq = 0; qq < 4; qq++) {
                             const uint32_t e = eb + qq;
                             if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
+                                s_live++;
                                 // Once the queue is full the set is redone by tier 2; stop inserting so
                                 // the table never holds more than QC + 64 keys (always has free slots).
                                 if (S.cnt >= (uint32_t)L::QC) {
@@ -283,8 +292,22 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
                 a.pos[b] = (uint32_t)at;
                 a.size[b] = (uint32_t)s;
             }
+            if (a.dctr) {
+                c_ph += work;
+                c_exp += s_exp;
+                c_edges += s_edges;
+                c_live += wave_sum(s_live);
+                c_mem += (uint64_t)s;
+            }
             wave_sync();
         }
+    }
+    if (a.dctr && lane == 0) {
+        atomicAdd(&a.dctr[DC_PHILOX], (unsigned long long)c_ph);
+        atomicAdd(&a.dctr[DC_EXPANDED], (unsigned long long)c_exp);
+        atomicAdd(&a.dctr[DC_EDGES], (unsigned long long)c_edges);
+        atomicAdd(&a.dctr[DC_LIVE], (unsigned long long)c_live);
+        atomicAdd(&a.dctr[DC_MEMBERS], (unsigned long long)c_mem);
     }
 }
 
@@ -352,9 +375,11 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
     __shared__ uint32_t item;
     __shared__ unsigned long long s_at;
     __shared__ int s_ok;
+    __shared__ unsigned long long s_ctr[DC_COUNT];
     uint32_t *bm = t.bitmap + (uint64_t)blockIdx.x * t.words;
     uint32_t *queue = t.queue + (uint64_t)blockIdx.x * (uint64_t)a.n;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
     for (;;) {
         if (threadIdx.x == 0) item = (uint32_t)atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
         __syncthreads();
@@ -392,6 +417,13 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
                     sT[threadIdx.x] = tv;
                     __syncthreads();
                     const uint32_t G = sP[T2_THREADS - 1];
+                    if (a.dctr) {
+                        if (threadIdx.x == 0) {
+                            s_ctr[DC_PHILOX] += G;
+                            s_ctr[DC_EXPANDED] += cn;
+                        }
+                        if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
+                    }
                     for (uint32_t g = threadIdx.x; g < G; g += T2_THREADS) {
                         const uint32_t i = upper_bound_dev<uint32_t, uint32_t>(sP, 0u, cn, g);
                         const uint32_t excl = i ? sP[i - 1] : 0u;
@@ -411,6 +443,7 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
                             const uint32_t e = eb + qq;
                             if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
                                 const uint32_t u = (uint32_t)a.in_src[e];
+                                if (a.dctr) atomicAdd(&s_ctr[DC_LIVE], 1ull);
                                 const uint32_t bit = 1u << (u & 31);
                                 const uint32_t old = atomicOr(&bm[u >> 5], bit);
                                 if (!(old & bit)) {
@@ -434,6 +467,11 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
                 const uint32_t r = y.x >> 8;
                 const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
                 const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                if (a.dctr) {
+                    s_ctr[DC_PHILOX] += 1;
+                    s_ctr[DC_EXPANDED] += 1;
+                    s_ctr[DC_PROBES] += 32 - __clz(e1 - e0);
+                }
                 if (e == e1) break;
                 const uint32_t s = (uint32_t)a.in_src[e];
                 const uint32_t bit = 1u << (s & 31);
@@ -447,6 +485,7 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
         __syncthreads();
         const uint32_t s = qn;
         if (threadIdx.x == 0) {
+            s_ctr[DC_MEMBERS] += s;
             const unsigned long long at = atomicAdd(&a.ctrl[CW_CURSOR], (unsigned long long)s);
             s_at = at;
             s_ok = at + s <= a.cap;
@@ -475,6 +514,7 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
         for (uint32_t i = threadIdx.x; i < s; i += T2_THREADS) bm[queue[i] >> 5] = 0u;
         __syncthreads();
     }
+    if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------- LT tier 1
@@ -488,6 +528,7 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
     bool active = false, exhausted = false;
     uint32_t b = 0, cur = 0, len = 0;
     uint64_t j = 0;
+    uint64_t c_steps = 0, c_probes = 0, c_mem = 0;  // per lane (profiling)
     for (;;) {
         // refill idle lanes with one atomic per wave
         const uint64_t idle = __ballot(!active && !exhausted);
@@ -518,6 +559,8 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
             const uint32_t r = y.x >> 8;
             const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
             const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+            c_steps++;
+            c_probes += 32 - __clz(e1 - e0);
             if (e == e1) {
                 finished = true;
             } else {
@@ -567,11 +610,22 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
                     for (uint32_t x = 0; x < len; x++) a.mem[o + x] = path[x * WAVE + lane];
                     a.pos[b] = (uint32_t)o;
                     a.size[b] = len;
+                    c_mem += len;
                 } else {
                     mark_ovf(a, b);
                 }
                 active = false;
             }
+        }
+    }
+    if (a.dctr) {
+        // steps of walks that were deferred are counted too: they are the work this kernel did
+        const uint64_t st = wave_sum(c_steps), pr = wave_sum(c_probes), mm = wave_sum(c_mem);
+        if (lane == 0) {
+            atomicAdd(&a.dctr[DC_PHILOX], (unsigned long long)st);
+            atomicAdd(&a.dctr[DC_EXPANDED], (unsigned long long)st);
+            atomicAdd(&a.dctr[DC_PROBES], (unsigned long long)pr);
+            atomicAdd(&a.dctr[DC_MEMBERS], (unsigned long long)mm);
         }
     }
 }
@@ -597,6 +651,7 @@ __global__ __launch_bounds__(WAVE) void k_lt_t2(Lt2Args t) {
     uint32_t *Sl = Pp + LT2_QC;  // hash slot of each path entry
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     WaveArena A;
+    uint64_t c_steps = 0, c_probes = 0, c_mem = 0;
     for (;;) {
         uint64_t it = 0;
         if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], (unsigned long long)WAVE);
@@ -617,6 +672,8 @@ __global__ __launch_bounds__(WAVE) void k_lt_t2(Lt2Args t) {
                 const uint32_t r = y.x >> 8;
                 const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
                 const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                c_steps++;
+                c_probes += 32 - __clz(e1 - e0);
                 if (e == e1) break;
                 const uint32_t s = (uint32_t)a.in_src[e];
                 uint32_t hs = hash32(s, LT2_HB);
@@ -667,9 +724,19 @@ __global__ __launch_bounds__(WAVE) void k_lt_t2(Lt2Args t) {
                 for (uint32_t x = 0; x < len; x++) a.mem[o + x] = Pp[x];
                 a.pos[b] = (uint32_t)o;
                 a.size[b] = len;
+                c_mem += len;
             } else {
                 mark_ovf(a, b);
             }
+        }
+    }
+    if (a.dctr) {
+        const uint64_t st = wave_sum(c_steps), pr = wave_sum(c_probes), mm = wave_sum(c_mem);
+        if (lane == 0) {
+            atomicAdd(&a.dctr[DC_PHILOX], (unsigned long long)st);
+            atomicAdd(&a.dctr[DC_EXPANDED], (unsigned long long)st);
+            atomicAdd(&a.dctr[DC_PROBES], (unsigned long long)pr);
+            atomicAdd(&a.dctr[DC_MEMBERS], (unsigned long long)mm);
         }
     }
 }
@@ -721,6 +788,27 @@ static void ensure_t2(Ctx &c) {
     sc.t2_slots = slots;
 }
 
+// Algorithmic traffic of the samplers from the work counters.
+//  IC, per expanded vertex: its in_ptr pair (16 B) and threshold (4 B per vertex
+//  under WC, 4 B per in-edge otherwise); 4 B per live in-edge (source id); 4 B per
+//  member written.  Ops: Philox calls.
+//  LT, per walk step: in_ptr pair (16 B), 4 B per binary-search probe, 4 B source
+//  id; 4 B per member written.  Ops: Philox calls (one per step).
+static void prof_sampler(Ctx &c, int slot) {
+    if (slot < 0) return;
+    unsigned long long k[DC_COUNT];
+    prof_read_counters(c, k);
+    double bytes;
+    if (c.g.model == HBM_IC) {
+        const bool wc = c.g.prob == HBM_PROB_WC;
+        bytes = 16.0 * k[DC_EXPANDED] + 4.0 * (wc ? k[DC_EXPANDED] : k[DC_EDGES]) + 4.0 * k[DC_LIVE] +
+                4.0 * k[DC_MEMBERS];
+    } else {
+        bytes = 20.0 * k[DC_EXPANDED] + 4.0 * k[DC_PROBES] + 4.0 * k[DC_MEMBERS];
+    }
+    prof_add(c, slot, bytes, (double)k[DC_PHILOX]);
+}
+
 int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
     Scratch &sc = c.sc;
     const int64_t nb = j1 - j0;
@@ -744,6 +832,9 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
     a.defer2 = sc.defer.as<uint32_t>() + sc.bcap;
 
     a.gbudget = (uint64_t)c.ic_t1_budget;
+    a.dctr = prof_counters(c);
+    const bool ic = c.g.model == HBM_IC;
+    const int s1 = (ic && !c.ic_tier1) ? -1 : prof_begin(c, ic ? "ic_sample_wave" : "lt_sample_lane");
     if (c.g.model == HBM_IC && !c.ic_tier1) {
         // every set goes to tier 2 (one workgroup per set)
         k_iota_u32<<<grid_for(nb, 256, 65536), 256, 0, c.stream>>>(a.defer, (uint64_t)nb);
@@ -758,7 +849,9 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
         k_lt_t1<<<grid, WAVE, 0, c.stream>>>(a);
     }
     HBM_HIP(hipGetLastError());
+    prof_end(c, s1);
     Ctrl r = read_ctrl(c);
+    prof_sampler(c, s1);
     const uint64_t nd = r.w[CW_NDEFER];
     if (nd > 0) {
         if (c.g.model == HBM_IC) {
@@ -772,8 +865,14 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
             t.nlist = (uint32_t)nd;
             t.model = HBM_IC;
             const unsigned grid = (unsigned)std::min<uint64_t>(nd, (uint64_t)sc.t2_slots);
+            const int s2 = prof_begin(c, "ic_sample_block");
             k_big<<<grid, T2_THREADS, 0, c.stream>>>(t);
             HBM_HIP(hipGetLastError());
+            prof_end(c, s2);
+            if (s2 >= 0) {
+                HBM_HIP(hipStreamSynchronize(c.stream));
+                prof_sampler(c, s2);
+            }
         } else {
             // tier 2: lane per walk with device-memory hash and path
             if (!sc.lt2_lanes) {
@@ -793,9 +892,12 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
             t.pathb = sc.lt2_path.as<uint32_t>();
             t.list = a.defer;
             t.nlist = (uint32_t)nd;
+            const int s2 = prof_begin(c, "lt_sample_lane_dev");
             k_lt_t2<<<(unsigned)(lanes / WAVE), WAVE, 0, c.stream>>>(t);
             HBM_HIP(hipGetLastError());
+            prof_end(c, s2);
             Ctrl r2 = read_ctrl(c);
+            prof_sampler(c, s2);
             const uint64_t nd3 = r2.w[CW_NDEFER];
             if (nd3 > 0) {
                 ensure_t2(c);
@@ -809,8 +911,14 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
                 t3.nlist = (uint32_t)nd3;
                 t3.model = HBM_LT;
                 const unsigned grid = (unsigned)std::min<uint64_t>(nd3, (uint64_t)sc.t2_slots);
+                const int s3 = prof_begin(c, "lt_sample_block");
                 k_big<<<grid, T2_THREADS, 0, c.stream>>>(t3);
                 HBM_HIP(hipGetLastError());
+                prof_end(c, s3);
+                if (s3 >= 0) {
+                    HBM_HIP(hipStreamSynchronize(c.stream));
+                    prof_sampler(c, s3);
+                }
             }
         }
         r = read_ctrl(c);

@@ -49,11 +49,13 @@ struct SelArgs {
     int32_t ustar_enc;
     int64_t nraw;                 // plain ids in the store
     unsigned long long *partial;  // per-block argmax partials
-    unsigned *ticket;             // blocks finished (reset by the last one)
+    int32_t nparts;               // argmax blocks
 };
 
-// Exact argmax over counts; also clears the `newly` words for this iteration's find step.
-// Each block reduces its slice, writes a partial, and the last block to finish reduces the partials.
+// Exact argmax over counts, stage 1: each block writes the best key of its slice to
+// partial[block]; the consumer kernels of the same iteration reduce the partials
+// themselves (no atomics or fences needed: kernel boundaries order the stream).
+// Also clears the `newly` words for this iteration's find step.
 __global__ __launch_bounds__(256) void k_argmax(SelArgs A, int t) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
@@ -81,35 +83,30 @@ __global__ __launch_bounds__(256) void k_argmax(SelArgs A, int t) {
     }
     best = wave_max_u64(best);
     __shared__ unsigned long long part[256 / WAVE];
-    __shared__ bool last;
     if (lane_id() == 0) part[threadIdx.x / WAVE] = best;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long b = part[0];
         for (int i = 1; i < (int)(blockDim.x / WAVE); i++) b = part[i] > b ? part[i] : b;
         A.partial[blockIdx.x] = b;
-        __threadfence();
-        const unsigned ticket = atomicAdd(A.ticket, 1u);
-        last = ticket == gridDim.x - 1;
     }
+}
+
+// Stage 2, run at the start of every consumer block: the key of u* (block-uniform).
+__device__ unsigned long long argmax_key(const SelArgs &A) {
+    __shared__ unsigned long long red[1024 / WAVE];
+    unsigned long long b = 0;
+    for (int i = threadIdx.x; i < A.nparts; i += blockDim.x) {
+        const unsigned long long x = A.partial[i];
+        b = x > b ? x : b;
+    }
+    b = wave_max_u64(b);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = b;
     __syncthreads();
-    if (last) {
-        __threadfence();
-        unsigned long long b = 0;
-        for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) {
-            const unsigned long long x = __hip_atomic_load(&A.partial[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            b = x > b ? x : b;
-        }
-        b = wave_max_u64(b);
-        if (lane_id() == 0) part[threadIdx.x / WAVE] = b;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long m = part[0];
-            for (int i = 1; i < (int)(blockDim.x / WAVE); i++) m = part[i] > m ? part[i] : m;
-            A.keys[t] = m;
-            *A.ticket = 0u;
-        }
-    }
+    unsigned long long m = red[0];
+    for (int i = 1; i < (int)(blockDim.x / WAVE); i++) m = red[i] > m ? red[i] : m;
+    __syncthreads();
+    return m;
 }
 
 struct Tabs {
@@ -170,7 +167,8 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, int64_t j) {
 }
 
 __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
-    key = A.keys[t];
+    (void)t;
+    key = argmax_key(A);
     return ~(uint32_t)key;
 }
 
@@ -246,7 +244,10 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
+        A.keys[t] = key;
+    }
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
     const unsigned lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
@@ -310,10 +311,7 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
     buf_grow(c, S.keys, (size_t)k * 8, false);
     const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256, (int64_t)c.num_cus * 2);
-    if (S.partial.bytes < (size_t)g_arg * 8 + 8) {
-        buf_grow(c, S.partial, (size_t)g_arg * 8 + 8, false);
-        buf_zero(c, S.partial, 0, S.partial.bytes);
-    }
+    buf_grow(c, S.partial, (size_t)g_arg * 8, false);
     if (T > 0) HBM_HIP(hipMemcpyAsync(S.counts.p, s.hist.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c.stream));
     else buf_zero(c, S.counts, 0, (size_t)n * 4);
     buf_zero(c, S.selmask, 0, ((size_t)n + 31) / 32 * 4);
@@ -348,7 +346,7 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     A.ustar_enc = s.cb.ustar_enc;
     A.nraw = huff ? 0 : s.raw_count;
     A.partial = S.partial.as<unsigned long long>();
-    A.ticket = reinterpret_cast<unsigned *>(S.partial.as<unsigned long long>() + g_arg);
+    A.nparts = (int32_t)g_arg;
 
     const unsigned g_mark = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
     const unsigned g_find = grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)c.num_cus * 4);
@@ -356,13 +354,34 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / hx));
     const int64_t seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
     nseg = std::max<int64_t>(1, (words + seg - 1) / seg);
+    // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
+    // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
+    // reads and writes the covered and newly words (and the hot row when u* is hot).
+    const double b_arg = 4.0 * n + 4.0 * ((n + 31) / 32) + 8.0 * words;
+    const double b_find = huff ? (double)((s.nbits + 7) / 8) + 16.0 * T : 4.0 * A.nraw;
+    const double b_apply = 24.0 * words;
     for (int t = 0; t < k; t++) {
+        int ps = prof_begin(c, "argmax");
         k_argmax<<<g_arg, 256, 0, c.stream>>>(A, t);
+        prof_end(c, ps, b_arg);
         if (T > 0) {
-            if (huff) k_find_huff<<<g_mark, 256, 0, c.stream>>>(A, t);
-            else if (A.nraw > 0) k_find_raw<<<g_find, 256, 0, c.stream>>>(A, t);
+            if (huff) {
+                ps = prof_begin(c, "find_huff");
+                k_find_huff<<<g_mark, 256, 0, c.stream>>>(A, t);
+                prof_end(c, ps, b_find);
+            } else if (A.nraw > 0) {
+                ps = prof_begin(c, "find_raw");
+                k_find_raw<<<g_find, 256, 0, c.stream>>>(A, t);
+                prof_end(c, ps, b_find);
+            }
+            ps = prof_begin(c, "apply");
             k_apply<<<g_mark, 256, 0, c.stream>>>(A, t);
-            if (s.nhot > 0) k_dec_hot<<<dim3(hx, (unsigned)nseg), 256, 0, c.stream>>>(A, seg);
+            prof_end(c, ps, b_apply);
+            if (s.nhot > 0) {
+                ps = prof_begin(c, "dec_hot");
+                k_dec_hot<<<dim3(hx, (unsigned)nseg), 256, 0, c.stream>>>(A, seg);
+                prof_end(c, ps);
+            }
         } else {
             k_apply<<<1, 64, 0, c.stream>>>(A, t);  // only records the selection
         }

@@ -545,7 +545,11 @@ static void append_block(Ctx &c, int64_t j0, int64_t done) {
     BlockView bv{sc.mem.as<uint32_t>(), sc.pos.as<uint32_t>(), sc.size.as<uint32_t>(), done};
     const unsigned gw = grid_for(done * WAVE, 256, 65536);
     const unsigned gt = grid_for(done, 256, 65536);
-    k_hist_add<<<gw, 256, 0, c.stream>>>(bv, s.hist.as<uint32_t>());
+    {
+        const int ps_ = prof_begin(c, "hist_add");
+        k_hist_add<<<gw, 256, 0, c.stream>>>(bv, s.hist.as<uint32_t>());
+        prof_end(c, ps_, 0);
+    }
     HBM_HIP(hipGetLastError());
     const bool hot = s.enc == HBM_ENC_HOT_BITMAP || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
@@ -558,7 +562,11 @@ static void append_block(Ctx &c, int64_t j0, int64_t done) {
     if (!huff) {
         // plain ids: sizes -> offsets -> copy
         uint32_t *cnt = sc.cnt.as<uint32_t>();
-        k_cold_count<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, cnt);
+        {
+            const int ps_ = prof_begin(c, "cold_count");
+            k_cold_count<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, cnt);
+            prof_end(c, ps_, 0);
+        }
         HBM_HIP(hipGetLastError());
         buf_grow(c, s.raw_off, (size_t)(new_sets + 1) * 8, true);
         // scan of the block's counts, placed after the existing offsets
@@ -566,15 +574,23 @@ static void append_block(Ctx &c, int64_t j0, int64_t done) {
         scan_u32_to_i64(c, cnt, s.raw_off.as<int64_t>() + j0, done + 1, s.raw_count);
         const int64_t total = read_dev<int64_t>(c, s.raw_off.as<int64_t>() + new_sets);
         buf_grow(c, s.raw_mem, (size_t)std::max<int64_t>(total, 1) * 4, true);
-        k_split<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, j0, s.raw_off.as<int64_t>() + j0,
+        {
+            const int ps_ = prof_begin(c, "split");
+            k_split<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, j0, s.raw_off.as<int64_t>() + j0,
                                           s.raw_mem.as<int32_t>(), s.bitmap.as<unsigned long long>(), s.nhot);
+            prof_end(c, ps_, 0);
+        }
         HBM_HIP(hipGetLastError());
         s.raw_count = total;
     } else {
         HuffEnc h{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
                   s.cb.ustar_enc, s.cb.wbits};
         uint64_t *bits = sc.aux.as<uint64_t>();
-        k_huff_bits<<<gt, 256, 0, c.stream>>>(bv, h, bits);
+        {
+            const int ps_ = prof_begin(c, "huff_bits");
+            k_huff_bits<<<gt, 256, 0, c.stream>>>(bv, h, bits);
+            prof_end(c, ps_, 0);
+        }
         HBM_HIP(hipGetLastError());
         HBM_HIP(hipMemsetAsync(bits + done, 0, 8, c.stream));
         buf_grow(c, s.bitoff, (size_t)(new_sets + 1) * 8, true);
@@ -582,8 +598,12 @@ static void append_block(Ctx &c, int64_t j0, int64_t done) {
         const int64_t total = read_dev<int64_t>(c, s.bitoff.as<int64_t>() + new_sets);
         buf_grow(c, s.payload, (size_t)((total + 31) / 32 + 2) * 4, true);
         HBM_HIP(hipMemsetAsync(sc.ctrl.as<unsigned long long>() + CW_SUM, 0, 8, c.stream));
-        k_huff_write<<<gt, 256, 0, c.stream>>>(bv, h, s.bitoff.as<int64_t>() + j0, s.payload.as<uint32_t>(),
+        {
+            const int ps_ = prof_begin(c, "huff_write");
+            k_huff_write<<<gt, 256, 0, c.stream>>>(bv, h, s.bitoff.as<int64_t>() + j0, s.payload.as<uint32_t>(),
                                                sc.ctrl.as<unsigned long long>() + CW_SUM);
+            prof_end(c, ps_, 0);
+        }
         HBM_HIP(hipGetLastError());
         if (hot)
             k_split<<<gw, 256, 0, c.stream>>>(bv, s.hot_rank.as<int32_t>(), j0, nullptr, nullptr,
