@@ -195,8 +195,10 @@ typedef enum hbm_tune_key {
                                      workgroup of its own */
     HBM_TUNE_IC_T1_BUDGET = 1,    /* edge groups (4 in-edges) one wave may expand before the set moves
                                      to a workgroup of its own; 0 = no limit.  Default 4096 */
-    HBM_TUNE_BLOCK_SETS = 2       /* RR sets sampled per block (scratch index size), >= 1024.
+    HBM_TUNE_BLOCK_SETS = 2,      /* RR sets sampled per block (scratch index size), >= 1024.
                                      Default 2^21 */
+    HBM_TUNE_LT_PATH = 3          /* LT walk length kept in LDS by one lane: 128 (default) or 256;
+                                     longer walks move to device memory */
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

@@ -28,7 +28,7 @@ ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uin
 EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
             "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_profile", "hbm_profile_read"]
-TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2}
+TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3}
 
 
 class HbmError(RuntimeError):

@@ -219,6 +219,10 @@ hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
                 HBM_REQUIRE(value >= 0, HBM_EINVAL, "IC_T1_BUDGET must be >= 0");
                 c.ic_t1_budget = value;
                 break;
+            case HBM_TUNE_LT_PATH:
+                HBM_REQUIRE(value == 128 || value == 256, HBM_EINVAL, "LT_PATH must be 128 or 256");
+                c.lt_lw = (int)value;
+                break;
             case HBM_TUNE_BLOCK_SETS:
                 HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
                 c.block_sets = value;

@@ -119,6 +119,28 @@ __global__ void k_thr_lt(const int64_t *__restrict__ in_ptr, const float *__rest
     }
 }
 
+// LT guide table (cut-point search): row v with d in-edges gets B = 2^ceil(log2 d) buckets
+// stored at [2 * in_ptr[v], 2 * in_ptr[v] + B).  Bucket k holds the first in-edge whose
+// threshold exceeds k * 2^24 / B, so the first edge with threshold > r is found by a
+// forward scan from bucket r * B / 2^24 -- the same edge a binary search would find.
+__global__ void k_guide_lt(const int64_t *__restrict__ in_ptr, const uint32_t *__restrict__ thr, int32_t n,
+                           uint32_t *__restrict__ guide) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e0 = (uint32_t)in_ptr[v], e1 = (uint32_t)in_ptr[v + 1];
+        if (e1 == e0) continue;
+        const uint32_t d = e1 - e0;
+        const uint32_t lb = d > 1 ? min(32 - __clz(d - 1), 24) : 0;
+        const uint32_t B = 1u << lb;
+        uint32_t e = e0;
+        uint32_t *G = guide + 2 * (uint64_t)e0;
+        for (uint32_t k = 0; k < B; k++) {
+            const uint32_t lo = k << (24 - lb);
+            while (e < e1 && thr[e] <= lo) e++;
+            G[k] = e;
+        }
+    }
+}
+
 static std::string flag_text(uint32_t f) {
     std::string s;
     if (f & BAD_ROWPTR) s += "row_ptr malformed; ";
@@ -142,6 +164,7 @@ void graph_free(Ctx &c) {
     buf_free(c, c.g.in_ptr);
     buf_free(c, c.g.in_src);
     buf_free(c, c.g.thr);
+    buf_free(c, c.g.guide);
     c.g.loaded = false;
     c.g.n = 0;
     c.g.m = 0;
@@ -239,6 +262,12 @@ void graph_load(Ctx &c, int32_t n, int64_t m, const int64_t *row_ptr, const int3
         HBM_HIP(hipGetLastError());
         f = read_flags(c, flags);
         HBM_REQUIRE(f == 0, HBM_EINVAL, flag_text(f));
+        if (model == HBM_LT) {
+            buf_alloc(c, g.guide, mm * 8);
+            k_guide_lt<<<grid_for(n, 64, 65536), 64, 0, c.stream>>>(g.in_ptr.as<int64_t>(), g.thr.as<uint32_t>(), n,
+                                                                    g.guide.as<uint32_t>());
+            HBM_HIP(hipGetLastError());
+        }
         cleanup();
     } catch (...) {
         cleanup();

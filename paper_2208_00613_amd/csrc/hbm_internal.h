@@ -53,10 +53,13 @@ struct DGraph {
     Buf in_ptr;  // int64[n+1]
     Buf in_src;  // int32[m]
     Buf thr;     // uint32[m] (IC-EDGE, LT) or uint32[n] (IC-WC)
+    Buf guide;   // uint32[2m] LT cut-point index (see graph.hip)
     bool loaded = false;
 };
 
 // ------------------------------------------------------------------ store
+constexpr int LUT_BITS = 11;
+
 struct Codebook {
     int32_t nsym = 0;       // coded vertices
     int32_t maxlen = 0;
@@ -95,6 +98,7 @@ struct Store {
     Buf codes;     // uint32[n]
     Buf symtab;    // int32[nsym] ids ordered by (length, id)
     Buf cbtab;     // uint64 lim[34], int64 base[34] decode tables
+    Buf lut;       // uint32[2^LUT_BITS]: (symbol << 5) | length for codes of <= LUT_BITS bits, else 0
     Buf bitoff;    // int64[nsets+1]
     Buf payload;   // uint32[]
     uint64_t nbits = 0;
@@ -116,9 +120,6 @@ struct Scratch {
     Buf t2_bitmap;  // uint32 words: slots * ceil(n/32)
     Buf t2_queue;   // uint32: slots * n
     int t2_slots = 0;
-    Buf lt2_hash;   // uint32: lanes * 4096, kept empty between walks
-    Buf lt2_path;   // uint32: lanes * 2 * 2048 (path, slots)
-    uint64_t lt2_lanes = 0;
     Buf aux;        // uint64 per set (+1): bit lengths
     Buf cnt;        // uint32 per set (+1): plain-id counts
 };
@@ -181,6 +182,7 @@ struct Ctx {
     int ic_tier1 = 1;
     int64_t ic_t1_budget = 4096;
     int64_t block_sets = int64_t(1) << 21;
+    int lt_lw = 128;
     DGraph g;
     Store s;
     Scratch sc;

@@ -35,6 +35,7 @@ struct SampleArgs {
     const int64_t *in_ptr;
     const int32_t *in_src;
     const uint32_t *thr;
+    const uint32_t *guide;  // LT cut-point index
     int32_t n;
     int wc;          // thresholds per vertex (IC-WC)
     uint64_t seed;
@@ -125,6 +126,24 @@ __device__ __forceinline__ void mark_ovf(const SampleArgs &a, uint32_t b) {
     a.pos[b] = POS_OVF;
     a.size[b] = 0;
     atomicMin(&a.ctrl[CW_FIRST_OVF], (unsigned long long)b);
+}
+
+// LT: the in-edge that vertex `cur` keeps for draw r -- the first e with thr[e] > r, or e1
+// when there is none -- via the cut-point index; *probes counts threshold reads.
+__device__ __forceinline__ uint32_t lt_pick(const SampleArgs &a, uint32_t cur, uint32_t r, uint32_t &e1,
+                                            uint32_t &probes) {
+    const uint32_t e0 = (uint32_t)a.in_ptr[cur];
+    e1 = (uint32_t)a.in_ptr[cur + 1];
+    if (e1 == e0) return e1;
+    const uint32_t d = e1 - e0;
+    const uint32_t lb = d > 1 ? min(32 - __clz(d - 1), 24) : 0;
+    uint32_t e = a.guide[2 * (uint64_t)e0 + (r >> (24 - lb))];
+    probes++;
+    while (e < e1 && a.thr[e] <= r) {
+        e++;
+        probes++;
+    }
+    return e;
 }
 
 // ---------------------------------------------------------------------------- IC tier 1
@@ -465,12 +484,12 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
             for (;;) {
                 const uint4 y = philox10(jlo, jhi, cur, 2u, k0, k1);
                 const uint32_t r = y.x >> 8;
-                const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
-                const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                uint32_t e1, probes = 0;
+                const uint32_t e = lt_pick(a, cur, r, e1, probes);
                 if (a.dctr) {
                     s_ctr[DC_PHILOX] += 1;
                     s_ctr[DC_EXPANDED] += 1;
-                    s_ctr[DC_PROBES] += 32 - __clz(e1 - e0);
+                    s_ctr[DC_PROBES] += probes;
                 }
                 if (e == e1) break;
                 const uint32_t s = (uint32_t)a.in_src[e];
@@ -518,8 +537,8 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
 }
 
 // ---------------------------------------------------------------------------- LT tier 1
-constexpr int LT_LW = 128;  // path capacity per lane in LDS
-
+// LT_LW: path capacity per lane in LDS (walks longer than this go to tier 2)
+template <int LT_LW>
 __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
     __shared__ uint32_t path[LT_LW * WAVE];  // path[k * WAVE + lane]
     const unsigned lane = lane_id();
@@ -557,10 +576,10 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
         if (active) {
             const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
             const uint32_t r = y.x >> 8;
-            const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
-            const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+            uint32_t e1, probes = 0;
+            const uint32_t e = lt_pick(a, cur, r, e1, probes);
             c_steps++;
-            c_probes += 32 - __clz(e1 - e0);
+            c_probes += probes;
             if (e == e1) {
                 finished = true;
             } else {
@@ -631,113 +650,92 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
 }
 
 // ---------------------------------------------------------------------------- LT tier 2
-constexpr int LT2_HB = 12;                 // hash slots per lane: 4096
-constexpr int LT2_QC = (1 << LT2_HB) / 2;  // path capacity: 2048
+// One wave per long walk: lane 0 draws and follows the walk; the path lives in LDS and
+// all 64 lanes scan it for the repeat check.  Walks longer than LT2_PC go to tier 3.
+constexpr int LT2_PC = 2048;
 
 struct Lt2Args {
     SampleArgs a;
-    uint32_t *hash;   // lanes * 4096
-    uint32_t *pathb;  // lanes * 2048
     const uint32_t *list;
     uint32_t nlist;
 };
 
-__global__ __launch_bounds__(WAVE) void k_lt_t2(Lt2Args t) {
+__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) {
+    __shared__ uint32_t path[LT2_PC];
     const SampleArgs &a = t.a;
     const unsigned lane = lane_id();
-    const uint64_t gl = (uint64_t)blockIdx.x * WAVE + lane;
-    uint32_t *H = t.hash + gl * (1u << LT2_HB);
-    uint32_t *Pp = t.pathb + gl * (2 * LT2_QC);
-    uint32_t *Sl = Pp + LT2_QC;  // hash slot of each path entry
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     WaveArena A;
-    uint64_t c_steps = 0, c_probes = 0, c_mem = 0;
+    uint64_t c_steps = 0, c_probes = 0, c_mem = 0;  // lane 0 (profiling)
     for (;;) {
         uint64_t it = 0;
-        if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], (unsigned long long)WAVE);
-        it = __shfl(it, 0, WAVE) + lane;
-        if (__ballot(it < t.nlist) == 0) break;
-        bool have = it < t.nlist;
-        uint32_t b = have ? t.list[it] : 0u, len = 0;
+        if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
+        it = __shfl(it, 0, WAVE);
+        if (it >= t.nlist) break;
+        const uint32_t b = t.list[it];
+        const uint64_t j = (uint64_t)a.j0 + b;
+        uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
+        if (lane == 0) path[0] = cur;
+        uint32_t len = 1;
         bool ok = true;
-        if (have) {
-            const uint64_t j = (uint64_t)a.j0 + b;
-            uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
-            Pp[0] = cur;
-            Sl[0] = hash32(cur, LT2_HB);
-            H[Sl[0]] = cur;
-            len = 1;
-            for (;;) {
+        for (;;) {
+            uint32_t s = 0, stop = 0;
+            if (lane == 0) {
                 const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
-                const uint32_t r = y.x >> 8;
-                const uint32_t e0 = (uint32_t)a.in_ptr[cur], e1 = (uint32_t)a.in_ptr[cur + 1];
-                const uint32_t e = upper_bound_dev<uint32_t, uint32_t>(a.thr, e0, e1, r);
+                uint32_t e1, probes = 0;
+                const uint32_t e = lt_pick(a, cur, y.x >> 8, e1, probes);
                 c_steps++;
-                c_probes += 32 - __clz(e1 - e0);
-                if (e == e1) break;
-                const uint32_t s = (uint32_t)a.in_src[e];
-                uint32_t hs = hash32(s, LT2_HB);
-                bool seen = false;
-                for (;;) {
-                    const uint32_t x = H[hs];
-                    if (x == s) { seen = true; break; }
-                    if (x == EMPTY) break;
-                    hs = (hs + 1) & ((1u << LT2_HB) - 1);
-                }
-                if (seen) break;
-                if (len == (uint32_t)LT2_QC) { ok = false; break; }
-                H[hs] = s;
-                Sl[len] = hs;
-                Pp[len++] = s;
-                cur = s;
+                c_probes += probes;
+                if (e == e1) stop = 1;
+                else s = (uint32_t)a.in_src[e];
             }
-            // release exactly the slots this walk filled
-            for (uint32_t x = 0; x < len; x++) H[Sl[x]] = EMPTY;
-            if (ok) {
-                // insertion sort of the path in device memory (short: tier-2 walks)
-                for (uint32_t x = 1; x < len; x++) {
-                    const uint32_t v = Pp[x];
-                    int y2 = (int)x - 1;
-                    while (y2 >= 0 && Pp[y2] > v) {
-                        Pp[y2 + 1] = Pp[y2];
-                        y2--;
-                    }
-                    Pp[y2 + 1] = v;
-                }
+            stop = __shfl(stop, 0, WAVE);
+            if (stop) break;
+            s = __shfl(s, 0, WAVE);
+            wave_sync();
+            bool seen = false;
+            for (uint32_t q = lane; q < len; q += WAVE) seen |= path[q] == s;
+            if (__ballot(seen)) break;
+            if (len == (uint32_t)LT2_PC) {
+                ok = false;
+                break;
             }
+            if (lane == 0) path[len] = s;
+            len++;
+            cur = s;
         }
-        if (have && !ok) {
-            a.pos[b] = POS_DEFER;
-            a.size[b] = 0;
-            const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
-            a.defer2[d] = b;
+        wave_sync();
+        if (!ok) {
+            if (lane == 0) {
+                a.pos[b] = POS_DEFER;
+                a.size[b] = 0;
+                const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
+                a.defer2[d] = b;
+            }
+            continue;
         }
-        const bool out = have && ok;
-        const uint32_t mine = out ? len : 0u;
-        const uint32_t incl = wave_incl_scan(mine);
-        const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+        const int P2 = pow2_at_least((int)len);
+        for (int q = (int)len + lane; q < P2; q += WAVE) path[q] = EMPTY;
+        wave_sync();
+        wave_bitonic(path, P2, lane);
         uint64_t at = 0;
-        const bool got = tot ? arena_claim(A, tot, a, at) : true;
-        if (out) {
-            if (got) {
-                const uint64_t o = at + incl - mine;
-                for (uint32_t x = 0; x < len; x++) a.mem[o + x] = Pp[x];
-                a.pos[b] = (uint32_t)o;
+        if (arena_claim(A, len, a, at)) {
+            for (uint32_t q = lane; q < len; q += WAVE) a.mem[at + q] = path[q];
+            if (lane == 0) {
+                a.pos[b] = (uint32_t)at;
                 a.size[b] = len;
                 c_mem += len;
-            } else {
-                mark_ovf(a, b);
             }
+        } else if (lane == 0) {
+            mark_ovf(a, b);
         }
+        wave_sync();
     }
-    if (a.dctr) {
-        const uint64_t st = wave_sum(c_steps), pr = wave_sum(c_probes), mm = wave_sum(c_mem);
-        if (lane == 0) {
-            atomicAdd(&a.dctr[DC_PHILOX], (unsigned long long)st);
-            atomicAdd(&a.dctr[DC_EXPANDED], (unsigned long long)st);
-            atomicAdd(&a.dctr[DC_PROBES], (unsigned long long)pr);
-            atomicAdd(&a.dctr[DC_MEMBERS], (unsigned long long)mm);
-        }
+    if (a.dctr && lane == 0) {
+        atomicAdd(&a.dctr[DC_PHILOX], (unsigned long long)c_steps);
+        atomicAdd(&a.dctr[DC_EXPANDED], (unsigned long long)c_steps);
+        atomicAdd(&a.dctr[DC_PROBES], (unsigned long long)c_probes);
+        atomicAdd(&a.dctr[DC_MEMBERS], (unsigned long long)c_mem);
     }
 }
 
@@ -818,6 +816,7 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
     a.in_ptr = c.g.in_ptr.as<int64_t>();
     a.in_src = c.g.in_src.as<int32_t>();
     a.thr = c.g.thr.as<uint32_t>();
+    a.guide = c.g.guide.as<uint32_t>();
     a.n = c.g.n;
     a.wc = c.g.model == HBM_IC && c.g.prob == HBM_PROB_WC;
     a.seed = seed;
@@ -845,8 +844,12 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
         const unsigned grid = (unsigned)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)c.num_cus * 8);
         k_ic_t1<9, WPB><<<grid, WPB * WAVE, 0, c.stream>>>(a);
     } else {
-        const unsigned grid = (unsigned)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)c.num_cus * 5);
-        k_lt_t1<<<grid, WAVE, 0, c.stream>>>(a);
+        // LDS per wave = lw * 256 B, so resident waves per CU = 640 / lw
+        const int lw = c.lt_lw;
+        const unsigned grid =
+            (unsigned)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)c.num_cus * std::max(1, 640 / lw));
+        if (lw == 128) k_lt_t1<128><<<grid, WAVE, 0, c.stream>>>(a);
+        else k_lt_t1<256><<<grid, WAVE, 0, c.stream>>>(a);
     }
     HBM_HIP(hipGetLastError());
     prof_end(c, s1);
@@ -874,26 +877,15 @@ int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
                 prof_sampler(c, s2);
             }
         } else {
-            // tier 2: lane per walk with device-memory hash and path
-            if (!sc.lt2_lanes) {
-                const uint64_t L = (uint64_t)c.num_cus * 2 * WAVE;
-                buf_alloc(c, sc.lt2_hash, L * (1u << LT2_HB) * 4);
-                buf_alloc(c, sc.lt2_path, L * 2 * LT2_QC * 4);
-                k_fill_u32<<<grid_for(L << LT2_HB, 256, 65536), 256, 0, c.stream>>>(sc.lt2_hash.as<uint32_t>(),
-                                                                                   L << LT2_HB, EMPTY);
-                HBM_HIP(hipGetLastError());
-                sc.lt2_lanes = L;
-            }
-            const uint64_t lanes = std::min<uint64_t>(((nd + WAVE - 1) / WAVE) * WAVE, sc.lt2_lanes);
+            // tier 2: one wave per walk, path in LDS
             reset_counter(c, CW_NDEFER);
             Lt2Args t;
             t.a = a;
-            t.hash = sc.lt2_hash.as<uint32_t>();
-            t.pathb = sc.lt2_path.as<uint32_t>();
             t.list = a.defer;
             t.nlist = (uint32_t)nd;
-            const int s2 = prof_begin(c, "lt_sample_lane_dev");
-            k_lt_t2<<<(unsigned)(lanes / WAVE), WAVE, 0, c.stream>>>(t);
+            const unsigned grid = (unsigned)std::min<uint64_t>(nd, (uint64_t)c.num_cus * 16);
+            const int s2 = prof_begin(c, "lt_sample_wave");
+            k_lt_wave<<<grid, WAVE, 0, c.stream>>>(t);
             HBM_HIP(hipGetLastError());
             prof_end(c, s2);
             Ctrl r2 = read_ctrl(c);

@@ -44,6 +44,8 @@ struct SelArgs {
     const int64_t *base;
     const int32_t *symtab;
     const uint8_t *lens;
+    const uint32_t *codes;
+    const uint32_t *lut;
     int32_t minlen;
     int32_t wbits;
     int32_t ustar_enc;
@@ -112,11 +114,27 @@ __device__ unsigned long long argmax_key(const SelArgs &A) {
 struct Tabs {
     uint64_t lim[34];
     int64_t base[34];
+    uint32_t lut[1 << LUT_BITS];
 };
 
-__device__ __forceinline__ uint32_t dec_code(const SelArgs &A, const Tabs &tb, uint64_t &pos) {
-    const uint32_t w = peek32(A.payload, pos);
-    int L = A.minlen;
+__device__ void load_tabs(const SelArgs &A, Tabs &tb) {
+    for (int i = threadIdx.x; i < 34; i += blockDim.x) {
+        tb.lim[i] = A.lim[i];
+        tb.base[i] = A.base[i];
+    }
+    for (int i = threadIdx.x; i < (1 << LUT_BITS); i += blockDim.x) tb.lut[i] = A.lut[i];
+}
+
+// one canonical code: the LDS table for short codes, the limit search for long ones.
+// `buf` is the stream (device memory or an LDS copy); `pos` a bit position in it.
+__device__ __forceinline__ uint32_t dec_code(const SelArgs &A, const Tabs &tb, const uint32_t *buf, uint64_t &pos) {
+    const uint32_t w = peek32(buf, pos);
+    const uint32_t ent = tb.lut[w >> (32 - LUT_BITS)];
+    if (ent) {
+        pos += ent & 31u;
+        return ent >> 5;
+    }
+    int L = LUT_BITS + 1 > A.minlen ? LUT_BITS + 1 : A.minlen;
     while ((uint64_t)w >= tb.lim[L]) L++;
     pos += (uint64_t)L;
     return (uint32_t)A.symtab[tb.base[L] + (int64_t)(w >> (32 - L))];
@@ -130,13 +148,24 @@ __device__ __forceinline__ uint32_t read_gamma(const uint32_t *payload, uint64_t
     return g;
 }
 
-__device__ bool huff_contains(const SelArgs &A, const Tabs &tb, int64_t j, uint32_t u, bool u_coded) {
-    uint64_t pos = (uint64_t)A.bitoff[j];
-    const uint64_t end = (uint64_t)A.bitoff[j + 1];
-    const uint32_t nesc = read_gamma(A.payload, pos) - 1;
-    if (!u_coded) {
+// length of the canonical code at the head of window w (LDS only)
+__device__ __forceinline__ uint32_t code_len(const SelArgs &A, const Tabs &tb, uint32_t w) {
+    const uint32_t ent = tb.lut[w >> (32 - LUT_BITS)];
+    if (ent) return ent & 31u;
+    int L = LUT_BITS + 1 > A.minlen ? LUT_BITS + 1 : A.minlen;
+    while ((uint64_t)w >= tb.lim[L]) L++;
+    return (uint32_t)L;
+}
+
+// Is u in the set whose bits are [pos, end) of buf?  Codeless ids come first, ascending,
+// and stop the scan at the first larger id; coded members are compared by their canonical
+// code (ustar_len, ustar_code), so no code is mapped back to an id.
+__device__ bool huff_contains(const SelArgs &A, const Tabs &tb, const uint32_t *buf, uint64_t pos, uint64_t end,
+                              uint32_t u, uint32_t ustar_len, uint32_t ustar_code) {
+    const uint32_t nesc = read_gamma(buf, pos) - 1;
+    if (!ustar_len) {
         for (uint32_t q = 0; q < nesc; q++) {
-            const uint32_t v = peek32(A.payload, pos) >> (32 - A.wbits);
+            const uint32_t v = peek32(buf, pos) >> (32 - A.wbits);
             pos += A.wbits;
             if (v == u) return true;
             if (v > u) return false;
@@ -144,26 +173,58 @@ __device__ bool huff_contains(const SelArgs &A, const Tabs &tb, int64_t j, uint3
         return false;
     }
     pos += (uint64_t)nesc * A.wbits;
-    bool first = true;
     while (pos < end) {
-        const uint32_t v = dec_code(A, tb, pos);
-        if (v == u) return true;
-        if (v > u && !(first && (int32_t)v == A.ustar_enc)) return false;
-        first = false;
+        const uint32_t w = peek32(buf, pos);
+        const uint32_t L = code_len(A, tb, w);
+        if (L == ustar_len && (w >> (32 - L)) == ustar_code) return true;
+        pos += L;
     }
     return false;
 }
 
-__device__ void huff_decrement(const SelArgs &A, const Tabs &tb, int64_t j) {
-    uint64_t pos = (uint64_t)A.bitoff[j];
-    const uint64_t end = (uint64_t)A.bitoff[j + 1];
-    const uint32_t nesc = read_gamma(A.payload, pos) - 1;
-    for (uint32_t q = 0; q < nesc; q++) {
-        const uint32_t v = peek32(A.payload, pos) >> (32 - A.wbits);
-        pos += A.wbits;
-        atomicSub(&A.counts[v], 1u);
+// Per-block combining cache for count decrements: the sets covered by one pick share
+// their hubs, and thousands of atomics on one address serialise.  Decrements of ids
+// that own a slot accumulate in LDS and are flushed once per block; an id whose slot is
+// taken by another id goes straight to device memory.
+constexpr int CC_SLOTS = 1024;
+struct DecCache {
+    uint32_t id[CC_SLOTS];
+    uint32_t cnt[CC_SLOTS];
+};
+
+__device__ __forceinline__ void cache_init(DecCache &C) {
+    for (int i = threadIdx.x; i < CC_SLOTS; i += blockDim.x) {
+        C.id[i] = 0xFFFFFFFFu;
+        C.cnt[i] = 0u;
     }
-    while (pos < end) atomicSub(&A.counts[dec_code(A, tb, pos)], 1u);
+}
+
+__device__ __forceinline__ void cache_dec(DecCache &C, uint32_t *counts, uint32_t v) {
+    const uint32_t h = (v * 0x9E3779B1u) >> (32 - 10);
+    uint32_t x = C.id[h];
+    if (x == 0xFFFFFFFFu) {
+        const uint32_t old = atomicCAS(&C.id[h], 0xFFFFFFFFu, v);
+        x = old == 0xFFFFFFFFu ? v : old;
+    }
+    if (x == v) atomicAdd(&C.cnt[h], 1u);
+    else atomicSub(&counts[v], 1u);
+}
+
+// after a __syncthreads: push the cached decrements to device memory
+__device__ __forceinline__ void cache_flush(DecCache &C, uint32_t *counts) {
+    for (int i = threadIdx.x; i < CC_SLOTS; i += blockDim.x)
+        if (C.cnt[i]) atomicSub(&counts[C.id[i]], C.cnt[i]);
+}
+
+__device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, const uint32_t *buf, uint64_t pos,
+                               uint64_t end) {
+    const uint32_t nesc = read_gamma(buf, pos) - 1;
+    for (uint32_t q = 0; q < nesc; q++) {
+        const uint32_t v = peek32(buf, pos) >> (32 - A.wbits);
+        pos += A.wbits;
+        cache_dec(C, A.counts, v);
+    }
+    while (pos < end) cache_dec(C, A.counts, dec_code(A, tb, buf, pos));
 }
 
 __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
@@ -207,40 +268,68 @@ __global__ __launch_bounds__(256) void k_find_raw(SelArgs A, int t) {
     }
 }
 
-// Huffman strings: one lane per uncovered set, partial decode that stops at u* or a larger id.
+// Huffman strings: one lane per uncovered set, partial decode that stops at u* or a
+// larger id; a set that holds u* is marked covered and its members decremented at once.
+// The 64 strings of a wave are contiguous in the stream: they are copied to LDS with
+// coalesced loads first (when they fit), so the lanes decode from LDS.
+constexpr int STAGE_WORDS = 1024;
+
 __global__ __launch_bounds__(256) void k_find_huff(SelArgs A, int t) {
     __shared__ Tabs tb;
-    for (int i = threadIdx.x; i < 34; i += blockDim.x) {
-        tb.lim[i] = A.lim[i];
-        tb.base[i] = A.base[i];
-    }
+    __shared__ uint32_t stage[256 / WAVE][STAGE_WORDS];
+    __shared__ DecCache C;
+    load_tabs(A, tb);
+    cache_init(C);
     __syncthreads();
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
-    const bool u_coded = A.lens[u] > 0;
+    const uint32_t ustar_len = A.lens[u];
+    const uint32_t ustar_code = ustar_len ? A.codes[u] : 0u;
     const unsigned lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
+    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + wv; w < A.words; w += nwaves) {
         const unsigned long long cov = A.covered[w];
-        const int64_t j = w * 64 + lane;
-        const bool found = j < A.T && !((cov >> lane) & 1ull) && huff_contains(A, tb, j, u, u_coded);
-        const unsigned long long nw = __ballot(found);
-        if (lane == 0 && nw) A.newly[w] = nw;
-    }
-}
-
-// Apply the pick: newly = (hot row or found sets) AND NOT covered; covered |= newly;
-// decrement the plain / coded members of newly covered sets.
-__global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
-    __shared__ Tabs tb;
-    if (A.huff) {
-        for (int i = threadIdx.x; i < 34; i += blockDim.x) {
-            tb.lim[i] = A.lim[i];
-            tb.base[i] = A.base[i];
+        const int64_t j0 = w * 64;
+        const int64_t j1 = j0 + 64 < A.T ? j0 + 64 : A.T;
+        const unsigned long long live = (j1 - j0 == 64 ? ~0ull : ((1ull << (j1 - j0)) - 1)) & ~cov;
+        if (!live) continue;
+        const int64_t j = j0 + lane;
+        const uint64_t b0 = (uint64_t)A.bitoff[j0], b1 = (uint64_t)A.bitoff[j1];
+        const uint64_t wlo = b0 >> 5;
+        const uint64_t nw = ((b1 + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
+        const bool staged = nw <= (uint64_t)STAGE_WORDS;
+        const uint32_t *buf = A.payload;
+        uint64_t off = 0;
+        if (staged) {
+            for (uint64_t q = lane; q < nw; q += WAVE) stage[wv][q] = A.payload[wlo + q];
+            wave_sync();
+            buf = stage[wv];
+            off = wlo * 32;
         }
+        bool found = false;
+        uint64_t p0 = 0, p1 = 0;
+        if ((live >> lane) & 1ull) {
+            p0 = (uint64_t)A.bitoff[j] - off;
+            p1 = (uint64_t)A.bitoff[j + 1] - off;
+            found = huff_contains(A, tb, buf, p0, p1, u, ustar_len, ustar_code);
+        }
+        const unsigned long long nwm = __ballot(found);
+        if (lane == 0 && nwm) {
+            A.newly[w] = nwm;
+            A.covered[w] = cov | nwm;
+        }
+        if (found) huff_decrement(A, tb, C, buf, p0, p1);
+        wave_sync();
     }
     __syncthreads();
+    cache_flush(C, A.counts);
+}
+
+__global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
+    __shared__ Tabs tb;
+    __shared__ DecCache C;
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
@@ -249,6 +338,10 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
         A.keys[t] = key;
     }
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
+    if (r < 0 && A.huff) return;  // the Huffman find step already covered and decremented
+    if (A.huff) load_tabs(A, tb);
+    cache_init(C);
+    __syncthreads();
     const unsigned lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
@@ -260,7 +353,10 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
         }
         if (!nw) continue;
         if (A.huff) {
-            if ((nw >> lane) & 1ull) huff_decrement(A, tb, w * 64 + lane);
+            if ((nw >> lane) & 1ull) {
+                const int64_t j = w * 64 + lane;
+                huff_decrement(A, tb, C, A.payload, (uint64_t)A.bitoff[j], (uint64_t)A.bitoff[j + 1]);
+            }
         } else if (A.raw_off) {
             unsigned long long rest = nw;
             while (rest) {
@@ -268,10 +364,12 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
                 rest &= rest - 1;
                 const int64_t j = w * 64 + b;
                 const int64_t e = A.raw_off[j + 1];
-                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) atomicSub(&A.counts[A.raw_mem[i]], 1u);
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A.counts, (uint32_t)A.raw_mem[i]);
             }
         }
     }
+    __syncthreads();
+    cache_flush(C, A.counts);
 }
 
 // hot counts -= popcount(row AND newly), over a segment of words per block row
@@ -341,6 +439,8 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     A.base = s.cbtab.as<int64_t>() + 34;
     A.symtab = s.symtab.as<int32_t>();
     A.lens = s.lens.as<uint8_t>();
+    A.lut = s.lut.as<uint32_t>();
+    A.codes = s.codes.as<uint32_t>();
     A.minlen = s.cb.minlen;
     A.wbits = s.cb.wbits;
     A.ustar_enc = s.cb.ustar_enc;
@@ -349,6 +449,7 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     A.nparts = (int32_t)g_arg;
 
     const unsigned g_mark = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
+    const unsigned g_fhuff = grid_for(std::max<int64_t>(words, 1), 4, (int64_t)c.num_cus * 8);
     const unsigned g_find = grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)c.num_cus * 4);
     const unsigned hx = (unsigned)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / hx));
@@ -367,7 +468,7 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
         if (T > 0) {
             if (huff) {
                 ps = prof_begin(c, "find_huff");
-                k_find_huff<<<g_mark, 256, 0, c.stream>>>(A, t);
+                k_find_huff<<<g_fhuff, 256, 0, c.stream>>>(A, t);
                 prof_end(c, ps, b_find);
             } else if (A.nraw > 0) {
                 ps = prof_begin(c, "find_raw");

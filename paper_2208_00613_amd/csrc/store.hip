@@ -313,16 +313,14 @@ void store_reset(Ctx &c) {
 void store_free(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.bitoff, &s.payload})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload})
         buf_free(c, *b);
     Scratch &sc = c.sc;
-    for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.lt2_hash,
-                   &sc.lt2_path, &sc.aux, &sc.cnt})
+    for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.aux, &sc.cnt})
         buf_free(c, *b);
     sc.cap = 0;
     sc.bcap = 0;
     sc.t2_slots = 0;
-    sc.lt2_lanes = 0;
 }
 
 int64_t store_bytes(const Ctx &c) {
@@ -434,6 +432,7 @@ static void build_model(Ctx &c) {
         for (int32_t v = 0; v < n; v++)
             if (warm[v] && (!hot || rank[v] < 0)) syms.push_back({warm[v], v});
         std::vector<uint8_t> L;
+        auto L_of = [&](size_t i) { return (int)L[i]; };
         Codebook &cb = s.cb;
         cb.maxlen = huffman_lengths_host(syms, L);
         cb.nsym = (int32_t)syms.size();
@@ -482,10 +481,23 @@ static void build_model(Ctx &c) {
             tab_base[l] = (int64_t)firstidx[l] - (int64_t)first[l];
         }
         tab_lim[33] = ~0ull;  // sentinel: never decoded past the longest code
+        // direct lookup for codes of at most LUT_BITS bits: every LUT_BITS-bit prefix that starts
+        // with such a code maps to (symbol << 5) | length; longer codes keep 0 (search the limits)
+        std::vector<uint32_t> lut((size_t)1 << LUT_BITS, 0u);
+        for (size_t q = 0; q < ord.size(); q++) {
+            const size_t i = ord[q];
+            const int L = L_of(i);
+            if (L > LUT_BITS) break;
+            const uint32_t cd = codes[syms[i].second];
+            const uint32_t lo = cd << (LUT_BITS - L), hi = (cd + 1) << (LUT_BITS - L);
+            for (uint32_t x = lo; x < hi; x++) lut[x] = ((uint32_t)syms[i].second << 5) | (uint32_t)L;
+        }
         buf_alloc(c, s.lens, (size_t)n);
         buf_alloc(c, s.codes, (size_t)n * 4);
         buf_alloc(c, s.symtab, symtab.size() * 4);
         buf_alloc(c, s.cbtab, 68 * 8);
+        buf_alloc(c, s.lut, lut.size() * 4);
+        HBM_HIP(hipMemcpyAsync(s.lut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, c.stream));
         HBM_HIP(hipMemcpyAsync(s.lens.p, lens.data(), (size_t)n, hipMemcpyHostToDevice, c.stream));
         HBM_HIP(hipMemcpyAsync(s.codes.p, codes.data(), (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
         HBM_HIP(hipMemcpyAsync(s.symtab.p, symtab.data(), symtab.size() * 4, hipMemcpyHostToDevice, c.stream));
