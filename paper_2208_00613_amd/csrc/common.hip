@@ -91,6 +91,13 @@ void scan_u64_to_i64(Ctx &c, const uint64_t *in, int64_t *out, int64_t count, in
     scan_impl(c, in, out, count, init);
 }
 
+void *stage_upload(Ctx &root, size_t off, const void *host, size_t bytes) {
+    if (root.stage.bytes < off + bytes) buf_grow(root, root.stage, off + bytes + (size_t(1) << 20), false);
+    void *d = (char *)root.stage.p + off;
+    HBM_HIP(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, root.stream));
+    return d;
+}
+
 // ------------------------------------------------------------------ profiler
 int prof_begin(Ctx &c, const char *name) {
     if (!c.prof.on) return -1;

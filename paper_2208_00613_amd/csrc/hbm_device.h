@@ -99,3 +99,39 @@ __device__ __forceinline__ I upper_bound_dev(const T *__restrict__ a, I lo, I hi
 }
 
 }  // namespace hbm
+
+namespace hbm {
+
+// ---------------------------------------------------------------- grouped launches
+// One launch serves many independent jobs: job i owns blocks [boff[i], boff[i+1]) of
+// the grid and reads its own argument block args[i].  A kernel body takes its block
+// position within its job explicitly, so the same body runs as a plain kernel (one job,
+// arguments by value) or as a grouped one.
+template <class Args>
+struct GroupArgs {
+    const Args *args;
+    const uint32_t *boff;  // count + 1 block offsets
+    uint32_t count;
+    int x;                 // extra scalar shared by all jobs (e.g. the selection iteration)
+};
+
+__device__ __forceinline__ uint32_t group_of(const uint32_t *boff, uint32_t count, uint32_t b) {
+    uint32_t lo = 0, hi = count - 1;  // last job whose first block is <= b
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+#define HBM_KERNEL(NAME, ARGS, THREADS)                                                              \
+    __device__ void NAME##_body(const ARGS &A, uint32_t bid, uint32_t nblk, int x);                  \
+    __global__ __launch_bounds__(THREADS) void NAME(ARGS A, int x) { NAME##_body(A, blockIdx.x, gridDim.x, x); } \
+    __global__ __launch_bounds__(THREADS) void NAME##_g(GroupArgs<ARGS> G) {                         \
+        const uint32_t i = group_of(G.boff, G.count, blockIdx.x);                                     \
+        NAME##_body(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i], G.x);               \
+    }                                                                                                \
+    __device__ void NAME##_body(const ARGS &A, uint32_t bid, uint32_t nblk, int x)
+
+}  // namespace hbm

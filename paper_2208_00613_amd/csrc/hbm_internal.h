@@ -188,6 +188,11 @@ struct Ctx {
     Scratch sc;
     SelState sel;
     Buf scan_tmp;  // rocPRIM temporary storage
+    // batched jobs (this context drives them): control words, launch descriptors, readbacks
+    Buf ctrl_arena;                        // uint64[jobs * CW_COUNT]
+    std::vector<unsigned long long> ctrl_host;
+    Buf stage;                             // grouped-launch descriptors
+    Buf tails;                             // uint64 per job: gathered totals
     Prof prof;
     Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)
     // timing of the last operations (ms)
@@ -202,12 +207,19 @@ void graph_free(Ctx &c);
 void store_reset(Ctx &c);
 void store_free(Ctx &c);
 void store_extend(Ctx &c, int64_t theta, uint64_t seed);
+void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
+                   const std::vector<uint64_t> &seed);
 int64_t store_bytes(const Ctx &c);
 void store_stats(Ctx &c, hbm_store_stats *out);
 void store_dump(Ctx &c, int64_t j0, int64_t j1, std::vector<int64_t> &off, std::vector<int32_t> &mem);
 
 // sample sets [j0, j1) into scratch; returns the number of sets completed (a prefix)
 int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed);
+// the same for several jobs at once (root drives the launches): job i samples
+// [j0[i], j0[i] + nb[i]) with seed[i]; done[i] gets its completed prefix
+void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &j0,
+                   const std::vector<int64_t> &nb, const std::vector<uint64_t> &seed, std::vector<int64_t> &done);
+void ensure_scratch(Ctx &c, size_t entries, int64_t bcap);
 
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
 void select_free(Ctx &c);
@@ -220,6 +232,29 @@ void prof_add(Ctx &c, int slot, double bytes, double ops);
 void prof_flush(Ctx &c);
 unsigned long long *prof_counters(Ctx &c);  // device counters, or null when profiling is off
 void prof_read_counters(Ctx &c, unsigned long long *host);  // and clear them
+
+// Upload `bytes` of host data to the context's descriptor staging buffer at `off`;
+// returns the device address.  Stream order makes reuse safe: a later copy into the same
+// bytes runs after the kernels that read them.
+void *stage_upload(Ctx &root, size_t off, const void *host, size_t bytes);
+
+// Grouped launch: one job runs the plain kernel with arguments by value; several jobs run
+// the grouped kernel over a descriptor array.  l1(args, blocks) / lg(GroupArgs, blocks).
+template <class Args, class L1, class LG>
+void glaunch(Ctx &root, const std::vector<Args> &args, const std::vector<uint32_t> &nblk, int x, L1 l1, LG lg) {
+    if (args.empty()) return;
+    if (args.size() == 1) {
+        if (nblk[0]) l1(args[0], nblk[0]);
+        return;
+    }
+    std::vector<uint32_t> boff(args.size() + 1, 0);
+    for (size_t i = 0; i < args.size(); i++) boff[i + 1] = boff[i] + nblk[i];
+    if (!boff.back()) return;
+    const size_t ab = (args.size() * sizeof(Args) + 255) & ~size_t(255);
+    Args *da = (Args *)stage_upload(root, 0, args.data(), args.size() * sizeof(Args));
+    uint32_t *db = (uint32_t *)stage_upload(root, ab, boff.data(), boff.size() * 4);
+    lg(da, db, (uint32_t)args.size(), boff.back(), x);
+}
 
 // launch helpers
 inline unsigned grid_for(int64_t items, int per_block, int64_t cap = 1 << 20) {

@@ -163,7 +163,7 @@ struct IcT1Lds {
 };
 
 template <int HB, int WPB>
-__global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
+__device__ void ic_t1_body(const SampleArgs &a) {
     using L = IcT1Lds<HB>;
     __shared__ L lds_all[WPB];
     const unsigned lane = lane_id();
@@ -330,6 +330,15 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
     }
 }
 
+template <int HB, int WPB>
+__global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
+    ic_t1_body<HB, WPB>(a);
+}
+template <int HB, int WPB>
+__global__ __launch_bounds__(WPB *WAVE) void k_ic_t1_g(GroupArgs<SampleArgs> G) {
+    ic_t1_body<HB, WPB>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+}
+
 // ---------------------------------------------------------------------------- IC tier 2
 constexpr int T2_THREADS = 512;
 constexpr int T2_WAVES = T2_THREADS / WAVE;
@@ -382,7 +391,7 @@ __device__ void emit_from_bitmap(const uint32_t *bm, uint64_t words, uint32_t *o
 // One workgroup per big set: a visited bitmap over V and a queue in device memory.
 // IC: each level's frontier is taken 512 vertices at a time; their edge groups are
 // spread over all threads of the block.  LT: one thread walks with the exact bitmap.
-__global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
+__device__ void big_body(const T2Args &t, uint32_t bid) {
     const SampleArgs &a = t.a;
     __shared__ uint32_t sP[T2_THREADS];
     __shared__ uint32_t sE0[T2_THREADS];
@@ -395,8 +404,8 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
     __shared__ unsigned long long s_at;
     __shared__ int s_ok;
     __shared__ unsigned long long s_ctr[DC_COUNT];
-    uint32_t *bm = t.bitmap + (uint64_t)blockIdx.x * t.words;
-    uint32_t *queue = t.queue + (uint64_t)blockIdx.x * (uint64_t)a.n;
+    uint32_t *bm = t.bitmap + (uint64_t)bid * t.words;
+    uint32_t *queue = t.queue + (uint64_t)bid * (uint64_t)a.n;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
     for (;;) {
@@ -536,10 +545,16 @@ __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) {
     if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
 }
 
+__global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) { big_body(t, blockIdx.x); }
+__global__ __launch_bounds__(T2_THREADS) void k_big_g(GroupArgs<T2Args> G) {
+    const uint32_t i = group_of(G.boff, G.count, blockIdx.x);
+    big_body(G.args[i], blockIdx.x - G.boff[i]);
+}
+
 // ---------------------------------------------------------------------------- LT tier 1
 // LT_LW: path capacity per lane in LDS (walks longer than this go to tier 2)
 template <int LT_LW>
-__global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
+__device__ void lt_t1_body(const SampleArgs &a) {
     __shared__ uint32_t path[LT_LW * WAVE];  // path[k * WAVE + lane]
     const unsigned lane = lane_id();
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -649,6 +664,15 @@ __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
     }
 }
 
+template <int LT_LW>
+__global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
+    lt_t1_body<LT_LW>(a);
+}
+template <int LT_LW>
+__global__ __launch_bounds__(WAVE) void k_lt_t1_g(GroupArgs<SampleArgs> G) {
+    lt_t1_body<LT_LW>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+}
+
 // ---------------------------------------------------------------------------- LT tier 2
 // One wave per long walk: lane 0 draws and follows the walk; the path lives in LDS and
 // all 64 lanes scan it for the repeat check.  Walks longer than LT2_PC go to tier 3.
@@ -660,7 +684,7 @@ struct Lt2Args {
     uint32_t nlist;
 };
 
-__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) {
+__device__ void lt_wave_body(const Lt2Args &t) {
     __shared__ uint32_t path[LT2_PC];
     const SampleArgs &a = t.a;
     const unsigned lane = lane_id();
@@ -739,6 +763,11 @@ __global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) {
     }
 }
 
+__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) { lt_wave_body(t); }
+__global__ __launch_bounds__(WAVE) void k_lt_wave_g(GroupArgs<Lt2Args> G) {
+    lt_wave_body(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+}
+
 __global__ void k_iota_u32(uint32_t *p, uint64_t count) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = (uint32_t)i;
@@ -750,27 +779,6 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------- host
-struct Ctrl {
-    unsigned long long w[CW_COUNT];
-};
-
-static Ctrl read_ctrl(Ctx &c) {
-    Ctrl r;
-    HBM_HIP(hipMemcpyAsync(r.w, c.sc.ctrl.p, sizeof(r.w), hipMemcpyDeviceToHost, c.stream));
-    HBM_HIP(hipStreamSynchronize(c.stream));
-    return r;
-}
-
-static void set_ctrl(Ctx &c, unsigned long long first_ovf) {
-    Ctrl r{};
-    r.w[CW_FIRST_OVF] = first_ovf;
-    HBM_HIP(hipMemcpyAsync(c.sc.ctrl.p, r.w, sizeof(r.w), hipMemcpyHostToDevice, c.stream));
-}
-
-static void reset_counter(Ctx &c, int which) {
-    HBM_HIP(hipMemsetAsync((char *)c.sc.ctrl.p + which * 8, 0, 8, c.stream));
-}
-
 static void ensure_t2(Ctx &c) {
     Scratch &sc = c.sc;
     if (sc.t2_slots) return;
@@ -792,130 +800,223 @@ static void ensure_t2(Ctx &c) {
 //  member written.  Ops: Philox calls.
 //  LT, per walk step: in_ptr pair (16 B), 4 B per binary-search probe, 4 B source
 //  id; 4 B per member written.  Ops: Philox calls (one per step).
-static void prof_sampler(Ctx &c, int slot) {
+static void prof_sampler(Ctx &root, int slot, bool ic, const std::vector<Ctx *> &J) {
     if (slot < 0) return;
     unsigned long long k[DC_COUNT];
-    prof_read_counters(c, k);
+    prof_read_counters(root, k);
+    bool wc = true;
+    for (Ctx *c : J)
+        if (c->g.model == HBM_IC) wc = c->g.prob == HBM_PROB_WC;
     double bytes;
-    if (c.g.model == HBM_IC) {
-        const bool wc = c.g.prob == HBM_PROB_WC;
+    if (ic) {
         bytes = 16.0 * k[DC_EXPANDED] + 4.0 * (wc ? k[DC_EXPANDED] : k[DC_EDGES]) + 4.0 * k[DC_LIVE] +
                 4.0 * k[DC_MEMBERS];
     } else {
         bytes = 20.0 * k[DC_EXPANDED] + 4.0 * k[DC_PROBES] + 4.0 * k[DC_MEMBERS];
     }
-    prof_add(c, slot, bytes, (double)k[DC_PHILOX]);
+    prof_add(root, slot, bytes, (double)k[DC_PHILOX]);
 }
 
-int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
-    Scratch &sc = c.sc;
-    const int64_t nb = j1 - j0;
-    HBM_REQUIRE(nb <= sc.bcap, HBM_EDEVICE, "internal: block larger than scratch index");
-    set_ctrl(c, (unsigned long long)nb);
-    SampleArgs a;
-    a.in_ptr = c.g.in_ptr.as<int64_t>();
-    a.in_src = c.g.in_src.as<int32_t>();
-    a.thr = c.g.thr.as<uint32_t>();
-    a.guide = c.g.guide.as<uint32_t>();
-    a.n = c.g.n;
-    a.wc = c.g.model == HBM_IC && c.g.prob == HBM_PROB_WC;
-    a.seed = seed;
-    a.j0 = j0;
-    a.nb = nb;
-    a.mem = sc.mem.as<uint32_t>();
-    a.cap = sc.cap;
-    a.pos = sc.pos.as<uint32_t>();
-    a.size = sc.size.as<uint32_t>();
-    a.ctrl = sc.ctrl.as<unsigned long long>();
-    a.defer = sc.defer.as<uint32_t>();
-    a.defer2 = sc.defer.as<uint32_t>() + sc.bcap;
+// control words of job i in the root's arena
+static unsigned long long *ctrl_of(Ctx &root, size_t i) {
+    return root.ctrl_arena.as<unsigned long long>() + i * CW_COUNT;
+}
 
-    a.gbudget = (uint64_t)c.ic_t1_budget;
-    a.dctr = prof_counters(c);
-    const bool ic = c.g.model == HBM_IC;
-    const int s1 = (ic && !c.ic_tier1) ? -1 : prof_begin(c, ic ? "ic_sample_wave" : "lt_sample_lane");
-    if (c.g.model == HBM_IC && !c.ic_tier1) {
-        // every set goes to tier 2 (one workgroup per set)
-        k_iota_u32<<<grid_for(nb, 256, 65536), 256, 0, c.stream>>>(a.defer, (uint64_t)nb);
-        const unsigned long long nbv = (unsigned long long)nb;
-        HBM_HIP(hipMemcpyAsync(a.ctrl + CW_NDEFER, &nbv, 8, hipMemcpyHostToDevice, c.stream));
-    } else if (c.g.model == HBM_IC) {
-        constexpr int WPB = 4;
-        const unsigned grid = (unsigned)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)c.num_cus * 8);
-        k_ic_t1<9, WPB><<<grid, WPB * WAVE, 0, c.stream>>>(a);
-    } else {
-        // LDS per wave = lw * 256 B, so resident waves per CU = 640 / lw
-        const int lw = c.lt_lw;
-        const unsigned grid =
-            (unsigned)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)c.num_cus * std::max(1, 640 / lw));
-        if (lw == 128) k_lt_t1<128><<<grid, WAVE, 0, c.stream>>>(a);
-        else k_lt_t1<256><<<grid, WAVE, 0, c.stream>>>(a);
+static void ctrl_push(Ctx &root) {
+    HBM_HIP(hipMemcpyAsync(root.ctrl_arena.p, root.ctrl_host.data(), root.ctrl_host.size() * 8,
+                           hipMemcpyHostToDevice, root.stream));
+}
+
+static void ctrl_pull(Ctx &root) {
+    HBM_HIP(hipMemcpyAsync(root.ctrl_host.data(), root.ctrl_arena.p, root.ctrl_host.size() * 8,
+                           hipMemcpyDeviceToHost, root.stream));
+    HBM_HIP(hipStreamSynchronize(root.stream));
+}
+
+void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &j0,
+                   const std::vector<int64_t> &nbv, const std::vector<uint64_t> &seed, std::vector<int64_t> &done) {
+    const size_t N = J.size();
+    done.assign(N, 0);
+    buf_grow(root, root.ctrl_arena, N * CW_COUNT * 8, false);
+    root.ctrl_host.assign(N * CW_COUNT, 0ull);
+    std::vector<SampleArgs> A(N);
+    for (size_t i = 0; i < N; i++) {
+        Ctx &c = *J[i];
+        Scratch &sc = c.sc;
+        HBM_REQUIRE(nbv[i] <= sc.bcap, HBM_EDEVICE, "internal: block larger than scratch index");
+        root.ctrl_host[i * CW_COUNT + CW_FIRST_OVF] = (unsigned long long)nbv[i];
+        SampleArgs &a = A[i];
+        a.in_ptr = c.g.in_ptr.as<int64_t>();
+        a.in_src = c.g.in_src.as<int32_t>();
+        a.thr = c.g.thr.as<uint32_t>();
+        a.guide = c.g.guide.as<uint32_t>();
+        a.n = c.g.n;
+        a.wc = c.g.model == HBM_IC && c.g.prob == HBM_PROB_WC;
+        a.seed = seed[i];
+        a.j0 = j0[i];
+        a.nb = nbv[i];
+        a.mem = sc.mem.as<uint32_t>();
+        a.cap = sc.cap;
+        a.pos = sc.pos.as<uint32_t>();
+        a.size = sc.size.as<uint32_t>();
+        a.ctrl = ctrl_of(root, i);
+        a.defer = sc.defer.as<uint32_t>();
+        a.defer2 = sc.defer.as<uint32_t>() + sc.bcap;
+        a.gbudget = (uint64_t)root.ic_t1_budget;
+        a.dctr = prof_counters(root);
+        if (c.g.model == HBM_IC && !root.ic_tier1) {
+            // every set goes to tier 2 (one workgroup per set)
+            root.ctrl_host[i * CW_COUNT + CW_NDEFER] = (unsigned long long)nbv[i];
+        }
     }
+    ctrl_push(root);
+    const hipStream_t st = root.stream;
+    const bool profiling = root.prof.on;
+    // ---- tier 1
+    std::vector<SampleArgs> ic, lt;
+    std::vector<uint32_t> icb, ltb;
+    constexpr int WPB = 4;
+    const int lw = root.lt_lw;
+    for (size_t i = 0; i < N; i++) {
+        const int64_t nb = nbv[i];
+        if (nb <= 0) continue;
+        if (J[i]->g.model == HBM_IC) {
+            if (!root.ic_tier1) {
+                k_iota_u32<<<grid_for(nb, 256, 65536), 256, 0, st>>>(A[i].defer, (uint64_t)nb);
+                continue;
+            }
+            ic.push_back(A[i]);
+            icb.push_back((uint32_t)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)root.num_cus * 8));
+        } else {
+            lt.push_back(A[i]);
+            ltb.push_back(
+                (uint32_t)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)root.num_cus * std::max(1, 640 / lw)));
+        }
+    }
+    int s1 = ic.empty() ? -1 : prof_begin(root, "ic_sample_wave");
+    glaunch(root, ic, icb, 0, [&](const SampleArgs &a, unsigned g) { k_ic_t1<9, WPB><<<g, WPB * WAVE, 0, st>>>(a); },
+            [&](const SampleArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                k_ic_t1_g<9, WPB><<<g, WPB * WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+            });
     HBM_HIP(hipGetLastError());
-    prof_end(c, s1);
-    Ctrl r = read_ctrl(c);
-    prof_sampler(c, s1);
-    const uint64_t nd = r.w[CW_NDEFER];
-    if (nd > 0) {
+    prof_end(root, s1);
+    if (profiling && s1 >= 0) {
+        HBM_HIP(hipStreamSynchronize(st));
+        prof_sampler(root, s1, true, J);
+    }
+    int s1b = lt.empty() ? -1 : prof_begin(root, "lt_sample_lane");
+    glaunch(root, lt, ltb, 0,
+            [&](const SampleArgs &a, unsigned g) {
+                if (lw == 128) k_lt_t1<128><<<g, WAVE, 0, st>>>(a);
+                else k_lt_t1<256><<<g, WAVE, 0, st>>>(a);
+            },
+            [&](const SampleArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                if (lw == 128) k_lt_t1_g<128><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+                else k_lt_t1_g<256><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+            });
+    HBM_HIP(hipGetLastError());
+    prof_end(root, s1b);
+    ctrl_pull(root);
+    if (s1b >= 0) prof_sampler(root, s1b, false, J);
+    // ---- tier 2: IC sets on a workgroup each; LT walks on a wave each
+    std::vector<T2Args> big;
+    std::vector<uint32_t> bigb;
+    std::vector<Lt2Args> ltw;
+    std::vector<uint32_t> ltwb;
+    bool lt_deferred = false;
+    for (size_t i = 0; i < N; i++) {
+        Ctx &c = *J[i];
+        const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
+        if (!nd) continue;
         if (c.g.model == HBM_IC) {
             ensure_t2(c);
             T2Args t;
-            t.a = a;
-            t.bitmap = sc.t2_bitmap.as<uint32_t>();
-            t.queue = sc.t2_queue.as<uint32_t>();
+            t.a = A[i];
+            t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
+            t.queue = c.sc.t2_queue.as<uint32_t>();
             t.words = ((uint64_t)c.g.n + 31) / 32;
-            t.list = a.defer;
+            t.list = A[i].defer;
             t.nlist = (uint32_t)nd;
             t.model = HBM_IC;
-            const unsigned grid = (unsigned)std::min<uint64_t>(nd, (uint64_t)sc.t2_slots);
-            const int s2 = prof_begin(c, "ic_sample_block");
-            k_big<<<grid, T2_THREADS, 0, c.stream>>>(t);
-            HBM_HIP(hipGetLastError());
-            prof_end(c, s2);
-            if (s2 >= 0) {
-                HBM_HIP(hipStreamSynchronize(c.stream));
-                prof_sampler(c, s2);
-            }
+            big.push_back(t);
+            bigb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)c.sc.t2_slots));
         } else {
-            // tier 2: one wave per walk, path in LDS
-            reset_counter(c, CW_NDEFER);
+            root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
+            lt_deferred = true;
             Lt2Args t;
-            t.a = a;
-            t.list = a.defer;
+            t.a = A[i];
+            t.list = A[i].defer;
             t.nlist = (uint32_t)nd;
-            const unsigned grid = (unsigned)std::min<uint64_t>(nd, (uint64_t)c.num_cus * 16);
-            const int s2 = prof_begin(c, "lt_sample_wave");
-            k_lt_wave<<<grid, WAVE, 0, c.stream>>>(t);
-            HBM_HIP(hipGetLastError());
-            prof_end(c, s2);
-            Ctrl r2 = read_ctrl(c);
-            prof_sampler(c, s2);
-            const uint64_t nd3 = r2.w[CW_NDEFER];
-            if (nd3 > 0) {
-                ensure_t2(c);
-                reset_counter(c, CW_NEXT2);
-                T2Args t3;
-                t3.a = a;
-                t3.bitmap = sc.t2_bitmap.as<uint32_t>();
-                t3.queue = sc.t2_queue.as<uint32_t>();
-                t3.words = ((uint64_t)c.g.n + 31) / 32;
-                t3.list = a.defer2;
-                t3.nlist = (uint32_t)nd3;
-                t3.model = HBM_LT;
-                const unsigned grid = (unsigned)std::min<uint64_t>(nd3, (uint64_t)sc.t2_slots);
-                const int s3 = prof_begin(c, "lt_sample_block");
-                k_big<<<grid, T2_THREADS, 0, c.stream>>>(t3);
-                HBM_HIP(hipGetLastError());
-                prof_end(c, s3);
-                if (s3 >= 0) {
-                    HBM_HIP(hipStreamSynchronize(c.stream));
-                    prof_sampler(c, s3);
-                }
-            }
+            ltw.push_back(t);
+            ltwb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 16));
         }
-        r = read_ctrl(c);
     }
-    return (int64_t)std::min<unsigned long long>(r.w[CW_FIRST_OVF], (unsigned long long)nb);
+    if (!big.empty() || !ltw.empty()) {
+        if (lt_deferred) ctrl_push(root);
+        int s2 = big.empty() ? -1 : prof_begin(root, "ic_sample_block");
+        glaunch(root, big, bigb, 0, [&](const T2Args &t, unsigned g) { k_big<<<g, T2_THREADS, 0, st>>>(t); },
+                [&](const T2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                    k_big_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2Args>{d, b, cnt, x});
+                });
+        HBM_HIP(hipGetLastError());
+        prof_end(root, s2);
+        if (profiling && s2 >= 0) {
+            HBM_HIP(hipStreamSynchronize(st));
+            prof_sampler(root, s2, true, J);
+        }
+        int s3 = ltw.empty() ? -1 : prof_begin(root, "lt_sample_wave");
+        glaunch(root, ltw, ltwb, 0, [&](const Lt2Args &t, unsigned g) { k_lt_wave<<<g, WAVE, 0, st>>>(t); },
+                [&](const Lt2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                    k_lt_wave_g<<<g, WAVE, 0, st>>>(GroupArgs<Lt2Args>{d, b, cnt, x});
+                });
+        HBM_HIP(hipGetLastError());
+        prof_end(root, s3);
+        ctrl_pull(root);
+        if (s3 >= 0) prof_sampler(root, s3, false, J);
+        // ---- tier 3: LT walks longer than the LDS path
+        std::vector<T2Args> t3;
+        std::vector<uint32_t> t3b;
+        for (size_t i = 0; i < N; i++) {
+            Ctx &c = *J[i];
+            if (c.g.model != HBM_LT) continue;
+            const uint64_t nd3 = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
+            if (!nd3) continue;
+            ensure_t2(c);
+            root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
+            T2Args t;
+            t.a = A[i];
+            t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
+            t.queue = c.sc.t2_queue.as<uint32_t>();
+            t.words = ((uint64_t)c.g.n + 31) / 32;
+            t.list = A[i].defer2;
+            t.nlist = (uint32_t)nd3;
+            t.model = HBM_LT;
+            t3.push_back(t);
+            t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));
+        }
+        if (!t3.empty()) {
+            ctrl_push(root);
+            int s4 = prof_begin(root, "lt_sample_block");
+            glaunch(root, t3, t3b, 0, [&](const T2Args &t, unsigned g) { k_big<<<g, T2_THREADS, 0, st>>>(t); },
+                    [&](const T2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                        k_big_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2Args>{d, b, cnt, x});
+                    });
+            HBM_HIP(hipGetLastError());
+            prof_end(root, s4);
+            ctrl_pull(root);
+            if (s4 >= 0) prof_sampler(root, s4, false, J);
+        }
+    }
+    for (size_t i = 0; i < N; i++)
+        done[i] = (int64_t)std::min<unsigned long long>(root.ctrl_host[i * CW_COUNT + CW_FIRST_OVF],
+                                                        (unsigned long long)nbv[i]);
+}
+
+int64_t sample_block(Ctx &c, int64_t j0, int64_t j1, uint64_t seed) {
+    std::vector<Ctx *> J{&c};
+    std::vector<int64_t> done;
+    sample_blocks(c, J, {j0}, {j1 - j0}, {seed}, done);
+    return done[0];
 }
 
 }  // namespace hbm

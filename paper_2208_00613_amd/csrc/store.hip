@@ -36,10 +36,16 @@ struct BlockView {
     int64_t nb;
 };
 
-__global__ void k_hist_add(BlockView bv, uint32_t *__restrict__ hist) {
-    // one wave per set: lanes stride over its members
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
-    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+// one wave per set: lanes stride over its members
+struct HistArgs {
+    BlockView bv;
+    uint32_t *hist;
+};
+HBM_KERNEL(k_hist_add, HistArgs, 256) {
+    const BlockView &bv = A.bv;
+    uint32_t *__restrict__ hist = A.hist;
+    const uint64_t wave = (bid * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)nblk * blockDim.x / WAVE;
     const unsigned lane = lane_id();
     for (uint64_t b = wave; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
@@ -48,9 +54,22 @@ __global__ void k_hist_add(BlockView bv, uint32_t *__restrict__ hist) {
 }
 
 // per-set count of members kept as plain ids (all of them when hot_rank is null); one wave per set
-__global__ void k_cold_count(BlockView bv, const int32_t *__restrict__ hot_rank, uint32_t *__restrict__ out) {
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
-    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+struct SplitArgs {
+    BlockView bv;
+    const int32_t *hot_rank;      // null: no hot rows
+    int64_t j0;
+    const int64_t *off;           // raw offsets of the block's sets (null: bitmap only)
+    int32_t *raw;
+    unsigned long long *bitmap;
+    int32_t nhot;
+    uint32_t *cnt;                // per-set plain-id counts (cold_count output)
+};
+HBM_KERNEL(k_cold_count, SplitArgs, 256) {
+    const BlockView &bv = A.bv;
+    const int32_t *__restrict__ hot_rank = A.hot_rank;
+    uint32_t *__restrict__ out = A.cnt;
+    const uint64_t wave = (bid * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)nblk * blockDim.x / WAVE;
     const unsigned lane = lane_id();
     for (uint64_t b = wave; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
@@ -62,13 +81,20 @@ __global__ void k_cold_count(BlockView bv, const int32_t *__restrict__ hot_rank,
         }
         if (lane == 0) out[b] = c;
     }
+    if (bid == 0 && threadIdx.x == 0) out[bv.nb] = 0u;  // the scan covers one extra element
 }
 
 // Copy plain ids to the raw store and set hot bits.  One wave per set.
-__global__ void k_split(BlockView bv, const int32_t *__restrict__ hot_rank, int64_t j0, const int64_t *__restrict__ off,
-                        int32_t *__restrict__ raw, unsigned long long *__restrict__ bitmap, int32_t nhot) {
-    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
-    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+HBM_KERNEL(k_split, SplitArgs, 256) {
+    const BlockView &bv = A.bv;
+    const int32_t *__restrict__ hot_rank = A.hot_rank;
+    const int64_t j0 = A.j0;
+    const int64_t *__restrict__ off = A.off;
+    int32_t *__restrict__ raw = A.raw;
+    unsigned long long *__restrict__ bitmap = A.bitmap;
+    const int32_t nhot = A.nhot;
+    const uint64_t wave = (bid * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)nblk * blockDim.x / WAVE;
     const unsigned lane = lane_id();
     for (uint64_t b = wave; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
@@ -100,12 +126,23 @@ struct HuffEnc {
     int32_t ustar;
     int32_t wbits;
 };
+struct HuffArgs {
+    BlockView bv;
+    HuffEnc h;
+    uint64_t *bits;                    // per-set bit lengths (huff_bits output)
+    const int64_t *bitoff;             // start bits of the block's sets
+    uint32_t *payload;
+    unsigned long long *nesc_total;
+};
 
 __device__ __forceinline__ int floor_log2_u32(uint32_t x) { return 31 - __clz(x); }
 
-__global__ void k_huff_bits(BlockView bv, HuffEnc h, uint64_t *__restrict__ bits_out) {
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
-         b += (uint64_t)gridDim.x * blockDim.x) {
+HBM_KERNEL(k_huff_bits, HuffArgs, 256) {
+    const BlockView &bv = A.bv;
+    const HuffEnc &h = A.h;
+    uint64_t *__restrict__ bits_out = A.bits;
+    for (uint64_t b = bid * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
+         b += (uint64_t)nblk * blockDim.x) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         uint64_t bits = 0;
         uint32_t nesc = 0;
@@ -119,6 +156,7 @@ __global__ void k_huff_bits(BlockView bv, HuffEnc h, uint64_t *__restrict__ bits
         bits += 2 * (uint64_t)floor_log2_u32(nesc + 1) + 1 + (uint64_t)nesc * h.wbits;
         bits_out[b] = bits;
     }
+    if (bid == 0 && threadIdx.x == 0) bits_out[bv.nb] = 0ull;  // the scan covers one extra element
 }
 
 // OR `nbits` (<= 32) bits of `value` into the stream at bit `pos`, MSB first.
@@ -132,11 +170,15 @@ __device__ __forceinline__ void put_bits(uint32_t *buf, uint64_t pos, uint32_t v
     if (lo) atomicOr(&buf[w + 1], lo);
 }
 
-__global__ void k_huff_write(BlockView bv, HuffEnc h, const int64_t *__restrict__ bitoff, uint32_t *__restrict__ payload,
-                             unsigned long long *__restrict__ nesc_total) {
+HBM_KERNEL(k_huff_write, HuffArgs, 256) {
+    const BlockView &bv = A.bv;
+    const HuffEnc &h = A.h;
+    const int64_t *__restrict__ bitoff = A.bitoff;
+    uint32_t *__restrict__ payload = A.payload;
+    unsigned long long *__restrict__ nesc_total = A.nesc_total;
     uint64_t esc_local = 0;
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
-         b += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t b = bid * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
+         b += (uint64_t)nblk * blockDim.x) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         uint64_t pos = (uint64_t)bitoff[b];
         uint32_t nesc = 0;
@@ -177,6 +219,18 @@ __global__ void k_huff_write(BlockView bv, HuffEnc h, const int64_t *__restrict_
         esc_local += nesc;
     }
     if (esc_local) atomicAdd(nesc_total, (unsigned long long)esc_local);
+}
+
+// gather one int64 per job (the last offset of its scan) into out[i]
+struct TailArgs {
+    const int64_t *src;
+    int64_t *dst;
+};
+HBM_KERNEL(k_tail, TailArgs, 64) {
+    (void)bid;
+    (void)nblk;
+    (void)x;
+    if (threadIdx.x == 0) *A.dst = *A.src;
 }
 
 // ------------------------------------------------------------------ decode of whole sets (inspection)
@@ -333,7 +387,7 @@ int64_t store_bytes(const Ctx &c) {
     return b;
 }
 
-static void ensure_scratch(Ctx &c, size_t entries, int64_t bcap) {
+void ensure_scratch(Ctx &c, size_t entries, int64_t bcap) {
     Scratch &sc = c.sc;
     if (entries > sc.cap) {
         buf_alloc(c, sc.mem, entries * 4);
@@ -549,159 +603,316 @@ static T read_dev(Ctx &c, const void *p) {
     return v;
 }
 
-// Append sets [j0, j0+done) from scratch to the store.
-static void append_block(Ctx &c, int64_t j0, int64_t done) {
-    Store &s = c.s;
-    Scratch &sc = c.sc;
-    const int32_t n = c.g.n;
-    BlockView bv{sc.mem.as<uint32_t>(), sc.pos.as<uint32_t>(), sc.size.as<uint32_t>(), done};
-    const unsigned gw = grid_for(done * WAVE, 256, 65536);
-    const unsigned gt = grid_for(done, 256, 65536);
-    {
-        const int ps_ = prof_begin(c, "hist_add");
-        k_hist_add<<<gw, 256, 0, c.stream>>>(bv, s.hist.as<uint32_t>());
-        prof_end(c, ps_, 0);
-    }
-    HBM_HIP(hipGetLastError());
-    const bool hot = s.enc == HBM_ENC_HOT_BITMAP || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    const int64_t new_sets = j0 + done;
-    if (hot) {
-        const int64_t words = (new_sets + 63) / 64;
-        buf_grow(c, s.bitmap, (size_t)std::max<int64_t>(words * s.nhot, 1) * 8, true);
-        s.bm_words = words;
-    }
-    if (!huff) {
-        // plain ids: sizes -> offsets -> copy
-        uint32_t *cnt = sc.cnt.as<uint32_t>();
-        {
-            const int ps_ = prof_begin(c, "cold_count");
-            k_cold_count<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, cnt);
-            prof_end(c, ps_, 0);
-        }
-        HBM_HIP(hipGetLastError());
-        buf_grow(c, s.raw_off, (size_t)(new_sets + 1) * 8, true);
-        // scan of the block's counts, placed after the existing offsets
-        HBM_HIP(hipMemsetAsync(cnt + done, 0, 4, c.stream));
-        scan_u32_to_i64(c, cnt, s.raw_off.as<int64_t>() + j0, done + 1, s.raw_count);
-        const int64_t total = read_dev<int64_t>(c, s.raw_off.as<int64_t>() + new_sets);
-        buf_grow(c, s.raw_mem, (size_t)std::max<int64_t>(total, 1) * 4, true);
-        {
-            const int ps_ = prof_begin(c, "split");
-            k_split<<<gw, 256, 0, c.stream>>>(bv, hot ? s.hot_rank.as<int32_t>() : nullptr, j0, s.raw_off.as<int64_t>() + j0,
-                                          s.raw_mem.as<int32_t>(), s.bitmap.as<unsigned long long>(), s.nhot);
-            prof_end(c, ps_, 0);
-        }
-        HBM_HIP(hipGetLastError());
-        s.raw_count = total;
-    } else {
-        HuffEnc h{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
-                  s.cb.ustar_enc, s.cb.wbits};
-        uint64_t *bits = sc.aux.as<uint64_t>();
-        {
-            const int ps_ = prof_begin(c, "huff_bits");
-            k_huff_bits<<<gt, 256, 0, c.stream>>>(bv, h, bits);
-            prof_end(c, ps_, 0);
-        }
-        HBM_HIP(hipGetLastError());
-        HBM_HIP(hipMemsetAsync(bits + done, 0, 8, c.stream));
-        buf_grow(c, s.bitoff, (size_t)(new_sets + 1) * 8, true);
-        scan_u64_to_i64(c, bits, s.bitoff.as<int64_t>() + j0, done + 1, (int64_t)s.nbits);
-        const int64_t total = read_dev<int64_t>(c, s.bitoff.as<int64_t>() + new_sets);
-        buf_grow(c, s.payload, (size_t)((total + 31) / 32 + 2) * 4, true);
-        HBM_HIP(hipMemsetAsync(sc.ctrl.as<unsigned long long>() + CW_SUM, 0, 8, c.stream));
-        {
-            const int ps_ = prof_begin(c, "huff_write");
-            k_huff_write<<<gt, 256, 0, c.stream>>>(bv, h, s.bitoff.as<int64_t>() + j0, s.payload.as<uint32_t>(),
-                                               sc.ctrl.as<unsigned long long>() + CW_SUM);
-            prof_end(c, ps_, 0);
-        }
-        HBM_HIP(hipGetLastError());
-        if (hot)
-            k_split<<<gw, 256, 0, c.stream>>>(bv, s.hot_rank.as<int32_t>(), j0, nullptr, nullptr,
-                                              s.bitmap.as<unsigned long long>(), s.nhot);
-        s.escapes += (int64_t)read_dev<unsigned long long>(c, sc.ctrl.as<unsigned long long>() + CW_SUM);
-        s.nbits = (uint64_t)total;
-    }
-    s.nsets = new_sets;
+static BlockView block_view(Ctx &c, int64_t done) {
+    return BlockView{c.sc.mem.as<uint32_t>(), c.sc.pos.as<uint32_t>(), c.sc.size.as<uint32_t>(), done};
 }
 
-void store_extend(Ctx &c, int64_t theta, uint64_t seed) {
-    HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
-    HBM_REQUIRE(theta >= 0 && theta < (int64_t(1) << 31), HBM_EINVAL, "theta must be in [0, 2^31)");
-    Store &s = c.s;
-    if ((s.has_seed && s.seed != seed) || theta < s.nsets) store_reset(c);
-    if (theta == s.nsets) {
+// Per job, the int64 at src[i] gathered into root.tails and copied to the host.
+static void gather_tails(Ctx &root, const std::vector<const int64_t *> &src, std::vector<int64_t> &out) {
+    const size_t N = src.size();
+    out.assign(N, 0);
+    if (!N) return;
+    buf_grow(root, root.tails, N * 8, false);
+    std::vector<TailArgs> ta(N);
+    std::vector<uint32_t> nb(N, 1);
+    for (size_t i = 0; i < N; i++) ta[i] = TailArgs{src[i], root.tails.as<int64_t>() + i};
+    const hipStream_t st = root.stream;
+    glaunch(root, ta, nb, 0, [&](const TailArgs &a, unsigned g) { k_tail<<<g, 64, 0, st>>>(a, 0); },
+            [&](const TailArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                k_tail_g<<<g, 64, 0, st>>>(GroupArgs<TailArgs>{d, b, cnt, x});
+            });
+    HBM_HIP(hipGetLastError());
+    HBM_HIP(hipMemcpyAsync(out.data(), root.tails.p, N * 8, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipStreamSynchronize(st));
+}
+
+#define HBM_GLAUNCH(ROOT, ARGS, NB, X, KERNEL, THREADS, ATYPE)                                                 \
+    glaunch(ROOT, ARGS, NB, X, [&](const ATYPE &a_, unsigned g_) { KERNEL<<<g_, THREADS, 0, (ROOT).stream>>>(a_, X); }, \
+            [&](const ATYPE *d_, const uint32_t *b_, uint32_t c_, uint32_t g_, int x_) {                     \
+                KERNEL##_g<<<g_, THREADS, 0, (ROOT).stream>>>(GroupArgs<ATYPE>{d_, b_, c_, x_});              \
+            })
+
+// Append sets [j0[i], j0[i] + done[i]) of every job from its scratch arena to its store
+// (UpdateHistogram, then the job's encoding), one grouped launch per step.
+static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &j0,
+                          const std::vector<int64_t> &done) {
+    const size_t N = J.size();
+    std::vector<HistArgs> ha;
+    std::vector<uint32_t> hb;
+    for (size_t i = 0; i < N; i++) {
+        ha.push_back(HistArgs{block_view(*J[i], done[i]), J[i]->s.hist.as<uint32_t>()});
+        hb.push_back(grid_for(done[i] * WAVE, 256, 65536));
+    }
+    {
+        const int ps = prof_begin(root, "hist_add");
+        HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
+        prof_end(root, ps);
+    }
+    HBM_HIP(hipGetLastError());
+    // plain-id jobs and Huffman jobs
+    std::vector<size_t> P, H;
+    for (size_t i = 0; i < N; i++) {
+        Store &s = J[i]->s;
+        const bool hot = s.enc == HBM_ENC_HOT_BITMAP || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+        const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+        const int64_t new_sets = j0[i] + done[i];
+        if (hot) {
+            const int64_t words = (new_sets + 63) / 64;
+            buf_grow(*J[i], s.bitmap, (size_t)std::max<int64_t>(words * s.nhot, 1) * 8, true);
+            s.bm_words = words;
+        }
+        (huff ? H : P).push_back(i);
+    }
+    if (!P.empty()) {
+        std::vector<SplitArgs> sa;
+        std::vector<uint32_t> sb;
+        for (size_t i : P) {
+            Ctx &c = *J[i];
+            Store &s = c.s;
+            const bool hot = s.enc == HBM_ENC_HOT_BITMAP;
+            buf_grow(c, s.raw_off, (size_t)(j0[i] + done[i] + 1) * 8, true);
+            SplitArgs a{};
+            a.bv = block_view(c, done[i]);
+            a.hot_rank = hot ? s.hot_rank.as<int32_t>() : nullptr;
+            a.j0 = j0[i];
+            a.off = s.raw_off.as<int64_t>() + j0[i];
+            a.bitmap = s.bitmap.as<unsigned long long>();
+            a.nhot = s.nhot;
+            a.cnt = c.sc.cnt.as<uint32_t>();
+            sa.push_back(a);
+            sb.push_back(grid_for(done[i] * WAVE, 256, 65536));
+        }
+        {
+            const int ps = prof_begin(root, "cold_count");
+            HBM_GLAUNCH(root, sa, sb, 0, k_cold_count, 256, SplitArgs);
+            prof_end(root, ps);
+        }
+        HBM_HIP(hipGetLastError());
+        std::vector<const int64_t *> tail;
+        for (size_t q = 0; q < P.size(); q++) {
+            Ctx &c = *J[P[q]];
+            scan_u32_to_i64(root, sa[q].cnt, c.s.raw_off.as<int64_t>() + j0[P[q]], done[P[q]] + 1, c.s.raw_count);
+            tail.push_back(c.s.raw_off.as<int64_t>() + j0[P[q]] + done[P[q]]);
+        }
+        std::vector<int64_t> total;
+        gather_tails(root, tail, total);
+        for (size_t q = 0; q < P.size(); q++) {
+            Ctx &c = *J[P[q]];
+            buf_grow(c, c.s.raw_mem, (size_t)std::max<int64_t>(total[q], 1) * 4, true);
+            sa[q].raw = c.s.raw_mem.as<int32_t>();
+            sa[q].bitmap = c.s.bitmap.as<unsigned long long>();
+            c.s.raw_count = total[q];
+        }
+        {
+            const int ps = prof_begin(root, "split");
+            HBM_GLAUNCH(root, sa, sb, 0, k_split, 256, SplitArgs);
+            prof_end(root, ps);
+        }
+        HBM_HIP(hipGetLastError());
+    }
+    if (!H.empty()) {
+        std::vector<HuffArgs> fa;
+        std::vector<uint32_t> fb;
+        for (size_t i : H) {
+            Ctx &c = *J[i];
+            Store &s = c.s;
+            const bool hot = s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+            buf_grow(c, s.bitoff, (size_t)(j0[i] + done[i] + 1) * 8, true);
+            HuffArgs a{};
+            a.bv = block_view(c, done[i]);
+            a.h = HuffEnc{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
+                          s.cb.ustar_enc, s.cb.wbits};
+            a.bits = c.sc.aux.as<uint64_t>();
+            a.bitoff = s.bitoff.as<int64_t>() + j0[i];
+            a.nesc_total = root.ctrl_arena.as<unsigned long long>() + i * CW_COUNT + CW_SUM;
+            fa.push_back(a);
+            fb.push_back(grid_for(done[i], 256, 65536));
+        }
+        {
+            const int ps = prof_begin(root, "huff_bits");
+            HBM_GLAUNCH(root, fa, fb, 0, k_huff_bits, 256, HuffArgs);
+            prof_end(root, ps);
+        }
+        HBM_HIP(hipGetLastError());
+        std::vector<const int64_t *> tail;
+        for (size_t q = 0; q < H.size(); q++) {
+            Ctx &c = *J[H[q]];
+            scan_u64_to_i64(root, fa[q].bits, c.s.bitoff.as<int64_t>() + j0[H[q]], done[H[q]] + 1, (int64_t)c.s.nbits);
+            tail.push_back(c.s.bitoff.as<int64_t>() + j0[H[q]] + done[H[q]]);
+        }
+        std::vector<int64_t> total;
+        gather_tails(root, tail, total);
+        std::vector<SplitArgs> sa;
+        std::vector<uint32_t> sb;
+        for (size_t q = 0; q < H.size(); q++) {
+            Ctx &c = *J[H[q]];
+            buf_grow(c, c.s.payload, (size_t)((total[q] + 31) / 32 + 2) * 4, true);
+            fa[q].payload = c.s.payload.as<uint32_t>();
+            c.s.nbits = (uint64_t)total[q];
+            if (c.s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP) {
+                SplitArgs a{};
+                a.bv = fa[q].bv;
+                a.hot_rank = c.s.hot_rank.as<int32_t>();
+                a.j0 = j0[H[q]];
+                a.bitmap = c.s.bitmap.as<unsigned long long>();
+                a.nhot = c.s.nhot;
+                sa.push_back(a);
+                sb.push_back(grid_for(done[H[q]] * WAVE, 256, 65536));
+            }
+        }
+        // escape counters: zero this block's slots (the arena is the root's control block)
+        HBM_HIP(hipMemsetAsync(root.ctrl_arena.p, 0, root.ctrl_arena.bytes, root.stream));
+        {
+            const int ps = prof_begin(root, "huff_write");
+            HBM_GLAUNCH(root, fa, fb, 0, k_huff_write, 256, HuffArgs);
+            prof_end(root, ps);
+        }
+        HBM_HIP(hipGetLastError());
+        HBM_GLAUNCH(root, sa, sb, 0, k_split, 256, SplitArgs);
+        HBM_HIP(hipGetLastError());
+        std::vector<unsigned long long> esc(root.ctrl_arena.bytes / 8);
+        HBM_HIP(hipMemcpyAsync(esc.data(), root.ctrl_arena.p, root.ctrl_arena.bytes, hipMemcpyDeviceToHost, root.stream));
+        HBM_HIP(hipStreamSynchronize(root.stream));
+        for (size_t i : H) J[i]->s.escapes += (int64_t)esc[i * CW_COUNT + CW_SUM];
+    }
+    for (size_t i = 0; i < N; i++) J[i]->s.nsets = j0[i] + done[i];
+}
+
+// Make every job's store hold sets 0..theta[i]-1 under seed[i] (see store_extend), all jobs
+// advancing together block by block.
+void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
+                   const std::vector<uint64_t> &seed) {
+    const size_t N = J.size();
+    std::vector<int64_t> before(N);
+    for (size_t i = 0; i < N; i++) {
+        Ctx &c = *J[i];
+        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+        HBM_REQUIRE(theta[i] >= 0 && theta[i] < (int64_t(1) << 31), HBM_EINVAL, "theta must be in [0, 2^31)");
+        Store &s = c.s;
+        if ((s.has_seed && s.seed != seed[i]) || theta[i] < s.nsets) store_reset(c);
         s.has_seed = true;
-        s.seed = seed;
-        return;
+        s.seed = seed[i];
+        before[i] = s.nsets;
+        if (theta[i] == s.nsets) continue;
+        if (!s.hist.p) {
+            buf_alloc(c, s.hist, (size_t)c.g.n * 4);
+            buf_zero(c, s.hist, 0, (size_t)c.g.n * 4);
+        }
+        if (s.W == 0) {
+            const int64_t w = (int64_t)std::ceil(s.warmup_frac * (double)theta[i]);
+            s.W = std::max<int64_t>(1, std::min<int64_t>(w, theta[i]));
+        }
+        // arena sized to the request (about 64 ids per set), within [4M, 64M] entries
+        const int64_t want_sets = std::min<int64_t>(theta[i] - s.nsets, root.block_sets);
+        const size_t entries = (size_t)std::min<int64_t>(std::max<int64_t>(want_sets * 64, int64_t(1) << 22),
+                                                         int64_t(64) << 20);
+        ensure_scratch(c, std::max<size_t>(c.sc.cap, entries), std::max<int64_t>(c.sc.bcap, want_sets));
     }
-    const int32_t n = c.g.n;
-    if (!s.hist.p) {
-        buf_alloc(c, s.hist, (size_t)n * 4);
-        buf_zero(c, s.hist, 0, (size_t)n * 4);
-    }
-    s.has_seed = true;
-    s.seed = seed;
-    if (s.W == 0) {
-        int64_t w = (int64_t)std::ceil(s.warmup_frac * (double)theta);
-        s.W = std::max<int64_t>(1, std::min<int64_t>(w, theta));
-    }
-    const int64_t nsets_before = s.nsets;
-    const int64_t budget = c.budget;
     hipEvent_t e0, e1;
     HBM_HIP(hipEventCreate(&e0));
     HBM_HIP(hipEventCreate(&e1));
-    HBM_HIP(hipEventRecord(e0, c.stream));
-    ensure_scratch(c, std::max<size_t>(c.sc.cap, size_t(64) << 20), std::max<int64_t>(c.sc.bcap, c.block_sets));
-    const bool encoded = s.enc != HBM_ENC_NONE;
+    HBM_HIP(hipEventRecord(e0, root.stream));
     try {
-        if (encoded && !s.model_ready) {
-            buf_grow(c, s.warm, (size_t)n * 4, false);
-            buf_zero(c, s.warm, 0, (size_t)n * 4);
-            s.warm_sizes.clear();
-            for (int64_t j = 0; j < s.W;) {
-                const int64_t nb = std::min<int64_t>(s.W - j, c.block_sets);
-                const int64_t done = sample_block(c, j, j + nb, seed);
-                if (done == 0) {
-                    ensure_scratch(c, c.sc.cap * 2, c.sc.bcap);
+        // warm-up pass of every encoded job without a model: frequencies of sets [0, W)
+        std::vector<int64_t> wcur(N, 0);
+        std::vector<size_t> warmers;
+        for (size_t i = 0; i < N; i++) {
+            Store &s = J[i]->s;
+            if (theta[i] > s.nsets && s.enc != HBM_ENC_NONE && !s.model_ready) {
+                warmers.push_back(i);
+                buf_grow(*J[i], s.warm, (size_t)J[i]->g.n * 4, false);
+                buf_zero(*J[i], s.warm, 0, (size_t)J[i]->g.n * 4);
+                s.warm_sizes.clear();
+            }
+        }
+        for (;;) {
+            std::vector<Ctx *> jobs;
+            std::vector<size_t> idx;
+            std::vector<int64_t> j0, nb, done;
+            std::vector<uint64_t> sd;
+            for (size_t i : warmers)
+                if (wcur[i] < J[i]->s.W) {
+                    idx.push_back(i);
+                    jobs.push_back(J[i]);
+                    j0.push_back(wcur[i]);
+                    nb.push_back(std::min<int64_t>({J[i]->s.W - wcur[i], root.block_sets, J[i]->sc.bcap}));
+                    sd.push_back(seed[i]);
+                }
+            if (jobs.empty()) break;
+            sample_blocks(root, jobs, j0, nb, sd, done);
+            std::vector<HistArgs> ha;
+            std::vector<uint32_t> hb;
+            for (size_t q = 0; q < jobs.size(); q++) {
+                if (done[q] == 0) {
+                    ensure_scratch(*jobs[q], jobs[q]->sc.cap * 2, jobs[q]->sc.bcap);
                     continue;
                 }
-                BlockView bv{c.sc.mem.as<uint32_t>(), c.sc.pos.as<uint32_t>(), c.sc.size.as<uint32_t>(), done};
-                k_hist_add<<<grid_for(done * WAVE, 256, 65536), 256, 0, c.stream>>>(bv, s.warm.as<uint32_t>());
-                HBM_HIP(hipGetLastError());
-                record_warm_sizes(c, j, done);
-                j += done;
+                ha.push_back(HistArgs{block_view(*jobs[q], done[q]), jobs[q]->s.warm.as<uint32_t>()});
+                hb.push_back(grid_for(done[q] * WAVE, 256, 65536));
             }
-            characterize(s, n);
-            build_model(c);
-        }
-        for (int64_t j = s.nsets; j < theta;) {
-            const int64_t nb = std::min<int64_t>(theta - j, c.block_sets);
-            const int64_t done = sample_block(c, j, j + nb, seed);
-            if (done == 0) {
-                ensure_scratch(c, c.sc.cap * 2, c.sc.bcap);
-                continue;
+            HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
+            HBM_HIP(hipGetLastError());
+            for (size_t q = 0; q < jobs.size(); q++) {
+                if (!done[q]) continue;
+                record_warm_sizes(*jobs[q], j0[q], done[q]);
+                wcur[idx[q]] += done[q];
             }
-            if (!encoded) record_warm_sizes(c, j, done);
-            append_block(c, j, done);
-            j += done;
-            if (budget > 0 && store_bytes(c) > budget)
-                throw Error{HBM_EBUDGET, "store budget exceeded at " + std::to_string(j) + " sets"};
         }
-        if (!encoded && nsets_before < s.W && s.nsets >= s.W) characterize(s, n);
+        for (size_t i : warmers) {
+            characterize(J[i]->s, J[i]->g.n);
+            build_model(*J[i]);
+        }
+        // sampling and encoding proper
+        for (;;) {
+            std::vector<Ctx *> jobs;
+            std::vector<int64_t> j0, nb, done;
+            std::vector<uint64_t> sd;
+            for (size_t i = 0; i < N; i++)
+                if (J[i]->s.nsets < theta[i]) {
+                    jobs.push_back(J[i]);
+                    j0.push_back(J[i]->s.nsets);
+                    nb.push_back(std::min<int64_t>({theta[i] - J[i]->s.nsets, root.block_sets, J[i]->sc.bcap}));
+                    sd.push_back(seed[i]);
+                }
+            if (jobs.empty()) break;
+            sample_blocks(root, jobs, j0, nb, sd, done);
+            std::vector<Ctx *> ajobs;
+            std::vector<int64_t> aj0, adone;
+            for (size_t q = 0; q < jobs.size(); q++) {
+                if (done[q] == 0) {
+                    ensure_scratch(*jobs[q], jobs[q]->sc.cap * 2, jobs[q]->sc.bcap);
+                    continue;
+                }
+                if (jobs[q]->s.enc == HBM_ENC_NONE) record_warm_sizes(*jobs[q], j0[q], done[q]);
+                ajobs.push_back(jobs[q]);
+                aj0.push_back(j0[q]);
+                adone.push_back(done[q]);
+            }
+            if (!ajobs.empty()) append_blocks(root, ajobs, aj0, adone);
+            for (Ctx *c : ajobs)
+                if (c->budget > 0 && store_bytes(*c) > c->budget)
+                    throw Error{HBM_EBUDGET, "store budget exceeded at " + std::to_string(c->s.nsets) + " sets"};
+        }
+        for (size_t i = 0; i < N; i++) {
+            Store &s = J[i]->s;
+            if (s.enc == HBM_ENC_NONE && before[i] < s.W && s.nsets >= s.W) characterize(s, J[i]->g.n);
+        }
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         throw;
     }
-    HBM_HIP(hipEventRecord(e1, c.stream));
+    HBM_HIP(hipEventRecord(e1, root.stream));
     HBM_HIP(hipEventSynchronize(e1));
     float ms = 0;
     HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    c.t_sample += ms;
+    root.t_sample += ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+}
+
+void store_extend(Ctx &c, int64_t theta, uint64_t seed) {
+    extend_stores(c, std::vector<Ctx *>{&c}, std::vector<int64_t>{theta}, std::vector<uint64_t>{seed});
 }
 
 void store_stats(Ctx &c, hbm_store_stats *o) {
