@@ -40,8 +40,8 @@ extern "C" {
 typedef enum hbm_status {
     HBM_OK = 0,
     HBM_EINVAL = 1,  /* bad argument or malformed graph */
-    HBM_ENOMEM = 2,  /* device allocation failed (state unchanged) */
-    HBM_EBUDGET = 3, /* request exceeds the context's store budget (state unchanged) */
+    HBM_ENOMEM = 2,  /* device allocation failed */
+    HBM_EBUDGET = 3, /* the store went over its budget, or a final theta reached 2^31 sets */
     HBM_EDEVICE = 4, /* a HIP call failed */
     HBM_ESTATE = 5   /* call made in the wrong order (e.g. sampling before a graph) */
 } hbm_status;
@@ -125,8 +125,9 @@ void hbm_destroy(hbm_ctx *ctx);
 /* Reason for the last non-OK status on this context ("" if none). */
 const char *hbm_last_error(const hbm_ctx *ctx);
 
-/* Cap, in bytes, on device memory held by the RR store (0 = no cap).
-   Sampling that would exceed it returns HBM_EBUDGET and leaves the store as it was. */
+/* Cap, in bytes, on the RR store (index + payload + bitmap rows, as counted in
+   hbm_store_stats.store_bytes; 0 = no cap).  Sampling stops with HBM_EBUDGET after
+   the block that took the store over the cap (see hbm_sample_rr). */
 hbm_status hbm_set_budget(hbm_ctx *ctx, int64_t store_bytes);
 
 /* ---------------------------------------------------------------- graph */
@@ -163,7 +164,10 @@ hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, doubl
 /* Make the store hold RR sets j = 0 .. theta-1 under `seed`.  Appends when the
  * seed matches and theta grows; a different seed, or a smaller theta, resets
  * the store first.  HBM_ESTATE without a graph; HBM_EINVAL if theta < 0 or
- * theta >= 2^31; HBM_EBUDGET / HBM_ENOMEM leave the store unchanged. */
+ * theta >= 2^31.  Sets are added in blocks; HBM_EBUDGET (the store went over
+ * hbm_set_budget's limit) and HBM_ENOMEM leave a valid prefix of sets in the
+ * store: those of the blocks completed up to and including the one that failed
+ * the budget. */
 hbm_status hbm_sample_rr(hbm_ctx *ctx, int64_t theta, uint64_t seed);
 
 /* Greedy max coverage over the store (the Seed Selection paragraph; Alg. 2 /
@@ -184,6 +188,86 @@ hbm_status hbm_select_seeds(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *g
  * int32[k], gains uint64[k] (may be NULL), stats (may be NULL). */
 hbm_status hbm_imm(hbm_ctx *ctx, int32_t k, double eps, double l, uint64_t seed, int32_t *seeds, uint64_t *gains,
                    hbm_imm_stats *stats);
+
+/* ---------------------------------------------------------------- batched instances */
+
+/* One IMM query: k seeds at accuracy eps with failure exponent l (l = 1 gives
+ * probability at least 1 - 1/n), RR sets drawn under Philox seed `seed`. */
+typedef struct hbm_query {
+    int32_t k;
+    double eps;
+    double l;
+    uint64_t seed;
+} hbm_query;
+
+/* Full IMM (as hbm_imm) for `count` independent instances at once, each on its
+ * own context with its own graph and encoding.  Every step of the method runs as
+ * one grouped launch over all instances still in that step (sampling blocks,
+ * encoding, each greedy iteration), so many small instances share launches
+ * instead of paying for each.  Each instance's result equals what hbm_imm gives
+ * on its context alone.  The contexts must be distinct and on one device; the
+ * work runs on ctxs[0]'s stream, ordered after work already queued on each
+ * context's own stream.  Outputs per instance i: seeds[i] int32[k_i] (host),
+ * gains[i] uint64[k_i] (gains or gains[i] may be NULL), stats[i] (may be NULL),
+ * status[i] (may be NULL).  Returns HBM_OK when every instance succeeded, else
+ * the first failing instance's code (its outputs are untouched; its context's
+ * last error tells why); device errors fail every instance. */
+hbm_status hbm_imm_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int32_t *const *seeds,
+                         uint64_t *const *gains, hbm_imm_stats *stats, hbm_status *status);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request loop over one device-resident graph: queries are submitted at any
+ * time and answered by a worker thread with continuous batching.  Each step of
+ * the loop admits queued queries (arrival order) while fewer than max_active run
+ * and the RR stores fit the budget, then advances every admitted query by one
+ * IMM step in shared launches; a finished query frees its slot and store at once.
+ * The sum of the admitted queries' store bytes is kept within store_budget:
+ * sampling blocks are sized to the room left; when nothing can move the
+ * youngest query is preempted (store dropped, re-queued at the head, recomputed
+ * later with the same result).  A query that does not fit even alone fails with
+ * HBM_EBUDGET.  Results are those of hbm_imm on the graph alone.
+ * The server borrows the graph context's device graph and its encoding settings
+ * (hbm_set_encoding) at creation: that context must not load another graph or be
+ * destroyed while the server exists.  Server memory comes from hipMalloc; its
+ * work runs on a stream of its own. */
+typedef struct hbm_server hbm_server;
+
+typedef struct hbm_serve_info {
+    int32_t done;        /* 1 once the query finished (status holds the outcome) */
+    hbm_status status;
+    int32_t preemptions; /* times the query was preempted and restarted */
+    double t_submit_ms;  /* server clock: ms since hbm_server_create */
+    double t_admit_ms;   /* last admission (-1 while queued) */
+    double t_done_ms;
+    char error[128];
+} hbm_serve_info;
+
+typedef struct hbm_server_stats {
+    int64_t submitted, admitted, completed, failed, preemptions;
+    int64_t steps;            /* batched IMM steps run */
+    int64_t peak_active;      /* most queries admitted at once */
+    int64_t peak_store_bytes; /* most store bytes held at once (after a step) */
+    int64_t active, queued;   /* now */
+} hbm_server_stats;
+
+/* HBM_EINVAL for a NULL argument, store_budget <= 0 or max_active < 1;
+ * HBM_ESTATE if the context has no graph. */
+hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_budget, int32_t max_active);
+/* Stops the loop after its current step; unfinished queries are dropped. */
+void hbm_server_destroy(hbm_server *srv);
+const char *hbm_server_last_error(const hbm_server *srv);
+/* Queue a query; *ticket identifies it.  Invalid queries are accepted and fail at
+ * admission (their status says why).  HBM_EDEVICE once the server has failed. */
+hbm_status hbm_server_submit(hbm_server *srv, const hbm_query *q, int64_t *ticket);
+/* State of a ticket (wait != 0 blocks until it finishes).  info->done = 0 while
+ * pending.  Once done, seeds int32[k] / gains uint64[k] / stats (each may be NULL)
+ * receive the result when info->status is HBM_OK, and the ticket is forgotten
+ * (a later poll of it returns HBM_EINVAL).  HBM_EINVAL for an unknown ticket. */
+hbm_status hbm_server_poll(hbm_server *srv, int64_t ticket, int32_t wait, int32_t *seeds, uint64_t *gains,
+                           hbm_imm_stats *stats, hbm_serve_info *info);
+/* Counters of the loop; HBM_EDEVICE (counters still filled) once it has failed. */
+hbm_status hbm_server_get_stats(hbm_server *srv, hbm_server_stats *out);
 
 /* ---------------------------------------------------------------- tuning */
 

@@ -27,7 +27,9 @@ ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uin
           "PAYLOAD": (12, np.uint32)}
 EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
-            "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_profile", "hbm_profile_read"]
+            "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
+            "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
+            "hbm_server_poll", "hbm_server_get_stats"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3}
 
 
@@ -70,6 +72,23 @@ class ImmStats(C.Structure):
         return d
 
 
+class Query(C.Structure):
+    _fields_ = [("k", C.c_int32), ("eps", C.c_double), ("l", C.c_double), ("seed", C.c_uint64)]
+
+
+class ServeInfo(C.Structure):
+    _fields_ = [("done", C.c_int32), ("status", C.c_int), ("preemptions", C.c_int32), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("error", C.c_char * 128)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "failed", "preemptions", "steps",
+                                         "peak_active", "peak_store_bytes", "active", "queued")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -100,6 +119,13 @@ def lib():
         "hbm_set_tuning": ([P, C.c_int, I64], C.c_int),
         "hbm_profile": ([P, I32], C.c_int),
         "hbm_profile_read": ([P, C.POINTER(KernelStat), I32, C.POINTER(I32)], C.c_int),
+        "hbm_imm_batch": ([P, I32, C.POINTER(Query), P, P, C.POINTER(ImmStats), P], C.c_int),
+        "hbm_server_create": ([C.POINTER(P), P, I64, I32], C.c_int),
+        "hbm_server_destroy": ([P], None),
+        "hbm_server_last_error": ([P], C.c_char_p),
+        "hbm_server_submit": ([P, C.POINTER(Query), C.POINTER(I64)], C.c_int),
+        "hbm_server_poll": ([P, I64, I32, P, P, C.POINTER(ImmStats), C.POINTER(ServeInfo)], C.c_int),
+        "hbm_server_get_stats": ([P, C.POINTER(ServerStats)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -169,13 +195,23 @@ class Context:
         self._check(lib().hbm_set_tuning(self.h, TUNE[key], int(value)))
 
     def hbm_load_graph(self, n, row_ptr, dst, w=None, model="IC", prob="EDGE"):
-        """Upload a forward CSR (numpy or torch) and load it; device copies live only for the call."""
+        """Load a forward CSR given as numpy arrays (copied to the device for the call) or as
+        contiguous device tensors of this context's GPU (int64 row_ptr, int32 dst, float32 w)."""
         torch = self._torch
         dev = torch.device("cuda", self.device)
+
+        def on_dev(a, dt_np, dt_t):
+            if isinstance(a, torch.Tensor):
+                if a.device != dev or a.dtype != dt_t or not a.is_contiguous():
+                    raise ValueError(f"device tensor must be contiguous {dt_t} on {dev}")
+                return a
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=dt_np)).to(dev)
+
+        torch.cuda.current_stream(self.device).synchronize()
         with torch.cuda.stream(self.stream):
-            rp = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int64)).to(dev)
-            ds = torch.as_tensor(np.ascontiguousarray(dst, dtype=np.int32)).to(dev)
-            ww = None if w is None else torch.as_tensor(np.ascontiguousarray(w, dtype=np.float32)).to(dev)
+            rp = on_dev(row_ptr, np.int64, torch.int64)
+            ds = on_dev(dst, np.int32, torch.int32)
+            ww = None if w is None else on_dev(w, np.float32, torch.float32)
         self.stream.synchronize()
         m = int(ds.numel())
         mod = HBM_IC if model in ("IC", HBM_IC) else HBM_LT
@@ -246,6 +282,88 @@ class Context:
         buf = np.zeros(max(nb.value // np.dtype(dt).itemsize, 1), dtype=dt)
         self._check(lib().hbm_export(self.h, code, _ptr(buf), buf.nbytes, C.byref(nb)))
         return buf[:nb.value // np.dtype(dt).itemsize]
+
+
+def imm_batch(contexts, queries):
+    """hbm_imm_batch over Context objects; queries are (k, eps, l, seed) tuples.  Returns a list
+    of (seeds, gains, stats) per instance; raises on the first failing instance."""
+    L = lib()
+    n = len(contexts)
+    hs = (C.c_void_p * n)(*[c.h for c in contexts])
+    q = (Query * n)(*[Query(int(k), float(e), float(l), int(sd)) for (k, e, l, sd) in queries])
+    seeds = [np.zeros(int(k), dtype=np.int32) for (k, _, _, _) in queries]
+    gains = [np.zeros(int(k), dtype=np.uint64) for (k, _, _, _) in queries]
+    sp = (C.c_void_p * n)(*[s.ctypes.data for s in seeds])
+    gp = (C.c_void_p * n)(*[g.ctypes.data for g in gains])
+    stats = (ImmStats * n)()
+    status = np.zeros(n, dtype=np.int32)
+    st = L.hbm_imm_batch(hs, n, q, sp, gp, stats, _ptr(status))
+    if st != HBM_OK:
+        bad = [i for i in range(n) if status[i] != HBM_OK]
+        i = bad[0] if bad else 0
+        msg = L.hbm_last_error(contexts[i].h)
+        raise HbmError(st, f"instance {i}: " + (msg.decode() if msg else ""))
+    return [(seeds[i], gains[i], stats[i].as_dict()) for i in range(n)]
+
+
+class Server:
+    """hbm_server over the graph (and encoding) of a Context."""
+
+    def __init__(self, ctx: Context, store_budget: int, max_active: int = 16):
+        h = C.c_void_p()
+        st = lib().hbm_server_create(C.byref(h), ctx.h, int(store_budget), int(max_active))
+        if st != HBM_OK:
+            raise HbmError(st, "hbm_server_create failed")
+        self.h = h
+        self.ctx = ctx  # keeps the graph alive
+        self.k = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hbm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hbm_server_submit(self, k: int, eps: float, l: float, seed: int) -> int:
+        t = C.c_int64()
+        q = Query(int(k), float(eps), float(l), int(seed))
+        st = lib().hbm_server_submit(self.h, C.byref(q), C.byref(t))
+        if st != HBM_OK:
+            msg = lib().hbm_server_last_error(self.h)
+            raise HbmError(st, msg.decode() if msg else "")
+        self.k[t.value] = int(k)
+        return t.value
+
+    def hbm_server_poll(self, ticket: int, wait: bool = False):
+        """None while pending; else a dict with status, seeds, gains, stats and times."""
+        k = self.k.get(ticket, 1)
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        st = ImmStats()
+        info = ServeInfo()
+        rc = lib().hbm_server_poll(self.h, int(ticket), 1 if wait else 0, _ptr(seeds), _ptr(gains), C.byref(st),
+                                   C.byref(info))
+        if rc != HBM_OK:
+            raise HbmError(rc, f"poll of ticket {ticket}")
+        if not info.done:
+            return None
+        self.k.pop(ticket, None)
+        out = dict(status=STATUS.get(info.status, info.status), preemptions=info.preemptions,
+                   t_submit_ms=info.t_submit_ms, t_admit_ms=info.t_admit_ms, t_done_ms=info.t_done_ms,
+                   error=info.error.decode())
+        if info.status == HBM_OK:
+            out.update(seeds=seeds, gains=gains, stats=st.as_dict())
+        return out
+
+    def hbm_server_get_stats(self) -> dict:
+        s = ServerStats()
+        lib().hbm_server_get_stats(self.h, C.byref(s))
+        return s.as_dict()
 
 
 def version() -> str:

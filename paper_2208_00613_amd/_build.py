@@ -11,14 +11,14 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libhbmax.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["common.hip", "graph.hip", "sample.hip", "store.hip", "select.hip", "api.hip"]
+SOURCES = ["common.hip", "graph.hip", "sample.hip", "store.hip", "select.hip", "imm.hip", "serve.hip", "api.hip"]
 ARCH = os.environ.get("HBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     # packed fp32 instructions are kept off for correctness on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", INCLUDE, "-Wno-unused-result",
+    "-I", INCLUDE, "-Wno-unused-result", "-pthread",
 ]
 
 
@@ -37,7 +37,7 @@ def build(jobs: int = 6) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    r = subprocess.run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs],
+    r = subprocess.run(["hipcc", "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

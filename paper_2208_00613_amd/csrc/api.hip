@@ -3,11 +3,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "hbm_internal.h"
-
-struct hbm_ctx {
-    hbm::Ctx c;
-};
+#include "hbm_imm.h"
 
 using hbm::Ctx;
 using hbm::Error;
@@ -33,28 +29,6 @@ hbm_status guard(hbm_ctx *ctx, F &&f) {
         ctx->c.last_error = e.what();
         return HBM_EDEVICE;
     }
-}
-
-// IMM parameters (Tang, Shi, Xiao 2015), evaluated in double in this order.
-struct ImmParams {
-    double l_adj, eps_prime, lnC, lambda_prime, lambda_star;
-};
-
-ImmParams imm_params(int32_t n, int32_t k, double eps, double l) {
-    ImmParams p;
-    const double dn = (double)n;
-    p.l_adj = l * (1.0 + log(2.0) / log(dn));
-    p.eps_prime = sqrt(2.0) * eps;
-    double lc = 0.0;
-    for (int32_t i = 1; i <= k; i++) lc += log((double)(n - k + i)) - log((double)i);
-    p.lnC = lc;
-    const double ep = p.eps_prime, la = p.l_adj;
-    p.lambda_prime = (2.0 + 2.0 * ep / 3.0) * (lc + la * log(dn) + log(log2(dn))) * dn / (ep * ep);
-    const double e1 = 1.0 - 1.0 / exp(1.0);
-    const double alpha = sqrt(la * log(dn) + log(2.0));
-    const double beta = sqrt(e1 * (lc + la * log(dn) + log(2.0)));
-    p.lambda_star = 2.0 * dn * (e1 * alpha + beta) * (e1 * alpha + beta) / (eps * eps);
-    return p;
 }
 
 }  // namespace
@@ -97,7 +71,10 @@ void hbm_destroy(hbm_ctx *ctx) {
         hbm::select_free(ctx->c);
         hbm::store_free(ctx->c);
         hbm::graph_free(ctx->c);
-        hbm::buf_free(ctx->c, ctx->c.scan_tmp);
+        for (hbm::Buf *b : {&ctx->c.scan_tmp, &ctx->c.ctrl_arena, &ctx->c.tails, &ctx->c.bkeys,
+                            &ctx->c.dctr})
+            hbm::buf_free(ctx->c, *b);
+        hbm::stage_free(ctx->c);
     } catch (...) {
     }
     delete ctx;
@@ -154,58 +131,83 @@ hbm_status hbm_imm(hbm_ctx *ctx, int32_t k, double eps, double l, uint64_t seed,
                    hbm_imm_stats *stats) {
     return guard(ctx, [&](Ctx &c) {
         HBM_REQUIRE(seeds, HBM_EINVAL, "null seeds");
-        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
-        const int32_t n = c.g.n;
-        HBM_REQUIRE(n >= 2, HBM_EINVAL, "IMM needs n >= 2");
-        HBM_REQUIRE(k >= 1 && k <= n, HBM_EINVAL, "k must be in [1, n]");
-        HBM_REQUIRE(eps > 0.0 && std::isfinite(eps), HBM_EINVAL, "eps must be positive");
-        HBM_REQUIRE(l > 0.0 && std::isfinite(l), HBM_EINVAL, "l must be positive");
-        const auto t0 = std::chrono::steady_clock::now();
-        c.t_sample = c.t_select = c.t_encode = 0;
-        hbm::store_reset(c);
-        const ImmParams P = imm_params(n, k, eps, l);
-        const double dn = (double)n;
-        hbm_imm_stats st{};
-        st.lambda_prime = P.lambda_prime;
-        st.lambda_star = P.lambda_star;
-        std::vector<int32_t> s((size_t)k);
-        std::vector<uint64_t> g((size_t)k);
-        uint64_t cov = 0;
-        double lb = 1.0;
-        for (int32_t i = 1; (double)i <= log2(dn) - 1.0; i++) {
-            const double x = dn / pow(2.0, (double)i);
-            const int64_t th = (int64_t)ceil(P.lambda_prime / x);
-            hbm::store_extend(c, th, seed);
-            hbm::select_seeds(c, k, s.data(), g.data(), &cov);
-            if (st.rounds < 64) {
-                st.theta_round[st.rounds] = th;
-                st.cov_round[st.rounds] = cov;
-            }
-            st.rounds++;
-            if (dn * (double)cov / (double)th >= (1.0 + P.eps_prime) * x) {
-                lb = dn * (double)cov / ((double)th * (1.0 + P.eps_prime));
-                break;
+        hbm::ImmJob J;
+        J.c = &c;
+        J.k = k;
+        J.eps = eps;
+        J.l = l;
+        J.seed = seed;
+        hbm::imm_run(c, {&J});
+        if (J.phase == hbm::ImmJob::FAILED) throw Error{J.status, J.error};
+        std::memcpy(seeds, J.seeds.data(), (size_t)k * 4);
+        if (gains) std::memcpy(gains, J.gains.data(), (size_t)k * 8);
+        if (stats) *stats = J.st;
+    });
+}
+
+hbm_status hbm_imm_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int32_t *const *seeds,
+                         uint64_t *const *gains, hbm_imm_stats *stats, hbm_status *status) {
+    if (!ctxs || count < 1 || !queries || !seeds) return HBM_EINVAL;
+    for (int32_t i = 0; i < count; i++) {
+        if (!ctxs[i] || !seeds[i]) return HBM_EINVAL;
+        for (int32_t j = 0; j < i; j++)
+            if (ctxs[j] == ctxs[i]) return HBM_EINVAL;
+        if (ctxs[i]->c.device != ctxs[0]->c.device) return HBM_EINVAL;
+    }
+    hbm_ctx *root = ctxs[0];
+    std::vector<hipStream_t> own((size_t)count);
+    std::vector<hbm::ImmJob> J((size_t)count);
+    bool streams_swapped = false;
+    const hbm_status rc = guard(root, [&](Ctx &r) {
+        // every instance's work goes on the first context's stream for the call
+        hipEvent_t ev;
+        HBM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        for (int32_t i = 0; i < count; i++) {
+            Ctx &c = ctxs[i]->c;
+            own[(size_t)i] = c.stream;
+            if (c.stream != r.stream) {
+                HBM_HIP(hipEventRecord(ev, c.stream));
+                HBM_HIP(hipStreamWaitEvent(r.stream, ev, 0));
             }
         }
-        const double thf = ceil(P.lambda_star / lb);
-        HBM_REQUIRE(thf < 2147483648.0, HBM_EBUDGET, "final theta exceeds 2^31 sets");
-        const int64_t theta = (int64_t)thf;
-        st.lb = lb;
-        st.theta_final = theta;
-        hbm::store_extend(c, std::max<int64_t>(theta, c.s.nsets), seed);
-        hbm::select_seeds(c, k, s.data(), g.data(), &cov);
-        st.nsets_final = c.s.nsets;
-        st.coverage = cov;
-        st.influence = dn * (double)cov / (double)c.s.nsets;
-        st.t_sample_ms = c.t_sample;
-        st.t_encode_ms = c.t_encode;
-        st.t_select_ms = c.t_select;
-        st.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        hbm::store_stats(c, &st.store);
-        std::memcpy(seeds, s.data(), (size_t)k * 4);
-        if (gains) std::memcpy(gains, g.data(), (size_t)k * 8);
-        if (stats) *stats = st;
+        (void)hipEventDestroy(ev);
+        for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = r.stream;
+        streams_swapped = true;
+        std::vector<hbm::ImmJob *> jp;
+        for (int32_t i = 0; i < count; i++) {
+            hbm::ImmJob &j = J[(size_t)i];
+            j.c = &ctxs[i]->c;
+            j.k = queries[i].k;
+            j.eps = queries[i].eps;
+            j.l = queries[i].l;
+            j.seed = queries[i].seed;
+            jp.push_back(&j);
+        }
+        hbm::imm_run(r, jp);
+        HBM_HIP(hipStreamSynchronize(r.stream));
     });
+    if (streams_swapped)
+        for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = own[(size_t)i];
+    if (rc != HBM_OK) {
+        if (status)
+            for (int32_t i = 0; i < count; i++) status[i] = rc;
+        return rc;
+    }
+    hbm_status first = HBM_OK;
+    for (int32_t i = 0; i < count; i++) {
+        const hbm::ImmJob &j = J[(size_t)i];
+        const hbm_status s = j.phase == hbm::ImmJob::DONE ? HBM_OK : j.status;
+        if (status) status[i] = s;
+        if (s != HBM_OK) {
+            ctxs[i]->c.last_error = j.error;
+            if (first == HBM_OK) first = s;
+            continue;
+        }
+        std::memcpy(seeds[i], j.seeds.data(), j.seeds.size() * 4);
+        if (gains && gains[i]) std::memcpy(gains[i], j.gains.data(), j.gains.size() * 8);
+        if (stats) stats[i] = j.st;
+    }
+    return first;
 }
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {

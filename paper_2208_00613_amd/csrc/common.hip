@@ -1,6 +1,9 @@
 // common.hip -- device memory through the context's allocator, and prefix sums.
 #include <rocprim/device/device_scan.hpp>
 
+#include <algorithm>
+#include <cstring>
+
 #include "hbm_internal.h"
 
 namespace hbm {
@@ -91,11 +94,42 @@ void scan_u64_to_i64(Ctx &c, const uint64_t *in, int64_t *out, int64_t count, in
     scan_impl(c, in, out, count, init);
 }
 
-void *stage_upload(Ctx &root, size_t off, const void *host, size_t bytes) {
-    if (root.stage.bytes < off + bytes) buf_grow(root, root.stage, off + bytes + (size_t(1) << 20), false);
-    void *d = (char *)root.stage.p + off;
-    HBM_HIP(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, root.stream));
+// Descriptors are bump-allocated in a device buffer and copied from a pinned host mirror
+// at the same offset, so no byte is rewritten while a queued copy or kernel may still use
+// it; the space is recycled only once the stream has drained (stage_reset, or a refill).
+void *stage_upload(Ctx &root, const void *host, size_t bytes) {
+    const size_t need = (bytes + 255) & ~size_t(255);
+    if (root.stage_pos + need > root.stage.bytes) {
+        HBM_HIP(hipStreamSynchronize(root.stream));
+        if (need > root.stage.bytes) {
+            const size_t cap = std::max<size_t>(need, std::max<size_t>(root.stage.bytes * 2, size_t(4) << 20));
+            buf_alloc(root, root.stage, cap);
+            if (root.hstage) (void)hipHostFree(root.hstage);
+            root.hstage = nullptr;
+            HBM_HIP(hipHostMalloc(&root.hstage, cap, hipHostMallocDefault));
+        }
+        root.stage_pos = 0;
+    }
+    char *h = (char *)root.hstage + root.stage_pos;
+    char *d = (char *)root.stage.p + root.stage_pos;
+    std::memcpy(h, host, bytes);
+    HBM_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, root.stream));
+    root.stage_pos += need;
     return d;
+}
+
+void stage_reset(Ctx &root) {
+    if (root.stage_pos == 0) return;
+    HBM_HIP(hipStreamSynchronize(root.stream));
+    root.stage_pos = 0;
+}
+
+void stage_free(Ctx &root) {
+    (void)hipStreamSynchronize(root.stream);
+    buf_free(root, root.stage);
+    if (root.hstage) (void)hipHostFree(root.hstage);
+    root.hstage = nullptr;
+    root.stage_pos = 0;
 }
 
 // ------------------------------------------------------------------ profiler

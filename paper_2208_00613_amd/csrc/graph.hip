@@ -161,6 +161,10 @@ static uint32_t read_flags(Ctx &c, Buf &flags) {
 }
 
 void graph_free(Ctx &c) {
+    if (c.g.borrowed) {
+        c.g = DGraph{};
+        return;
+    }
     buf_free(c, c.g.in_ptr);
     buf_free(c, c.g.in_src);
     buf_free(c, c.g.thr);

@@ -130,7 +130,8 @@ __device__ __forceinline__ uint32_t group_of(const uint32_t *boff, uint32_t coun
     __global__ __launch_bounds__(THREADS) void NAME(ARGS A, int x) { NAME##_body(A, blockIdx.x, gridDim.x, x); } \
     __global__ __launch_bounds__(THREADS) void NAME##_g(GroupArgs<ARGS> G) {                         \
         const uint32_t i = group_of(G.boff, G.count, blockIdx.x);                                     \
-        NAME##_body(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i], G.x);               \
+        const ARGS a_ = G.args[i]; /* uniform: held in scalar registers, not re-read */              \
+        NAME##_body(a_, blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i], G.x);                      \
     }                                                                                                \
     __device__ void NAME##_body(const ARGS &A, uint32_t bid, uint32_t nblk, int x)
 

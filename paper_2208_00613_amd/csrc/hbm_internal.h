@@ -55,6 +55,7 @@ struct DGraph {
     Buf thr;     // uint32[m] (IC-EDGE, LT) or uint32[n] (IC-WC)
     Buf guide;   // uint32[2m] LT cut-point index (see graph.hip)
     bool loaded = false;
+    bool borrowed = false;  // a copy of another context's graph: never freed here
 };
 
 // ------------------------------------------------------------------ store
@@ -77,6 +78,7 @@ struct Store {
     uint64_t seed = 0;
     int64_t nsets = 0;
     int64_t W = 0;          // warm-up sets (0 until the first request)
+    int64_t wcur = 0;       // warm-up sets counted so far
     bool model_ready = false;
     int64_t members = 0;
 
@@ -183,6 +185,7 @@ struct Ctx {
     int64_t ic_t1_budget = 4096;
     int64_t block_sets = int64_t(1) << 21;
     int lt_lw = 128;
+    int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
     DGraph g;
     Store s;
     Scratch sc;
@@ -191,8 +194,11 @@ struct Ctx {
     // batched jobs (this context drives them): control words, launch descriptors, readbacks
     Buf ctrl_arena;                        // uint64[jobs * CW_COUNT]
     std::vector<unsigned long long> ctrl_host;
-    Buf stage;                             // grouped-launch descriptors
+    Buf stage;                             // grouped-launch descriptors (device)
+    void *hstage = nullptr;                // pinned host mirror of `stage`
+    size_t stage_pos = 0;                  // bump offset into both
     Buf tails;                             // uint64 per job: gathered totals
+    Buf bkeys;                             // uint64 selection keys of every job
     Prof prof;
     Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)
     // timing of the last operations (ms)
@@ -209,6 +215,11 @@ void store_free(Ctx &c);
 void store_extend(Ctx &c, int64_t theta, uint64_t seed);
 void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
                    const std::vector<uint64_t> &seed);
+// One block of progress for every job towards theta[i] (a warm-up block while the job's
+// codebook is not built yet): cap[i] >= 0 bounds the job's sets in this step (empty: no
+// bound).  st[i] is EBUDGET when the job's store went over its context budget.
+void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
+                 const std::vector<uint64_t> &seed, const std::vector<int64_t> &cap, std::vector<hbm_status> &st);
 int64_t store_bytes(const Ctx &c);
 void store_stats(Ctx &c, hbm_store_stats *out);
 void store_dump(Ctx &c, int64_t j0, int64_t j1, std::vector<int64_t> &off, std::vector<int32_t> &mem);
@@ -222,6 +233,10 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
 void ensure_scratch(Ctx &c, size_t entries, int64_t bcap);
 
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
+// greedy selection for several jobs at once (root drives the launches)
+void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
+                  std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
+                  std::vector<uint64_t> &coverage);
 void select_free(Ctx &c);
 
 // profiler: prof_begin records the start event of a launch (returns -1 when off),
@@ -233,10 +248,12 @@ void prof_flush(Ctx &c);
 unsigned long long *prof_counters(Ctx &c);  // device counters, or null when profiling is off
 void prof_read_counters(Ctx &c, unsigned long long *host);  // and clear them
 
-// Upload `bytes` of host data to the context's descriptor staging buffer at `off`;
-// returns the device address.  Stream order makes reuse safe: a later copy into the same
-// bytes runs after the kernels that read them.
-void *stage_upload(Ctx &root, size_t off, const void *host, size_t bytes);
+// Copy `bytes` of host data into fresh descriptor space on the device (ordered on the
+// root's stream) and return its device address.  stage_reset recycles the space once the
+// stream is idle; stage_free releases it.
+void *stage_upload(Ctx &root, const void *host, size_t bytes);
+void stage_reset(Ctx &root);
+void stage_free(Ctx &root);
 
 // Grouped launch: one job runs the plain kernel with arguments by value; several jobs run
 // the grouped kernel over a descriptor array.  l1(args, blocks) / lg(GroupArgs, blocks).
@@ -250,9 +267,8 @@ void glaunch(Ctx &root, const std::vector<Args> &args, const std::vector<uint32_
     std::vector<uint32_t> boff(args.size() + 1, 0);
     for (size_t i = 0; i < args.size(); i++) boff[i + 1] = boff[i] + nblk[i];
     if (!boff.back()) return;
-    const size_t ab = (args.size() * sizeof(Args) + 255) & ~size_t(255);
-    Args *da = (Args *)stage_upload(root, 0, args.data(), args.size() * sizeof(Args));
-    uint32_t *db = (uint32_t *)stage_upload(root, ab, boff.data(), boff.size() * 4);
+    Args *da = (Args *)stage_upload(root, args.data(), args.size() * sizeof(Args));
+    uint32_t *db = (uint32_t *)stage_upload(root, boff.data(), boff.size() * 4);
     lg(da, db, (uint32_t)args.size(), boff.back(), x);
 }
 

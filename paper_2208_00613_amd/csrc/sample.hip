@@ -786,7 +786,7 @@ static void ensure_t2(Ctx &c) {
     const uint64_t words = (n + 31) / 32;
     int slots = 2 * c.num_cus;
     const uint64_t per = words * 4 + n * 4;
-    const uint64_t cap_bytes = uint64_t(8) << 30;  // at most 8 GiB for big-set slots
+    const uint64_t cap_bytes = (uint64_t)c.t2_cap;  // bytes allowed for big-set slots
     while (slots > 8 && per * slots > cap_bytes) slots /= 2;
     buf_alloc(c, sc.t2_bitmap, words * 4 * slots);
     buf_zero(c, sc.t2_bitmap, 0, words * 4 * slots);

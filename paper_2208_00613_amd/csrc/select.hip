@@ -52,15 +52,32 @@ struct SelArgs {
     int64_t nraw;                 // plain ids in the store
     unsigned long long *partial;  // per-block argmax partials
     int32_t nparts;               // argmax blocks
+    const uint32_t *hist;         // store frequencies (initial counts)
+    int32_t k;                    // seeds to pick
+    int32_t hx;                   // hot-count blocks per word segment
+    int64_t seg;                  // words per hot-count segment
 };
 
 // Exact argmax over counts, stage 1: each block writes the best key of its slice to
 // partial[block]; the consumer kernels of the same iteration reduce the partials
 // themselves (no atomics or fences needed: kernel boundaries order the stream).
 // Also clears the `newly` words for this iteration's find step.
-__global__ __launch_bounds__(256) void k_argmax(SelArgs A, int t) {
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+// Selection state at the start: counts = store frequencies, nothing selected or covered.
+HBM_KERNEL(k_sel_init, SelArgs, 256) {
+    const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)nblk * blockDim.x;
+    const int64_t sw = ((int64_t)A.n + 31) / 32;
+    for (int64_t v = tid; v < A.n; v += nthr) A.counts[v] = A.hist ? A.hist[v] : 0u;
+    for (int64_t v = tid; v < sw; v += nthr) A.selmask[v] = 0u;
+    for (int64_t w = tid; w < A.words; w += nthr) A.covered[w] = 0ull;
+    for (int64_t i = tid; i < A.k; i += nthr) A.keys[i] = 0ull;
+}
+
+HBM_KERNEL(k_argmax, SelArgs, 256) {
+    const int t = x;
+    (void)t;
+    const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)nblk * blockDim.x;
     for (int64_t w = tid; w < A.words; w += nthr) A.newly[w] = 0ull;
     unsigned long long best = 0;
     const int64_t n4 = A.n >> 2;
@@ -90,7 +107,7 @@ __global__ __launch_bounds__(256) void k_argmax(SelArgs A, int t) {
     if (threadIdx.x == 0) {
         unsigned long long b = part[0];
         for (int i = 1; i < (int)(blockDim.x / WAVE); i++) b = part[i] > b ? part[i] : b;
-        A.partial[blockIdx.x] = b;
+        A.partial[bid] = b;
     }
 }
 
@@ -234,12 +251,12 @@ __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned l
 }
 
 // Plain ids: one coalesced pass over every stored id; a match marks its set (if uncovered) in `newly`.
-__global__ __launch_bounds__(256) void k_find_raw(SelArgs A, int t) {
+HBM_KERNEL(k_find_raw, SelArgs, 256) {
     unsigned long long key;
-    const uint32_t u = ustar_of(A, t, key);
+    const uint32_t u = ustar_of(A, x, key);
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
-    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)nblk * blockDim.x;
     const int64_t n4 = A.nraw >> 2;
     const uint4 *m4 = reinterpret_cast<const uint4 *>(A.raw_mem);
     for (int64_t q = tid; q <= n4; q += nthr) {
@@ -274,7 +291,7 @@ __global__ __launch_bounds__(256) void k_find_raw(SelArgs A, int t) {
 // coalesced loads first (when they fit), so the lanes decode from LDS.
 constexpr int STAGE_WORDS = 1024;
 
-__global__ __launch_bounds__(256) void k_find_huff(SelArgs A, int t) {
+HBM_KERNEL(k_find_huff, SelArgs, 256) {
     __shared__ Tabs tb;
     __shared__ uint32_t stage[256 / WAVE][STAGE_WORDS];
     __shared__ DecCache C;
@@ -282,14 +299,14 @@ __global__ __launch_bounds__(256) void k_find_huff(SelArgs A, int t) {
     cache_init(C);
     __syncthreads();
     unsigned long long key;
-    const uint32_t u = ustar_of(A, t, key);
+    const uint32_t u = ustar_of(A, x, key);
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
     const uint32_t ustar_len = A.lens[u];
     const uint32_t ustar_code = ustar_len ? A.codes[u] : 0u;
     const unsigned lane = lane_id();
     const int wv = threadIdx.x / WAVE;
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + wv; w < A.words; w += nwaves) {
+    const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
+    for (int64_t w = bid * (int64_t)(blockDim.x / WAVE) + wv; w < A.words; w += nwaves) {
         const unsigned long long cov = A.covered[w];
         const int64_t j0 = w * 64;
         const int64_t j1 = j0 + 64 < A.T ? j0 + 64 : A.T;
@@ -327,13 +344,14 @@ __global__ __launch_bounds__(256) void k_find_huff(SelArgs A, int t) {
     cache_flush(C, A.counts);
 }
 
-__global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
+HBM_KERNEL(k_apply, SelArgs, 256) {
+    const int t = x;
     __shared__ Tabs tb;
     __shared__ DecCache C;
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
         A.keys[t] = key;
     }
@@ -343,8 +361,8 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
     cache_init(C);
     __syncthreads();
     const unsigned lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / WAVE);
-    for (int64_t w = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
+    const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
+    for (int64_t w = bid * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
         const unsigned long long cov = A.covered[w];
         const unsigned long long nw = (r >= 0 ? A.bitmap[w * (int64_t)A.nhot + r] : A.newly[w]) & ~cov;
         if (lane == 0) {
@@ -372,11 +390,14 @@ __global__ __launch_bounds__(256) void k_apply(SelArgs A, int t) {
     cache_flush(C, A.counts);
 }
 
-// hot counts -= popcount(row AND newly), over a segment of words per block row
-__global__ __launch_bounds__(256) void k_dec_hot(SelArgs A, int64_t seg) {
-    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t w0 = blockIdx.y * seg;
-    const int64_t w1 = w0 + seg < A.words ? w0 + seg : A.words;
+// hot counts -= popcount(row AND newly): block b covers hot ranks [256 (b mod hx), +256)
+// over the words of segment b / hx
+HBM_KERNEL(k_dec_hot, SelArgs, 256) {
+    (void)nblk;
+    (void)x;
+    const int64_t h = (int64_t)(bid % (uint32_t)A.hx) * blockDim.x + threadIdx.x;
+    const int64_t w0 = (int64_t)(bid / (uint32_t)A.hx) * A.seg;
+    const int64_t w1 = w0 + A.seg < A.words ? w0 + A.seg : A.words;
     uint32_t acc = 0;
     for (int64_t w = w0; w < w1; w++) {
         const unsigned long long nwv = A.newly[w];
@@ -391,33 +412,31 @@ void select_free(Ctx &c) {
     S.words_cap = 0;
 }
 
-void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
-    HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
-    HBM_REQUIRE(k >= 1 && k <= c.g.n, HBM_EINVAL, "k must be in [1, n]");
+namespace {
+
+// Per-job launch geometry and algorithmic bytes of one selection iteration.
+struct SelJob {
+    SelArgs A;
+    bool huff;
+    uint32_t g_arg, g_find, g_apply, g_hot;
+    double b_arg, b_find, b_apply;
+};
+
+SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     Store &s = c.s;
     SelState &S = c.sel;
     const int32_t n = c.g.n;
     const int64_t T = s.nsets;
     const int64_t words = (T + 63) / 64;
-    hipEvent_t e0, e1;
-    HBM_HIP(hipEventCreate(&e0));
-    HBM_HIP(hipEventCreate(&e1));
-    HBM_HIP(hipEventRecord(e0, c.stream));
+    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256, (int64_t)root.num_cus * 2);
     buf_grow(c, S.counts, (size_t)n * 4, false);
     buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
     buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
     buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
-    buf_grow(c, S.keys, (size_t)k * 8, false);
-    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256, (int64_t)c.num_cus * 2);
     buf_grow(c, S.partial, (size_t)g_arg * 8, false);
-    if (T > 0) HBM_HIP(hipMemcpyAsync(S.counts.p, s.hist.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c.stream));
-    else buf_zero(c, S.counts, 0, (size_t)n * 4);
-    buf_zero(c, S.selmask, 0, ((size_t)n + 31) / 32 * 4);
-    buf_zero(c, S.covered, 0, (size_t)std::max<int64_t>(words, 1) * 8);
-    buf_zero(c, S.keys, 0, (size_t)k * 8);
-
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    SelArgs A{};
+    SelJob J{};
+    SelArgs &A = J.A;
     A.T = T;
     A.words = words;
     A.n = n;
@@ -425,7 +444,7 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     A.selmask = S.selmask.as<uint32_t>();
     A.covered = S.covered.as<unsigned long long>();
     A.newly = S.newly.as<unsigned long long>();
-    A.keys = S.keys.as<unsigned long long>();
+    A.keys = keys;
     A.nhot = s.nhot;
     A.hot = s.hot.as<int32_t>();
     A.hot_rank = s.nhot ? s.hot_rank.as<int32_t>() : nullptr;
@@ -447,65 +466,202 @@ void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *
     A.nraw = huff ? 0 : s.raw_count;
     A.partial = S.partial.as<unsigned long long>();
     A.nparts = (int32_t)g_arg;
-
-    const unsigned g_mark = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
-    const unsigned g_fhuff = grid_for(std::max<int64_t>(words, 1), 4, (int64_t)c.num_cus * 8);
-    const unsigned g_find = grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)c.num_cus * 4);
-    const unsigned hx = (unsigned)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
-    int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / hx));
-    const int64_t seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
-    nseg = std::max<int64_t>(1, (words + seg - 1) / seg);
+    A.hist = T > 0 ? s.hist.as<uint32_t>() : nullptr;
+    A.k = k;
+    A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
+    int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
+    A.seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
+    nseg = std::max<int64_t>(1, (words + A.seg - 1) / A.seg);
+    J.huff = huff;
+    J.g_arg = g_arg;
+    if (T == 0) J.g_find = 0;
+    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 8);
+    else J.g_find = A.nraw > 0 ? grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4) : 0;
+    J.g_apply = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
+    J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * nseg) : 0;
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
     // reads and writes the covered and newly words (and the hot row when u* is hot).
-    const double b_arg = 4.0 * n + 4.0 * ((n + 31) / 32) + 8.0 * words;
-    const double b_find = huff ? (double)((s.nbits + 7) / 8) + 16.0 * T : 4.0 * A.nraw;
-    const double b_apply = 24.0 * words;
-    for (int t = 0; t < k; t++) {
-        int ps = prof_begin(c, "argmax");
-        k_argmax<<<g_arg, 256, 0, c.stream>>>(A, t);
-        prof_end(c, ps, b_arg);
-        if (T > 0) {
-            if (huff) {
-                ps = prof_begin(c, "find_huff");
-                k_find_huff<<<g_fhuff, 256, 0, c.stream>>>(A, t);
-                prof_end(c, ps, b_find);
-            } else if (A.nraw > 0) {
-                ps = prof_begin(c, "find_raw");
-                k_find_raw<<<g_find, 256, 0, c.stream>>>(A, t);
-                prof_end(c, ps, b_find);
-            }
-            ps = prof_begin(c, "apply");
-            k_apply<<<g_mark, 256, 0, c.stream>>>(A, t);
-            prof_end(c, ps, b_apply);
-            if (s.nhot > 0) {
-                ps = prof_begin(c, "dec_hot");
-                k_dec_hot<<<dim3(hx, (unsigned)nseg), 256, 0, c.stream>>>(A, seg);
-                prof_end(c, ps);
-            }
-        } else {
-            k_apply<<<1, 64, 0, c.stream>>>(A, t);  // only records the selection
+    J.b_arg = 4.0 * n + 4.0 * ((n + 31) / 32) + 8.0 * words;
+    J.b_find = huff ? (double)((s.nbits + 7) / 8) + 16.0 * T : 4.0 * A.nraw;
+    J.b_apply = 24.0 * words;
+    return J;
+}
+
+// A grouped launch over a prefix of a job list that is sorted by k (descending): at
+// iteration t the jobs with k > t are a prefix, so one descriptor upload serves all
+// iterations.
+struct Plan {
+    std::vector<size_t> jobs;  // indices into the job table, k descending
+    std::vector<uint32_t> boff;
+    const SelArgs *dargs = nullptr;
+    const uint32_t *dboff = nullptr;
+};
+
+}  // namespace
+
+void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
+                  std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
+                  std::vector<uint64_t> &coverage) {
+    const size_t N = C.size();
+    seeds.assign(N, {});
+    gains.assign(N, {});
+    coverage.assign(N, 0);
+    if (!N) return;
+    int32_t kmax = 0;
+    std::vector<int64_t> koff(N + 1, 0);
+    for (size_t i = 0; i < N; i++) {
+        HBM_REQUIRE(C[i]->g.loaded, HBM_ESTATE, "no graph loaded");
+        HBM_REQUIRE(k[i] >= 1 && k[i] <= C[i]->g.n, HBM_EINVAL, "k must be in [1, n]");
+        kmax = std::max(kmax, k[i]);
+        koff[i + 1] = koff[i] + k[i];
+    }
+    stage_reset(root);
+    hipEvent_t e0, e1;
+    HBM_HIP(hipEventCreate(&e0));
+    HBM_HIP(hipEventCreate(&e1));
+    HBM_HIP(hipEventRecord(e0, root.stream));
+    buf_grow(root, root.bkeys, (size_t)koff[N] * 8, false);
+    std::vector<SelJob> J(N);
+    for (size_t i = 0; i < N; i++) J[i] = plan_job(root, *C[i], k[i], root.bkeys.as<unsigned long long>() + koff[i]);
+
+    // job order: k descending (stable on the index)
+    std::vector<size_t> order(N);
+    for (size_t i = 0; i < N; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return k[a] > k[b]; });
+    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, NPLAN };
+    Plan plans[NPLAN];
+    for (size_t i : order) {
+        plans[P_ALL_ARG].jobs.push_back(i);
+        plans[P_ALL_APPLY].jobs.push_back(i);
+        plans[P_INIT].jobs.push_back(i);
+        if (J[i].g_find && J[i].huff) plans[P_HUFF].jobs.push_back(i);
+        if (J[i].g_find && !J[i].huff) plans[P_RAW].jobs.push_back(i);
+        if (J[i].g_hot) plans[P_HOT].jobs.push_back(i);
+    }
+    auto blocks = [&](int p, size_t i) -> uint32_t {
+        switch (p) {
+            case P_ALL_ARG: return J[i].g_arg;
+            case P_ALL_APPLY: return J[i].g_apply;
+            case P_HUFF:
+            case P_RAW: return J[i].g_find;
+            case P_HOT: return J[i].g_hot;
+            default: return grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
+        }
+    };
+    // one upload of every plan's descriptors and block offsets
+    std::vector<char> host;
+    std::vector<size_t> aoff(NPLAN), boff_off(NPLAN);
+    auto align = [&]() { host.resize((host.size() + 255) & ~size_t(255)); };
+    for (int p = 0; p < NPLAN; p++) {
+        Plan &P = plans[p];
+        P.boff.assign(P.jobs.size() + 1, 0);
+        for (size_t q = 0; q < P.jobs.size(); q++) P.boff[q + 1] = P.boff[q] + blocks(p, P.jobs[q]);
+        if (N == 1) continue;
+        align();
+        aoff[p] = host.size();
+        for (size_t i : P.jobs) {
+            const char *a = reinterpret_cast<const char *>(&J[i].A);
+            host.insert(host.end(), a, a + sizeof(SelArgs));
+        }
+        align();
+        boff_off[p] = host.size();
+        const char *b = reinterpret_cast<const char *>(P.boff.data());
+        host.insert(host.end(), b, b + P.boff.size() * 4);
+    }
+    if (N > 1) {
+        char *d = (char *)stage_upload(root, host.data(), host.size());
+        for (int p = 0; p < NPLAN; p++) {
+            plans[p].dargs = reinterpret_cast<const SelArgs *>(d + aoff[p]);
+            plans[p].dboff = reinterpret_cast<const uint32_t *>(d + boff_off[p]);
         }
     }
+    const hipStream_t st = root.stream;
+    // number of jobs of plan p still running at iteration t
+    auto active = [&](int p, int t) -> uint32_t {
+        const Plan &P = plans[p];
+        uint32_t lo = 0, hi = (uint32_t)P.jobs.size();
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (k[P.jobs[mid]] > t) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+#define HBM_SEL_LAUNCH(PLAN, KERNEL, T_)                                                                  \
+    do {                                                                                                \
+        const Plan &P_ = plans[PLAN];                                                                   \
+        const uint32_t cnt_ = active(PLAN, T_);                                                         \
+        if (cnt_ && P_.boff[cnt_]) {                                                                    \
+            if (N == 1) KERNEL<<<P_.boff[1], 256, 0, st>>>(J[P_.jobs[0]].A, T_);                         \
+            else KERNEL##_g<<<P_.boff[cnt_], 256, 0, st>>>(GroupArgs<SelArgs>{P_.dargs, P_.dboff, cnt_, T_}); \
+        }                                                                                               \
+    } while (0)
+    auto bytes_of = [&](int p, int t, double SelJob::*f) {
+        double b = 0;
+        const uint32_t cnt = active(p, t);
+        for (uint32_t q = 0; q < cnt; q++) b += J[plans[p].jobs[q]].*f;
+        return b;
+    };
+    HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
     HBM_HIP(hipGetLastError());
-    std::vector<unsigned long long> keys((size_t)k);
-    HBM_HIP(hipMemcpyAsync(keys.data(), S.keys.p, (size_t)k * 8, hipMemcpyDeviceToHost, c.stream));
-    HBM_HIP(hipEventRecord(e1, c.stream));
+    for (int t = 0; t < kmax; t++) {
+        int ps = prof_begin(root, "argmax");
+        HBM_SEL_LAUNCH(P_ALL_ARG, k_argmax, t);
+        prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_ARG, t, &SelJob::b_arg) : 0);
+        if (active(P_HUFF, t)) {
+            ps = prof_begin(root, "find_huff");
+            HBM_SEL_LAUNCH(P_HUFF, k_find_huff, t);
+            prof_end(root, ps, ps >= 0 ? bytes_of(P_HUFF, t, &SelJob::b_find) : 0);
+        }
+        if (active(P_RAW, t)) {
+            ps = prof_begin(root, "find_raw");
+            HBM_SEL_LAUNCH(P_RAW, k_find_raw, t);
+            prof_end(root, ps, ps >= 0 ? bytes_of(P_RAW, t, &SelJob::b_find) : 0);
+        }
+        ps = prof_begin(root, "apply");
+        HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
+        prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
+        if (active(P_HOT, t)) {
+            ps = prof_begin(root, "dec_hot");
+            HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
+            prof_end(root, ps);
+        }
+    }
+#undef HBM_SEL_LAUNCH
+    HBM_HIP(hipGetLastError());
+    std::vector<unsigned long long> keys((size_t)koff[N]);
+    HBM_HIP(hipMemcpyAsync(keys.data(), root.bkeys.p, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipEventRecord(e1, st));
     HBM_HIP(hipEventSynchronize(e1));
     float ms = 0;
     HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    c.t_select += ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    uint64_t cov = 0;
-    for (int t = 0; t < k; t++) {
-        const unsigned long long key = keys[(size_t)t];
-        HBM_REQUIRE(key != 0, HBM_EDEVICE, "internal: empty argmax");
-        seeds[t] = (int32_t)(~(uint32_t)key);
-        gains[t] = (uint64_t)(key >> 32) - 1;
-        cov += gains[t];
+    for (size_t i = 0; i < N; i++) {
+        C[i]->t_select += ms;
+        seeds[i].resize((size_t)k[i]);
+        gains[i].resize((size_t)k[i]);
+        uint64_t cov = 0;
+        for (int t = 0; t < k[i]; t++) {
+            const unsigned long long key = keys[(size_t)(koff[i] + t)];
+            HBM_REQUIRE(key != 0, HBM_EDEVICE, "internal: empty argmax");
+            seeds[i][(size_t)t] = (int32_t)(~(uint32_t)key);
+            gains[i][(size_t)t] = (uint64_t)(key >> 32) - 1;
+            cov += gains[i][(size_t)t];
+        }
+        coverage[i] = cov;
     }
-    *coverage = cov;
+}
+
+void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
+    std::vector<std::vector<int32_t>> s;
+    std::vector<std::vector<uint64_t>> g;
+    std::vector<uint64_t> cov;
+    select_batch(c, std::vector<Ctx *>{&c}, std::vector<int32_t>{k}, s, g, cov);
+    std::copy(s[0].begin(), s[0].end(), seeds);
+    std::copy(g[0].begin(), g[0].end(), gains);
+    *coverage = cov[0];
 }
 
 }  // namespace hbm

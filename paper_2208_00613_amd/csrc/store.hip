@@ -347,6 +347,7 @@ void store_reset(Ctx &c) {
     s.has_seed = false;
     s.nsets = 0;
     s.W = 0;
+    s.wcur = 0;
     s.model_ready = false;
     s.members = 0;
     s.nhot = 0;
@@ -778,124 +779,110 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
     for (size_t i = 0; i < N; i++) J[i]->s.nsets = j0[i] + done[i];
 }
 
-// Make every job's store hold sets 0..theta[i]-1 under seed[i] (see store_extend), all jobs
-// advancing together block by block.
-void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
-                   const std::vector<uint64_t> &seed) {
-    const size_t N = J.size();
-    std::vector<int64_t> before(N);
-    for (size_t i = 0; i < N; i++) {
-        Ctx &c = *J[i];
-        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
-        HBM_REQUIRE(theta[i] >= 0 && theta[i] < (int64_t(1) << 31), HBM_EINVAL, "theta must be in [0, 2^31)");
-        Store &s = c.s;
-        if ((s.has_seed && s.seed != seed[i]) || theta[i] < s.nsets) store_reset(c);
-        s.has_seed = true;
-        s.seed = seed[i];
-        before[i] = s.nsets;
-        if (theta[i] == s.nsets) continue;
-        if (!s.hist.p) {
-            buf_alloc(c, s.hist, (size_t)c.g.n * 4);
-            buf_zero(c, s.hist, 0, (size_t)c.g.n * 4);
-        }
-        if (s.W == 0) {
-            const int64_t w = (int64_t)std::ceil(s.warmup_frac * (double)theta[i]);
-            s.W = std::max<int64_t>(1, std::min<int64_t>(w, theta[i]));
-        }
-        // arena sized to the request (about 64 ids per set), within [4M, 64M] entries
-        const int64_t want_sets = std::min<int64_t>(theta[i] - s.nsets, root.block_sets);
-        const size_t entries = (size_t)std::min<int64_t>(std::max<int64_t>(want_sets * 64, int64_t(1) << 22),
-                                                         int64_t(64) << 20);
-        ensure_scratch(c, std::max<size_t>(c.sc.cap, entries), std::max<int64_t>(c.sc.bcap, want_sets));
+// Bring a job's store in line with a request for sets [0, theta) under `seed`: a new seed
+// or a smaller theta starts over; the warm-up size is fixed by the first request.
+static void extend_prepare(Ctx &root, Ctx &c, int64_t theta, uint64_t seed) {
+    HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+    HBM_REQUIRE(theta >= 0 && theta < (int64_t(1) << 31), HBM_EINVAL, "theta must be in [0, 2^31)");
+    Store &s = c.s;
+    if ((s.has_seed && s.seed != seed) || theta < s.nsets) store_reset(c);
+    s.has_seed = true;
+    s.seed = seed;
+    if (theta == s.nsets) return;
+    if (!s.hist.p) {
+        buf_alloc(c, s.hist, (size_t)c.g.n * 4);
+        buf_zero(c, s.hist, 0, (size_t)c.g.n * 4);
     }
+    if (s.W == 0) {
+        const int64_t w = (int64_t)std::ceil(s.warmup_frac * (double)theta);
+        s.W = std::max<int64_t>(1, std::min<int64_t>(w, theta));
+    }
+    if (s.enc != HBM_ENC_NONE && !s.model_ready && s.wcur == 0) {
+        buf_grow(c, s.warm, (size_t)c.g.n * 4, false);
+        buf_zero(c, s.warm, 0, (size_t)c.g.n * 4);
+        s.warm_sizes.clear();
+    }
+    // arena sized to the request (about 64 ids per set), within [4M, 64M] entries
+    const int64_t want_sets = std::min<int64_t>(theta - s.nsets, root.block_sets);
+    const size_t entries =
+        (size_t)std::min<int64_t>(std::max<int64_t>(want_sets * 64, int64_t(1) << 22), int64_t(64) << 20);
+    ensure_scratch(c, std::max<size_t>(c.sc.cap, entries), std::max<int64_t>(c.sc.bcap, want_sets));
+}
+
+void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
+                 const std::vector<uint64_t> &seed, const std::vector<int64_t> &cap, std::vector<hbm_status> &st) {
+    const size_t N = J.size();
+    st.assign(N, HBM_OK);
+    stage_reset(root);
     hipEvent_t e0, e1;
     HBM_HIP(hipEventCreate(&e0));
     HBM_HIP(hipEventCreate(&e1));
     HBM_HIP(hipEventRecord(e0, root.stream));
     try {
-        // warm-up pass of every encoded job without a model: frequencies of sets [0, W)
-        std::vector<int64_t> wcur(N, 0);
-        std::vector<size_t> warmers;
+        std::vector<Ctx *> jobs;
+        std::vector<size_t> idx;
+        std::vector<int64_t> j0, nb, done;
+        std::vector<uint64_t> sd;
+        std::vector<char> warm;
         for (size_t i = 0; i < N; i++) {
-            Store &s = J[i]->s;
-            if (theta[i] > s.nsets && s.enc != HBM_ENC_NONE && !s.model_ready) {
-                warmers.push_back(i);
-                buf_grow(*J[i], s.warm, (size_t)J[i]->g.n * 4, false);
-                buf_zero(*J[i], s.warm, 0, (size_t)J[i]->g.n * 4);
-                s.warm_sizes.clear();
-            }
+            Ctx &c = *J[i];
+            extend_prepare(root, c, theta[i], seed[i]);
+            Store &s = c.s;
+            if (s.nsets >= theta[i]) continue;
+            const bool w = s.enc != HBM_ENC_NONE && !s.model_ready;
+            const int64_t from = w ? s.wcur : s.nsets, to = w ? s.W : theta[i];
+            int64_t b = std::min<int64_t>({to - from, root.block_sets, c.sc.bcap});
+            if (!cap.empty() && cap[i] >= 0) b = std::min<int64_t>(b, cap[i]);
+            if (b <= 0) continue;
+            idx.push_back(i);
+            jobs.push_back(&c);
+            j0.push_back(from);
+            nb.push_back(b);
+            sd.push_back(seed[i]);
+            warm.push_back(w);
         }
-        for (;;) {
-            std::vector<Ctx *> jobs;
-            std::vector<size_t> idx;
-            std::vector<int64_t> j0, nb, done;
-            std::vector<uint64_t> sd;
-            for (size_t i : warmers)
-                if (wcur[i] < J[i]->s.W) {
-                    idx.push_back(i);
-                    jobs.push_back(J[i]);
-                    j0.push_back(wcur[i]);
-                    nb.push_back(std::min<int64_t>({J[i]->s.W - wcur[i], root.block_sets, J[i]->sc.bcap}));
-                    sd.push_back(seed[i]);
-                }
-            if (jobs.empty()) break;
-            sample_blocks(root, jobs, j0, nb, sd, done);
-            std::vector<HistArgs> ha;
-            std::vector<uint32_t> hb;
-            for (size_t q = 0; q < jobs.size(); q++) {
-                if (done[q] == 0) {
-                    ensure_scratch(*jobs[q], jobs[q]->sc.cap * 2, jobs[q]->sc.bcap);
-                    continue;
-                }
-                ha.push_back(HistArgs{block_view(*jobs[q], done[q]), jobs[q]->s.warm.as<uint32_t>()});
+        if (!jobs.empty()) sample_blocks(root, jobs, j0, nb, sd, done);
+        // warm-up blocks: frequencies of sets [0, W) only
+        std::vector<HistArgs> ha;
+        std::vector<uint32_t> hb;
+        std::vector<Ctx *> ajobs;
+        std::vector<int64_t> aj0, adone;
+        for (size_t q = 0; q < jobs.size(); q++) {
+            Ctx &c = *jobs[q];
+            if (done[q] == 0) {  // the first set did not fit the arena: retry with twice the room
+                ensure_scratch(c, c.sc.cap * 2, c.sc.bcap);
+                continue;
+            }
+            if (warm[q]) {
+                ha.push_back(HistArgs{block_view(c, done[q]), c.s.warm.as<uint32_t>()});
                 hb.push_back(grid_for(done[q] * WAVE, 256, 65536));
-            }
-            HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
-            HBM_HIP(hipGetLastError());
-            for (size_t q = 0; q < jobs.size(); q++) {
-                if (!done[q]) continue;
-                record_warm_sizes(*jobs[q], j0[q], done[q]);
-                wcur[idx[q]] += done[q];
-            }
-        }
-        for (size_t i : warmers) {
-            characterize(J[i]->s, J[i]->g.n);
-            build_model(*J[i]);
-        }
-        // sampling and encoding proper
-        for (;;) {
-            std::vector<Ctx *> jobs;
-            std::vector<int64_t> j0, nb, done;
-            std::vector<uint64_t> sd;
-            for (size_t i = 0; i < N; i++)
-                if (J[i]->s.nsets < theta[i]) {
-                    jobs.push_back(J[i]);
-                    j0.push_back(J[i]->s.nsets);
-                    nb.push_back(std::min<int64_t>({theta[i] - J[i]->s.nsets, root.block_sets, J[i]->sc.bcap}));
-                    sd.push_back(seed[i]);
-                }
-            if (jobs.empty()) break;
-            sample_blocks(root, jobs, j0, nb, sd, done);
-            std::vector<Ctx *> ajobs;
-            std::vector<int64_t> aj0, adone;
-            for (size_t q = 0; q < jobs.size(); q++) {
-                if (done[q] == 0) {
-                    ensure_scratch(*jobs[q], jobs[q]->sc.cap * 2, jobs[q]->sc.bcap);
-                    continue;
-                }
-                if (jobs[q]->s.enc == HBM_ENC_NONE) record_warm_sizes(*jobs[q], j0[q], done[q]);
-                ajobs.push_back(jobs[q]);
+            } else {
+                if (c.s.enc == HBM_ENC_NONE) record_warm_sizes(c, j0[q], done[q]);
+                ajobs.push_back(&c);
                 aj0.push_back(j0[q]);
                 adone.push_back(done[q]);
             }
-            if (!ajobs.empty()) append_blocks(root, ajobs, aj0, adone);
-            for (Ctx *c : ajobs)
-                if (c->budget > 0 && store_bytes(*c) > c->budget)
-                    throw Error{HBM_EBUDGET, "store budget exceeded at " + std::to_string(c->s.nsets) + " sets"};
         }
-        for (size_t i = 0; i < N; i++) {
-            Store &s = J[i]->s;
-            if (s.enc == HBM_ENC_NONE && before[i] < s.W && s.nsets >= s.W) characterize(s, J[i]->g.n);
+        HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
+        HBM_HIP(hipGetLastError());
+        for (size_t q = 0; q < jobs.size(); q++) {
+            Ctx &c = *jobs[q];
+            if (!warm[q] || !done[q]) continue;
+            record_warm_sizes(c, j0[q], done[q]);
+            c.s.wcur += done[q];
+            if (c.s.wcur >= c.s.W) {
+                characterize(c.s, c.g.n);
+                build_model(c);
+            }
+        }
+        if (!ajobs.empty()) append_blocks(root, ajobs, aj0, adone);
+        for (size_t q = 0; q < ajobs.size(); q++) {
+            Ctx &c = *ajobs[q];
+            if (c.s.enc == HBM_ENC_NONE && aj0[q] < c.s.W && c.s.nsets >= c.s.W) characterize(c.s, c.g.n);
+        }
+        for (size_t q = 0; q < jobs.size(); q++) {
+            Ctx &c = *jobs[q];
+            if (c.budget > 0 && store_bytes(c) > c.budget) st[idx[q]] = HBM_EBUDGET;
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -906,9 +893,28 @@ void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     HBM_HIP(hipEventSynchronize(e1));
     float ms = 0;
     HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    root.t_sample += ms;
+    for (Ctx *c : J) c->t_sample += ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+}
+
+// Make every job's store hold sets 0..theta[i]-1 under seed[i], all jobs advancing together
+// block by block.  A job over its budget stops the call with EBUDGET.
+void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
+                   const std::vector<uint64_t> &seed) {
+    std::vector<hbm_status> st;
+    for (;;) {
+        bool more = false;
+        for (size_t i = 0; i < J.size(); i++) more |= J[i]->s.nsets < theta[i] || (J[i]->s.has_seed && J[i]->s.seed != seed[i]);
+        if (!more) {
+            for (size_t i = 0; i < J.size(); i++) extend_prepare(root, *J[i], theta[i], seed[i]);
+            return;
+        }
+        extend_step(root, J, theta, seed, {}, st);
+        for (size_t i = 0; i < J.size(); i++)
+            if (st[i] == HBM_EBUDGET)
+                throw Error{HBM_EBUDGET, "store budget exceeded at " + std::to_string(J[i]->s.nsets) + " sets"};
+    }
 }
 
 void store_extend(Ctx &c, int64_t theta, uint64_t seed) {
