@@ -3,7 +3,7 @@
 
 A step is one complete IMM run (hbm_imm): estimation rounds with RR-set
 sampling, hot-bitmap encoding and k-seed greedy selection each, then the final
-sampling and selection.  Default workload: R-MAT scale 20 (a=.57, b=.19,
+sampling and selection.  Default workload (c2): R-MAT scale 20 (a=.57, b=.19,
 c=.19, 16 * 2^20 samples, self-loops and duplicates removed), IC with weighted
 cascade probabilities, eps=0.5, l=1, k=50, hot bitmap for the top 1% of
 vertices by frequency in the first 10% of sets, Philox seed 42.  The graph is
@@ -11,7 +11,14 @@ loaded into HBM before timing; the timed region holds only hbm_imm calls.
 
 value = RR sets per second of the whole IMM run (final store size / step
 time).  Extra fields report IMM seconds, compressed bytes per RR set, the
-roofline of the dominant kernel and the CPU oracle baseline.
+roofline of the dominant kernel, the CPU oracle baseline, and (unless
+--no-batched) the batched workload's whole time batched vs plain on the same
+GPU: 256 R-MAT instances of scale U{12..18}, IC-WC + hot bitmap and LT +
+Huffman alternating, k ~ U{5..100}, eps in {.5, .3}.
+
+--workload c3: R-MAT scale 23 under LT, eps=.13, k=100, Huffman (5% warm-up).
+--workload c4: the batched workload as the main line (value = RR sets/s of
+hbm_imm_batch over all 256 instances).
 """
 
 from __future__ import annotations
@@ -32,6 +39,7 @@ METRIC = "RR sets/s and IMM end-to-end s (batched vs plain, same GPU); compresse
 WORKLOADS = {
     "c2": dict(name="imm_ic_wc_rmat20_eps0.5_k50_hotbitmap", cfg="c2"),
     "c3": dict(name="imm_lt_rmat23_eps0.13_k100_huffman", cfg="c3"),
+    "c4": dict(name="imm_batch256_rmat12-18_icwc-hotbitmap_lt-huffman", cfg="c4"),
 }
 
 
@@ -122,6 +130,116 @@ def cpu_baseline(g, c, budget_s=12.0):
             "seconds": t_sample + t_select}
 
 
+def _instance_graph(inst):
+    from synth import graphs as G
+
+    return G.instance_graph(inst)
+
+
+def batched_graphs(count=256, workers=8):
+    """The batched workload's instances and graphs, generated in a process pool.  Call it
+    before anything touches the GPU: the pool forks."""
+    import concurrent.futures as cf
+
+    from synth import graphs as G
+
+    insts = G.batched_instances(count=count)
+    t0 = time.time()
+    with cf.ProcessPoolExecutor(workers) as ex:
+        graphs = list(ex.map(_instance_graph, insts, chunksize=4))
+    log(f"[bench] {count} instance graphs generated ({time.time() - t0:.1f}s), "
+        f"{sum(g.m for g in graphs) / 1e6:.1f}M edges in all")
+    return insts, graphs
+
+
+def batched_setup(P, insts, graphs):
+    """Load every instance graph into its own context (resident in HBM) with its encoding."""
+    ctxs = []
+    for inst, g in zip(insts, graphs):
+        c = P.Context(0)
+        c.load_synth(g, inst["model"], inst["prob"])
+        c.hbm_set_encoding(inst["enc"], inst["warmup"], inst["hot"] or 0.01)
+        ctxs.append(c)
+    return ctxs
+
+
+def batched_vs_plain(P, torch, ctxs, insts, reps=1):
+    """Whole-workload seconds of hbm_imm_batch vs one hbm_imm per instance, same GPU, same
+    queries; the results must agree instance by instance."""
+    qs = [(i["k"], i["eps"], i["l"], i["seed"]) for i in insts]
+    P.imm_batch(ctxs, qs)  # warm-up: allocations of both paths
+    for c, q in zip(ctxs, qs):
+        c.hbm_imm(*q)
+    tb, tp = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = P.imm_batch(ctxs, qs)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        plain = [c.hbm_imm(*q) for c, q in zip(ctxs, qs)]
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
+    same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(out, plain))
+    sets = sum(o[2]["nsets_final"] for o in out)
+    store = sum(o[2]["store"]["store_bytes"] for o in out)
+    raw = sum(4 * o[2]["store"]["members"] + 8 * (o[2]["nsets_final"] + 1) for o in out)
+    return dict(instances=len(ctxs), batched_s=min(tb), plain_s=min(tp), speedup=min(tp) / min(tb),
+                identical_results=bool(same), rr_sets=sets, bytes_per_rr=store / max(sets, 1),
+                raw_bytes_per_rr=raw / max(sets, 1)), out
+
+
+def main_c4(args, P, torch, insts, graphs):
+    wl = WORKLOADS["c4"]
+    ctxs = batched_setup(P, insts, graphs)
+    cmp_, out = batched_vs_plain(P, torch, ctxs, insts, reps=max(1, args.steps))
+    qs = [(i["k"], i["eps"], i["l"], i["seed"]) for i in insts]
+    ctxs[0].hbm_profile(True)
+    P.imm_batch(ctxs, qs)
+    kstats = ctxs[0].hbm_profile_read()
+    ctxs[0].hbm_profile(False)
+    ms = cmp_["batched_s"] * 1e3
+    res = {
+        "metric": METRIC, "value": cmp_["rr_sets"] / cmp_["batched_s"], "unit": "RR sets/s", "n_gpus": 1,
+        "steps": max(1, args.steps), "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded R-MAT instances; no public dataset)",
+        "config": {"workload": wl["name"], "instances": len(insts), "scales": "U{12..18}", "k": "U{5..100}",
+                   "eps": [0.5, 0.3]},
+        "imm_s": cmp_["batched_s"], "batched_vs_plain": cmp_,
+        "phase_ms": {"sample_encode": out[0][2]["t_sample_ms"], "select": out[0][2]["t_select_ms"]},
+        "roofline": roofline(kstats, "IC", "WC"),
+        "kernels": sorted(({"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3)}
+                           for r in kstats), key=lambda r: -r["ms"])[:8],
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_batched(insts, graphs)
+    print(json.dumps(res), flush=True)
+    for c in ctxs:
+        c.close()
+
+
+def cpu_baseline_batched(insts, graphs, budget_s=12.0):
+    """The oracle's full IMM, instance after instance in workload order, until the time budget."""
+    import oracle
+
+    oracle.build()
+    t0 = time.perf_counter()
+    sets, done = 0, 0
+    for inst, g in zip(insts, graphs):
+        og = oracle.Graph(g.n, g.row_ptr, g.dst, g.w if inst["prob"] == "EDGE" else None, model=inst["model"],
+                          prob=inst["prob"])
+        _, _, st, _ = oracle.imm(og, inst["k"], inst["eps"], inst["l"], inst["seed"])
+        sets += st["nsets_final"]
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    secs = time.perf_counter() - t0
+    return {"value": sets / secs, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle IMM of the first {done} of {len(insts)} instances ({sets} RR sets, graph "
+                      f"transposes included)", "seconds": secs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +247,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain summary of the c2 line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is described in "
@@ -140,6 +259,11 @@ def main():
     import paper_2208_00613_amd as P
     from synth import graphs as G
 
+    batched = None
+    if args.workload == "c4" or (args.workload == "c2" and not args.no_batched):
+        batched = batched_graphs()
+    if args.workload == "c4":
+        return main_c4(args, P, torch, *batched)
     wl = WORKLOADS[args.workload]
     c = G.CONFIGS[wl["cfg"]]
     t0 = time.time()
@@ -202,8 +326,15 @@ def main():
                              for r in kstats), key=lambda r: -r["ms"])[:8]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, c)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if args.workload == "c2" and not args.no_batched:
+        # the batched form on its own workload, same GPU (256 instances, batched vs plain)
+        ctxs = batched_setup(P, *batched)
+        out["batched_vs_plain"], _ = batched_vs_plain(P, torch, ctxs, batched[0], reps=1)
+        out["batched_vs_plain"]["workload"] = WORKLOADS["c4"]["name"]
+        for c4 in ctxs:
+            c4.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
