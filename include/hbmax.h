@@ -161,6 +161,14 @@ hbm_status hbm_load_graph(hbm_ctx *ctx, int32_t n, int64_t m, const int64_t *row
  * Resets the store.  HBM_EINVAL for fractions outside (0, 1] where used. */
 hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, double hot_frac);
 
+/* Density gate of the hot set: a vertex qualifies only if it is in at least
+ * max(1, ceil(min_density * W)) of the W warm-up sets.  A bitmap row costs one bit
+ * per set and a stored id 32 bits per occurrence, so with min_density = 1/32 a
+ * vertex gets a row only where the row is the smaller form (the density threshold
+ * of the RRR-set characterization section, applied per vertex).  Default 0 (the
+ * plain top-fraction rule).  Resets the store.  HBM_EINVAL outside [0, 1]. */
+hbm_status hbm_set_hot_density(hbm_ctx *ctx, double min_density);
+
 /* Make the store hold RR sets j = 0 .. theta-1 under `seed`.  Appends when the
  * seed matches and theta grows; a different seed, or a smaller theta, resets
  * the store first.  HBM_ESTATE without a graph; HBM_EINVAL if theta < 0 or

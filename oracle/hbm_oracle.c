@@ -602,7 +602,13 @@ static int floor_log2_u64(uint64_t x) {
     return l;
 }
 
-int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_frac, orc_encoded **out) {
+/* hot set: the ceil(hot_frac * n) vertices with the most warm-up occurrences (ties to the
+ * lower id), counting only vertices in at least ceil(hot_min_density * W) warm-up sets
+ * (and in at least one).  A bitmap row costs one bit per set, a stored id 32 bits per
+ * occurrence, so a row pays for itself above density 1/32 (the density threshold of the
+ * RRR-set characterization section), here applied vertex by vertex. */
+int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_frac, double hot_min_density,
+               orc_encoded **out) {
     orc_encoded *e = (orc_encoded *)calloc(1, sizeof(orc_encoded));
     int64_t T = s->nsets;
     e->enc = enc; e->n = n; e->nsets = T; e->W = W;
@@ -614,11 +620,13 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
     for (int32_t v = 0; v < n; v++) rank[v] = -1;
     if (use_hot) {
         int64_t want = (int64_t)ceil(hot_frac * (double)n);
-        /* order vertices with a warm-up count by (count desc, id asc) */
+        uint64_t min_cnt = (uint64_t)ceil(hot_min_density * (double)W);
+        if (min_cnt < 1) min_cnt = 1;
+        /* order eligible vertices by (count desc, id asc) */
         leaf_t *c = (leaf_t *)malloc(sizeof(leaf_t) * (size_t)n);
         int64_t q = 0;
         for (int32_t v = 0; v < n; v++)
-            if (e->warm[v] > 0) { c[q].w = UINT64_MAX - e->warm[v]; c[q].id = v; q++; }
+            if (e->warm[v] >= min_cnt) { c[q].w = UINT64_MAX - e->warm[v]; c[q].id = v; q++; }
         qsort(c, (size_t)q, sizeof(leaf_t), cmp_leaf);
         e->nhot = (int32_t)(q < want ? q : want);
         e->hot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(e->nhot ? e->nhot : 1));

@@ -27,7 +27,7 @@ ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uin
           "PAYLOAD": (12, np.uint32)}
 EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
-            "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
+            "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_set_hot_density", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
             "hbm_server_poll", "hbm_server_get_stats"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3}
@@ -108,6 +108,7 @@ def lib():
         "hbm_set_budget": ([P, I64], C.c_int),
         "hbm_load_graph": ([P, I32, I64, P, P, P, C.c_int, C.c_int], C.c_int),
         "hbm_set_encoding": ([P, C.c_int, D, D], C.c_int),
+        "hbm_set_hot_density": ([P, D], C.c_int),
         "hbm_sample_rr": ([P, I64, U64], C.c_int),
         "hbm_select_seeds": ([P, I32, P, P, P], C.c_int),
         "hbm_imm": ([P, I32, D, D, U64, P, P, C.POINTER(ImmStats)], C.c_int),
@@ -230,6 +231,9 @@ class Context:
     def hbm_set_encoding(self, enc="NONE", warmup_frac=0.1, hot_frac=0.01):
         self._check(lib().hbm_set_encoding(self.h, ENC[enc] if isinstance(enc, str) else int(enc),
                                            float(warmup_frac), float(hot_frac)))
+
+    def hbm_set_hot_density(self, min_density: float):
+        self._check(lib().hbm_set_hot_density(self.h, float(min_density)))
 
     def hbm_sample_rr(self, theta: int, seed: int):
         self._check(lib().hbm_sample_rr(self.h, int(theta), int(seed)))

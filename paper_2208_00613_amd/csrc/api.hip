@@ -108,6 +108,14 @@ hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, doubl
     });
 }
 
+hbm_status hbm_set_hot_density(hbm_ctx *ctx, double min_density) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(min_density >= 0.0 && min_density <= 1.0, HBM_EINVAL, "min_density must be in [0, 1]");
+        hbm::store_reset(c);
+        c.s.hot_min_density = min_density;
+    });
+}
+
 hbm_status hbm_sample_rr(hbm_ctx *ctx, int64_t theta, uint64_t seed) {
     return guard(ctx, [&](Ctx &c) { hbm::store_extend(c, theta, seed); });
 }

@@ -74,6 +74,7 @@ struct Codebook {
 struct Store {
     int enc = HBM_ENC_NONE;
     double warmup_frac = 0.1, hot_frac = 0.01;
+    double hot_min_density = 0.0;  // a hot vertex is in at least this fraction of warm-up sets
     bool has_seed = false;
     uint64_t seed = 0;
     int64_t nsets = 0;

@@ -77,7 +77,7 @@ struct hbm_server {
     int64_t budget = 0;
     int32_t max_active = 1;
     int enc = HBM_ENC_NONE;
-    double warmup_frac = 0.1, hot_frac = 0.01;
+    double warmup_frac = 0.1, hot_frac = 0.01, hot_min_density = 0.0;
     hbm::DGraph graph;  // borrowed from the graph context
     std::chrono::steady_clock::time_point t0;
 
@@ -222,6 +222,7 @@ void hbm_server::admit_locked() {
         c.s.enc = enc;
         c.s.warmup_frac = warmup_frac;
         c.s.hot_frac = hot_frac;
+        c.s.hot_min_density = hot_min_density;
         s->t = t;
         s->t_admit = now_ms();
         s->order = next_order++;
@@ -365,6 +366,7 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     s->enc = g.s.enc;
     s->warmup_frac = g.s.warmup_frac;
     s->hot_frac = g.s.hot_frac;
+    s->hot_min_density = g.s.hot_min_density;
     s->graph = g.g;
     s->graph.borrowed = true;
     s->t0 = std::chrono::steady_clock::now();

@@ -465,9 +465,12 @@ static void build_model(Ctx &c) {
     std::vector<int32_t> rank;
     s.nhot = 0;
     if (hot) {
+        // eligible: in at least max(1, ceil(min_density * W)) warm-up sets (a bitmap row costs a
+        // bit per set, a stored id 32 bits per occurrence: rows pay above density 1/32)
+        const uint64_t min_cnt = std::max<uint64_t>(1, (uint64_t)std::ceil(s.hot_min_density * (double)s.W));
         std::vector<int32_t> seen;
         for (int32_t v = 0; v < n; v++)
-            if (warm[v]) seen.push_back(v);
+            if ((uint64_t)warm[v] >= min_cnt) seen.push_back(v);
         const int64_t want = (int64_t)std::ceil(s.hot_frac * (double)n);
         const size_t keep = (size_t)std::min<int64_t>(want, (int64_t)seen.size());
         std::partial_sort(seen.begin(), seen.begin() + keep, seen.end(), [&](int32_t a, int32_t b) {

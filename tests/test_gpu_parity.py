@@ -234,10 +234,11 @@ def test_append_equals_direct(orc, ctx):
 
 
 # ---------------------------------------------------------------- encodings
-@pytest.mark.parametrize("enc", ["HUFFMAN", "HOT_BITMAP", "HUFFMAN_HOT_BITMAP"])
+@pytest.mark.parametrize("enc,dens", [("HUFFMAN", 0.0), ("HOT_BITMAP", 0.0), ("HUFFMAN_HOT_BITMAP", 0.0),
+                                      ("HUFFMAN_HOT_BITMAP", 1.0 / 32)])
 @pytest.mark.parametrize("model", ["IC", "LT"])
-def test_encoding_bit_exact(orc, ctx, enc, model):
-    _say("encoding", enc, model)
+def test_encoding_bit_exact(orc, ctx, enc, dens, model):
+    _say("encoding", enc, "density gate", dens, model)
     g = G.rmat(13, seed=21)
     prob = "WC" if model == "IC" else "EDGE"
     if model == "LT":
@@ -245,11 +246,12 @@ def test_encoding_bit_exact(orc, ctx, enc, model):
     theta, wf, hf = 12_000, 0.1, 0.01
     ctx.load_synth(g, model, prob)
     ctx.hbm_set_encoding(enc, wf, hf)
+    ctx.hbm_set_hot_density(dens)
     ctx.hbm_sample_rr(theta, 42)
     og = _ograph(orc, g, model, prob)
     st = orc.sample_store(og, 42, theta)
     W = orc.warmup_count(wf, theta)
-    e = orc.Encoded(st, g.n, enc, W, hot_frac=hf)
+    e = orc.Encoded(st, g.n, enc, W, hot_frac=hf, hot_min_density=dens)
     assert np.array_equal(ctx.hbm_export("WARM").astype(np.uint64), e.warm)
     if e.nhot:
         assert np.array_equal(ctx.hbm_export("HOT"), e.hot)

@@ -528,6 +528,29 @@ def test_encode_roundtrip(orc, enc, model):
             assert pc == full[v]
 
 
+@pytest.mark.parametrize("dens", [0.0, 1.0 / 32, 0.25, 1.0])
+def test_hot_density_gate(orc, dens):
+    """The gated hot set holds exactly the top vertices among those in at least
+    ceil(dens * W) warm-up sets, its rows are cheaper than 32-bit ids once dens >= 1/32,
+    and decoding still gives back every set."""
+    g = G.rmat(10, seed=5)
+    og = orc.Graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
+    theta = 2000
+    st = orc.sample_store(og, 42, theta)
+    W = orc.warmup_count(0.2, theta)
+    e = orc.Encoded(st, g.n, "HUFFMAN_HOT_BITMAP", W, hot_frac=0.05, hot_min_density=dens)
+    warm = st.counts(g.n, 0, W)
+    thr = max(1, math.ceil(dens * W))
+    eligible = sorted([v for v in range(g.n) if warm[v] >= thr], key=lambda v: (-int(warm[v]), v))
+    assert list(e.hot) == eligible[:math.ceil(0.05 * g.n)]
+    if dens >= 1.0 / 32:
+        # each row (one bit per warm-up set) costs no more than the vertex's ids would
+        assert all(W <= 32 * int(warm[v]) for v in e.hot)
+    off, mem = st.arrays()
+    for j in range(0, theta, 7):
+        assert np.array_equal(e.decode_set(j), mem[off[j]:off[j + 1]])
+
+
 def test_characterize_eq2(orc):
     g = G.rmat(10, seed=4)
     og = orc.Graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
