@@ -19,6 +19,11 @@ Huffman alternating, k ~ U{5..100}, eps in {.5, .3}.
 --workload c3: R-MAT scale 23 under LT, eps=.13, k=100, Huffman (5% warm-up).
 --workload c4: the batched workload as the main line (value = RR sets/s of
 hbm_imm_batch over all 256 instances).
+--workload c5: the serving loop on a Chung-Lu digraph shaped like twitter7
+(41.7M vertices, ~1.44B edges, exponent 2.2, weighted cascade): Poisson
+arrivals of queries (k ~ U{10..200}, eps in {.5, .2}) at fractions of the
+measured single-query service rate, 200 GB store budget; p50/p99 latency,
+throughput, and each served answer against the same query run alone.
 """
 
 from __future__ import annotations
@@ -40,6 +45,7 @@ WORKLOADS = {
     "c2": dict(name="imm_ic_wc_rmat20_eps0.5_k50_hotbitmap", cfg="c2"),
     "c3": dict(name="imm_lt_rmat23_eps0.13_k100_huffman", cfg="c3"),
     "c4": dict(name="imm_batch256_rmat12-18_icwc-hotbitmap_lt-huffman", cfg="c4"),
+    "c5": dict(name="serve_chunglu41.7M_1.44Bedges_icwc_huffman-hotbitmap_poisson", cfg="c5"),
 }
 
 
@@ -240,6 +246,95 @@ def cpu_baseline_batched(insts, graphs, budget_s=12.0):
                       f"transposes included)", "seconds": secs}
 
 
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def serve_level(P, ctx, queries, budget, max_active):
+    """Replay one Poisson arrival stream against a fresh server; returns per-query results."""
+    srv = P.Server(ctx, store_budget=budget, max_active=max_active)
+    t0 = time.perf_counter()
+    tickets = []
+    for q in queries:
+        while time.perf_counter() - t0 < q["t"]:
+            time.sleep(min(0.005, max(0.0, q["t"] - (time.perf_counter() - t0))))
+        tickets.append(srv.hbm_server_submit(q["k"], q["eps"], q["l"], q["seed"]))
+    res = [srv.hbm_server_poll(t, wait=True) for t in tickets]
+    st = srv.hbm_server_get_stats()
+    srv.close()
+    return res, st
+
+
+def main_c5(args, P, torch):
+    """The serving loop on the Chung-Lu graph: Poisson arrivals at fractions of the measured
+    single-query service rate; p50/p99 latency, throughput, and served == alone."""
+    from synth import graphs as G
+
+    wl = WORKLOADS["c5"]
+    c = G.C5
+    t0 = time.time()
+    rp, dst = G.chung_lu_csr(c["n"], c["avg_deg"], c["gamma"], c["gseed"], c["max_deg"], device="cuda")
+    torch.cuda.synchronize()
+    m = int(dst.numel())
+    log(f"[bench] Chung-Lu n={c['n']} m={m} generated on the GPU ({time.time() - t0:.1f}s)")
+    ctx = P.Context(0)
+    ctx.hbm_load_graph(c["n"], rp, dst, None, "IC", "WC")
+    del rp, dst
+    torch.cuda.empty_cache()
+    ctx.hbm_set_encoding(c["enc"], c["warmup"], c["hot"])
+    ctx.hbm_set_hot_density(c["hot_density"])
+    ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)  # short steps: arrivals join within a block's time
+    nq = args.queries
+    base = G.serving_queries(nq, seed=c["gseed"], rate=1.0)
+    # alone: every query of the stream on its own (service times, reference answers)
+    alone = {}
+    t_alone = []
+    for q in base:
+        t1 = time.perf_counter()
+        s_, g_, st = ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+        t_alone.append(time.perf_counter() - t1)
+        alone[q["q"]] = (s_, g_, st)
+    svc = float(np.mean(t_alone))
+    log(f"[bench] {nq} queries alone: mean service {svc:.3f}s, max {max(t_alone):.3f}s")
+    levels = {}
+    identical = True
+    for load in args.loads:
+        qs = G.serving_queries(nq, seed=c["gseed"], rate=load / svc)
+        res, st = serve_level(P, ctx, qs, c["budget"], 16)
+        lat = [r["t_done_ms"] - r["t_submit_ms"] for r in res]
+        span = (max(r["t_done_ms"] for r in res) - min(r["t_submit_ms"] for r in res)) / 1e3
+        ok = all(r["status"] == "OK" for r in res)
+        same = ok and all(np.array_equal(r["seeds"], alone[q["q"]][0]) and np.array_equal(r["gains"], alone[q["q"]][1])
+                          for r, q in zip(res, qs))
+        identical &= same
+        sets = sum(r["stats"]["nsets_final"] for r in res if r["status"] == "OK")
+        levels[str(load)] = dict(rate_qps=load / svc, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
+                                 mean_ms=float(np.mean(lat)), makespan_s=span, queries_per_s=nq / span,
+                                 rr_sets_per_s=sets / span, served_equals_alone=bool(same),
+                                 peak_active=st["peak_active"], preemptions=st["preemptions"],
+                                 peak_store_bytes=st["peak_store_bytes"], steps=st["steps"])
+        log(f"[bench] load {load}: p50 {levels[str(load)]['p50_ms']:.0f} ms p99 {levels[str(load)]['p99_ms']:.0f} ms "
+            f"{nq / span:.2f} q/s peak_active {st['peak_active']} same={same}")
+    top = levels[str(max(args.loads))]
+    sets_alone = sum(a[2]["nsets_final"] for a in alone.values())
+    stores = [a[2]["store"] for a in alone.values()]
+    res_line = {
+        "metric": METRIC, "value": top["rr_sets_per_s"], "unit": "RR sets/s", "n_gpus": 1, "steps": nq,
+        "warmup": 0, "ms_per_step": top["makespan_s"] * 1e3 / nq, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded Chung-Lu digraph; no public dataset)",
+        "config": {"workload": wl["name"], "n": c["n"], "m": m, "gamma": c["gamma"], "model": "IC", "prob": "WC",
+                   "k": "U{10..200}", "eps": [0.5, 0.2], "queries": nq, "arrivals": "Poisson",
+                   "loads": list(args.loads), "store_budget_bytes": c["budget"], "encoding": c["enc"],
+                   "hot_min_density": c["hot_density"]},
+        "alone": {"mean_service_s": svc, "max_service_s": max(t_alone), "rr_sets_per_s": sets_alone / sum(t_alone)},
+        "levels": levels, "served_equals_alone": bool(identical),
+        "bytes_per_rr": sum(s_["store_bytes"] for s_ in stores) / max(sets_alone, 1),
+        "raw_bytes_per_rr": sum(4 * s_["members"] + 8 * (s_["nsets"] + 1) for s_ in stores) / max(sets_alone, 1),
+    }
+    print(json.dumps(res_line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +343,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain summary of the c2 line")
+    ap.add_argument("--queries", type=int, default=24, help="c5: queries per load level")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 1.0],
+                    help="c5: arrival rates as fractions of the measured single-query service rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is described in "
@@ -264,6 +362,8 @@ def main():
         batched = batched_graphs()
     if args.workload == "c4":
         return main_c4(args, P, torch, *batched)
+    if args.workload == "c5":
+        return main_c5(args, P, torch)
     wl = WORKLOADS[args.workload]
     c = G.CONFIGS[wl["cfg"]]
     t0 = time.time()

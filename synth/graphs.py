@@ -8,7 +8,7 @@ benchmark configurations name:
 * ``erdos_renyi``  directed G(n, m) with distinct ordered pairs, no self-loops;
 * ``rmat``         R-MAT (a, b, c, d) = (.57, .19, .19, .05), 16 * 2**scale samples,
                    seeded label permutation, self-loops and duplicates removed;
-* ``chung_lu``     power-law digraph (exponent gamma) drawn target by target,
+* ``chung_lu``     power-law digraph (exponent gamma) drawn source by source,
                    shaped like twitter7 (41.7M vertices, ~1.47B edges);
 * ``lt_weights``   U(0,1) float32 in-weights rescaled so every vertex's in-weights
                    sum to at most 1 (rows whose sum exceeds 1 are divided by it).
@@ -173,17 +173,18 @@ def tiny_graph(n: int, m: int, seed: int, p_lo=0.0, p_hi=1.0) -> Graph:
     return _csr_from_pairs(n, u, v, p, name=f"tiny_n{n}_m{m}_s{seed}")
 
 
-def chung_lu(n: int, avg_deg: float, gamma: float, seed: int, max_deg: float, device: str = "cpu",
-             chunk: int = 1 << 22) -> Graph:
-    """Chung-Lu power-law digraph drawn target by target.
+def chung_lu_csr(n: int, avg_deg: float, gamma: float, seed: int, max_deg: float, device: str = "cpu",
+                 chunk: int = 1 << 22):
+    """Chung-Lu power-law digraph as a forward CSR of torch tensors on ``device``.
 
-    In- and out-weights are proportional to (i + i0)^(-1/(gamma-1)) and are
-    permuted independently; i0 is chosen so the largest expected degree is
-    about ``max_deg``.  Each target draws a Poisson in-degree with mean
-    proportional to its in-weight, then that many sources with probability
-    proportional to out-weight; duplicates and self-loops are dropped.
-    Generation runs in torch on ``device`` (a GPU makes the 1.47B-edge case
-    take seconds); results are reproducible for a given seed and device type.
+    Out- and in-weights are proportional to (i + i0)^(-1/(gamma-1)), permuted
+    independently; i0 is chosen so the largest expected degree is about
+    ``max_deg`` (the expected edge count is avg_deg * n).  Source by source,
+    each vertex draws a Poisson out-degree with mean proportional to its
+    out-weight, then that many targets with probability proportional to
+    in-weight; duplicates and self-loops are dropped, so rows come out sorted
+    and the CSR needs no global sort.  Deterministic for a seed and device type.
+    Returns (row_ptr int64[n+1], dst int32[m]).
     """
     import torch
 
@@ -191,64 +192,62 @@ def chung_lu(n: int, avg_deg: float, gamma: float, seed: int, max_deg: float, de
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     expo = 1.0 / (gamma - 1.0)
-    # choose i0 so that max expected degree ~= max_deg: w_i = (i+i0)^-expo, deg_i = m * w_i / sum(w)
     idx = torch.arange(n, dtype=torch.float64, device=dev)
-
-    def weights(i0):
-        return (idx + i0) ** (-expo)
-
     m_target = avg_deg * n
     lo, hi = 1e-3, float(n)
-    for _ in range(80):
+    for _ in range(80):  # i0 by bisection: the top expected degree ~= max_deg
         mid = (lo * hi) ** 0.5
-        wv = weights(mid)
-        top = float(m_target * wv[0] / wv.sum())
-        if top > max_deg:
+        wv = (idx + mid) ** (-expo)
+        if float(m_target * wv[0] / wv.sum()) > max_deg:
             lo = mid
         else:
             hi = mid
-    i0 = hi
-    wv = weights(i0)
-    p_in = torch.randperm(n, generator=gen, device=dev)
+    wv = (idx + hi) ** (-expo)
+    del idx
     p_out = torch.randperm(n, generator=gen, device=dev)
-    w_in = torch.empty_like(wv)
-    w_in[p_in] = wv
+    p_in = torch.randperm(n, generator=gen, device=dev)
     w_out = torch.empty_like(wv)
     w_out[p_out] = wv
-    lam = m_target * w_in / w_in.sum()
-    cdf = torch.cumsum(w_out / w_out.sum(), 0)
+    w_in = torch.empty_like(wv)
+    w_in[p_in] = wv
+    del wv, p_out, p_in
+    lam = m_target * w_out / w_out.sum()
+    cdf = torch.cumsum(w_in / w_in.sum(), 0)
     cdf[-1] = 1.0
-    indeg = torch.poisson(lam, generator=gen).to(torch.int64)
-    srcs, dsts = [], []
+    del w_in, w_out
+    outdeg = torch.poisson(lam, generator=gen).to(torch.int64)
+    del lam
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    dsts = []
+    cum = torch.cumsum(outdeg, 0)
     v0 = 0
     while v0 < n:
-        v1 = v0
-        tot = 0
-        # take targets until the chunk budget is reached
-        cum = torch.cumsum(indeg[v0:], 0)
-        v1 = v0 + int(torch.searchsorted(cum, torch.tensor(chunk, device=dev, dtype=torch.int64)).item()) + 1
+        base = int(cum[v0 - 1].item()) if v0 else 0
+        v1 = int(torch.searchsorted(cum, torch.tensor(base + chunk, device=dev, dtype=torch.int64)).item()) + 1
         v1 = min(max(v1, v0 + 1), n)
-        d = indeg[v0:v1]
+        d = outdeg[v0:v1]
         tot = int(d.sum().item())
         if tot:
             r = torch.rand(tot, generator=gen, device=dev, dtype=torch.float64)
-            s = torch.searchsorted(cdf, r).clamp_(max=n - 1)
-            t = torch.repeat_interleave(torch.arange(v0, v1, device=dev, dtype=torch.int64), d)
+            t = torch.searchsorted(cdf, r).clamp_(max=n - 1)
+            s = torch.repeat_interleave(torch.arange(v0, v1, device=dev, dtype=torch.int64), d)
             keep = s != t
-            key = torch.unique(s[keep] * n + t[keep])
-            srcs.append((key // n).to(torch.int32))
+            key = torch.unique(s[keep] * n + t[keep])  # sorted by (source, target)
+            counts[v0:v1] = torch.bincount(key // n - v0, minlength=v1 - v0)
             dsts.append((key % n).to(torch.int32))
+            del r, t, s, keep, key
         v0 = v1
-    s = torch.cat(srcs)
-    t = torch.cat(dsts)
-    key = s.to(torch.int64) * n + t.to(torch.int64)
-    key, _ = torch.sort(key)
-    del s, t
-    u = (key // n)
-    dst = (key % n).to(torch.int32)
-    counts = torch.bincount(u, minlength=n)
+    dst = torch.cat(dsts) if dsts else torch.zeros(0, dtype=torch.int32, device=dev)
+    del dsts
     row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
     torch.cumsum(counts, 0, out=row_ptr[1:])
+    return row_ptr, dst
+
+
+def chung_lu(n: int, avg_deg: float, gamma: float, seed: int, max_deg: float, device: str = "cpu",
+             chunk: int = 1 << 22) -> Graph:
+    """``chung_lu_csr`` as a host Graph (numpy arrays)."""
+    row_ptr, dst = chung_lu_csr(n, avg_deg, gamma, seed, max_deg, device=device, chunk=chunk)
     return Graph(n=n, row_ptr=row_ptr.cpu().numpy(), dst=dst.cpu().numpy(), w=None,
                  name=f"chunglu_n{n}_g{gamma}_s{seed}")
 
@@ -268,6 +267,24 @@ CONFIGS = {
     "c3": dict(kind="rmat", scale=23, gseed=3, model="LT", prob="EDGE", eps=0.13, l=1.0, k=100, seed=42,
                enc="HUFFMAN", warmup=0.05, hot=0.0),
 }
+
+
+# the served graph: Chung-Lu shaped like twitter7 (41,652,230 vertices, 1,468,365,182 edges,
+# largest degree 770,155), exponent 2.2, weighted cascade; queries k ~ U{10..200}, eps in {.5, .2}
+C5 = dict(n=41_700_000, avg_deg=1_468_365_182 / 41_652_230, gamma=2.2, max_deg=770_155, gseed=5,
+          model="IC", prob="WC", enc="HUFFMAN_HOT_BITMAP", warmup=0.05, hot=0.01, hot_density=1.0 / 32,
+          budget=200 * 10 ** 9)
+
+
+def serving_queries(count: int, seed: int = 5, rate: float = 1.0):
+    """Poisson arrivals (mean gap 1/rate seconds) of IMM queries: k ~ U{10..200}, eps in
+    {.5, .2}, l = 1, sampling seed 1000 + q."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    ks = rng.integers(10, 201, size=count)
+    eps = rng.choice(np.array([0.5, 0.2]), size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    return [dict(q=q, t=float(t[q]), k=int(ks[q]), eps=float(eps[q]), l=1.0, seed=1000 + q) for q in range(count)]
 
 
 def config_graph(name: str, scale_override: Optional[int] = None) -> Graph:
