@@ -233,6 +233,16 @@ hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
                 HBM_REQUIRE(value == 128 || value == 256, HBM_EINVAL, "LT_PATH must be 128 or 256");
                 c.lt_lw = (int)value;
                 break;
+            case HBM_TUNE_T2_QUEUE:
+                HBM_REQUIRE(value >= 64 && value <= (int64_t(1) << 31), HBM_EINVAL, "T2_QUEUE out of range");
+                if (value != c.t2_queue) {
+                    c.t2_queue = value;
+                    // reallocated at the next use with the new queue size
+                    hbm::buf_free(c, c.sc.t2_bitmap);
+                    hbm::buf_free(c, c.sc.t2_queue);
+                    c.sc.t2_slots = 0;
+                }
+                break;
             case HBM_TUNE_BLOCK_SETS:
                 HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
                 c.block_sets = value;

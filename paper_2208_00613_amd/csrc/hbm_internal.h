@@ -121,8 +121,11 @@ struct Scratch {
     int64_t bcap = 0;
     // big-set slots
     Buf t2_bitmap;  // uint32 words: slots * ceil(n/32)
-    Buf t2_queue;   // uint32: slots * n
+    Buf t2_queue;   // uint32: slots * min(n, 2^20)
     int t2_slots = 0;
+    Buf t2h_bitmap; // huge-set slots: bitmap + full n-entry queue each
+    Buf t2h_queue;
+    int t2h_slots = 0;
     Buf aux;        // uint64 per set (+1): bit lengths
     Buf cnt;        // uint32 per set (+1): plain-id counts
 };
@@ -135,6 +138,7 @@ enum : int {
     CW_FIRST_OVF = 3,  // lowest block offset that ran out of scratch
     CW_NEXT2 = 4,      // tier-2 work counter
     CW_SUM = 5,        // generic accumulator
+    CW_NHUGE = 6,      // sets that outgrew a big-set slot's queue
     CW_COUNT = 8
 };
 constexpr uint32_t POS_DEFER = 0xFFFFFFFFu;
@@ -187,6 +191,7 @@ struct Ctx {
     int64_t block_sets = int64_t(1) << 21;
     int lt_lw = 128;
     int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
+    int64_t t2_queue = int64_t(1) << 20; // queue entries of a big-set slot
     DGraph g;
     Store s;
     Scratch sc;

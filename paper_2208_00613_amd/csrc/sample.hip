@@ -50,6 +50,7 @@ struct SampleArgs {
     uint64_t gbudget;  // edge groups a tier-1 wave may expand per set (0 = no limit)
     unsigned long long *dctr;  // work counters (DC_*), or null
     uint32_t *defer2;  // deferred block offsets (tier 2 -> tier 3)
+    uint32_t *defer3;  // sets that outgrew a big-set slot's queue (-> the huge pass)
 };
 
 __device__ __forceinline__ uint32_t hash32(uint32_t v, int bits) { return (v * 0x9E3779B1u) >> (32 - bits); }
@@ -225,10 +226,11 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                 S.sT[lane] = tv;
                 wave_sync();
                 head += nbat;
+                uint32_t i = 0;  // vertex of this lane's group: searched only when g leaves it
                 for (uint32_t base = 0; base < G; base += WAVE) {
                     const uint32_t g = base + lane;
                     if (g < G) {
-                        const uint32_t i = upper_bound_dev<uint32_t, uint32_t>(S.sP, 0u, (uint32_t)WAVE, g);
+                        if (S.sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(S.sP, i + 1, (uint32_t)WAVE, g);
                         const uint32_t excl = i ? S.sP[i - 1] : 0u;
                         const uint32_t E0 = S.sE0[i], E1 = S.sE1[i];
                         const uint32_t grp = (E0 >> 2) + (g - excl);
@@ -347,11 +349,13 @@ constexpr int T2_SORT_CAP = 8192;
 struct T2Args {
     SampleArgs a;
     uint32_t *bitmap;  // slots * words
-    uint32_t *queue;   // slots * n
+    uint32_t *queue;   // slots * qcap
     uint64_t words;    // ceil(n / 32)
     const uint32_t *list;
     uint32_t nlist;
     int model;         // HBM_IC or HBM_LT
+    uint32_t qcap;     // queue entries per slot (n for the huge-set pass)
+    int can_defer;     // a set outgrowing qcap goes to the huge list (else qcap == n)
 };
 
 // Block-wide inclusive scan of one value per thread (wave shuffles + one LDS pass).
@@ -405,7 +409,7 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
     __shared__ int s_ok;
     __shared__ unsigned long long s_ctr[DC_COUNT];
     uint32_t *bm = t.bitmap + (uint64_t)bid * t.words;
-    uint32_t *queue = t.queue + (uint64_t)bid * (uint64_t)a.n;
+    uint32_t *queue = t.queue + (uint64_t)bid * (uint64_t)t.qcap;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
     for (;;) {
@@ -427,7 +431,7 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
         if (t.model == HBM_IC) {
             uint32_t head = 0;
             uint32_t tail = qn;
-            while (head < tail) {
+            while (head < tail && tail <= t.qcap) {
                 for (uint32_t c0 = head; c0 < tail; c0 += T2_THREADS) {
                     const uint32_t cn = tail - c0 < (uint32_t)T2_THREADS ? tail - c0 : (uint32_t)T2_THREADS;
                     uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
@@ -452,8 +456,9 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
                         }
                         if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
                     }
+                    uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
                     for (uint32_t g = threadIdx.x; g < G; g += T2_THREADS) {
-                        const uint32_t i = upper_bound_dev<uint32_t, uint32_t>(sP, 0u, cn, g);
+                        if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
                         const uint32_t excl = i ? sP[i - 1] : 0u;
                         const uint32_t E0 = sE0[i], E1 = sE1[i];
                         const uint32_t grp = (E0 >> 2) + (g - excl);
@@ -476,7 +481,7 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
                                 const uint32_t old = atomicOr(&bm[u >> 5], bit);
                                 if (!(old & bit)) {
                                     const uint32_t p = atomicAdd(&qn, 1u);
-                                    queue[p] = u;
+                                    if (p < t.qcap) queue[p] = u;  // else the set is redone with a full queue
                                 }
                             }
                         }
@@ -505,12 +510,27 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
                 const uint32_t bit = 1u << (s & 31);
                 if (bm[s >> 5] & bit) break;
                 bm[s >> 5] |= bit;
+                if (len >= t.qcap) {  // the walk outgrew the queue: redone with a full one
+                    len++;
+                    break;
+                }
                 queue[len++] = s;
                 cur = s;
             }
             qn = len;
         }
         __syncthreads();
+        if (qn > t.qcap) {
+            // outgrew this slot's queue (only when can_defer): the visited bits of dropped members
+            // are not in the queue, so clear the whole bitmap and hand the set to the huge pass
+            for (uint64_t w = threadIdx.x; w < t.words; w += T2_THREADS) bm[w] = 0u;
+            if (threadIdx.x == 0) {
+                const uint64_t d = atomicAdd(&a.ctrl[CW_NHUGE], 1ull);
+                a.defer3[d] = b;
+            }
+            __syncthreads();
+            continue;
+        }
         const uint32_t s = qn;
         if (threadIdx.x == 0) {
             s_ctr[DC_MEMBERS] += s;
@@ -779,19 +799,38 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------- host
+// Big-set slots: a visited bitmap over V and a queue of qcap = min(n, t2_queue) entries each, as
+// many slots as fit the context's byte cap (at most 2 per CU).  A set larger than qcap is
+// redone in the huge pass, whose few slots hold a full n-entry queue.
+static uint32_t t2_qcap(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.g.n, c.t2_queue); }
+
 static void ensure_t2(Ctx &c) {
     Scratch &sc = c.sc;
     if (sc.t2_slots) return;
     const uint64_t n = (uint64_t)c.g.n;
     const uint64_t words = (n + 31) / 32;
+    const uint64_t qcap = t2_qcap(c);
     int slots = 2 * c.num_cus;
-    const uint64_t per = words * 4 + n * 4;
-    const uint64_t cap_bytes = (uint64_t)c.t2_cap;  // bytes allowed for big-set slots
+    const uint64_t per = words * 4 + qcap * 4;
+    const uint64_t cap_bytes = (uint64_t)c.t2_cap;
     while (slots > 8 && per * slots > cap_bytes) slots /= 2;
     buf_alloc(c, sc.t2_bitmap, words * 4 * slots);
     buf_zero(c, sc.t2_bitmap, 0, words * 4 * slots);
-    buf_alloc(c, sc.t2_queue, n * 4 * slots);
+    buf_alloc(c, sc.t2_queue, qcap * 4 * slots);
     sc.t2_slots = slots;
+}
+
+static void ensure_t2_huge(Ctx &c) {
+    Scratch &sc = c.sc;
+    if (sc.t2h_slots) return;
+    const uint64_t n = (uint64_t)c.g.n;
+    const uint64_t words = (n + 31) / 32;
+    const uint64_t per = words * 4 + n * 4;
+    const int slots = (int)std::max<uint64_t>(1, std::min<uint64_t>(16, (uint64_t)c.t2_cap / per));
+    buf_alloc(c, sc.t2h_bitmap, words * 4 * slots);
+    buf_zero(c, sc.t2h_bitmap, 0, words * 4 * slots);
+    buf_alloc(c, sc.t2h_queue, n * 4 * slots);
+    sc.t2h_slots = slots;
 }
 
 // Algorithmic traffic of the samplers from the work counters.
@@ -862,6 +901,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         a.ctrl = ctrl_of(root, i);
         a.defer = sc.defer.as<uint32_t>();
         a.defer2 = sc.defer.as<uint32_t>() + sc.bcap;
+        a.defer3 = sc.defer.as<uint32_t>() + 2 * sc.bcap;
         a.gbudget = (uint64_t)root.ic_t1_budget;
         a.dctr = prof_counters(root);
         if (c.g.model == HBM_IC && !root.ic_tier1) {
@@ -938,6 +978,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             t.list = A[i].defer;
             t.nlist = (uint32_t)nd;
             t.model = HBM_IC;
+            t.qcap = t2_qcap(c);
+            t.can_defer = 1;
             big.push_back(t);
             bigb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)c.sc.t2_slots));
         } else {
@@ -991,6 +1033,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             t.list = A[i].defer2;
             t.nlist = (uint32_t)nd3;
             t.model = HBM_LT;
+            t.qcap = t2_qcap(c);
+            t.can_defer = 1;
             t3.push_back(t);
             t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));
         }
@@ -1006,6 +1050,40 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             ctrl_pull(root);
             if (s4 >= 0) prof_sampler(root, s4, false, J);
         }
+    }
+    // ---- huge pass: sets that outgrew a big-set slot's queue, redone with a full queue
+    std::vector<T2Args> th;
+    std::vector<uint32_t> thb;
+    for (size_t i = 0; i < N; i++) {
+        Ctx &c = *J[i];
+        const uint64_t nh = root.ctrl_host[i * CW_COUNT + CW_NHUGE];
+        if (!nh) continue;
+        ensure_t2_huge(c);
+        root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
+        T2Args t;
+        t.a = A[i];
+        t.bitmap = c.sc.t2h_bitmap.as<uint32_t>();
+        t.queue = c.sc.t2h_queue.as<uint32_t>();
+        t.words = ((uint64_t)c.g.n + 31) / 32;
+        t.list = A[i].defer3;
+        t.nlist = (uint32_t)nh;
+        t.model = c.g.model;
+        t.qcap = (uint32_t)c.g.n;
+        t.can_defer = 0;
+        th.push_back(t);
+        thb.push_back((uint32_t)std::min<uint64_t>(nh, (uint64_t)c.sc.t2h_slots));
+    }
+    if (!th.empty()) {
+        ctrl_push(root);
+        int s5 = prof_begin(root, "sample_huge");
+        glaunch(root, th, thb, 0, [&](const T2Args &t, unsigned g) { k_big<<<g, T2_THREADS, 0, st>>>(t); },
+                [&](const T2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                    k_big_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2Args>{d, b, cnt, x});
+                });
+        HBM_HIP(hipGetLastError());
+        prof_end(root, s5);
+        ctrl_pull(root);
+        if (s5 >= 0) prof_sampler(root, s5, J[0]->g.model == HBM_IC, J);
     }
     for (size_t i = 0; i < N; i++)
         done[i] = (int64_t)std::min<unsigned long long>(root.ctrl_host[i * CW_COUNT + CW_FIRST_OVF],

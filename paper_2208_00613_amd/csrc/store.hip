@@ -371,11 +371,13 @@ void store_free(Ctx &c) {
                    &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload})
         buf_free(c, *b);
     Scratch &sc = c.sc;
-    for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.aux, &sc.cnt})
+    for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.t2h_bitmap,
+                   &sc.t2h_queue, &sc.aux, &sc.cnt})
         buf_free(c, *b);
     sc.cap = 0;
     sc.bcap = 0;
     sc.t2_slots = 0;
+    sc.t2h_slots = 0;
 }
 
 int64_t store_bytes(const Ctx &c) {
@@ -397,7 +399,7 @@ void ensure_scratch(Ctx &c, size_t entries, int64_t bcap) {
     if (bcap > sc.bcap) {
         buf_alloc(c, sc.pos, (size_t)bcap * 4);
         buf_alloc(c, sc.size, (size_t)(bcap + 1) * 4);
-        buf_alloc(c, sc.defer, (size_t)bcap * 2 * 4);
+        buf_alloc(c, sc.defer, (size_t)bcap * 3 * 4);
         buf_alloc(c, sc.aux, (size_t)(bcap + 1) * 8);
         buf_alloc(c, sc.cnt, (size_t)(bcap + 1) * 4);
         sc.bcap = bcap;

@@ -202,13 +202,16 @@ def test_sets_and_seeds_rmat(orc, ctx, model, prob, scale, theta):
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
 
 
-def test_lt_long_walks_all_tiers(orc, ctx):
-    """A directed path with weight 1: walk length = root id + 1, crossing every LT tier."""
-    _say("lt long walks")
+@pytest.mark.parametrize("queue", [1 << 20, 300])
+def test_lt_long_walks_all_tiers(orc, ctx, queue):
+    """A directed path with weight 1: walk length = root id + 1, crossing every LT tier
+    (with a 300-entry big-set queue, walks beyond it go through the huge-set pass)."""
+    _say("lt long walks, big-set queue", queue)
     n = 5000
     g = G._csr_from_pairs(n, np.arange(n - 1), np.arange(1, n))
     g = G.with_weights(g, np.ones(g.m, dtype=np.float32))
     ctx.load_synth(g, "LT", "EDGE")
+    ctx.hbm_set_tuning("T2_QUEUE", queue)
     ctx.hbm_set_encoding("NONE")
     ctx.hbm_sample_rr(400, 9)
     og = _ograph(orc, g, "LT", "EDGE")
@@ -297,15 +300,19 @@ def test_imm_small(orc, ctx, model, enc):
 
 
 # ---------------------------------------------------------------- launch-shape invariance
-@pytest.mark.parametrize("tier1,budget,block", [(0, 0, 1 << 21), (1, 0, 1 << 21), (1, 256, 1024), (1, 4096, 3000)])
-def test_tuning_invariance(orc, ctx, tier1, budget, block):
-    """Tier choice, tier-1 work budget and block size change speed only, never the sets."""
-    _say("tuning invariance", tier1, budget, block)
+@pytest.mark.parametrize("tier1,budget,block,queue", [(0, 0, 1 << 21, 1 << 20), (1, 0, 1 << 21, 1 << 20),
+                                                      (1, 256, 1024, 1 << 20), (1, 4096, 3000, 1 << 20),
+                                                      (1, 64, 1 << 21, 64), (0, 0, 5000, 100)])
+def test_tuning_invariance(orc, ctx, tier1, budget, block, queue):
+    """Tier choice, tier-1 work budget, block size and big-set queue size (small queues
+    send sets to the huge-set pass) change speed only, never the sets."""
+    _say("tuning invariance", tier1, budget, block, queue)
     g = G.rmat(14, seed=14)
     ctx.load_synth(g, "IC", "WC")
     ctx.hbm_set_tuning("IC_TIER1", tier1)
     ctx.hbm_set_tuning("IC_T1_BUDGET", budget)
     ctx.hbm_set_tuning("BLOCK_SETS", block)
+    ctx.hbm_set_tuning("T2_QUEUE", queue)
     ctx.hbm_set_encoding("HOT_BITMAP", 0.1, 0.01)
     theta = 20_000
     ctx.hbm_sample_rr(theta, 42)
