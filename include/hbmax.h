@@ -89,7 +89,7 @@ typedef struct hbm_store_stats {
     int32_t escape_bits;    /* width of a verbatim id */
     int64_t escapes;        /* codeless occurrences copied verbatim */
     uint64_t payload_bits;  /* Huffman stream bits */
-    int64_t index_bytes;    /* per-set offsets */
+    int64_t index_bytes;    /* per-set offsets (Huffman: + one code-boundary byte per 1024 payload bits) */
     int64_t bitmap_bytes;   /* hot rows */
     int64_t raw_bytes;      /* plain ids (NONE / cold part of HOT_BITMAP) */
     int64_t codebook_bytes; /* lengths + symbol table + hot list */

@@ -26,7 +26,8 @@
  *   coding      Huffman codebook from the warm-up block (Alg. 1, Huffmax
  *               encoding section), codeless vertices copied verbatim (the
  *               CP array), the warm-up top vertex moved to the front of
- *               each coded string; hot-vertex bitmap rows (Bitmax encoding
+ *               each coded string and the other codes in canonical order
+ *               (length, then id); hot-vertex bitmap rows (Bitmax encoding
  *               section, restricted to the top fraction of vertices).
  *
  * Nothing here is blocked, fused or reordered beyond those definitions.
@@ -703,7 +704,8 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
                 }
             }
             e->n_escapes += (int64_t)nesc;
-            /* coded members: the warm-up top vertex first, then the rest ascending */
+            /* coded members: the warm-up top vertex first, then the rest in canonical code
+               order, i.e. by (code length, id), which is ascending left-justified code value */
             int has_front = 0;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
                 if (s->mem[i] == e->ustar_enc) has_front = 1;
@@ -712,13 +714,14 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
                 pos += e->lens[e->ustar_enc];
                 e->n_coded++;
             }
-            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
-                int32_t v = s->mem[i];
-                if (rank[v] >= 0 || e->lens[v] == 0 || v == e->ustar_enc) continue;
-                put_bits(e->payload, pos, e->codes[v], e->lens[v]);
-                pos += e->lens[v];
-                e->n_coded++;
-            }
+            for (int clen = 1; clen <= 32; clen++)
+                for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
+                    int32_t v = s->mem[i];
+                    if (rank[v] >= 0 || e->lens[v] != clen || v == e->ustar_enc) continue;
+                    put_bits(e->payload, pos, e->codes[v], e->lens[v]);
+                    pos += e->lens[v];
+                    e->n_coded++;
+                }
         }
     }
     free(rank);

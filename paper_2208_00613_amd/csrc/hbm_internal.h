@@ -60,6 +60,11 @@ struct DGraph {
 
 // ------------------------------------------------------------------ store
 constexpr int LUT_BITS = 11;
+// Code-boundary slots of the Huffman payload: slot m holds the distance from bit m * CK_SLOT
+// to the first code boundary at or after it (0..31) when that bit lies inside a code, so a
+// long string can be decoded by many lanes at once, one slot interval each.
+constexpr int CK_SLOT = 1024;
+constexpr int BIG_BITS = 2 * CK_SLOT;  // strings longer than this are decremented by a whole wave
 
 struct Codebook {
     int32_t nsym = 0;       // coded vertices
@@ -104,6 +109,7 @@ struct Store {
     Buf lut;       // uint32[2^LUT_BITS]: (symbol << 5) | length for codes of <= LUT_BITS bits, else 0
     Buf bitoff;    // int64[nsets+1]
     Buf payload;   // uint32[]
+    Buf ckb;       // uint8 per CK_SLOT payload bits: code-boundary slots
     uint64_t nbits = 0;
     int64_t escapes = 0;
     double skew = 0.0, density = 0.0;
@@ -152,6 +158,7 @@ struct SelState {
     Buf newly;    // uint64[words]
     Buf keys;     // uint64[k]
     Buf partial;  // uint64 per argmax block + a ticket counter
+    Buf big;      // uint32: newly covered sets with long strings (+2 counters in front)
     int64_t words_cap = 0;
 };
 

@@ -56,6 +56,8 @@ struct SelArgs {
     int32_t k;                    // seeds to pick
     int32_t hx;                   // hot-count blocks per word segment
     int64_t seg;                  // words per hot-count segment
+    const uint8_t *ckb;           // code-boundary slots of the payload
+    uint32_t *big;                // [0] sets queued, [1] sets taken, [2..] newly covered long strings
 };
 
 // Exact argmax over counts, stage 1: each block writes the best key of its slice to
@@ -79,6 +81,7 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     for (int64_t w = tid; w < A.words; w += nthr) A.newly[w] = 0ull;
+    if (A.big && tid < 2) A.big[tid] = 0u;
     unsigned long long best = 0;
     const int64_t n4 = A.n >> 2;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
@@ -147,11 +150,11 @@ __device__ void load_tabs(const SelArgs &A, Tabs &tb) {
 __device__ __forceinline__ uint32_t dec_code(const SelArgs &A, const Tabs &tb, const uint32_t *buf, uint64_t &pos) {
     const uint32_t w = peek32(buf, pos);
     const uint32_t ent = tb.lut[w >> (32 - LUT_BITS)];
-    if (ent) {
+    if (ent & 31u) {
         pos += ent & 31u;
         return ent >> 5;
     }
-    int L = LUT_BITS + 1 > A.minlen ? LUT_BITS + 1 : A.minlen;
+    int L = (int)(ent >> 5);  // shortest length a code with this prefix can have
     while ((uint64_t)w >= tb.lim[L]) L++;
     pos += (uint64_t)L;
     return (uint32_t)A.symtab[tb.base[L] + (int64_t)(w >> (32 - L))];
@@ -168,17 +171,20 @@ __device__ __forceinline__ uint32_t read_gamma(const uint32_t *payload, uint64_t
 // length of the canonical code at the head of window w (LDS only)
 __device__ __forceinline__ uint32_t code_len(const SelArgs &A, const Tabs &tb, uint32_t w) {
     const uint32_t ent = tb.lut[w >> (32 - LUT_BITS)];
-    if (ent) return ent & 31u;
-    int L = LUT_BITS + 1 > A.minlen ? LUT_BITS + 1 : A.minlen;
+    if (ent & 31u) return ent & 31u;
+    int L = (int)(ent >> 5);  // shortest length a code with this prefix can have
     while ((uint64_t)w >= tb.lim[L]) L++;
     return (uint32_t)L;
 }
 
 // Is u in the set whose bits are [pos, end) of buf?  Codeless ids come first, ascending,
-// and stop the scan at the first larger id; coded members are compared by their canonical
-// code (ustar_len, ustar_code), so no code is mapped back to an id.
+// and stop the scan at the first larger id.  Coded members are compared by their canonical
+// code (ustar_len, ustar_code), so no code is mapped back to an id; after the front code
+// (u*_enc, whose code is (fe_len, fe_code)) codes come in ascending left-justified value,
+// so the scan stops at the first code above u's.
 __device__ bool huff_contains(const SelArgs &A, const Tabs &tb, const uint32_t *buf, uint64_t pos, uint64_t end,
-                              uint32_t u, uint32_t ustar_len, uint32_t ustar_code) {
+                              uint32_t u, uint32_t ustar_len, uint32_t ustar_code, uint32_t fe_len,
+                              uint32_t fe_code) {
     const uint32_t nesc = read_gamma(buf, pos) - 1;
     if (!ustar_len) {
         for (uint32_t q = 0; q < nesc; q++) {
@@ -190,10 +196,15 @@ __device__ bool huff_contains(const SelArgs &A, const Tabs &tb, const uint32_t *
         return false;
     }
     pos += (uint64_t)nesc * A.wbits;
+    const uint32_t U = ustar_code << (32 - ustar_len);
+    bool first = true;
     while (pos < end) {
         const uint32_t w = peek32(buf, pos);
         const uint32_t L = code_len(A, tb, w);
-        if (L == ustar_len && (w >> (32 - L)) == ustar_code) return true;
+        const uint32_t c = w >> (32 - L);
+        if (L == ustar_len && c == ustar_code) return true;
+        if (!(first && L == fe_len && c == fe_code) && (c << (32 - L)) > U) return false;
+        first = false;
         pos += L;
     }
     return false;
@@ -244,6 +255,12 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, co
     while (pos < end) cache_dec(C, A.counts, dec_code(A, tb, buf, pos));
 }
 
+// A newly covered set whose string is long: its members are decremented by k_dec_big.
+__device__ __forceinline__ void queue_big(const SelArgs &A, int64_t j) {
+    const uint32_t q = atomicAdd(&A.big[0], 1u);
+    A.big[2 + q] = (uint32_t)j;
+}
+
 __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
     (void)t;
     key = argmax_key(A);
@@ -285,10 +302,14 @@ HBM_KERNEL(k_find_raw, SelArgs, 256) {
     }
 }
 
-// Huffman strings: one lane per uncovered set, partial decode that stops at u* or a
-// larger id; a set that holds u* is marked covered and its members decremented at once.
-// The 64 strings of a wave are contiguous in the stream: they are copied to LDS with
-// coalesced loads first (when they fit), so the lanes decode from LDS.
+// Huffman strings (Alg. 2's DecodeFind), one wave per 64-set word and one lane per set:
+// a partial decode that stops at u* (a codeless u* is sought among the escaped ids, which
+// come first and ascending; a coded u* is matched by its canonical code and the scan ends
+// at the first larger code).  A set holding u* is marked covered and its members are
+// decremented at once (a long string is queued for k_dec_big, which spreads it over a
+// wave).  The word's strings are contiguous: they are copied to LDS with coalesced loads
+// first (when they fit).  Each wave loads the next word's covered mask and bit offsets
+// before decoding the current one, and the grid is sized to stay resident.
 constexpr int STAGE_WORDS = 1024;
 
 HBM_KERNEL(k_find_huff, SelArgs, 256) {
@@ -303,19 +324,37 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
     const uint32_t ustar_len = A.lens[u];
     const uint32_t ustar_code = ustar_len ? A.codes[u] : 0u;
+    const uint32_t fe_len = A.ustar_enc >= 0 ? A.lens[A.ustar_enc] : 0u;  // the front code
+    const uint32_t fe_code = fe_len ? A.codes[A.ustar_enc] : 0u;
     const unsigned lane = lane_id();
     const int wv = threadIdx.x / WAVE;
     const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
-    for (int64_t w = bid * (int64_t)(blockDim.x / WAVE) + wv; w < A.words; w += nwaves) {
-        const unsigned long long cov = A.covered[w];
+    int64_t w = (int64_t)bid * (blockDim.x / WAVE) + wv;
+    // next word's covered mask, this lane's set start and the word's end offset
+    unsigned long long cov_n = 0;
+    uint64_t bo_n = 0, be_n = 0;
+    auto fetch = [&](int64_t ww) {
+        const int64_t j0 = ww * 64;
+        const int64_t j1 = j0 + 64 < A.T ? j0 + 64 : A.T;
+        cov_n = A.covered[ww];
+        bo_n = (uint64_t)A.bitoff[j0 + lane < j1 ? j0 + lane : j1];
+        be_n = (uint64_t)A.bitoff[j1];
+    };
+    if (w < A.words) fetch(w);
+    for (; w < A.words; w += nwaves) {
+        const unsigned long long cov = cov_n;
+        const uint64_t bo = bo_n, be = be_n;
+        if (w + nwaves < A.words) fetch(w + nwaves);
         const int64_t j0 = w * 64;
         const int64_t j1 = j0 + 64 < A.T ? j0 + 64 : A.T;
         const unsigned long long live = (j1 - j0 == 64 ? ~0ull : ((1ull << (j1 - j0)) - 1)) & ~cov;
         if (!live) continue;
-        const int64_t j = j0 + lane;
-        const uint64_t b0 = (uint64_t)A.bitoff[j0], b1 = (uint64_t)A.bitoff[j1];
+        const uint64_t b0 = (uint64_t)__shfl((unsigned long long)bo, 0, WAVE);
+        // the next set's start ends this lane's set
+        uint64_t bnext = (uint64_t)__shfl_down((unsigned long long)bo, 1, WAVE);
+        if (j0 + lane + 1 >= j1) bnext = be;
         const uint64_t wlo = b0 >> 5;
-        const uint64_t nw = ((b1 + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
+        const uint64_t nw = ((be + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
         const bool staged = nw <= (uint64_t)STAGE_WORDS;
         const uint32_t *buf = A.payload;
         uint64_t off = 0;
@@ -328,16 +367,19 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         bool found = false;
         uint64_t p0 = 0, p1 = 0;
         if ((live >> lane) & 1ull) {
-            p0 = (uint64_t)A.bitoff[j] - off;
-            p1 = (uint64_t)A.bitoff[j + 1] - off;
-            found = huff_contains(A, tb, buf, p0, p1, u, ustar_len, ustar_code);
+            p0 = bo - off;
+            p1 = bnext - off;
+            found = huff_contains(A, tb, buf, p0, p1, u, ustar_len, ustar_code, fe_len, fe_code);
         }
         const unsigned long long nwm = __ballot(found);
         if (lane == 0 && nwm) {
             A.newly[w] = nwm;
             A.covered[w] = cov | nwm;
         }
-        if (found) huff_decrement(A, tb, C, buf, p0, p1);
+        if (found) {
+            if (p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j0 + lane);  // a whole wave decrements it later
+            else huff_decrement(A, tb, C, buf, p0, p1);
+        }
         wave_sync();
     }
     __syncthreads();
@@ -373,7 +415,9 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
         if (A.huff) {
             if ((nw >> lane) & 1ull) {
                 const int64_t j = w * 64 + lane;
-                huff_decrement(A, tb, C, A.payload, (uint64_t)A.bitoff[j], (uint64_t)A.bitoff[j + 1]);
+                const uint64_t p0 = (uint64_t)A.bitoff[j], p1 = (uint64_t)A.bitoff[j + 1];
+                if (p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j);
+                else huff_decrement(A, tb, C, A.payload, p0, p1);
             }
         } else if (A.raw_off) {
             unsigned long long rest = nw;
@@ -384,6 +428,71 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
                 const int64_t e = A.raw_off[j + 1];
                 for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A.counts, (uint32_t)A.raw_mem[i]);
             }
+        }
+    }
+    __syncthreads();
+    cache_flush(C, A.counts);
+}
+
+// Members of the queued long strings, one wave per string: the escaped ids have fixed width,
+// so each lane takes every 64th; the coded part is cut at the code-boundary slots (one per
+// CK_SLOT bits) and the lanes decode 64 slot intervals at a time from an LDS copy of their
+// bits (one interval per lane).
+constexpr int DB_STAGE = (WAVE * CK_SLOT) / 32 + 4;  // words of 64 intervals, +look-ahead
+
+HBM_KERNEL(k_dec_big, SelArgs, 256) {
+    (void)x;
+    // blocks past the queue have nothing to take: leave before any set-up
+    if ((uint64_t)bid * (blockDim.x / WAVE) >= (uint64_t)A.big[0]) return;
+    __shared__ Tabs tb;
+    __shared__ DecCache C;
+    __shared__ uint32_t stage[256 / WAVE][DB_STAGE];
+    load_tabs(A, tb);
+    cache_init(C);
+    __syncthreads();
+    const unsigned lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const uint32_t W = (uint32_t)A.wbits;
+    const uint32_t nq = A.big[0];
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(&A.big[1], 1u);
+        it = __shfl(it, 0, WAVE);
+        if (it >= nq) break;
+        const int64_t j = A.big[2 + it];
+        uint64_t pos = (uint64_t)A.bitoff[j];
+        const uint64_t ce = (uint64_t)A.bitoff[j + 1];
+        const uint32_t nesc = read_gamma(A.payload, pos) - 1;
+        for (uint32_t q = lane; q < nesc; q += WAVE)
+            cache_dec(C, A.counts, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W));
+        const uint64_t cs = pos + (uint64_t)nesc * W;
+        // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
+        const uint64_t m0 = cs / CK_SLOT + 1;
+        const uint64_t m1 = ce > 0 ? (ce - 1) / CK_SLOT : 0;
+        const uint64_t nseg = m1 >= m0 ? m1 - m0 + 2 : 1;
+        auto seg_start = [&](uint64_t sg) -> uint64_t {
+            if (sg == 0) return cs;
+            if (sg >= nseg) return ce;
+            const uint64_t b = (m0 + sg - 1) * CK_SLOT + A.ckb[m0 + sg - 1];
+            return b < ce ? b : ce;
+        };
+        for (uint64_t g0 = 0; g0 < nseg; g0 += WAVE) {
+            const uint64_t sg = g0 + lane;
+            const uint64_t p = seg_start(sg), e = seg_start(sg + 1);
+            // bits of the 64 intervals: [start of g0, end of the group's last interval)
+            const uint64_t lo = __shfl((unsigned long long)p, 0, WAVE);
+            const uint64_t gl = g0 + WAVE < nseg ? g0 + WAVE : nseg;
+            const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
+            const uint64_t wlo = lo >> 5;
+            const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
+            for (uint64_t q = lane; q < nw; q += WAVE) stage[wv][q] = A.payload[wlo + q];
+            wave_sync();
+            if (sg < nseg) {
+                uint64_t pp = p - wlo * 32;
+                const uint64_t ee = e - wlo * 32;
+                while (pp < ee) cache_dec(C, A.counts, dec_code(A, tb, stage[wv], pp));
+            }
+            wave_sync();
         }
     }
     __syncthreads();
@@ -408,7 +517,7 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
 
 void select_free(Ctx &c) {
     SelState &S = c.sel;
-    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial}) buf_free(c, *b);
+    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big}) buf_free(c, *b);
     S.words_cap = 0;
 }
 
@@ -418,7 +527,7 @@ namespace {
 struct SelJob {
     SelArgs A;
     bool huff;
-    uint32_t g_arg, g_find, g_apply, g_hot;
+    uint32_t g_arg, g_find, g_apply, g_hot, g_big;
     double b_arg, b_find, b_apply;
 };
 
@@ -435,6 +544,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
     buf_grow(c, S.partial, (size_t)g_arg * 8, false);
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+    if (huff && T > 0) buf_grow(c, S.big, (size_t)(T + 2) * 4, false);
     SelJob J{};
     SelArgs &A = J.A;
     A.T = T;
@@ -467,6 +577,8 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     A.partial = S.partial.as<unsigned long long>();
     A.nparts = (int32_t)g_arg;
     A.hist = T > 0 ? s.hist.as<uint32_t>() : nullptr;
+    A.ckb = s.ckb.as<uint8_t>();
+    A.big = huff && T > 0 ? S.big.as<uint32_t>() : nullptr;
     A.k = k;
     A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
@@ -475,10 +587,11 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     J.huff = huff;
     J.g_arg = g_arg;
     if (T == 0) J.g_find = 0;
-    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 8);
+    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 4);  // resident: 4 blocks per CU
     else J.g_find = A.nraw > 0 ? grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4) : 0;
     J.g_apply = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * nseg) : 0;
+    J.g_big = A.big ? grid_for(T, 256, (int64_t)root.num_cus * 3) : 0;  // idle blocks leave at once
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
     // reads and writes the covered and newly words (and the hot row when u* is hot).
@@ -529,7 +642,7 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
     std::vector<size_t> order(N);
     for (size_t i = 0; i < N; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return k[a] > k[b]; });
-    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, NPLAN };
+    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_BIG, NPLAN };
     Plan plans[NPLAN];
     for (size_t i : order) {
         plans[P_ALL_ARG].jobs.push_back(i);
@@ -538,6 +651,7 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         if (J[i].g_find && J[i].huff) plans[P_HUFF].jobs.push_back(i);
         if (J[i].g_find && !J[i].huff) plans[P_RAW].jobs.push_back(i);
         if (J[i].g_hot) plans[P_HOT].jobs.push_back(i);
+        if (J[i].g_big) plans[P_BIG].jobs.push_back(i);
     }
     auto blocks = [&](int p, size_t i) -> uint32_t {
         switch (p) {
@@ -546,6 +660,7 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
             case P_HUFF:
             case P_RAW: return J[i].g_find;
             case P_HOT: return J[i].g_hot;
+            case P_BIG: return J[i].g_big;
             default: return grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
         }
     };
@@ -622,6 +737,11 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         ps = prof_begin(root, "apply");
         HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
         prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
+        if (active(P_BIG, t)) {
+            ps = prof_begin(root, "dec_big");
+            HBM_SEL_LAUNCH(P_BIG, k_dec_big, t);
+            prof_end(root, ps);
+        }
         if (active(P_HOT, t)) {
             ps = prof_begin(root, "dec_hot");
             HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);

@@ -62,7 +62,7 @@ struct Slot {
 void release_store(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb})
         buf_free(c, *b);
     store_reset(c);
 }
@@ -214,6 +214,7 @@ void hbm_server::admit_locked() {
             c.ic_t1_budget = root.ic_t1_budget;
             c.block_sets = root.block_sets;
             c.lt_lw = root.lt_lw;
+            c.t2_queue = root.t2_queue;
             c.t2_cap = int64_t(1) << 30;  // many queries share the device: fewer big-set slots each
             c.g = graph;
         }
@@ -357,6 +358,7 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     s->root.ic_t1_budget = g.ic_t1_budget;
     s->root.block_sets = g.block_sets;
     s->root.lt_lw = g.lt_lw;
+    s->root.t2_queue = g.t2_queue;
     if (hipStreamCreateWithFlags(&s->root.stream, hipStreamNonBlocking) != hipSuccess) {
         delete s;
         return HBM_EDEVICE;

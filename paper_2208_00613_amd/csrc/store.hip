@@ -130,33 +130,52 @@ struct HuffArgs {
     BlockView bv;
     HuffEnc h;
     uint64_t *bits;                    // per-set bit lengths (huff_bits output)
+    uint32_t *meta;                    // per set: escapes | (u*_enc present) << 31
     const int64_t *bitoff;             // start bits of the block's sets
     uint32_t *payload;
+    uint8_t *ckb;                      // code-boundary slots (see CK_SLOT)
     unsigned long long *nesc_total;
 };
 
 __device__ __forceinline__ int floor_log2_u32(uint32_t x) { return 31 - __clz(x); }
 
+// One wave per set (sets range from a few members to millions): lanes stride over the
+// members; the set's bit length is gamma(nesc + 1) + nesc * W + the code lengths.
+// The escape count and whether u*_enc is present are kept in `meta` for the writer.
 HBM_KERNEL(k_huff_bits, HuffArgs, 256) {
     const BlockView &bv = A.bv;
     const HuffEnc &h = A.h;
-    uint64_t *__restrict__ bits_out = A.bits;
-    for (uint64_t b = bid * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
-         b += (uint64_t)nblk * blockDim.x) {
+    const unsigned lane = lane_id();
+    const uint64_t nw = (uint64_t)nblk * (blockDim.x / WAVE);
+    for (uint64_t b = bid * (uint64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         uint64_t bits = 0;
-        uint32_t nesc = 0;
-        for (uint32_t i = 0; i < s; i++) {
+        uint32_t nesc = 0, front = 0;
+        for (uint32_t i = lane; i < s; i += WAVE) {
             const uint32_t v = bv.mem[p + i];
             if (h.hot_rank && h.hot_rank[v] >= 0) continue;
             const uint32_t L = h.lens[v];
             if (L) bits += L;
             else nesc++;
+            front |= (int32_t)v == h.ustar;
         }
-        bits += 2 * (uint64_t)floor_log2_u32(nesc + 1) + 1 + (uint64_t)nesc * h.wbits;
-        bits_out[b] = bits;
+        bits = wave_sum(bits);
+        nesc = wave_sum(nesc);
+        front = wave_sum(front);
+        if (lane == 0) {
+            A.bits[b] = bits + 2 * (uint64_t)floor_log2_u32(nesc + 1) + 1 + (uint64_t)nesc * h.wbits;
+            A.meta[b] = nesc | (front ? 0x80000000u : 0u);
+        }
     }
-    if (bid == 0 && threadIdx.x == 0) bits_out[bv.nb] = 0ull;  // the scan covers one extra element
+    if (bid == 0 && threadIdx.x == 0) A.bits[bv.nb] = 0ull;  // the scan covers one extra element
+}
+
+// Record the code at bits [p, p + len) in the boundary slots: a slot position inside it (or at
+// its start) gets the distance to the first boundary at or after it.
+__device__ __forceinline__ void mark_slot(uint8_t *ckb, uint64_t p, uint32_t len) {
+    const uint64_t m = (p + CK_SLOT - 1) / CK_SLOT;
+    const uint64_t at = m * CK_SLOT;
+    if (at < p + len) ckb[m] = (uint8_t)(at == p ? 0 : p + len - at);
 }
 
 // OR `nbits` (<= 32) bits of `value` into the stream at bit `pos`, MSB first.
@@ -170,55 +189,97 @@ __device__ __forceinline__ void put_bits(uint32_t *buf, uint64_t pos, uint32_t v
     if (lo) atomicOr(&buf[w + 1], lo);
 }
 
+// One wave per set.  Layout of a set's string: gamma(nesc + 1), the escaped (codeless)
+// ids ascending at W bits, the code of u*_enc if present, then the other codes in
+// canonical order (by code length, then id: ascending left-justified code value).
+// Members arrive ascending by id, so an escape's place is its rank among the escapes
+// (a ballot) and a code's place is its length class's offset (from a per-set histogram
+// of code lengths) plus its rank among the earlier members of the same length.
 HBM_KERNEL(k_huff_write, HuffArgs, 256) {
     const BlockView &bv = A.bv;
     const HuffEnc &h = A.h;
-    const int64_t *__restrict__ bitoff = A.bitoff;
     uint32_t *__restrict__ payload = A.payload;
-    unsigned long long *__restrict__ nesc_total = A.nesc_total;
+    __shared__ uint32_t cls_n[256 / WAVE][33];  // members per code length
+    __shared__ uint64_t cls_at[256 / WAVE][33]; // next bit of each length class
+    const unsigned lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
+    const unsigned long long below = lane ? (~0ull >> (WAVE - lane)) : 0ull;
+    const uint64_t nw = (uint64_t)nblk * (blockDim.x / WAVE);
     uint64_t esc_local = 0;
-    for (uint64_t b = bid * (uint64_t)blockDim.x + threadIdx.x; b < (uint64_t)bv.nb;
-         b += (uint64_t)nblk * blockDim.x) {
+    for (uint64_t b = bid * (uint64_t)(blockDim.x / WAVE) + wv; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
-        uint64_t pos = (uint64_t)bitoff[b];
-        uint32_t nesc = 0;
-        bool has_front = false;
-        for (uint32_t i = 0; i < s; i++) {
-            const uint32_t v = bv.mem[p + i];
-            if (h.hot_rank && h.hot_rank[v] >= 0) continue;
-            if (!h.lens[v]) nesc++;
-            if ((int32_t)v == h.ustar) has_front = true;
-        }
+        const uint32_t meta = A.meta[b];
+        const uint32_t nesc = meta & 0x7FFFFFFFu;
+        const bool has_front = meta >> 31;
+        const uint64_t pos0 = (uint64_t)A.bitoff[b];
         const uint32_t L = (uint32_t)floor_log2_u32(nesc + 1);
-        pos += L;
-        put_bits(payload, pos, nesc + 1, L + 1);
-        pos += L + 1;
-        for (uint32_t i = 0; i < s && nesc; i++) {
-            const uint32_t v = bv.mem[p + i];
-            if (h.hot_rank && h.hot_rank[v] >= 0) continue;
-            if (!h.lens[v]) {
-                put_bits(payload, pos, v, h.wbits);
-                pos += h.wbits;
+        uint64_t esc_pos = pos0 + 2 * L + 1;
+        uint64_t code_pos = esc_pos + (uint64_t)nesc * h.wbits;
+        if (lane == 0) {
+            put_bits(payload, pos0 + L, nesc + 1, L + 1);
+            if (has_front) {
+                put_bits(payload, code_pos, h.codes[h.ustar], h.lens[h.ustar]);
+                mark_slot(A.ckb, code_pos, h.lens[h.ustar]);
             }
         }
-        if (has_front) {
-            const uint32_t Lf = h.lens[h.ustar];
-            put_bits(payload, pos, h.codes[h.ustar], Lf);
-            pos += Lf;
+        if (has_front) code_pos += h.lens[h.ustar];
+        // code length of member i in the coded part (0: hot, escaped or the front vertex)
+        auto code_of = [&](uint32_t i, uint32_t &v, bool &esc) -> uint32_t {
+            v = bv.mem[p + i];
+            esc = false;
+            if (h.hot_rank && h.hot_rank[v] >= 0) return 0u;
+            const uint32_t len = h.lens[v];
+            esc = len == 0;
+            return (int32_t)v == h.ustar ? 0u : len;
+        };
+        if (lane < 33) cls_n[wv][lane] = 0u;
+        wave_sync();
+        for (uint32_t c0 = 0; c0 < s; c0 += WAVE) {
+            uint32_t v;
+            bool esc;
+            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc) : 0u;
+            if (len) atomicAdd(&cls_n[wv][len], 1u);
         }
-        for (uint32_t i = 0; i < s; i++) {
-            const uint32_t v = bv.mem[p + i];
-            if ((int32_t)v == h.ustar) continue;
-            if (h.hot_rank && h.hot_rank[v] >= 0) continue;
-            const uint32_t Lv = h.lens[v];
-            if (Lv) {
-                put_bits(payload, pos, h.codes[v], Lv);
-                pos += Lv;
+        wave_sync();
+        {  // class offsets: exclusive prefix of count * length over lengths 1..32
+            const uint64_t mine = lane >= 1 && lane <= 32 ? (uint64_t)cls_n[wv][lane] * lane : 0ull;
+            const uint64_t incl = wave_incl_scan(mine);
+            if (lane >= 1 && lane <= 32) cls_at[wv][lane] = code_pos + incl - mine;
+        }
+        wave_sync();
+        for (uint32_t c0 = 0; c0 < s; c0 += WAVE) {
+            uint32_t v = 0;
+            bool esc = false;
+            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc) : 0u;
+            const unsigned long long em = __ballot(esc);
+            if (esc) put_bits(payload, esc_pos + (uint64_t)__popcll(em & below) * h.wbits, v, h.wbits);
+            esc_pos += (uint64_t)__popcll(em) * h.wbits;
+            // rank among this chunk's members of the same length, one length class at a time
+            unsigned long long pending = __ballot(len != 0);
+            uint32_t rank = 0, lead_n = 0, lead_len = 0;
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const uint32_t ll = __shfl(len, leader, WAVE);
+                const unsigned long long m = __ballot(len == ll) & pending;
+                if (len == ll) rank = (uint32_t)__popcll(m & below);
+                if ((int)lane == leader) {
+                    lead_n = (uint32_t)__popcll(m);
+                    lead_len = ll;
+                }
+                pending &= ~m;
             }
+            if (len) {
+                const uint64_t at = cls_at[wv][len] + (uint64_t)rank * len;
+                put_bits(payload, at, h.codes[v], len);
+                mark_slot(A.ckb, at, len);
+            }
+            wave_sync();
+            if (lead_n) cls_at[wv][lead_len] += (uint64_t)lead_n * lead_len;
+            wave_sync();
         }
         esc_local += nesc;
     }
-    if (esc_local) atomicAdd(nesc_total, (unsigned long long)esc_local);
+    if (lane == 0 && esc_local) atomicAdd(A.nesc_total, (unsigned long long)esc_local);
 }
 
 // gather one int64 per job (the last offset of its scan) into out[i]
@@ -368,7 +429,7 @@ void store_reset(Ctx &c) {
 void store_free(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb})
         buf_free(c, *b);
     Scratch &sc = c.sc;
     for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.t2h_bitmap,
@@ -384,7 +445,7 @@ int64_t store_bytes(const Ctx &c) {
     const Store &s = c.s;
     int64_t b = 0;
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    if (huff) b += (s.nsets + 1) * 8 + (int64_t)((s.nbits + 7) / 8);
+    if (huff) b += (s.nsets + 1) * 8 + (int64_t)((s.nbits + 7) / 8) + (int64_t)(s.nbits / CK_SLOT + 1);
     else b += (s.nsets + 1) * 8 + s.raw_count * 4;
     b += s.bm_words * (int64_t)s.nhot * 8;
     return b;
@@ -542,7 +603,9 @@ static void build_model(Ctx &c) {
         }
         tab_lim[33] = ~0ull;  // sentinel: never decoded past the longest code
         // direct lookup for codes of at most LUT_BITS bits: every LUT_BITS-bit prefix that starts
-        // with such a code maps to (symbol << 5) | length; longer codes keep 0 (search the limits)
+        // with such a code maps to (symbol << 5) | length.  Any other prefix maps to Lmin << 5
+        // (length field 0): the shortest length of a code starting with it, i.e. the first L
+        // whose limit exceeds the prefix, so a decoder searches the limits from there.
         std::vector<uint32_t> lut((size_t)1 << LUT_BITS, 0u);
         for (size_t q = 0; q < ord.size(); q++) {
             const size_t i = ord[q];
@@ -551,6 +614,12 @@ static void build_model(Ctx &c) {
             const uint32_t cd = codes[syms[i].second];
             const uint32_t lo = cd << (LUT_BITS - L), hi = (cd + 1) << (LUT_BITS - L);
             for (uint32_t x = lo; x < hi; x++) lut[x] = ((uint32_t)syms[i].second << 5) | (uint32_t)L;
+        }
+        for (uint32_t t = 0; t < (1u << LUT_BITS); t++) {
+            if (lut[t]) continue;
+            int L = LUT_BITS + 1;
+            while (L < 33 && tab_lim[L] <= ((uint64_t)t << (32 - LUT_BITS))) L++;
+            lut[t] = (uint32_t)L << 5;
         }
         buf_alloc(c, s.lens, (size_t)n);
         buf_alloc(c, s.codes, (size_t)n * 4);
@@ -729,10 +798,11 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             a.h = HuffEnc{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
                           s.cb.ustar_enc, s.cb.wbits};
             a.bits = c.sc.aux.as<uint64_t>();
+            a.meta = c.sc.cnt.as<uint32_t>();
             a.bitoff = s.bitoff.as<int64_t>() + j0[i];
             a.nesc_total = root.ctrl_arena.as<unsigned long long>() + i * CW_COUNT + CW_SUM;
             fa.push_back(a);
-            fb.push_back(grid_for(done[i], 256, 65536));
+            fb.push_back(grid_for(done[i] * WAVE, 256, 65536));
         }
         {
             const int ps = prof_begin(root, "huff_bits");
@@ -753,7 +823,9 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
         for (size_t q = 0; q < H.size(); q++) {
             Ctx &c = *J[H[q]];
             buf_grow(c, c.s.payload, (size_t)((total[q] + 31) / 32 + 2) * 4, true);
+            buf_grow(c, c.s.ckb, (size_t)(total[q] / CK_SLOT + 2), true);
             fa[q].payload = c.s.payload.as<uint32_t>();
+            fa[q].ckb = c.s.ckb.as<uint8_t>();
             c.s.nbits = (uint64_t)total[q];
             if (c.s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP) {
                 SplitArgs a{};
@@ -940,7 +1012,7 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     o->escapes = s.escapes;
     o->payload_bits = s.nbits;
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    o->index_bytes = s.nsets ? (s.nsets + 1) * 8 : 0;
+    o->index_bytes = s.nsets ? (s.nsets + 1) * 8 + (huff ? (int64_t)(s.nbits / CK_SLOT + 1) : 0) : 0;
     o->bitmap_bytes = s.bm_words * (int64_t)s.nhot * 8;
     o->raw_bytes = huff ? 0 : s.raw_count * 4;
     o->codebook_bytes = huff ? (int64_t)c.g.n + (int64_t)s.cb.nsym * 4 + 68 * 8 : 0;

@@ -551,6 +551,63 @@ def test_hot_density_gate(orc, dens):
         assert np.array_equal(e.decode_set(j), mem[off[j]:off[j + 1]])
 
 
+def _stream_order(e, j):
+    """Members of encoded set j in stream order: (escaped ids, coded ids), read bit by bit."""
+    pay = e.payload
+    bit = lambda p: (int(pay[p >> 5]) >> (31 - (p & 31))) & 1
+    pos, end = int(e.bitoff[j]), int(e.bitoff[j + 1])
+    L = 0
+    while bit(pos) == 0:
+        L, pos = L + 1, pos + 1
+    g = 0
+    for _ in range(L + 1):
+        g, pos = (g << 1) | bit(pos), pos + 1
+    esc = []
+    for _ in range(g - 1):
+        v = 0
+        for _ in range(e.wbits):
+            v, pos = (v << 1) | bit(pos), pos + 1
+        esc.append(v)
+    book = {(int(e.lens[v]), int(e.codes[v])): v for v in np.nonzero(e.lens)[0]}
+    coded = []
+    while pos < end:
+        c, ln = 0, 0
+        while (ln, c) not in book:
+            c, ln, pos = (c << 1) | bit(pos), ln + 1, pos + 1
+            assert ln <= 32
+        coded.append(book[(ln, c)])
+    return esc, coded
+
+
+@pytest.mark.parametrize("model", ["IC", "LT"])
+def test_huffman_string_order(orc, model):
+    """Escaped ids ascend; u*_enc (the warm-up top vertex) leads the coded part; the other codes
+    follow in canonical order, i.e. by (code length, id)."""
+    g = G.rmat(10, seed=6)
+    w = G.lt_weights(g, 9) if model == "LT" else None
+    og = orc.Graph(g.n, g.row_ptr, g.dst, w, model=model, prob="WC" if model == "IC" else "EDGE")
+    theta = 800
+    st = orc.sample_store(og, 42, theta)
+    W = orc.warmup_count(0.1, theta)
+    e = orc.Encoded(st, g.n, "HUFFMAN", W)
+    warm = st.counts(g.n, 0, W)
+    assert e.ustar_enc == int(np.argmax(warm))  # most frequent, lowest id on ties
+    off, mem = st.arrays()
+    fronts = 0
+    for j in range(theta):
+        esc, coded = _stream_order(e, j)
+        assert sorted(esc + coded) == list(mem[off[j]:off[j + 1]])
+        assert esc == sorted(esc) and all(e.lens[v] == 0 for v in esc)
+        rest = coded
+        if e.ustar_enc in coded:
+            assert coded[0] == e.ustar_enc
+            rest = coded[1:]
+            fronts += 1
+        keys = [(int(e.lens[v]), int(v)) for v in rest]
+        assert keys == sorted(keys)
+    assert fronts > 0
+
+
 def test_characterize_eq2(orc):
     g = G.rmat(10, seed=4)
     og = orc.Graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
