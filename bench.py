@@ -60,7 +60,8 @@ CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 # i.e. 10 x (4 x 4 + 4) = 200 full-rate VALU lane slots.
 PHILOX_SLOTS = 200.0
 PHILOX_PEAK_G = CUS * SIMDS * LANES * CLOCK_GHZ / PHILOX_SLOTS  # G calls/s
-SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "lt_sample_lane", "lt_sample_wave", "lt_sample_block")
+SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_bitmap", "lt_sample_lane", "lt_sample_wave",
+                   "lt_sample_block", "sample_huge")
 
 
 def roofline(kstats, model, prob):

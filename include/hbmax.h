@@ -291,8 +291,10 @@ typedef enum hbm_tune_key {
                                      Default 2^21 */
     HBM_TUNE_LT_PATH = 3,         /* LT walk length kept in LDS by one lane: 128 (default) or 256;
                                      longer walks move to device memory */
-    HBM_TUNE_T2_QUEUE = 4         /* queue entries of a big-set slot (>= 64, default 2^20); a set with
+    HBM_TUNE_T2_QUEUE = 4,        /* queue entries of a big-set slot (>= 64, default 2^20); a set with
                                      more members is redone by a few slots with full-size queues */
+    HBM_TUNE_T2_SLOTS = 5         /* big-set workgroups per CU, 1..4 (default 4), each with its own
+                                     visited bitmap and queue */
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

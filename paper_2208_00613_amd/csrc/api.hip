@@ -243,6 +243,15 @@ hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
                     c.sc.t2_slots = 0;
                 }
                 break;
+            case HBM_TUNE_T2_SLOTS:
+                HBM_REQUIRE(value >= 1 && value <= 4, HBM_EINVAL, "T2_SLOTS must be in [1, 4]");
+                if (value != c.t2_per_cu) {
+                    c.t2_per_cu = (int)value;
+                    hbm::buf_free(c, c.sc.t2_bitmap);
+                    hbm::buf_free(c, c.sc.t2_queue);
+                    c.sc.t2_slots = 0;
+                }
+                break;
             case HBM_TUNE_BLOCK_SETS:
                 HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
                 c.block_sets = value;

@@ -145,6 +145,7 @@ enum : int {
     CW_NEXT2 = 4,      // tier-2 work counter
     CW_SUM = 5,        // generic accumulator
     CW_NHUGE = 6,      // sets that outgrew a big-set slot's queue
+    CW_NDEFER2 = 7,    // IC sets that outgrew the LDS tier (-> device-bitmap tier)
     CW_COUNT = 8
 };
 constexpr uint32_t POS_DEFER = 0xFFFFFFFFu;
@@ -199,6 +200,7 @@ struct Ctx {
     int lt_lw = 128;
     int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
     int64_t t2_queue = int64_t(1) << 20; // queue entries of a big-set slot
+    int t2_per_cu = 4;                   // big-set slots (workgroups) per CU
     DGraph g;
     Store s;
     Scratch sc;

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1_g(GroupArgs<SampleArgs> G) 
 // ---------------------------------------------------------------------------- IC tier 2
 constexpr int T2_THREADS = 512;
 constexpr int T2_WAVES = T2_THREADS / WAVE;
-constexpr int T2_SORT_CAP = 8192;
+constexpr int T2_SORT_CAP = 4096;  // 24 KB of LDS per block: 4 blocks (32 waves) fit a CU
 
 struct T2Args {
     SampleArgs a;
@@ -563,6 +563,172 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
         __syncthreads();
     }
     if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
+}
+
+// IC sets with few members but heavy expansions (hubs of large in-degree): one 512-thread
+// workgroup per set with its visited set in an LDS hash and its queue in LDS, so a BFS level
+// costs two dependent device loads (offsets, then sources) instead of four.  A set that
+// outgrows the LDS queue clears the hash and moves to the device-bitmap kernel (k_big).
+constexpr int T2L_HASH_BITS = 13;
+constexpr int T2L_HASH = 1 << T2L_HASH_BITS;  // 8192 slots: at most T2L_CAP + 4 * T2_THREADS in use
+constexpr int T2L_CAP = 2048;                 // members kept
+
+struct T2LArgs {
+    SampleArgs a;
+    const uint32_t *list;
+    uint32_t nlist;
+};
+
+__device__ void big_lds_body(const T2LArgs &t) {
+    const SampleArgs &a = t.a;
+    __shared__ uint32_t h[T2L_HASH];
+    __shared__ uint32_t q[T2L_CAP];
+    __shared__ uint32_t sP[T2_THREADS];
+    __shared__ uint32_t sE0[T2_THREADS];
+    __shared__ uint32_t sE1[T2_THREADS];
+    __shared__ uint32_t sT[T2_THREADS];
+    __shared__ uint32_t wsum[T2_WAVES];
+    __shared__ uint32_t qn;
+    __shared__ uint32_t item;
+    __shared__ int ovf;
+    __shared__ unsigned long long s_at;
+    __shared__ int s_ok;
+    __shared__ unsigned long long s_ctr[DC_COUNT];
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < T2L_HASH; i += T2_THREADS) h[i] = EMPTY;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) item = (uint32_t)atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
+        __syncthreads();
+        const uint32_t it = item;
+        __syncthreads();
+        if (it >= t.nlist) break;
+        const uint32_t b = t.list[it];
+        const uint64_t j = (uint64_t)a.j0 + b;
+        const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
+        const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
+        if (threadIdx.x == 0) {
+            h[hash32(root, T2L_HASH_BITS)] = root;
+            q[0] = root;
+            qn = 1;
+            ovf = 0;
+        }
+        __syncthreads();
+        uint32_t head = 0, tail = 1;
+        while (head < tail && !ovf) {
+            for (uint32_t c0 = head; c0 < tail; c0 += T2_THREADS) {
+                const uint32_t cn = tail - c0 < (uint32_t)T2_THREADS ? tail - c0 : (uint32_t)T2_THREADS;
+                uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
+                if (threadIdx.x < cn) {
+                    const uint32_t v = q[c0 + threadIdx.x];
+                    e0 = (uint32_t)a.in_ptr[v];
+                    e1 = (uint32_t)a.in_ptr[v + 1];
+                    ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
+                    if (a.wc) tv = a.thr[v];
+                }
+                const uint32_t P = block_incl_scan(ng, wsum);
+                sP[threadIdx.x] = P;
+                sE0[threadIdx.x] = e0;
+                sE1[threadIdx.x] = e1;
+                sT[threadIdx.x] = tv;
+                __syncthreads();
+                const uint32_t G = sP[T2_THREADS - 1];
+                if (a.dctr) {
+                    if (threadIdx.x == 0) {
+                        s_ctr[DC_PHILOX] += G;
+                        s_ctr[DC_EXPANDED] += cn;
+                    }
+                    if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
+                }
+                uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
+                for (uint32_t g = threadIdx.x; g < G; g += T2_THREADS) {
+                    if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
+                    const uint32_t excl = i ? sP[i - 1] : 0u;
+                    const uint32_t E0 = sE0[i], E1 = sE1[i];
+                    const uint32_t grp = (E0 >> 2) + (g - excl);
+                    const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
+                    uint4 t4;
+                    if (a.wc) {
+                        const uint32_t T = sT[i];
+                        t4 = make_uint4(T, T, T, T);
+                    } else {
+                        t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
+                    }
+                    const uint32_t eb = grp * 4;
+#pragma unroll
+                    for (uint32_t qq = 0; qq < 4; qq++) {
+                        const uint32_t e = eb + qq;
+                        if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
+                            if (a.dctr) atomicAdd(&s_ctr[DC_LIVE], 1ull);
+                            // a full queue: the set moves to k_big; stop inserting so the hash
+                            // never holds more than T2L_CAP + 4 * T2_THREADS keys
+                            if (qn >= (uint32_t)T2L_CAP) {
+                                ovf = 1;
+                                continue;
+                            }
+                            const uint32_t u = (uint32_t)a.in_src[e];
+                            uint32_t hs = hash32(u, T2L_HASH_BITS);
+                            for (;;) {
+                                const uint32_t old = atomicCAS(&h[hs], EMPTY, u);
+                                if (old == EMPTY) {
+                                    const uint32_t p = atomicAdd(&qn, 1u);
+                                    if (p < (uint32_t)T2L_CAP) q[p] = u;
+                                    else ovf = 1;
+                                    break;
+                                }
+                                if (old == u) break;
+                                hs = (hs + 1) & (T2L_HASH - 1);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            head = tail;
+            tail = qn < (uint32_t)T2L_CAP ? qn : (uint32_t)T2L_CAP;
+            __syncthreads();
+        }
+        if (ovf) {
+            for (int x = threadIdx.x; x < T2L_HASH; x += T2_THREADS) h[x] = EMPTY;
+            if (threadIdx.x == 0) {
+                const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER2], 1ull);
+                a.defer2[d] = b;
+            }
+            __syncthreads();
+            continue;
+        }
+        const uint32_t s = qn;
+        if (threadIdx.x == 0) {
+            s_ctr[DC_MEMBERS] += s;
+            const unsigned long long at = atomicAdd(&a.ctrl[CW_CURSOR], (unsigned long long)s);
+            s_at = at;
+            s_ok = at + s <= a.cap;
+        }
+        // canonical order: sort the members in LDS (pads hold EMPTY, above every id)
+        const int P2 = pow2_at_least((int)s);
+        for (int x = (int)s + threadIdx.x; x < P2; x += T2_THREADS) q[x] = EMPTY;
+        __syncthreads();
+        if (s > 1) block_bitonic(q, P2);
+        const uint64_t at = s_at;
+        if (s_ok) {
+            for (int x = threadIdx.x; x < (int)s; x += T2_THREADS) a.mem[at + x] = q[x];
+            if (threadIdx.x == 0) {
+                a.pos[b] = (uint32_t)at;
+                a.size[b] = s;
+            }
+        } else if (threadIdx.x == 0) {
+            mark_ovf(a, b);
+        }
+        for (int x = threadIdx.x; x < T2L_HASH; x += T2_THREADS) h[x] = EMPTY;
+        __syncthreads();
+    }
+    if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(T2_THREADS) void k_big_lds(T2LArgs t) { big_lds_body(t); }
+__global__ __launch_bounds__(T2_THREADS) void k_big_lds_g(GroupArgs<T2LArgs> G) {
+    big_lds_body(G.args[group_of(G.boff, G.count, blockIdx.x)]);
 }
 
 __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) { big_body(t, blockIdx.x); }
@@ -800,7 +966,7 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
 
 // ---------------------------------------------------------------------------- host
 // Big-set slots: a visited bitmap over V and a queue of qcap = min(n, t2_queue) entries each, as
-// many slots as fit the context's byte cap (at most 2 per CU).  A set larger than qcap is
+// many slots as fit the context's byte cap (at most t2_per_cu per CU).  A set larger than qcap is
 // redone in the huge pass, whose few slots hold a full n-entry queue.
 static uint32_t t2_qcap(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.g.n, c.t2_queue); }
 
@@ -810,7 +976,7 @@ static void ensure_t2(Ctx &c) {
     const uint64_t n = (uint64_t)c.g.n;
     const uint64_t words = (n + 31) / 32;
     const uint64_t qcap = t2_qcap(c);
-    int slots = 2 * c.num_cus;
+    int slots = c.t2_per_cu * c.num_cus;
     const uint64_t per = words * 4 + qcap * 4;
     const uint64_t cap_bytes = (uint64_t)c.t2_cap;
     while (slots > 8 && per * slots > cap_bytes) slots /= 2;
@@ -958,9 +1124,9 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     prof_end(root, s1b);
     ctrl_pull(root);
     if (s1b >= 0) prof_sampler(root, s1b, false, J);
-    // ---- tier 2: IC sets on a workgroup each; LT walks on a wave each
-    std::vector<T2Args> big;
-    std::vector<uint32_t> bigb;
+    // ---- tier 2: IC sets on a workgroup each (visited set in LDS); LT walks on a wave each
+    std::vector<T2LArgs> lds;
+    std::vector<uint32_t> ldsb;
     std::vector<Lt2Args> ltw;
     std::vector<uint32_t> ltwb;
     bool lt_deferred = false;
@@ -969,19 +1135,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
-            ensure_t2(c);
-            T2Args t;
-            t.a = A[i];
-            t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
-            t.queue = c.sc.t2_queue.as<uint32_t>();
-            t.words = ((uint64_t)c.g.n + 31) / 32;
-            t.list = A[i].defer;
-            t.nlist = (uint32_t)nd;
-            t.model = HBM_IC;
-            t.qcap = t2_qcap(c);
-            t.can_defer = 1;
-            big.push_back(t);
-            bigb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)c.sc.t2_slots));
+            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd});
+            ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 3));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
             lt_deferred = true;
@@ -993,12 +1148,12 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             ltwb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 16));
         }
     }
-    if (!big.empty() || !ltw.empty()) {
+    if (!lds.empty() || !ltw.empty()) {
         if (lt_deferred) ctrl_push(root);
-        int s2 = big.empty() ? -1 : prof_begin(root, "ic_sample_block");
-        glaunch(root, big, bigb, 0, [&](const T2Args &t, unsigned g) { k_big<<<g, T2_THREADS, 0, st>>>(t); },
-                [&](const T2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
-                    k_big_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2Args>{d, b, cnt, x});
+        int s2 = lds.empty() ? -1 : prof_begin(root, "ic_sample_block");
+        glaunch(root, lds, ldsb, 0, [&](const T2LArgs &t, unsigned g) { k_big_lds<<<g, T2_THREADS, 0, st>>>(t); },
+                [&](const T2LArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                    k_big_lds_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
                 });
         HBM_HIP(hipGetLastError());
         prof_end(root, s2);
@@ -1015,32 +1170,34 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         prof_end(root, s3);
         ctrl_pull(root);
         if (s3 >= 0) prof_sampler(root, s3, false, J);
-        // ---- tier 3: LT walks longer than the LDS path
-        std::vector<T2Args> t3;
-        std::vector<uint32_t> t3b;
-        for (size_t i = 0; i < N; i++) {
-            Ctx &c = *J[i];
-            if (c.g.model != HBM_LT) continue;
-            const uint64_t nd3 = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
-            if (!nd3) continue;
-            ensure_t2(c);
-            root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
-            T2Args t;
-            t.a = A[i];
-            t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
-            t.queue = c.sc.t2_queue.as<uint32_t>();
-            t.words = ((uint64_t)c.g.n + 31) / 32;
-            t.list = A[i].defer2;
-            t.nlist = (uint32_t)nd3;
-            t.model = HBM_LT;
-            t.qcap = t2_qcap(c);
-            t.can_defer = 1;
-            t3.push_back(t);
-            t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));
-        }
-        if (!t3.empty()) {
+        // ---- tier 3: IC sets that outgrew the LDS tier and LT walks longer than the LDS path,
+        // a workgroup each with its visited bitmap and queue in device memory
+        for (int model : {HBM_IC, HBM_LT}) {
+            std::vector<T2Args> t3;
+            std::vector<uint32_t> t3b;
+            for (size_t i = 0; i < N; i++) {
+                Ctx &c = *J[i];
+                if (c.g.model != model) continue;
+                const uint64_t nd3 = root.ctrl_host[i * CW_COUNT + (model == HBM_IC ? CW_NDEFER2 : CW_NDEFER)];
+                if (!nd3) continue;
+                ensure_t2(c);
+                root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
+                T2Args t;
+                t.a = A[i];
+                t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
+                t.queue = c.sc.t2_queue.as<uint32_t>();
+                t.words = ((uint64_t)c.g.n + 31) / 32;
+                t.list = A[i].defer2;
+                t.nlist = (uint32_t)nd3;
+                t.model = model;
+                t.qcap = t2_qcap(c);
+                t.can_defer = 1;
+                t3.push_back(t);
+                t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));
+            }
+            if (t3.empty()) continue;
             ctrl_push(root);
-            int s4 = prof_begin(root, "lt_sample_block");
+            int s4 = prof_begin(root, model == HBM_IC ? "ic_sample_bitmap" : "lt_sample_block");
             glaunch(root, t3, t3b, 0, [&](const T2Args &t, unsigned g) { k_big<<<g, T2_THREADS, 0, st>>>(t); },
                     [&](const T2Args *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
                         k_big_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2Args>{d, b, cnt, x});
@@ -1048,7 +1205,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             HBM_HIP(hipGetLastError());
             prof_end(root, s4);
             ctrl_pull(root);
-            if (s4 >= 0) prof_sampler(root, s4, false, J);
+            if (s4 >= 0) prof_sampler(root, s4, model == HBM_IC, J);
         }
     }
     // ---- huge pass: sets that outgrew a big-set slot's queue, redone with a full queue

@@ -215,6 +215,7 @@ void hbm_server::admit_locked() {
             c.block_sets = root.block_sets;
             c.lt_lw = root.lt_lw;
             c.t2_queue = root.t2_queue;
+            c.t2_per_cu = root.t2_per_cu;
             c.t2_cap = int64_t(1) << 30;  // many queries share the device: fewer big-set slots each
             c.g = graph;
         }
@@ -359,6 +360,7 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     s->root.block_sets = g.block_sets;
     s->root.lt_lw = g.lt_lw;
     s->root.t2_queue = g.t2_queue;
+    s->root.t2_per_cu = g.t2_per_cu;
     if (hipStreamCreateWithFlags(&s->root.stream, hipStreamNonBlocking) != hipSuccess) {
         delete s;
         return HBM_EDEVICE;

@@ -182,8 +182,11 @@ def test_c1_tiny_ic_full(orc, ctx):
 
 
 @pytest.mark.parametrize("model,prob,scale,theta", [("IC", "WC", 14, 30_000), ("LT", "EDGE", 14, 30_000),
-                                                    ("IC", "EDGE", 11, 3_000)])
+                                                    ("IC", "EDGE", 11, 3_000), ("IC", "EDGE", 13, 1_500)])
 def test_sets_and_seeds_rmat(orc, ctx, model, prob, scale, theta):
+    """Exact RR sets and seeds; with a constant p = 0.25 most sets reach thousands of
+    vertices, so the workgroup tiers run: the LDS one and, past its 2048 members, the
+    device-bitmap one."""
     _say("rmat sets", model, prob, scale, theta)
     g = G.rmat(scale, seed=scale)
     if model == "LT":
