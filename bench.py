@@ -98,6 +98,83 @@ def csrc_digest():
     return h.hexdigest()[:16]
 
 
+# hbm_profile names -> the HIP kernels behind them (plain and grouped forms)
+PROFILE_KERNELS = {
+    "ic_sample_wave": "k_ic_t1", "ic_sample_block": "k_big_lds", "ic_sample_bitmap": "k_big",
+    "lt_sample_lane": "k_lt_t1", "lt_sample_wave": "k_lt_wave", "lt_sample_block": "k_big", "sample_huge": "k_big",
+    "hist_add": "k_hist_add", "cold_count": "k_cold_count", "split": "k_split", "huff_bits": "k_huff_bits",
+    "huff_write": "k_huff_write", "argmax": "k_argmax", "find_raw": "k_find_raw", "find_huff": "k_find_huff",
+    "apply": "k_apply", "dec_big": "k_dec_big", "dec_hot": "k_dec_hot",
+}
+COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
+
+
+def traffic_probe(args):
+    """The workload of the counter runs: one profiled-size IMM step of the chosen workload, then
+    a plain 1 GiB device copy whose counter readings calibrate FETCH_SIZE and WRITE_SIZE."""
+    import torch
+
+    import paper_2208_00613_amd as P
+    from synth import graphs as G
+
+    c = G.CONFIGS[WORKLOADS[args.workload]["cfg"]]
+    g = G.config_graph(WORKLOADS[args.workload]["cfg"])
+    ctx = P.Context(0)
+    ctx.load_synth(g, model=c["model"], prob=c["prob"])
+    ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
+    ctx.hbm_imm(c["k"], c["eps"], c["l"], c["seed"])
+    torch.cuda.synchronize()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("[traffic] probe done")
+    ctx.close()
+
+
+def traffic_summarize(fetch_csv, write_csv, out_path):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel from two rocprofv3 --pmc runs,
+    each scaled by the reading of the 1 GiB copy; writes HBM bytes per launch per profile name."""
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    # the 1 GiB copies are the largest dispatches of the runtime's copy kernel
+    copy = [k for k in fetch if re.search(r"copy", k, re.I) and "hbm::" not in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the counter run")
+    ck = max(copy, key=lambda k: max(fetch[k]))
+    f_scale, w_scale = COPY_BYTES / max(fetch[ck]), COPY_BYTES / max(write.get(ck, [COPY_BYTES]))
+    kernels = {}
+    mean = lambda v: sum(v) / len(v)
+    for prof, sym in PROFILE_KERNELS.items():
+        pat = re.compile(r"hbm::" + sym + r"(_g)?\b")
+        fs = [x for k, v in fetch.items() if pat.search(k) for x in v]
+        ws = [x for k, v in write.items() if pat.search(k) for x in v]
+        if fs:
+            kernels[prof] = mean(fs) * f_scale + (mean(ws) * w_scale if ws else 0.0)
+    cmds = ["cd /tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o f -- "
+            "python $GRAFT_REPO_ROOT/bench.py --traffic-probe",
+            "cd /tmp && rocprofv3 --pmc WRITE_SIZE -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o w -- "
+            "python $GRAFT_REPO_ROOT/bench.py --traffic-probe",
+            "python bench.py --traffic-summarize gpurun_out/pmc_fetch/f_counter_collection.csv "
+            "gpurun_out/pmc_write/w_counter_collection.csv"]
+    out = {"commands": cmds, "workload": "bench.py default workload, one IMM step",
+           "csrc_digest": csrc_digest(), "copy_kernel": ck[:80], "fetch_scale": f_scale, "write_scale": w_scale,
+           "unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "kernels": kernels}
+    json.dump(out, open(out_path, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def traffic_for(kernel):
     """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -345,9 +422,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain summary of the c2 line")
     ap.add_argument("--queries", type=int, default=24, help="c5: queries per load level")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the workload of the counter runs (one IMM, then a 1 GiB copy) and exit")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter files into profiles/traffic.json and exit")
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 1.0],
                     help="c5: arrival rates as fractions of the measured single-query service rate")
     args = ap.parse_args()
+    if args.traffic_summarize:
+        return traffic_summarize(*args.traffic_summarize, os.path.join(ROOT, "profiles", "traffic.json"))
+    if args.traffic_probe:
+        return traffic_probe(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
