@@ -251,6 +251,9 @@ def batched_vs_plain(P, torch, ctxs, insts, reps=1):
     """Whole-workload seconds of hbm_imm_batch vs one hbm_imm per instance, same GPU, same
     queries; the results must agree instance by instance."""
     qs = [(i["k"], i["eps"], i["l"], i["seed"]) for i in insts]
+    # launch shapes from the autotuner (applied to every context: both paths use them)
+    tuning, _ = P.imm_autotune(ctxs, qs)
+    log(f"[bench] autotuned: {tuning}")
     P.imm_batch(ctxs, qs)  # warm-up: allocations of both paths
     for c, q in zip(ctxs, qs):
         c.hbm_imm(*q)
@@ -269,7 +272,7 @@ def batched_vs_plain(P, torch, ctxs, insts, reps=1):
     sets = sum(o[2]["nsets_final"] for o in out)
     store = sum(o[2]["store"]["store_bytes"] for o in out)
     raw = sum(4 * o[2]["store"]["members"] + 8 * (o[2]["nsets_final"] + 1) for o in out)
-    return dict(instances=len(ctxs), batched_s=min(tb), plain_s=min(tp), speedup=min(tp) / min(tb),
+    return dict(instances=len(ctxs), tuning=tuning, batched_s=min(tb), plain_s=min(tp), speedup=min(tp) / min(tb),
                 identical_results=bool(same), rr_sets=sets, bytes_per_rr=store / max(sets, 1),
                 raw_bytes_per_rr=raw / max(sets, 1)), out
 

@@ -293,11 +293,23 @@ typedef enum hbm_tune_key {
                                      longer walks move to device memory */
     HBM_TUNE_T2_QUEUE = 4,        /* queue entries of a big-set slot (>= 64, default 2^20); a set with
                                      more members is redone by a few slots with full-size queues */
-    HBM_TUNE_T2_SLOTS = 5         /* big-set workgroups per CU, 1..4 (default 4), each with its own
+    HBM_TUNE_T2_SLOTS = 5,        /* big-set workgroups per CU, 1..4 (default 4), each with its own
                                      visited bitmap and queue */
+    HBM_TUNE_COUNT = 6
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);
+
+/* Autotuner: picks the launch shapes for the given instances (one, or many as
+ * hbm_imm_batch runs them) by timing whole IMM runs of the queries under candidate
+ * settings, one key at a time (coordinate descent over BLOCK_SETS, IC_T1_BUDGET,
+ * T2_SLOTS and LT_PATH), and leaves the fastest applied to every context.  The
+ * contexts' stores end up holding the probes' last run.  chosen int64[HBM_TUNE_COUNT]
+ * (may be NULL) receives every key's setting, best_ms (may be NULL) the time of the
+ * chosen one.  Results never depend on these settings.  Same argument rules as
+ * hbm_imm_batch; a failing probe query returns its error. */
+hbm_status hbm_autotune(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int64_t *chosen,
+                        double *best_ms);
 
 /* ---------------------------------------------------------------- profiling */
 

@@ -29,8 +29,9 @@ EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hb
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
             "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_set_hot_density", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
-            "hbm_server_poll", "hbm_server_get_stats"]
+            "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5}
+TUNE_COUNT = 6
 
 
 class HbmError(RuntimeError):
@@ -127,6 +128,7 @@ def lib():
         "hbm_server_submit": ([P, C.POINTER(Query), C.POINTER(I64)], C.c_int),
         "hbm_server_poll": ([P, I64, I32, P, P, C.POINTER(ImmStats), C.POINTER(ServeInfo)], C.c_int),
         "hbm_server_get_stats": ([P, C.POINTER(ServerStats)], C.c_int),
+        "hbm_autotune": ([P, I32, C.POINTER(Query), P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -308,6 +310,22 @@ def imm_batch(contexts, queries):
         msg = L.hbm_last_error(contexts[i].h)
         raise HbmError(st, f"instance {i}: " + (msg.decode() if msg else ""))
     return [(seeds[i], gains[i], stats[i].as_dict()) for i in range(n)]
+
+
+def imm_autotune(contexts, queries):
+    """hbm_autotune over Context objects and (k, eps, l, seed) queries: the chosen launch shapes
+    (left applied to every context) and the probe time of the chosen setting."""
+    L = lib()
+    n = len(contexts)
+    hs = (C.c_void_p * n)(*[c.h for c in contexts])
+    q = (Query * n)(*[Query(int(k), float(e), float(l), int(sd)) for (k, e, l, sd) in queries])
+    chosen = np.zeros(TUNE_COUNT, dtype=np.int64)
+    best = C.c_double()
+    st = L.hbm_autotune(hs, n, q, _ptr(chosen), C.byref(best))
+    if st != HBM_OK:
+        msg = L.hbm_last_error(contexts[0].h)
+        raise HbmError(st, msg.decode() if msg else "")
+    return {k: int(chosen[v]) for k, v in TUNE.items()}, best.value
 
 
 class Server:

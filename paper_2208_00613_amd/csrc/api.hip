@@ -153,49 +153,74 @@ hbm_status hbm_imm(hbm_ctx *ctx, int32_t k, double eps, double l, uint64_t seed,
     });
 }
 
-hbm_status hbm_imm_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int32_t *const *seeds,
-                         uint64_t *const *gains, hbm_imm_stats *stats, hbm_status *status) {
-    if (!ctxs || count < 1 || !queries || !seeds) return HBM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the batched calls: distinct contexts on one device.
+bool batch_ok(hbm_ctx *const *ctxs, int32_t count) {
+    if (!ctxs || count < 1) return false;
     for (int32_t i = 0; i < count; i++) {
-        if (!ctxs[i] || !seeds[i]) return HBM_EINVAL;
+        if (!ctxs[i]) return false;
         for (int32_t j = 0; j < i; j++)
-            if (ctxs[j] == ctxs[i]) return HBM_EINVAL;
-        if (ctxs[i]->c.device != ctxs[0]->c.device) return HBM_EINVAL;
+            if (ctxs[j] == ctxs[i]) return false;
+        if (ctxs[i]->c.device != ctxs[0]->c.device) return false;
     }
-    hbm_ctx *root = ctxs[0];
+    return true;
+}
+
+// IMM for every instance at once on ctxs[0]'s stream (ordered after each context's own
+// stream), leaving the jobs' outcomes in J.  Device errors throw.
+void run_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, std::vector<hbm::ImmJob> &J) {
+    Ctx &r = ctxs[0]->c;
     std::vector<hipStream_t> own((size_t)count);
-    std::vector<hbm::ImmJob> J((size_t)count);
-    bool streams_swapped = false;
-    const hbm_status rc = guard(root, [&](Ctx &r) {
-        // every instance's work goes on the first context's stream for the call
-        hipEvent_t ev;
-        HBM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        for (int32_t i = 0; i < count; i++) {
-            Ctx &c = ctxs[i]->c;
-            own[(size_t)i] = c.stream;
-            if (c.stream != r.stream) {
-                HBM_HIP(hipEventRecord(ev, c.stream));
-                HBM_HIP(hipStreamWaitEvent(r.stream, ev, 0));
-            }
+    hipEvent_t ev;
+    HBM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    for (int32_t i = 0; i < count; i++) {
+        Ctx &c = ctxs[i]->c;
+        own[(size_t)i] = c.stream;
+        if (c.stream != r.stream) {
+            HBM_HIP(hipEventRecord(ev, c.stream));
+            HBM_HIP(hipStreamWaitEvent(r.stream, ev, 0));
         }
-        (void)hipEventDestroy(ev);
-        for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = r.stream;
-        streams_swapped = true;
-        std::vector<hbm::ImmJob *> jp;
-        for (int32_t i = 0; i < count; i++) {
-            hbm::ImmJob &j = J[(size_t)i];
-            j.c = &ctxs[i]->c;
-            j.k = queries[i].k;
-            j.eps = queries[i].eps;
-            j.l = queries[i].l;
-            j.seed = queries[i].seed;
-            jp.push_back(&j);
-        }
+    }
+    (void)hipEventDestroy(ev);
+    for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = r.stream;
+    J.assign((size_t)count, hbm::ImmJob{});
+    std::vector<hbm::ImmJob *> jp;
+    for (int32_t i = 0; i < count; i++) {
+        hbm::ImmJob &j = J[(size_t)i];
+        j.c = &ctxs[i]->c;
+        j.k = queries[i].k;
+        j.eps = queries[i].eps;
+        j.l = queries[i].l;
+        j.seed = queries[i].seed;
+        jp.push_back(&j);
+    }
+    try {
         hbm::imm_run(r, jp);
         HBM_HIP(hipStreamSynchronize(r.stream));
-    });
-    if (streams_swapped)
+    } catch (...) {
         for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = own[(size_t)i];
+        throw;
+    }
+    for (int32_t i = 0; i < count; i++) ctxs[i]->c.stream = own[(size_t)i];
+}
+
+void set_tuning(Ctx &c, hbm_tune_key key, int64_t value);
+int64_t get_tuning(const Ctx &c, hbm_tune_key key);
+
+}  // namespace
+
+extern "C" {
+
+hbm_status hbm_imm_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int32_t *const *seeds,
+                         uint64_t *const *gains, hbm_imm_stats *stats, hbm_status *status) {
+    if (!batch_ok(ctxs, count) || !queries || !seeds) return HBM_EINVAL;
+    for (int32_t i = 0; i < count; i++)
+        if (!seeds[i]) return HBM_EINVAL;
+    std::vector<hbm::ImmJob> J;
+    const hbm_status rc = guard(ctxs[0], [&](Ctx &) { run_batch(ctxs, count, queries, J); });
     if (rc != HBM_OK) {
         if (status)
             for (int32_t i = 0; i < count; i++) status[i] = rc;
@@ -218,48 +243,63 @@ hbm_status hbm_imm_batch(hbm_ctx *const *ctxs, int32_t count, const hbm_query *q
     return first;
 }
 
-hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
-    return guard(ctx, [&](Ctx &c) {
-        switch (key) {
-            case HBM_TUNE_IC_TIER1:
-                HBM_REQUIRE(value == 0 || value == 1, HBM_EINVAL, "IC_TIER1 must be 0 or 1");
-                c.ic_tier1 = (int)value;
-                break;
-            case HBM_TUNE_IC_T1_BUDGET:
-                HBM_REQUIRE(value >= 0, HBM_EINVAL, "IC_T1_BUDGET must be >= 0");
-                c.ic_t1_budget = value;
-                break;
-            case HBM_TUNE_LT_PATH:
-                HBM_REQUIRE(value == 128 || value == 256, HBM_EINVAL, "LT_PATH must be 128 or 256");
-                c.lt_lw = (int)value;
-                break;
-            case HBM_TUNE_T2_QUEUE:
-                HBM_REQUIRE(value >= 64 && value <= (int64_t(1) << 31), HBM_EINVAL, "T2_QUEUE out of range");
-                if (value != c.t2_queue) {
-                    c.t2_queue = value;
-                    // reallocated at the next use with the new queue size
-                    hbm::buf_free(c, c.sc.t2_bitmap);
-                    hbm::buf_free(c, c.sc.t2_queue);
-                    c.sc.t2_slots = 0;
-                }
-                break;
-            case HBM_TUNE_T2_SLOTS:
-                HBM_REQUIRE(value >= 1 && value <= 4, HBM_EINVAL, "T2_SLOTS must be in [1, 4]");
-                if (value != c.t2_per_cu) {
-                    c.t2_per_cu = (int)value;
-                    hbm::buf_free(c, c.sc.t2_bitmap);
-                    hbm::buf_free(c, c.sc.t2_queue);
-                    c.sc.t2_slots = 0;
-                }
-                break;
-            case HBM_TUNE_BLOCK_SETS:
-                HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
-                c.block_sets = value;
-                break;
-            default:
-                throw Error{HBM_EINVAL, "unknown tuning key"};
+hbm_status hbm_autotune(hbm_ctx *const *ctxs, int32_t count, const hbm_query *queries, int64_t *chosen,
+                        double *best_ms) {
+    if (!batch_ok(ctxs, count) || !queries) return HBM_EINVAL;
+    return guard(ctxs[0], [&](Ctx &r) {
+        bool ic = false, lt = false;
+        for (int32_t i = 0; i < count; i++) {
+            HBM_REQUIRE(ctxs[i]->c.g.loaded, HBM_ESTATE, "no graph loaded");
+            (ctxs[i]->c.g.model == HBM_IC ? ic : lt) = true;
         }
+        auto apply = [&](hbm_tune_key key, int64_t v) {
+            for (int32_t i = 0; i < count; i++) set_tuning(ctxs[i]->c, key, v);
+        };
+        std::vector<hbm::ImmJob> J;
+        auto timed = [&]() {
+            const auto t0 = std::chrono::steady_clock::now();
+            run_batch(ctxs, count, queries, J);
+            for (const hbm::ImmJob &j : J)
+                if (j.phase != hbm::ImmJob::DONE) throw Error{j.status, "autotune probe: " + j.error};
+            return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        };
+        struct Axis {
+            hbm_tune_key key;
+            std::vector<int64_t> values;
+            bool used;
+        };
+        const std::vector<Axis> axes = {
+            {HBM_TUNE_BLOCK_SETS, {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 21}, true},
+            {HBM_TUNE_IC_T1_BUDGET, {1024, 4096, 16384}, ic},
+            {HBM_TUNE_T2_SLOTS, {2, 3, 4}, true},
+            {HBM_TUNE_LT_PATH, {128, 256}, lt},
+        };
+        timed();  // warm-up: allocations at the current settings
+        double best = timed();
+        // coordinate descent, one key at a time, keeping the best value of each
+        for (const Axis &ax : axes) {
+            if (!ax.used) continue;
+            int64_t keep = get_tuning(r, ax.key);
+            for (int64_t v : ax.values) {
+                if (v == keep) continue;
+                apply(ax.key, v);
+                timed();  // the first run at a new shape may allocate
+                const double ms = timed();
+                if (ms < best) {
+                    best = ms;
+                    keep = v;
+                }
+            }
+            apply(ax.key, keep);
+        }
+        if (chosen)
+            for (int k = 0; k < HBM_TUNE_COUNT; k++) chosen[k] = get_tuning(r, (hbm_tune_key)k);
+        if (best_ms) *best_ms = best;
     });
+}
+
+hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value) {
+    return guard(ctx, [&](Ctx &c) { set_tuning(c, key, value); });
 }
 
 hbm_status hbm_profile(hbm_ctx *ctx, int32_t enable) {
@@ -362,3 +402,61 @@ hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_
 }
 
 }  // extern "C"
+
+namespace {
+
+void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
+    switch (key) {
+        case HBM_TUNE_IC_TIER1:
+            HBM_REQUIRE(value == 0 || value == 1, HBM_EINVAL, "IC_TIER1 must be 0 or 1");
+            c.ic_tier1 = (int)value;
+            break;
+        case HBM_TUNE_IC_T1_BUDGET:
+            HBM_REQUIRE(value >= 0, HBM_EINVAL, "IC_T1_BUDGET must be >= 0");
+            c.ic_t1_budget = value;
+            break;
+        case HBM_TUNE_LT_PATH:
+            HBM_REQUIRE(value == 128 || value == 256, HBM_EINVAL, "LT_PATH must be 128 or 256");
+            c.lt_lw = (int)value;
+            break;
+        case HBM_TUNE_T2_QUEUE:
+            HBM_REQUIRE(value >= 64 && value <= (int64_t(1) << 31), HBM_EINVAL, "T2_QUEUE out of range");
+            if (value != c.t2_queue) {
+                c.t2_queue = value;
+                // reallocated at the next use with the new queue size
+                hbm::buf_free(c, c.sc.t2_bitmap);
+                hbm::buf_free(c, c.sc.t2_queue);
+                c.sc.t2_slots = 0;
+            }
+            break;
+        case HBM_TUNE_T2_SLOTS:
+            HBM_REQUIRE(value >= 1 && value <= 4, HBM_EINVAL, "T2_SLOTS must be in [1, 4]");
+            if (value != c.t2_per_cu) {
+                c.t2_per_cu = (int)value;
+                hbm::buf_free(c, c.sc.t2_bitmap);
+                hbm::buf_free(c, c.sc.t2_queue);
+                c.sc.t2_slots = 0;
+            }
+            break;
+        case HBM_TUNE_BLOCK_SETS:
+            HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
+            c.block_sets = value;
+            break;
+        default:
+            throw Error{HBM_EINVAL, "unknown tuning key"};
+    }
+}
+
+int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
+    switch (key) {
+        case HBM_TUNE_IC_TIER1: return c.ic_tier1;
+        case HBM_TUNE_IC_T1_BUDGET: return c.ic_t1_budget;
+        case HBM_TUNE_BLOCK_SETS: return c.block_sets;
+        case HBM_TUNE_LT_PATH: return c.lt_lw;
+        case HBM_TUNE_T2_QUEUE: return c.t2_queue;
+        case HBM_TUNE_T2_SLOTS: return c.t2_per_cu;
+        default: return -1;
+    }
+}
+
+}  // namespace

@@ -48,6 +48,12 @@ bool imm_sampling(const ImmJob &J);
 // its target (cap[i] >= 0 bounds its sets in this step; cap[i] == 0 skips it; empty: no bound),
 // then one batched selection for every job whose target is met.  Device errors throw.
 void imm_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<int64_t> &cap);
+// The two halves of a step, for drivers that run them on different streams: sampling blocks
+// (jobs that meet their target move to their selection phase), and the batched selection of
+// every job in a selection phase (which then moves on: next round, final round or DONE).
+void imm_sample_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<int64_t> &cap);
+void imm_select_step(Ctx &root, const std::vector<ImmJob *> &jobs);
+bool imm_selecting(const ImmJob &J);
 // imm_start every job, then step until each is DONE or FAILED.
 void imm_run(Ctx &root, const std::vector<ImmJob *> &jobs);
 

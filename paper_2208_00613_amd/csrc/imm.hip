@@ -120,14 +120,17 @@ static void selected(ImmJob &J, std::vector<int32_t> &&s, std::vector<uint64_t> 
 
 bool imm_sampling(const ImmJob &J) { return J.phase == ImmJob::EST_SAMPLE || J.phase == ImmJob::FIN_SAMPLE; }
 
-void imm_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<int64_t> &cap) {
-    // targets already met (the final round may need no new sets)
-    auto promote = [&]() {
-        for (ImmJob *J : jobs)
-            if (imm_sampling(*J) && J->c->s.nsets >= J->target)
-                J->phase = J->phase == ImmJob::EST_SAMPLE ? ImmJob::EST_SELECT : ImmJob::FIN_SELECT;
-    };
-    promote();
+// Jobs whose sampling target is met move on to their selection.
+static void promote(const std::vector<ImmJob *> &jobs) {
+    for (ImmJob *J : jobs)
+        if (imm_sampling(*J) && J->c->s.nsets >= J->target)
+            J->phase = J->phase == ImmJob::EST_SAMPLE ? ImmJob::EST_SELECT : ImmJob::FIN_SELECT;
+}
+
+bool imm_selecting(const ImmJob &J) { return J.phase == ImmJob::EST_SELECT || J.phase == ImmJob::FIN_SELECT; }
+
+void imm_sample_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<int64_t> &cap) {
+    promote(jobs);
     std::vector<Ctx *> sc;
     std::vector<int64_t> th, cp;
     std::vector<uint64_t> sd;
@@ -149,23 +152,30 @@ void imm_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<in
             if (st[q] != HBM_OK)
                 fail(*sj[q], st[q], "store budget exceeded at " + std::to_string(sj[q]->c->s.nsets) + " sets");
     }
-    promote();
+    promote(jobs);
+}
+
+void imm_select_step(Ctx &root, const std::vector<ImmJob *> &jobs) {
     std::vector<Ctx *> lc;
     std::vector<int32_t> lk;
     std::vector<ImmJob *> lj;
     for (ImmJob *J : jobs)
-        if (J->phase == ImmJob::EST_SELECT || J->phase == ImmJob::FIN_SELECT) {
+        if (imm_selecting(*J)) {
             lj.push_back(J);
             lc.push_back(J->c);
             lk.push_back(J->k);
         }
-    if (!lc.empty()) {
-        std::vector<std::vector<int32_t>> s;
-        std::vector<std::vector<uint64_t>> g;
-        std::vector<uint64_t> cov;
-        select_batch(root, lc, lk, s, g, cov);
-        for (size_t q = 0; q < lj.size(); q++) selected(*lj[q], std::move(s[q]), std::move(g[q]), cov[q]);
-    }
+    if (lc.empty()) return;
+    std::vector<std::vector<int32_t>> s;
+    std::vector<std::vector<uint64_t>> g;
+    std::vector<uint64_t> cov;
+    select_batch(root, lc, lk, s, g, cov);
+    for (size_t q = 0; q < lj.size(); q++) selected(*lj[q], std::move(s[q]), std::move(g[q]), cov[q]);
+}
+
+void imm_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::vector<int64_t> &cap) {
+    imm_sample_step(root, jobs, cap);
+    imm_select_step(root, jobs);
 }
 
 void imm_run(Ctx &root, const std::vector<ImmJob *> &jobs) {

@@ -1,11 +1,13 @@
 // serve.hip -- the serving loop: IMM queries against one device-resident graph with
 // continuous batching under a budget for RR stores.
 //
-// A worker thread owns the device work.  Each iteration it admits queued queries while
-// slots and store memory allow, then runs one IMM step over every admitted query at once
-// (one sampling block each for the queries short of their target, one batched selection
-// for the queries that reached it).  A query that arrives while others run joins at the
-// next step; a finished query frees its slot and its store at once.
+// Two worker threads own the device work, each on a stream of its own, so sampling and
+// selection of different queries overlap.  The sampler admits queued queries while slots
+// and store memory allow, then runs one sampling block for every admitted query short of
+// its target, all in shared launches; a query that reaches its target passes to the
+// selector, which runs one batched greedy selection over every query handed to it and
+// passes each back (next round) or finishes it.  A query that arrives while others run
+// joins at the sampler's next step; a finished query frees its slot and store at once.
 //
 // Budget: the sum of the admitted queries' store bytes (index + payload + bitmap rows, as
 // reported in hbm_store_stats) stays within the budget.  A sampling block is bounded by
@@ -55,6 +57,7 @@ struct Slot {
     double t_admit = 0;
     int64_t order = 0;  // admission sequence number
     bool busy = false;
+    bool selecting = false;  // owned by the selector thread (else by the sampler)
 };
 
 // The store buffers of a finished query go back to the device; its sampling arena stays
@@ -73,7 +76,8 @@ void release_store(Ctx &c) {
 using hbm::Ctx;
 
 struct hbm_server {
-    Ctx root;  // stream, launch descriptors and scan space of the batched steps
+    Ctx root;   // the sampler's stream, launch descriptors and scan space
+    Ctx rootL;  // the selector's
     int64_t budget = 0;
     int32_t max_active = 1;
     int enc = HBM_ENC_NONE;
@@ -82,7 +86,9 @@ struct hbm_server {
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
-    std::condition_variable cv;       // work arrived, or stop
+    std::condition_variable cv;       // sampler: an event (arrival, hand-back, completion) or stop
+    std::condition_variable cvL;      // selector: a query handed over, or stop
+    uint64_t events = 0;              // counts the sampler's wake-up events
     std::condition_variable cv_done;  // a query finished
     std::deque<hbm::Ticket> queue;
     std::map<int64_t, hbm::Result> results;
@@ -98,7 +104,7 @@ struct hbm_server {
     double bps_mean = 0;                            // store bytes per set of finished queries
     int64_t bps_n = 0;
     bool hold = false;  // no admissions between a preemption and the next completion
-    std::thread worker;
+    std::thread worker, worker_sel;
 
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -109,8 +115,9 @@ struct hbm_server {
         return bps_n ? bps_mean : 64.0;
     }
     void loop();
+    void loop_select();
     void admit_locked();
-    void step();
+    bool step(std::vector<hbm::Slot *> live);
     void finish_locked(hbm::Slot &s);
     void preempt_locked(hbm::Slot &s);
     void fail_all_locked(hbm_status st, const std::string &msg);
@@ -139,13 +146,17 @@ void hbm_server::finish_locked(hbm::Slot &s) {
     }
     hbm::release_store(*s.c);
     s.busy = false;
+    s.selecting = false;
     active--;
     hold = false;
+    events++;
+    cv.notify_all();
     cv_done.notify_all();
 }
 
 void hbm_server::fail_all_locked(hbm_status st, const std::string &msg) {
     broken = true;
+    stop = true;
     error = msg;
     for (auto &sp : slots)
         if (sp->busy) {
@@ -172,6 +183,8 @@ void hbm_server::fail_all_locked(hbm_status st, const std::string &msg) {
         stats.failed++;
     }
     queue.clear();
+    cv.notify_all();
+    cvL.notify_all();
     cv_done.notify_all();
 }
 
@@ -184,7 +197,9 @@ void hbm_server::admit_locked() {
             const hbm::Ctx &c = *sp->c;
             // a query still short of its first round holds a reservation for it
             const double have = (double)hbm::store_bytes(c);
-            const double need = sp->job.st.rounds == 0 ? (double)sp->job.target * est_bps(*sp) : 0.0;
+            // (the selector's queries are not read: their job state is the selector's)
+            const double need =
+                !sp->selecting && sp->job.st.rounds == 0 ? (double)sp->job.target * est_bps(*sp) : 0.0;
             used += std::max(have, need);
         }
     while (!queue.empty() && active < max_active && !(hold && active > 0)) {
@@ -229,6 +244,8 @@ void hbm_server::admit_locked() {
         s->t_admit = now_ms();
         s->order = next_order++;
         s->busy = true;
+        s->selecting = false;
+        c.stream = root.stream;
         active++;
         stats.admitted++;
         hbm::ImmJob &J = s->job;
@@ -248,63 +265,77 @@ void hbm_server::admit_locked() {
     }
 }
 
-void hbm_server::step() {
-    std::vector<hbm::Slot *> live;
-    for (auto &sp : slots)
-        if (sp->busy) live.push_back(sp.get());
+// One sampling step over the sampler's queries (oldest first).  Returns whether anything
+// moved; if nothing could, the caller waits for the selector or a completion.
+bool hbm_server::step(std::vector<hbm::Slot *> live) {
     std::sort(live.begin(), live.end(), [](const hbm::Slot *a, const hbm::Slot *b) { return a->order < b->order; });
-    if (live.empty()) return;
-    // sampling caps, oldest query first
-    double used = 0;
-    for (hbm::Slot *s : live) used += (double)hbm::store_bytes(*s->c);
-    double room = (double)budget - used;
     std::vector<int64_t> cap(live.size(), -1);
-    bool moves = false;
-    for (size_t i = 0; i < live.size(); i++) {
-        hbm::ImmJob &J = live[i]->job;
-        const Ctx &c = *live[i]->c;
-        if (!hbm::imm_sampling(J) || c.s.nsets >= J.target) {
-            moves = true;  // ready to select (or finished)
-            continue;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        // sampling caps from the room the budget leaves over every admitted store
+        double used = 0;
+        bool selector_busy = false;
+        for (auto &sp : slots)
+            if (sp->busy) {
+                used += (double)hbm::store_bytes(*sp->c);
+                selector_busy |= sp->selecting;
+            }
+        double room = (double)budget - used;
+        bool moves = false;
+        for (size_t i = 0; i < live.size(); i++) {
+            hbm::ImmJob &J = live[i]->job;
+            const Ctx &c = *live[i]->c;
+            if (!hbm::imm_sampling(J) || c.s.nsets >= J.target) {
+                moves = true;  // ready to select
+                continue;
+            }
+            if (c.s.enc != HBM_ENC_NONE && !c.s.model_ready) {
+                moves = true;  // warm-up blocks only count frequencies
+                continue;
+            }
+            const int64_t want = std::min<int64_t>(J.target - c.s.nsets, root.block_sets);
+            const double bps = est_bps(*live[i]);
+            const int64_t allow = room > 0 ? (int64_t)std::min(room / bps, 9.0e18) : 0;
+            int64_t cp = std::min(want, allow);
+            if (cp < std::min<int64_t>(want, 4096)) cp = 0;  // wait for room rather than crawl
+            cap[i] = cp;
+            room -= (double)cp * bps;
+            moves |= cp > 0;
         }
-        if (c.s.enc != HBM_ENC_NONE && !c.s.model_ready) {
-            moves = true;  // warm-up blocks only count frequencies
-            continue;
+        if (!moves) {
+            if (selector_busy) return false;  // its queries will finish or hand back room
+            if (live.size() > 1) {
+                preempt_locked(*live.back());  // the youngest restarts later with the same result
+                return true;
+            }
+            cap[0] = -1;  // alone: the context budget decides (HBM_EBUDGET if it cannot fit)
         }
-        const int64_t want = std::min<int64_t>(J.target - c.s.nsets, root.block_sets);
-        const double bps = est_bps(*live[i]);
-        const int64_t allow = room > 0 ? (int64_t)std::min(room / bps, 9.0e18) : 0;
-        int64_t cp = std::min(want, allow);
-        if (cp < std::min<int64_t>(want, 4096)) cp = 0;  // wait for room rather than crawl
-        cap[i] = cp;
-        room -= (double)cp * bps;
-        moves |= cp > 0;
-    }
-    if (!moves) {
-        if (live.size() > 1) {
-            std::lock_guard<std::mutex> lk(mu);
-            preempt_locked(*live.back());  // the youngest restarts later with the same result
-            return;
-        }
-        cap[0] = -1;  // alone: the context budget decides (HBM_EBUDGET if it cannot fit)
     }
     std::vector<hbm::ImmJob *> jobs;
     for (hbm::Slot *s : live) jobs.push_back(&s->job);
-    hbm::imm_step(root, jobs, cap);
+    hbm::imm_sample_step(root, jobs, cap);
     std::lock_guard<std::mutex> lk(mu);
     stats.steps++;
-    for (hbm::Slot *s : live)
-        if (s->job.phase == hbm::ImmJob::DONE || s->job.phase == hbm::ImmJob::FAILED) finish_locked(*s);
-    // a block priced too low may overshoot: the youngest queries give their room back
+    for (hbm::Slot *s : live) {
+        if (s->job.phase == hbm::ImmJob::FAILED) {
+            finish_locked(*s);
+        } else if (hbm::imm_selecting(s->job)) {
+            s->selecting = true;  // hand over: the selector runs on its own stream
+            s->c->stream = rootL.stream;
+            cvL.notify_all();
+        }
+    }
+    // a block priced too low may overshoot: the youngest sampling queries give their room back
     int64_t bytes = 0;
-    for (hbm::Slot *s : live)
-        if (s->busy) bytes += hbm::store_bytes(*s->c);
+    for (auto &sp : slots)
+        if (sp->busy) bytes += hbm::store_bytes(*sp->c);
     for (size_t i = live.size(); i-- > 0 && bytes > budget;) {
-        if (!live[i]->busy || active <= 1) continue;
+        if (!live[i]->busy || live[i]->selecting || active <= 1) continue;
         bytes -= hbm::store_bytes(*live[i]->c);
         preempt_locked(*live[i]);
     }
     stats.peak_store_bytes = std::max<int64_t>(stats.peak_store_bytes, bytes);
+    return true;
 }
 
 void hbm_server::preempt_locked(hbm::Slot &y) {
@@ -316,20 +347,36 @@ void hbm_server::preempt_locked(hbm::Slot &y) {
     active--;
     hold = true;
     stats.preemptions++;
+    events++;
 }
 
 void hbm_server::loop() {
     (void)hipSetDevice(root.device);
+    uint64_t seen = ~0ull;
+    bool progressed = true;
     for (;;) {
+        std::vector<hbm::Slot *> live;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return stop || !queue.empty() || active > 0; });
+            cv.wait(lk, [&] {
+                if (stop || events != seen) return true;
+                if (!progressed) return false;
+                for (auto &sp : slots)
+                    if (sp->busy && !sp->selecting) return true;
+                return false;
+            });
             if (stop) break;
+            seen = events;
             admit_locked();
-            if (active == 0) continue;
+            for (auto &sp : slots)
+                if (sp->busy && !sp->selecting) live.push_back(sp.get());
+        }
+        if (live.empty()) {
+            progressed = false;
+            continue;
         }
         try {
-            step();
+            progressed = step(live);
         } catch (const hbm::Error &e) {
             std::lock_guard<std::mutex> lk(mu);
             fail_all_locked(e.st, e.msg);
@@ -339,6 +386,50 @@ void hbm_server::loop() {
             fail_all_locked(HBM_EDEVICE, e.what());
             break;
         }
+    }
+}
+
+void hbm_server::loop_select() {
+    (void)hipSetDevice(rootL.device);
+    for (;;) {
+        std::vector<hbm::Slot *> live;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cvL.wait(lk, [&] {
+                if (stop) return true;
+                for (auto &sp : slots)
+                    if (sp->busy && sp->selecting) return true;
+                return false;
+            });
+            if (stop) break;
+            for (auto &sp : slots)
+                if (sp->busy && sp->selecting) live.push_back(sp.get());
+        }
+        try {
+            std::vector<hbm::ImmJob *> jobs;
+            for (hbm::Slot *s : live) jobs.push_back(&s->job);
+            hbm::imm_select_step(rootL, jobs);
+        } catch (const hbm::Error &e) {
+            std::lock_guard<std::mutex> lk(mu);
+            fail_all_locked(e.st, e.msg);
+            break;
+        } catch (const std::exception &e) {
+            std::lock_guard<std::mutex> lk(mu);
+            fail_all_locked(HBM_EDEVICE, e.what());
+            break;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        stats.steps++;
+        for (hbm::Slot *s : live) {
+            if (s->job.phase == hbm::ImmJob::DONE || s->job.phase == hbm::ImmJob::FAILED) {
+                finish_locked(*s);
+            } else {
+                s->selecting = false;  // hand back to the sampler for the next round
+                s->c->stream = root.stream;
+            }
+        }
+        events++;
+        cv.notify_all();
     }
 }
 
@@ -365,6 +456,13 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
         delete s;
         return HBM_EDEVICE;
     }
+    s->rootL.device = g.device;
+    s->rootL.num_cus = g.num_cus;
+    if (hipStreamCreateWithFlags(&s->rootL.stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->root.stream);
+        delete s;
+        return HBM_EDEVICE;
+    }
     s->budget = store_budget;
     s->max_active = max_active;
     s->enc = g.s.enc;
@@ -376,8 +474,17 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     s->t0 = std::chrono::steady_clock::now();
     try {
         s->worker = std::thread([s] { s->loop(); });
+        s->worker_sel = std::thread([s] { s->loop_select(); });
     } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv.notify_all();
+        s->cvL.notify_all();
+        if (s->worker.joinable()) s->worker.join();
         (void)hipStreamDestroy(s->root.stream);
+        (void)hipStreamDestroy(s->rootL.stream);
         delete s;
         return HBM_ENOMEM;
     }
@@ -392,9 +499,12 @@ void hbm_server_destroy(hbm_server *s) {
         s->stop = true;
     }
     s->cv.notify_all();
+    s->cvL.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->worker_sel.joinable()) s->worker_sel.join();
     (void)hipSetDevice(s->root.device);
     (void)hipStreamSynchronize(s->root.stream);
+    (void)hipStreamSynchronize(s->rootL.stream);
     for (auto &sp : s->slots) {
         Ctx &c = *sp->c;
         try {
@@ -410,9 +520,13 @@ void hbm_server_destroy(hbm_server *s) {
                             &s->root.dctr})
             hbm::buf_free(s->root, *b);
         hbm::stage_free(s->root);
+        for (hbm::Buf *b : {&s->rootL.scan_tmp, &s->rootL.ctrl_arena, &s->rootL.tails, &s->rootL.bkeys, &s->rootL.dctr})
+            hbm::buf_free(s->rootL, *b);
+        hbm::stage_free(s->rootL);
     } catch (...) {
     }
     (void)hipStreamDestroy(s->root.stream);
+    (void)hipStreamDestroy(s->rootL.stream);
     delete s;
 }
 
@@ -431,6 +545,7 @@ hbm_status hbm_server_submit(hbm_server *s, const hbm_query *q, int64_t *ticket)
     s->results[t.id].t_submit = t.t_submit;
     s->stats.submitted++;
     *ticket = t.id;
+    s->events++;
     s->cv.notify_all();
     return HBM_OK;
 }

@@ -124,3 +124,23 @@ def test_batch_instance_errors_are_isolated(P):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_autotune_picks_valid_shapes_and_keeps_results(P):
+    insts = _small_mix(6, 9, 11, seed=8)
+    _say("autotune over", len(insts), "instances")
+    ctxs, _ = _contexts(P, insts)
+    try:
+        qs = [(i["k"], i["eps"], i["l"], i["seed"]) for i in insts]
+        before = P.imm_batch(ctxs, qs)
+        tuning, best_ms = P.imm_autotune(ctxs, qs)
+        _say("chosen", tuning, "ms", round(best_ms, 2))
+        assert tuning["BLOCK_SETS"] in (1 << 16, 1 << 18, 1 << 21)
+        assert tuning["IC_T1_BUDGET"] in (1024, 4096, 16384) and tuning["T2_SLOTS"] in (2, 3, 4)
+        assert tuning["LT_PATH"] in (128, 256) and best_ms > 0
+        after = P.imm_batch(ctxs, qs)
+        for (s0, g0, _), (s1, g1, _) in zip(before, after):
+            assert np.array_equal(s0, s1) and np.array_equal(g0, g1)
+    finally:
+        for c in ctxs:
+            c.close()
