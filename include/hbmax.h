@@ -295,7 +295,10 @@ typedef enum hbm_tune_key {
                                      more members is redone by a few slots with full-size queues */
     HBM_TUNE_T2_SLOTS = 5,        /* big-set workgroups per CU, 1..4 (default 4), each with its own
                                      visited bitmap and queue */
-    HBM_TUNE_COUNT = 6
+    HBM_TUNE_LDS_THREADS = 6,     /* threads of a workgroup of the LDS tier (IC sets past the wave
+                                     budget, visited set and queue in LDS): 512 (default) or 1024 */
+    HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4 (default 3) */
+    HBM_TUNE_COUNT = 8
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

@@ -438,6 +438,14 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
                 c.sc.t2_slots = 0;
             }
             break;
+        case HBM_TUNE_LDS_THREADS:
+            HBM_REQUIRE(value == 512 || value == 1024, HBM_EINVAL, "LDS_THREADS must be 512 or 1024");
+            c.lds_threads = (int)value;
+            break;
+        case HBM_TUNE_LDS_PER_CU:
+            HBM_REQUIRE(value >= 1 && value <= 4, HBM_EINVAL, "LDS_PER_CU must be in [1, 4]");
+            c.lds_per_cu = (int)value;
+            break;
         case HBM_TUNE_BLOCK_SETS:
             HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
             c.block_sets = value;
@@ -455,6 +463,8 @@ int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
         case HBM_TUNE_LT_PATH: return c.lt_lw;
         case HBM_TUNE_T2_QUEUE: return c.t2_queue;
         case HBM_TUNE_T2_SLOTS: return c.t2_per_cu;
+        case HBM_TUNE_LDS_THREADS: return c.lds_threads;
+        case HBM_TUNE_LDS_PER_CU: return c.lds_per_cu;
         default: return -1;
     }
 }

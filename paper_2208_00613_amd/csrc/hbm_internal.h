@@ -110,6 +110,7 @@ struct Store {
     Buf bitoff;    // int64[nsets+1]
     Buf payload;   // uint32[]
     Buf ckb;       // uint8 per CK_SLOT payload bits: code-boundary slots
+    Buf mtmp;      // model building: warm-up symbol lists and their uploads
     uint64_t nbits = 0;
     int64_t escapes = 0;
     double skew = 0.0, density = 0.0;
@@ -201,6 +202,8 @@ struct Ctx {
     int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
     int64_t t2_queue = int64_t(1) << 20; // queue entries of a big-set slot
     int t2_per_cu = 4;                   // big-set slots (workgroups) per CU
+    int lds_threads = 512;               // threads of an LDS-tier workgroup (512 or 1024)
+    int lds_per_cu = 3;                  // LDS-tier workgroups launched per CU
     DGraph g;
     Store s;
     Scratch sc;

@@ -565,12 +565,12 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
     if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
 }
 
-// IC sets with few members but heavy expansions (hubs of large in-degree): one 512-thread
-// workgroup per set with its visited set in an LDS hash and its queue in LDS, so a BFS level
-// costs two dependent device loads (offsets, then sources) instead of four.  A set that
+// IC sets with few members but heavy expansions (hubs of large in-degree): one workgroup of
+// NT threads (512 or 1024) per set with its visited set in an LDS hash and its queue in LDS,
+// so a BFS level costs two dependent device loads (offsets, then sources) instead of four.  A set that
 // outgrows the LDS queue clears the hash and moves to the device-bitmap kernel (k_big).
 constexpr int T2L_HASH_BITS = 13;
-constexpr int T2L_HASH = 1 << T2L_HASH_BITS;  // 8192 slots: at most T2L_CAP + 4 * T2_THREADS in use
+constexpr int T2L_HASH = 1 << T2L_HASH_BITS;  // 8192 slots: at most T2L_CAP + NT keys in use
 constexpr int T2L_CAP = 2048;                 // members kept
 
 struct T2LArgs {
@@ -579,15 +579,16 @@ struct T2LArgs {
     uint32_t nlist;
 };
 
+template <int NT>
 __device__ void big_lds_body(const T2LArgs &t) {
     const SampleArgs &a = t.a;
     __shared__ uint32_t h[T2L_HASH];
     __shared__ uint32_t q[T2L_CAP];
-    __shared__ uint32_t sP[T2_THREADS];
-    __shared__ uint32_t sE0[T2_THREADS];
-    __shared__ uint32_t sE1[T2_THREADS];
-    __shared__ uint32_t sT[T2_THREADS];
-    __shared__ uint32_t wsum[T2_WAVES];
+    __shared__ uint32_t sP[NT];
+    __shared__ uint32_t sE0[NT];
+    __shared__ uint32_t sE1[NT];
+    __shared__ uint32_t sT[NT];
+    __shared__ uint32_t wsum[NT / WAVE];
     __shared__ uint32_t qn;
     __shared__ uint32_t item;
     __shared__ int ovf;
@@ -596,7 +597,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
     __shared__ unsigned long long s_ctr[DC_COUNT];
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
-    for (int i = threadIdx.x; i < T2L_HASH; i += T2_THREADS) h[i] = EMPTY;
+    for (int i = threadIdx.x; i < T2L_HASH; i += NT) h[i] = EMPTY;
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) item = (uint32_t)atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
@@ -617,8 +618,8 @@ __device__ void big_lds_body(const T2LArgs &t) {
         __syncthreads();
         uint32_t head = 0, tail = 1;
         while (head < tail && !ovf) {
-            for (uint32_t c0 = head; c0 < tail; c0 += T2_THREADS) {
-                const uint32_t cn = tail - c0 < (uint32_t)T2_THREADS ? tail - c0 : (uint32_t)T2_THREADS;
+            for (uint32_t c0 = head; c0 < tail; c0 += NT) {
+                const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
                 uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
                 if (threadIdx.x < cn) {
                     const uint32_t v = q[c0 + threadIdx.x];
@@ -633,7 +634,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 sE1[threadIdx.x] = e1;
                 sT[threadIdx.x] = tv;
                 __syncthreads();
-                const uint32_t G = sP[T2_THREADS - 1];
+                const uint32_t G = sP[NT - 1];
                 if (a.dctr) {
                     if (threadIdx.x == 0) {
                         s_ctr[DC_PHILOX] += G;
@@ -642,7 +643,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
                 }
                 uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
-                for (uint32_t g = threadIdx.x; g < G; g += T2_THREADS) {
+                for (uint32_t g = threadIdx.x; g < G; g += NT) {
                     if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
                     const uint32_t excl = i ? sP[i - 1] : 0u;
                     const uint32_t E0 = sE0[i], E1 = sE1[i];
@@ -662,7 +663,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
                         if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
                             if (a.dctr) atomicAdd(&s_ctr[DC_LIVE], 1ull);
                             // a full queue: the set moves to k_big; stop inserting so the hash
-                            // never holds more than T2L_CAP + 4 * T2_THREADS keys
+                            // never holds more than T2L_CAP + NT keys (one insert per thread in flight)
                             if (qn >= (uint32_t)T2L_CAP) {
                                 ovf = 1;
                                 continue;
@@ -690,7 +691,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
             __syncthreads();
         }
         if (ovf) {
-            for (int x = threadIdx.x; x < T2L_HASH; x += T2_THREADS) h[x] = EMPTY;
+            for (int x = threadIdx.x; x < T2L_HASH; x += NT) h[x] = EMPTY;
             if (threadIdx.x == 0) {
                 const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER2], 1ull);
                 a.defer2[d] = b;
@@ -707,12 +708,12 @@ __device__ void big_lds_body(const T2LArgs &t) {
         }
         // canonical order: sort the members in LDS (pads hold EMPTY, above every id)
         const int P2 = pow2_at_least((int)s);
-        for (int x = (int)s + threadIdx.x; x < P2; x += T2_THREADS) q[x] = EMPTY;
+        for (int x = (int)s + threadIdx.x; x < P2; x += NT) q[x] = EMPTY;
         __syncthreads();
         if (s > 1) block_bitonic(q, P2);
         const uint64_t at = s_at;
         if (s_ok) {
-            for (int x = threadIdx.x; x < (int)s; x += T2_THREADS) a.mem[at + x] = q[x];
+            for (int x = threadIdx.x; x < (int)s; x += NT) a.mem[at + x] = q[x];
             if (threadIdx.x == 0) {
                 a.pos[b] = (uint32_t)at;
                 a.size[b] = s;
@@ -720,15 +721,19 @@ __device__ void big_lds_body(const T2LArgs &t) {
         } else if (threadIdx.x == 0) {
             mark_ovf(a, b);
         }
-        for (int x = threadIdx.x; x < T2L_HASH; x += T2_THREADS) h[x] = EMPTY;
+        for (int x = threadIdx.x; x < T2L_HASH; x += NT) h[x] = EMPTY;
         __syncthreads();
     }
     if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(T2_THREADS) void k_big_lds(T2LArgs t) { big_lds_body(t); }
-__global__ __launch_bounds__(T2_THREADS) void k_big_lds_g(GroupArgs<T2LArgs> G) {
-    big_lds_body(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+template <int NT>
+__global__ __launch_bounds__(NT) void k_big_lds(T2LArgs t) {
+    big_lds_body<NT>(t);
+}
+template <int NT>
+__global__ __launch_bounds__(NT) void k_big_lds_g(GroupArgs<T2LArgs> G) {
+    big_lds_body<NT>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
 }
 
 __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) { big_body(t, blockIdx.x); }
@@ -1136,7 +1141,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
             lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd});
-            ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 3));
+            ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * root.lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
             lt_deferred = true;
@@ -1151,9 +1156,15 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     if (!lds.empty() || !ltw.empty()) {
         if (lt_deferred) ctrl_push(root);
         int s2 = lds.empty() ? -1 : prof_begin(root, "ic_sample_block");
-        glaunch(root, lds, ldsb, 0, [&](const T2LArgs &t, unsigned g) { k_big_lds<<<g, T2_THREADS, 0, st>>>(t); },
+        const bool wide = root.lds_threads == 1024;
+        glaunch(root, lds, ldsb, 0,
+                [&](const T2LArgs &t, unsigned g) {
+                    if (wide) k_big_lds<1024><<<g, 1024, 0, st>>>(t);
+                    else k_big_lds<512><<<g, 512, 0, st>>>(t);
+                },
                 [&](const T2LArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
-                    k_big_lds_g<<<g, T2_THREADS, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    if (wide) k_big_lds_g<1024><<<g, 1024, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    else k_big_lds_g<512><<<g, 512, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
                 });
         HBM_HIP(hipGetLastError());
         prof_end(root, s2);

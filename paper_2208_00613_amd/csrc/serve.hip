@@ -65,7 +65,7 @@ struct Slot {
 void release_store(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp})
         buf_free(c, *b);
     store_reset(c);
 }

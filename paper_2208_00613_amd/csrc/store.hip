@@ -429,7 +429,7 @@ void store_reset(Ctx &c) {
 void store_free(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp})
         buf_free(c, *b);
     Scratch &sc = c.sc;
     for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.t2h_bitmap,
@@ -517,41 +517,160 @@ static int huffman_lengths_host(const std::vector<std::pair<uint64_t, int32_t>> 
     }
 }
 
+// ---------------------------------------------------------------- warm-up symbols on the device
+// The ids with a nonzero warm-up count, ascending, with their counts: every block of NZ_SPAN
+// vertices counts its nonzero ones, the counts are scanned, and each block writes its ids in
+// order from its offset.  Only this list (at most the warm-up's member count) goes to the
+// host; the per-vertex tables are filled on the device from compact lists.
+constexpr int NZ_T = 256, NZ_ITEMS = 16, NZ_SPAN = NZ_T * NZ_ITEMS;
+
+__global__ __launch_bounds__(NZ_T) void k_nz_count(const uint32_t *warm, int32_t n, uint32_t *bcnt) {
+    __shared__ uint32_t ws[NZ_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * NZ_SPAN;
+    uint32_t c = 0;
+    for (int i = 0; i < NZ_ITEMS; i++) {
+        const int64_t v = base + (int64_t)i * NZ_T + threadIdx.x;
+        if (v < n && warm[v]) c++;
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < NZ_T / WAVE; w++) t += ws[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(NZ_T) void k_nz_write(const uint32_t *warm, int32_t n, const int64_t *boff, uint32_t *ids,
+                                                   uint32_t *cnt) {
+    __shared__ uint32_t ws[NZ_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * NZ_SPAN;
+    const int wv = threadIdx.x / WAVE;
+    int64_t at = boff[blockIdx.x];
+    for (int i = 0; i < NZ_ITEMS; i++) {
+        const int64_t v = base + (int64_t)i * NZ_T + threadIdx.x;
+        const uint32_t w = v < n ? warm[v] : 0u;
+        const uint32_t f = w ? 1u : 0u;
+        const uint32_t inc = wave_incl_scan(f);
+        if (lane_id() == WAVE - 1) ws[wv] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int x = 0; x < NZ_T / WAVE; x++) {
+            if (x < wv) before += ws[x];
+            tot += ws[x];
+        }
+        if (f) {
+            const int64_t p = at + before + inc - 1;
+            ids[p] = (uint32_t)v;
+            cnt[p] = w;
+        }
+        at += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// rank[ids[r]] = r (hot ranks)
+__global__ void k_scatter_rank(const uint32_t *ids, int64_t k, int32_t *rank) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < k; r += (int64_t)gridDim.x * blockDim.x)
+        rank[ids[r]] = (int32_t)r;
+}
+
+// lens[ids[i]] = len[i], codes[ids[i]] = code[i] (coded vertices)
+__global__ void k_scatter_codes(const uint32_t *ids, const uint8_t *len, const uint32_t *code, int64_t m,
+                                uint8_t *lens, uint32_t *codes) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        lens[ids[i]] = len[i];
+        codes[ids[i]] = code[i];
+    }
+}
+
+// Vertices with a nonzero warm-up count, ascending, and their counts (device work; host copy
+// of the compact list).
+static void warm_symbols(Ctx &c, std::vector<uint32_t> &ids, std::vector<uint32_t> &cnt) {
+    Store &s = c.s;
+    const int32_t n = c.g.n;
+    const hipStream_t st = c.stream;
+    const int64_t nblk = ((int64_t)n + NZ_SPAN - 1) / NZ_SPAN;
+    const size_t off_at = ((size_t)(nblk + 1) * 4 + 255) & ~size_t(255);
+    buf_grow(c, s.mtmp, off_at + (size_t)(nblk + 1) * 8, false);
+    uint32_t *bcnt = s.mtmp.as<uint32_t>();
+    int64_t *boff = reinterpret_cast<int64_t *>(s.mtmp.as<char>() + off_at);
+    buf_zero(c, s.mtmp, (size_t)nblk * 4, 4);  // the scan's last input (its output is the total)
+    k_nz_count<<<(unsigned)nblk, NZ_T, 0, st>>>(s.warm.as<uint32_t>(), n, bcnt);
+    HBM_HIP(hipGetLastError());
+    scan_u32_to_i64(c, bcnt, boff, nblk + 1, 0);
+    int64_t m = 0;
+    HBM_HIP(hipMemcpyAsync(&m, boff + nblk, 8, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipStreamSynchronize(st));
+    ids.assign((size_t)m, 0);
+    cnt.assign((size_t)m, 0);
+    if (m == 0) return;
+    const size_t ids_at = ((off_at + (size_t)(nblk + 1) * 8) + 255) & ~size_t(255);
+    const size_t cnt_at = (ids_at + (size_t)m * 4 + 255) & ~size_t(255);
+    buf_grow(c, s.mtmp, cnt_at + (size_t)m * 4, true);
+    boff = reinterpret_cast<int64_t *>(s.mtmp.as<char>() + off_at);
+    uint32_t *dids = reinterpret_cast<uint32_t *>(s.mtmp.as<char>() + ids_at);
+    uint32_t *dcnt = reinterpret_cast<uint32_t *>(s.mtmp.as<char>() + cnt_at);
+    k_nz_write<<<(unsigned)nblk, NZ_T, 0, st>>>(s.warm.as<uint32_t>(), n, boff, dids, dcnt);
+    HBM_HIP(hipGetLastError());
+    HBM_HIP(hipMemcpyAsync(ids.data(), dids, (size_t)m * 4, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipMemcpyAsync(cnt.data(), dcnt, (size_t)m * 4, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipStreamSynchronize(st));
+}
+
+static unsigned fill_grid(int64_t count) { return grid_for(count, 256, 8192); }
+
 static void build_model(Ctx &c) {
     Store &s = c.s;
     const int32_t n = c.g.n;
-    std::vector<uint32_t> warm(n);
-    HBM_HIP(hipMemcpyAsync(warm.data(), s.warm.p, (size_t)n * 4, hipMemcpyDeviceToHost, c.stream));
-    HBM_HIP(hipStreamSynchronize(c.stream));
+    const hipStream_t st = c.stream;
+    // the warm-up's symbols in ascending id order: every choice below is a total order
+    // over (count, id), so it matches a scan over all n vertices
+    std::vector<uint32_t> ids, wcnt;
+    warm_symbols(c, ids, wcnt);
+    const size_t m = ids.size();
     const bool hot = s.enc == HBM_ENC_HOT_BITMAP || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
     const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    std::vector<int32_t> rank;
+    std::vector<char> is_hot(m, 0);
     s.nhot = 0;
     if (hot) {
         // eligible: in at least max(1, ceil(min_density * W)) warm-up sets (a bitmap row costs a
         // bit per set, a stored id 32 bits per occurrence: rows pay above density 1/32)
         const uint64_t min_cnt = std::max<uint64_t>(1, (uint64_t)std::ceil(s.hot_min_density * (double)s.W));
-        std::vector<int32_t> seen;
-        for (int32_t v = 0; v < n; v++)
-            if ((uint64_t)warm[v] >= min_cnt) seen.push_back(v);
+        std::vector<size_t> seen;  // indices into ids
+        for (size_t i = 0; i < m; i++)
+            if ((uint64_t)wcnt[i] >= min_cnt) seen.push_back(i);
         const int64_t want = (int64_t)std::ceil(s.hot_frac * (double)n);
         const size_t keep = (size_t)std::min<int64_t>(want, (int64_t)seen.size());
-        std::partial_sort(seen.begin(), seen.begin() + keep, seen.end(), [&](int32_t a, int32_t b) {
-            return warm[a] != warm[b] ? warm[a] > warm[b] : a < b;
+        std::partial_sort(seen.begin(), seen.begin() + keep, seen.end(), [&](size_t a, size_t b) {
+            return wcnt[a] != wcnt[b] ? wcnt[a] > wcnt[b] : ids[a] < ids[b];
         });
-        seen.resize(keep);
+        std::vector<uint32_t> hot_ids(std::max<size_t>(keep, 1), 0u);
+        for (size_t r = 0; r < keep; r++) {
+            hot_ids[r] = ids[seen[r]];
+            is_hot[seen[r]] = 1;
+        }
         s.nhot = (int32_t)keep;
-        rank.assign(n, -1);
-        for (size_t r = 0; r < keep; r++) rank[seen[r]] = (int32_t)r;
-        buf_alloc(c, s.hot, std::max<size_t>(keep, 1) * 4);
-        buf_alloc(c, s.hot_rank, (size_t)n * 4);
-        HBM_HIP(hipMemcpyAsync(s.hot.p, seen.data(), keep * 4, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.hot_rank.p, rank.data(), (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+        buf_alloc(c, s.hot, hot_ids.size() * 4);
+        buf_grow(c, s.hot_rank, (size_t)n * 4, false);
+        HBM_HIP(hipMemcpyAsync(s.hot.p, hot_ids.data(), hot_ids.size() * 4, hipMemcpyHostToDevice, st));
+        k_fill_i32<<<fill_grid(n), 256, 0, st>>>(s.hot_rank.as<int32_t>(), n, -1);
+        if (keep) k_scatter_rank<<<fill_grid((int64_t)keep), 256, 0, st>>>(s.hot.as<uint32_t>(), (int64_t)keep,
+                                                                        s.hot_rank.as<int32_t>());
+        HBM_HIP(hipGetLastError());
+        // the host vector is freed at return: the queued copy must have read it
+        HBM_HIP(hipStreamSynchronize(st));
     }
     if (huff) {
         std::vector<std::pair<uint64_t, int32_t>> syms;
-        for (int32_t v = 0; v < n; v++)
-            if (warm[v] && (!hot || rank[v] < 0)) syms.push_back({warm[v], v});
+        for (size_t i = 0; i < m; i++)
+            if (!is_hot[i]) syms.push_back({wcnt[i], (int32_t)ids[i]});
         std::vector<uint8_t> L;
         auto L_of = [&](size_t i) { return (int)L[i]; };
         Codebook &cb = s.cb;
@@ -568,8 +687,7 @@ static void build_model(Ctx &c) {
         std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
             return L[a] != L[b] ? L[a] < L[b] : syms[a].second < syms[b].second;
         });
-        std::vector<uint8_t> lens(n, 0);
-        std::vector<uint32_t> codes(n, 0);
+        std::vector<uint32_t> sym_code(syms.size(), 0), sym_id(std::max<size_t>(syms.size(), 1), 0);
         std::vector<int32_t> symtab(std::max<size_t>(syms.size(), 1), 0);
         uint64_t count[34] = {}, first[34] = {}, firstidx[34] = {};
         for (size_t i = 0; i < syms.size(); i++) count[L[i]]++;
@@ -577,10 +695,10 @@ static void build_model(Ctx &c) {
         for (size_t q = 0; q < ord.size(); q++) {
             const size_t i = ord[q];
             if (q > 0) code = (code + 1) << (L[i] - L[ord[q - 1]]);
-            lens[syms[i].second] = L[i];
-            codes[syms[i].second] = (uint32_t)code;
+            sym_code[i] = (uint32_t)code;
             symtab[q] = syms[i].second;
         }
+        for (size_t i = 0; i < syms.size(); i++) sym_id[i] = (uint32_t)syms[i].second;
         cb.minlen = 33;
         for (int l = 1; l <= 32; l++)
             if (count[l]) { cb.minlen = std::min(cb.minlen, l); }
@@ -611,7 +729,7 @@ static void build_model(Ctx &c) {
             const size_t i = ord[q];
             const int L = L_of(i);
             if (L > LUT_BITS) break;
-            const uint32_t cd = codes[syms[i].second];
+            const uint32_t cd = sym_code[i];
             const uint32_t lo = cd << (LUT_BITS - L), hi = (cd + 1) << (LUT_BITS - L);
             for (uint32_t x = lo; x < hi; x++) lut[x] = ((uint32_t)syms[i].second << 5) | (uint32_t)L;
         }
@@ -621,20 +739,32 @@ static void build_model(Ctx &c) {
             while (L < 33 && tab_lim[L] <= ((uint64_t)t << (32 - LUT_BITS))) L++;
             lut[t] = (uint32_t)L << 5;
         }
-        buf_alloc(c, s.lens, (size_t)n);
-        buf_alloc(c, s.codes, (size_t)n * 4);
+        // per-vertex tables: zero, then the coded vertices scattered from compact lists
+        const size_t ms = syms.size();
+        buf_grow(c, s.lens, (size_t)n, false);
+        buf_grow(c, s.codes, (size_t)n * 4, false);
+        buf_zero(c, s.lens, 0, (size_t)n);
+        buf_zero(c, s.codes, 0, (size_t)n * 4);
+        const size_t len_at = (ms * 4 + 255) & ~size_t(255), code_at = (len_at + ms + 255) & ~size_t(255);
+        buf_grow(c, s.mtmp, code_at + ms * 4 + 4, false);
+        char *tb = s.mtmp.as<char>();
+        if (ms) {
+            HBM_HIP(hipMemcpyAsync(tb, sym_id.data(), ms * 4, hipMemcpyHostToDevice, st));
+            HBM_HIP(hipMemcpyAsync(tb + len_at, L.data(), ms, hipMemcpyHostToDevice, st));
+            HBM_HIP(hipMemcpyAsync(tb + code_at, sym_code.data(), ms * 4, hipMemcpyHostToDevice, st));
+            k_scatter_codes<<<fill_grid((int64_t)ms), 256, 0, st>>>(
+                reinterpret_cast<const uint32_t *>(tb), reinterpret_cast<const uint8_t *>(tb + len_at),
+                reinterpret_cast<const uint32_t *>(tb + code_at), (int64_t)ms, s.lens.as<uint8_t>(), s.codes.as<uint32_t>());
+            HBM_HIP(hipGetLastError());
+        }
         buf_alloc(c, s.symtab, symtab.size() * 4);
         buf_alloc(c, s.cbtab, 68 * 8);
         buf_alloc(c, s.lut, lut.size() * 4);
-        HBM_HIP(hipMemcpyAsync(s.lut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.lens.p, lens.data(), (size_t)n, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.codes.p, codes.data(), (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.symtab.p, symtab.data(), symtab.size() * 4, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.cbtab.p, tab_lim, 34 * 8, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipMemcpyAsync(s.cbtab.as<int64_t>() + 34, tab_base, 34 * 8, hipMemcpyHostToDevice, c.stream));
-        HBM_HIP(hipStreamSynchronize(c.stream));
-    } else if (hot) {
-        HBM_HIP(hipStreamSynchronize(c.stream));
+        HBM_HIP(hipMemcpyAsync(s.lut.p, lut.data(), lut.size() * 4, hipMemcpyHostToDevice, st));
+        HBM_HIP(hipMemcpyAsync(s.symtab.p, symtab.data(), symtab.size() * 4, hipMemcpyHostToDevice, st));
+        HBM_HIP(hipMemcpyAsync(s.cbtab.p, tab_lim, 34 * 8, hipMemcpyHostToDevice, st));
+        HBM_HIP(hipMemcpyAsync(s.cbtab.as<int64_t>() + 34, tab_base, 34 * 8, hipMemcpyHostToDevice, st));
+        HBM_HIP(hipStreamSynchronize(st));
     }
     s.model_ready = true;
 }

@@ -303,19 +303,26 @@ def test_imm_small(orc, ctx, model, enc):
 
 
 # ---------------------------------------------------------------- launch-shape invariance
-@pytest.mark.parametrize("tier1,budget,block,queue", [(0, 0, 1 << 21, 1 << 20), (1, 0, 1 << 21, 1 << 20),
-                                                      (1, 256, 1024, 1 << 20), (1, 4096, 3000, 1 << 20),
-                                                      (1, 64, 1 << 21, 64), (0, 0, 5000, 100)])
-def test_tuning_invariance(orc, ctx, tier1, budget, block, queue):
-    """Tier choice, tier-1 work budget, block size and big-set queue size (small queues
-    send sets to the huge-set pass) change speed only, never the sets."""
-    _say("tuning invariance", tier1, budget, block, queue)
+@pytest.mark.parametrize("tier1,budget,block,queue,lds", [(0, 0, 1 << 21, 1 << 20, (512, 3)),
+                                                          (1, 0, 1 << 21, 1 << 20, (512, 3)),
+                                                          (1, 256, 1024, 1 << 20, (1024, 1)),
+                                                          (1, 4096, 3000, 1 << 20, (512, 1)),
+                                                          (1, 64, 1 << 21, 64, (1024, 2)),
+                                                          (1, 128, 1 << 21, 1 << 20, (512, 4)),
+                                                          (0, 0, 5000, 100, (1024, 4))])
+def test_tuning_invariance(orc, ctx, tier1, budget, block, queue, lds):
+    """Tier choice, tier-1 work budget, block size, big-set queue size (small queues
+    send sets to the huge-set pass) and the LDS tier's workgroup shape change speed
+    only, never the sets."""
+    _say("tuning invariance", tier1, budget, block, queue, lds)
     g = G.rmat(14, seed=14)
     ctx.load_synth(g, "IC", "WC")
     ctx.hbm_set_tuning("IC_TIER1", tier1)
     ctx.hbm_set_tuning("IC_T1_BUDGET", budget)
     ctx.hbm_set_tuning("BLOCK_SETS", block)
     ctx.hbm_set_tuning("T2_QUEUE", queue)
+    ctx.hbm_set_tuning("LDS_THREADS", lds[0])
+    ctx.hbm_set_tuning("LDS_PER_CU", lds[1])
     ctx.hbm_set_encoding("HOT_BITMAP", 0.1, 0.01)
     theta = 20_000
     ctx.hbm_sample_rr(theta, 42)
