@@ -369,26 +369,50 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t *wsum) 
     return inc + before;
 }
 
-// Emit the set held in `bm` ascending by scanning the bitmap (sets too large for an LDS sort).
-__device__ void emit_from_bitmap(const uint32_t *bm, uint64_t words, uint32_t *out, uint32_t *wsum) {
-    __shared__ uint32_t running;
-    if (threadIdx.x == 0) running = 0;
-    __syncthreads();
-    for (uint64_t w0 = 0; w0 < words; w0 += blockDim.x) {
-        const uint64_t w = w0 + threadIdx.x;
-        const uint32_t word = w < words ? bm[w] : 0u;
-        const uint32_t c = __popc(word);
-        const uint32_t inc = block_incl_scan(c, wsum);
-        uint32_t o = running + inc - c;
-        uint32_t x = word;
-        while (x) {
-            const int bit = __ffs(x) - 1;
-            out[o++] = (uint32_t)(w * 32 + bit);
-            x &= x - 1;
-        }
+// Merge the ascending runs src[lo, mid) and src[mid, hi) into dst[lo, hi) with the whole
+// block: each thread writes an equal share of the output, starting where a merge-path search
+// on its first output index puts it (ids are distinct, so there are no ties).
+__device__ void block_merge(const uint32_t *src, uint32_t *dst, uint32_t lo, uint32_t mid, uint32_t hi) {
+    const uint32_t la = mid - lo, lb = hi - mid, tot = la + lb;
+    const uint32_t per = (tot + blockDim.x - 1) / blockDim.x;
+    const uint32_t d0 = min(tot, threadIdx.x * per), d1 = min(tot, d0 + per);
+    if (d0 >= d1) return;
+    const uint32_t *A = src + lo, *B = src + mid;
+    // i = how many of the first d0 outputs come from A: the first i with A[i] > B[d0 - 1 - i]
+    uint32_t ilo = d0 > lb ? d0 - lb : 0, ihi = min(d0, la);
+    while (ilo < ihi) {
+        const uint32_t i = (ilo + ihi) / 2;
+        if (A[i] < B[d0 - 1 - i]) ilo = i + 1;
+        else ihi = i;
+    }
+    uint32_t i = ilo, k = d0 - ilo;
+    for (uint32_t d = d0; d < d1; d++) dst[lo + d] = (k >= lb || (i < la && A[i] < B[k])) ? A[i++] : B[k++];
+}
+
+// Sort the s members in `queue` (device memory, s > T2_SORT_CAP) into `out`: runs of
+// T2_SORT_CAP sorted in LDS, then pairwise merges between `queue` and `out`, the first run
+// placed so that the last merge lands in `out`.  `queue` keeps a permutation of the set.
+__device__ void block_sort_long(uint32_t *queue, uint32_t *out, uint32_t s, uint32_t *sbuf) {
+    const uint32_t runs = (s + T2_SORT_CAP - 1) / T2_SORT_CAP;
+    int passes = 0;
+    while ((1u << passes) < runs) passes++;
+    uint32_t *src = (passes & 1) ? queue : out;
+    uint32_t *dst = (passes & 1) ? out : queue;
+    for (uint32_t r0 = 0; r0 < s; r0 += T2_SORT_CAP) {
+        const uint32_t len = min((uint32_t)T2_SORT_CAP, s - r0);
+        const int P2 = pow2_at_least((int)len);
+        for (int i = threadIdx.x; i < P2; i += blockDim.x) sbuf[i] = i < (int)len ? queue[r0 + i] : EMPTY;
         __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) running += inc;
+        block_bitonic(sbuf, P2);
+        for (int i = threadIdx.x; i < (int)len; i += blockDim.x) src[r0 + i] = sbuf[i];
         __syncthreads();
+    }
+    for (uint32_t w = T2_SORT_CAP; w < s; w *= 2) {
+        for (uint32_t lo = 0; lo < s; lo += 2 * w) block_merge(src, dst, lo, min(lo + w, s), min(lo + 2 * w, s));
+        __syncthreads();
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
     }
 }
 
@@ -548,7 +572,7 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
                 block_bitonic(sort_buf, P2);
                 for (int i = threadIdx.x; i < (int)s; i += T2_THREADS) a.mem[at + i] = sort_buf[i];
             } else {
-                emit_from_bitmap(bm, t.words, a.mem + at, wsum);
+                block_sort_long(queue, a.mem + at, s, sort_buf);
             }
             if (threadIdx.x == 0) {
                 a.pos[b] = (uint32_t)at;

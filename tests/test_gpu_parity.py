@@ -182,11 +182,13 @@ def test_c1_tiny_ic_full(orc, ctx):
 
 
 @pytest.mark.parametrize("model,prob,scale,theta", [("IC", "WC", 14, 30_000), ("LT", "EDGE", 14, 30_000),
-                                                    ("IC", "EDGE", 11, 3_000), ("IC", "EDGE", 13, 1_500)])
+                                                    ("IC", "EDGE", 11, 3_000), ("IC", "EDGE", 13, 1_500),
+                                                    ("IC", "EDGE", 15, 300), ("IC", "EDGE", 16, 200)])
 def test_sets_and_seeds_rmat(orc, ctx, model, prob, scale, theta):
     """Exact RR sets and seeds; with a constant p = 0.25 most sets reach thousands of
     vertices, so the workgroup tiers run: the LDS one and, past its 2048 members, the
-    device-bitmap one."""
+    device-bitmap one (at scales 15 and 16 sets of 8-27 K members: sorted runs merged over two and three
+    passes)."""
     _say("rmat sets", model, prob, scale, theta)
     g = G.rmat(scale, seed=scale)
     if model == "LT":
