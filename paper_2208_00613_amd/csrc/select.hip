@@ -75,6 +75,8 @@ HBM_KERNEL(k_sel_init, SelArgs, 256) {
     for (int64_t i = tid; i < A.k; i += nthr) A.keys[i] = 0ull;
 }
 
+constexpr int AM_UNROLL = 4;
+
 HBM_KERNEL(k_argmax, SelArgs, 256) {
     const int t = x;
     (void)t;
@@ -85,16 +87,33 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     unsigned long long best = 0;
     const int64_t n4 = A.n >> 2;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
-    for (int64_t q = tid; q < n4; q += nthr) {
-        const uint4 c = c4[q];
-        const uint32_t sm = A.selmask[q >> 3] >> ((q & 7) * 4);
-        const uint32_t v0 = (uint32_t)(q * 4);
+    // AM_UNROLL independent 16-byte loads in flight per thread: the pass is bound by HBM, and
+    // one outstanding load per wave would leave it latency-bound
+    for (int64_t q0 = tid; q0 < n4; q0 += nthr * AM_UNROLL) {
+        uint4 c[AM_UNROLL];
+        uint32_t smw[AM_UNROLL];
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const uint32_t cr = r == 0 ? c.x : r == 1 ? c.y : r == 2 ? c.z : c.w;
-            const unsigned long long key =
-                ((sm >> r) & 1u) ? 0ull : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~(v0 + r));
-            best = key > best ? key : best;
+        for (int u = 0; u < AM_UNROLL; u++) {
+            const int64_t q = q0 + (int64_t)u * nthr;
+            if (q < n4) {
+                c[u] = c4[q];
+                smw[u] = A.selmask[q >> 3];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AM_UNROLL; u++) {
+            const int64_t q = q0 + (int64_t)u * nthr;
+            if (q >= n4) break;
+            const uint32_t sm = smw[u] >> ((q & 7) * 4);
+            const uint32_t v0 = (uint32_t)(q * 4);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t cr = r == 0 ? c[u].x : r == 1 ? c[u].y : r == 2 ? c[u].z : c[u].w;
+                const unsigned long long key = ((sm >> r) & 1u) ? 0ull
+                                                                : (((unsigned long long)cr + 1ull) << 32) |
+                                                                      (unsigned long long)(~(v0 + r));
+                best = key > best ? key : best;
+            }
         }
     }
     for (int64_t v = n4 * 4 + tid; v < A.n; v += nthr) {
@@ -537,7 +556,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     const int32_t n = c.g.n;
     const int64_t T = s.nsets;
     const int64_t words = (T + 63) / 64;
-    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256, (int64_t)root.num_cus * 2);
+    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256 * AM_UNROLL, (int64_t)root.num_cus * 8);
     buf_grow(c, S.counts, (size_t)n * 4, false);
     buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
     buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
