@@ -296,8 +296,8 @@ typedef enum hbm_tune_key {
     HBM_TUNE_T2_SLOTS = 5,        /* big-set workgroups per CU, 1..4 (default 4), each with its own
                                      visited bitmap and queue */
     HBM_TUNE_LDS_THREADS = 6,     /* threads of a workgroup of the LDS tier (IC sets past the wave
-                                     budget, visited set and queue in LDS): 512 (default) or 1024 */
-    HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4 (default 3) */
+                                     budget, visited set and queue in LDS): 512 or 1024 (default) */
+    HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4 (default 2) */
     HBM_TUNE_COUNT = 8
 } hbm_tune_key;
 
@@ -306,7 +306,7 @@ hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);
 /* Autotuner: picks the launch shapes for the given instances (one, or many as
  * hbm_imm_batch runs them) by timing whole IMM runs of the queries under candidate
  * settings, one key at a time (coordinate descent over BLOCK_SETS, IC_T1_BUDGET,
- * T2_SLOTS and LT_PATH), and leaves the fastest applied to every context.  The
+ * T2_SLOTS, LDS_THREADS, LDS_PER_CU and LT_PATH), and leaves the fastest applied to every context.  The
  * contexts' stores end up holding the probes' last run.  chosen int64[HBM_TUNE_COUNT]
  * (may be NULL) receives every key's setting, best_ms (may be NULL) the time of the
  * chosen one.  Results never depend on these settings.  Same argument rules as

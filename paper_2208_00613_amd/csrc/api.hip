@@ -272,6 +272,8 @@ hbm_status hbm_autotune(hbm_ctx *const *ctxs, int32_t count, const hbm_query *qu
             {HBM_TUNE_BLOCK_SETS, {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 21}, true},
             {HBM_TUNE_IC_T1_BUDGET, {1024, 4096, 16384}, ic},
             {HBM_TUNE_T2_SLOTS, {2, 3, 4}, true},
+            {HBM_TUNE_LDS_THREADS, {512, 1024}, ic},
+            {HBM_TUNE_LDS_PER_CU, {2, 3}, ic},
             {HBM_TUNE_LT_PATH, {128, 256}, lt},
         };
         timed();  // warm-up: allocations at the current settings
