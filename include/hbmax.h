@@ -296,8 +296,10 @@ typedef enum hbm_tune_key {
     HBM_TUNE_T2_SLOTS = 5,        /* big-set workgroups per CU, 1..4 (default 4), each with its own
                                      visited bitmap and queue */
     HBM_TUNE_LDS_THREADS = 6,     /* threads of a workgroup of the LDS tier (IC sets past the wave
-                                     budget, visited set and queue in LDS): 512 or 1024 (default) */
-    HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4 (default 2) */
+                                     budget, visited set and queue in LDS): 512, 1024, or 0 (default)
+                                     = 1024 on graphs below 2^22 vertices, else 512 */
+    HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4, or 0 (default) = 2
+                                     on graphs below 2^22 vertices, else 3 */
     HBM_TUNE_COUNT = 8
 } hbm_tune_key;
 

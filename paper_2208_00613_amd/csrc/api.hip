@@ -441,11 +441,11 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             }
             break;
         case HBM_TUNE_LDS_THREADS:
-            HBM_REQUIRE(value == 512 || value == 1024, HBM_EINVAL, "LDS_THREADS must be 512 or 1024");
+            HBM_REQUIRE(value == 0 || value == 512 || value == 1024, HBM_EINVAL, "LDS_THREADS must be 0, 512 or 1024");
             c.lds_threads = (int)value;
             break;
         case HBM_TUNE_LDS_PER_CU:
-            HBM_REQUIRE(value >= 1 && value <= 4, HBM_EINVAL, "LDS_PER_CU must be in [1, 4]");
+            HBM_REQUIRE(value >= 0 && value <= 4, HBM_EINVAL, "LDS_PER_CU must be in [0, 4]");
             c.lds_per_cu = (int)value;
             break;
         case HBM_TUNE_BLOCK_SETS:

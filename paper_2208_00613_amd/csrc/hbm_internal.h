@@ -202,8 +202,8 @@ struct Ctx {
     int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
     int64_t t2_queue = int64_t(1) << 20; // queue entries of a big-set slot
     int t2_per_cu = 4;                   // big-set slots (workgroups) per CU
-    int lds_threads = 1024;              // threads of an LDS-tier workgroup (512 or 1024)
-    int lds_per_cu = 2;                  // LDS-tier workgroups launched per CU
+    int lds_threads = 0;                 // threads of an LDS-tier workgroup (512 or 1024; 0 = by n)
+    int lds_per_cu = 0;                  // LDS-tier workgroups launched per CU (0 = by n)
     DGraph g;
     Store s;
     Scratch sc;

@@ -1154,6 +1154,13 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     ctrl_pull(root);
     if (s1b >= 0) prof_sampler(root, s1b, false, J);
     // ---- tier 2: IC sets on a workgroup each (visited set in LDS); LT walks on a wave each
+    // LDS-tier shape: by default 1024 threads, two per CU, on graphs below 2^22 vertices
+    // (heavy sets there are few and deep) and 512 threads, three per CU, above (measured)
+    int gmax = 0;
+    for (size_t i = 0; i < N; i++) gmax = std::max(gmax, J[i]->g.n);
+    const bool small_g = gmax < (1 << 22);
+    const int lds_threads = root.lds_threads ? root.lds_threads : (small_g ? 1024 : 512);
+    const int lds_per_cu = root.lds_per_cu ? root.lds_per_cu : (small_g ? 2 : 3);
     std::vector<T2LArgs> lds;
     std::vector<uint32_t> ldsb;
     std::vector<Lt2Args> ltw;
@@ -1165,7 +1172,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
             lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd});
-            ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * root.lds_per_cu));
+            ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
             lt_deferred = true;
@@ -1180,7 +1187,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     if (!lds.empty() || !ltw.empty()) {
         if (lt_deferred) ctrl_push(root);
         int s2 = lds.empty() ? -1 : prof_begin(root, "ic_sample_block");
-        const bool wide = root.lds_threads == 1024;
+        const bool wide = lds_threads == 1024;
         glaunch(root, lds, ldsb, 0,
                 [&](const T2LArgs &t, unsigned g) {
                     if (wide) k_big_lds<1024><<<g, 1024, 0, st>>>(t);

@@ -1128,6 +1128,22 @@ void store_extend(Ctx &c, int64_t theta, uint64_t seed) {
     extend_stores(c, std::vector<Ctx *>{&c}, std::vector<int64_t>{theta}, std::vector<uint64_t>{seed});
 }
 
+// sum of x[0, n) into *out (added with one atomic per wave; *out starts at zero)
+__global__ __launch_bounds__(256) void k_sum_u32(const uint32_t *x, int64_t n, unsigned long long *out) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long t = 0;
+    const int64_t n4 = n >> 2;
+    const uint4 *x4 = reinterpret_cast<const uint4 *>(x);
+    for (int64_t q = tid; q < n4; q += nthr) {
+        const uint4 v = x4[q];
+        t += (unsigned long long)v.x + v.y + v.z + v.w;
+    }
+    for (int64_t i = n4 * 4 + tid; i < n; i += nthr) t += x[i];
+    t = wave_sum(t);
+    if (lane_id() == 0 && t) atomicAdd(out, t);
+}
+
 void store_stats(Ctx &c, hbm_store_stats *o) {
     Store &s = c.s;
     *o = hbm_store_stats{};
@@ -1150,14 +1166,17 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     o->store_bytes = store_bytes(c);
     o->skewness = s.skew;
     o->density = s.density;
-    // total members = sum of the histogram
+    // total members = sum of the histogram (reduced on the device; 8 bytes come back)
     if (s.hist.p && s.nsets) {
-        std::vector<uint32_t> h(c.g.n);
-        HBM_HIP(hipMemcpyAsync(h.data(), s.hist.p, (size_t)c.g.n * 4, hipMemcpyDeviceToHost, c.stream));
+        buf_grow(c, s.mtmp, 8, true);
+        buf_zero(c, s.mtmp, 0, 8);
+        k_sum_u32<<<grid_for(((int64_t)c.g.n + 3) / 4, 256, (int64_t)c.num_cus * 4), 256, 0, c.stream>>>(
+            s.hist.as<uint32_t>(), c.g.n, s.mtmp.as<unsigned long long>());
+        HBM_HIP(hipGetLastError());
+        unsigned long long t = 0;
+        HBM_HIP(hipMemcpyAsync(&t, s.mtmp.p, 8, hipMemcpyDeviceToHost, c.stream));
         HBM_HIP(hipStreamSynchronize(c.stream));
-        int64_t t = 0;
-        for (uint32_t x : h) t += x;
-        o->members = t;
+        o->members = (int64_t)t;
     }
 }
 
