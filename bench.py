@@ -60,8 +60,8 @@ CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 # i.e. 10 x (4 x 4 + 4) = 200 full-rate VALU lane slots.
 PHILOX_SLOTS = 200.0
 PHILOX_PEAK_G = CUS * SIMDS * LANES * CLOCK_GHZ / PHILOX_SLOTS  # G calls/s
-SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_bitmap", "lt_sample_lane", "lt_sample_wave",
-                   "lt_sample_block", "sample_huge")
+SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_block_xl", "ic_sample_bitmap", "lt_sample_lane",
+                   "lt_sample_wave", "lt_sample_block", "sample_huge")
 
 
 def roofline(kstats, model, prob):
@@ -98,14 +98,18 @@ def csrc_digest():
     return h.hexdigest()[:16]
 
 
-# hbm_profile names -> the HIP kernels behind them (plain and grouped forms)
+# hbm_profile names -> the HIP kernels behind them (regular expressions over the symbol after
+# "hbm::", matching the plain and grouped forms; the LDS tier's two capacities are told apart by
+# their template arguments)
 PROFILE_KERNELS = {
-    "ic_sample_wave": "k_ic_t1", "ic_sample_block": "k_big_lds", "ic_sample_bitmap": "k_big",
-    "lt_sample_lane": "k_lt_t1", "lt_sample_wave": "k_lt_wave", "lt_sample_block": "k_big", "sample_huge": "k_big",
-    "hist_add": "k_hist_add", "cold_count": "k_cold_count", "split": "k_split", "huff_bits": "k_huff_bits",
-    "huff_write": "k_huff_write", "argmax": "k_argmax", "find_raw": "k_find_raw", "find_huff": "k_find_huff",
-    "apply": "k_apply", "dec_big": "k_dec_big", "dec_hot": "k_dec_hot",
+    "ic_sample_wave": r"k_ic_t1(_g)?\b", "ic_sample_block": r"k_big_lds(_g)?<\d+, 2048,",
+    "ic_sample_block_xl": r"k_big_lds(_g)?<\d+, 8192,", "ic_sample_bitmap": r"k_big(_g)?\b",
+    "lt_sample_lane": r"k_lt_t1(_g)?\b", "lt_sample_wave": r"k_lt_wave(_g)?\b", "lt_sample_block": r"k_big(_g)?\b",
+    "sample_huge": r"k_big(_g)?\b",
 }
+for _k in ("hist_add", "cold_count", "split", "huff_bits", "huff_write", "argmax", "find_raw", "find_huff", "apply",
+           "dec_big", "dec_hot"):
+    PROFILE_KERNELS[_k] = r"k_" + _k + r"(_g)?\b"
 COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
 
 
@@ -157,7 +161,7 @@ def traffic_summarize(fetch_csv, write_csv, out_path):
     kernels = {}
     mean = lambda v: sum(v) / len(v)
     for prof, sym in PROFILE_KERNELS.items():
-        pat = re.compile(r"hbm::" + sym + r"(_g)?\b")
+        pat = re.compile(r"hbm::" + sym)
         fs = [x for k, v in fetch.items() if pat.search(k) for x in v]
         ws = [x for k, v in write.items() if pat.search(k) for x in v]
         if fs:

@@ -593,18 +593,28 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
 // NT threads (512 or 1024) per set with its visited set in an LDS hash and its queue in LDS,
 // so a BFS level costs two dependent device loads (offsets, then sources) instead of four.  A set that
 // outgrows the LDS queue clears the hash and moves to the device-bitmap kernel (k_big).
+// Two capacities: the regular tier keeps 2048 members (hash of 8192 slots, 49-57 KB of LDS,
+// two or three workgroups per CU); its overflow goes to an extra-large pass that keeps 8192
+// (hash of 16384 slots, 112 KB, one 1024-thread workgroup per CU), and only sets beyond that
+// reach the device-bitmap tier.  The hash never holds more than CAP + NT keys.
+constexpr int T2L_CAP = 2048;
 constexpr int T2L_HASH_BITS = 13;
-constexpr int T2L_HASH = 1 << T2L_HASH_BITS;  // 8192 slots: at most T2L_CAP + NT keys in use
-constexpr int T2L_CAP = 2048;                 // members kept
+constexpr int T2X_CAP = 8192;
+constexpr int T2X_HASH_BITS = 14;
 
 struct T2LArgs {
     SampleArgs a;
     const uint32_t *list;
     uint32_t nlist;
+    uint32_t *ovf_list;  // where sets that outgrow the LDS queue go
+    int ovf_cw;          // control word counting them
 };
 
-template <int NT>
+template <int NT, int CAP, int HBITS>
 __device__ void big_lds_body(const T2LArgs &t) {
+    constexpr int T2L_HASH = 1 << HBITS;
+    constexpr int T2L_HASH_BITS = HBITS;
+    constexpr int T2L_CAP = CAP;
     const SampleArgs &a = t.a;
     __shared__ uint32_t h[T2L_HASH];
     __shared__ uint32_t q[T2L_CAP];
@@ -717,8 +727,8 @@ __device__ void big_lds_body(const T2LArgs &t) {
         if (ovf) {
             for (int x = threadIdx.x; x < T2L_HASH; x += NT) h[x] = EMPTY;
             if (threadIdx.x == 0) {
-                const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER2], 1ull);
-                a.defer2[d] = b;
+                const uint64_t d = atomicAdd(&a.ctrl[t.ovf_cw], 1ull);
+                t.ovf_list[d] = b;
             }
             __syncthreads();
             continue;
@@ -751,13 +761,13 @@ __device__ void big_lds_body(const T2LArgs &t) {
     if (a.dctr && threadIdx.x < DC_COUNT && s_ctr[threadIdx.x]) atomicAdd(&a.dctr[threadIdx.x], s_ctr[threadIdx.x]);
 }
 
-template <int NT>
+template <int NT, int CAP, int HBITS>
 __global__ __launch_bounds__(NT) void k_big_lds(T2LArgs t) {
-    big_lds_body<NT>(t);
+    big_lds_body<NT, CAP, HBITS>(t);
 }
-template <int NT>
+template <int NT, int CAP, int HBITS>
 __global__ __launch_bounds__(NT) void k_big_lds_g(GroupArgs<T2LArgs> G) {
-    big_lds_body<NT>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+    big_lds_body<NT, CAP, HBITS>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
 }
 
 __global__ __launch_bounds__(T2_THREADS) void k_big(T2Args t) { big_body(t, blockIdx.x); }
@@ -1171,7 +1181,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
-            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd});
+            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2});
             ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
@@ -1190,12 +1200,13 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         const bool wide = lds_threads == 1024;
         glaunch(root, lds, ldsb, 0,
                 [&](const T2LArgs &t, unsigned g) {
-                    if (wide) k_big_lds<1024><<<g, 1024, 0, st>>>(t);
-                    else k_big_lds<512><<<g, 512, 0, st>>>(t);
+                    if (wide) k_big_lds<1024, T2L_CAP, T2L_HASH_BITS><<<g, 1024, 0, st>>>(t);
+                    else k_big_lds<512, T2L_CAP, T2L_HASH_BITS><<<g, 512, 0, st>>>(t);
                 },
                 [&](const T2LArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
-                    if (wide) k_big_lds_g<1024><<<g, 1024, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
-                    else k_big_lds_g<512><<<g, 512, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    if (wide)
+                        k_big_lds_g<1024, T2L_CAP, T2L_HASH_BITS><<<g, 1024, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    else k_big_lds_g<512, T2L_CAP, T2L_HASH_BITS><<<g, 512, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
                 });
         HBM_HIP(hipGetLastError());
         prof_end(root, s2);
@@ -1212,15 +1223,46 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         prof_end(root, s3);
         ctrl_pull(root);
         if (s3 >= 0) prof_sampler(root, s3, false, J);
-        // ---- tier 3: IC sets that outgrew the LDS tier and LT walks longer than the LDS path,
-        // a workgroup each with its visited bitmap and queue in device memory
+        // ---- extra-large LDS pass: IC sets past the LDS tier's 2048 members, one 1024-thread
+        // workgroup per CU with room for 8192; the rest go on to tier 3 (list `defer`, whose
+        // entries the LDS tier has consumed)
+        std::vector<T2LArgs> xl;
+        std::vector<uint32_t> xlb;
+        for (size_t i = 0; i < N; i++) {
+            Ctx &c = *J[i];
+            if (c.g.model != HBM_IC) continue;
+            // CW_NDEFER still counts the LDS tier's input: from here on it counts tier 3's
+            root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;
+            const uint64_t nd2 = root.ctrl_host[i * CW_COUNT + CW_NDEFER2];
+            if (!nd2) continue;
+            root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
+            xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER});
+            xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));
+        }
+        if (!xl.empty()) {
+            ctrl_push(root);
+            int sx = prof_begin(root, "ic_sample_block_xl");
+            glaunch(root, xl, xlb, 0,
+                    [&](const T2LArgs &t, unsigned g) {
+                        k_big_lds<1024, T2X_CAP, T2X_HASH_BITS><<<g, 1024, 0, st>>>(t);
+                    },
+                    [&](const T2LArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                        k_big_lds_g<1024, T2X_CAP, T2X_HASH_BITS><<<g, 1024, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    });
+            HBM_HIP(hipGetLastError());
+            prof_end(root, sx);
+            ctrl_pull(root);
+            if (sx >= 0) prof_sampler(root, sx, true, J);
+        }
+        // ---- tier 3: IC sets that outgrew the extra-large pass and LT walks longer than the LDS
+        // path, a workgroup each with its visited bitmap and queue in device memory
         for (int model : {HBM_IC, HBM_LT}) {
             std::vector<T2Args> t3;
             std::vector<uint32_t> t3b;
             for (size_t i = 0; i < N; i++) {
                 Ctx &c = *J[i];
                 if (c.g.model != model) continue;
-                const uint64_t nd3 = root.ctrl_host[i * CW_COUNT + (model == HBM_IC ? CW_NDEFER2 : CW_NDEFER)];
+                const uint64_t nd3 = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
                 if (!nd3) continue;
                 ensure_t2(c);
                 root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
@@ -1229,7 +1271,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                 t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
                 t.queue = c.sc.t2_queue.as<uint32_t>();
                 t.words = ((uint64_t)c.g.n + 31) / 32;
-                t.list = A[i].defer2;
+                t.list = model == HBM_IC ? A[i].defer : A[i].defer2;
                 t.nlist = (uint32_t)nd3;
                 t.model = model;
                 t.qcap = t2_qcap(c);
