@@ -63,8 +63,8 @@ constexpr int LUT_BITS = 11;
 // Code-boundary slots of the Huffman payload: slot m holds the distance from bit m * CK_SLOT
 // to the first code boundary at or after it (0..31) when that bit lies inside a code, so a
 // long string can be decoded by many lanes at once, one slot interval each.
-constexpr int CK_SLOT = 1024;
-constexpr int BIG_BITS = 2 * CK_SLOT;  // strings longer than this are decremented by a whole wave
+constexpr int CK_SLOT = 256;
+constexpr int BIG_BITS = 2048;  // strings longer than this are decremented by a whole wave
 
 struct Codebook {
     int32_t nsym = 0;       // coded vertices
