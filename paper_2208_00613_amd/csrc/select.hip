@@ -396,7 +396,10 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
             A.covered[w] = cov | nwm;
         }
         if (found) {
-            if (p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j0 + lane);  // a whole wave decrements it later
+            // a long string, or any string not staged in LDS (decoding it from device memory
+            // would be one dependent load per code in this lane): a whole wave decrements it
+            // later from an LDS copy
+            if (!staged || p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j0 + lane);
             else huff_decrement(A, tb, C, buf, p0, p1);
         }
         wave_sync();
@@ -405,9 +408,11 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
     cache_flush(C, A.counts);
 }
 
+// Records u* (bit 0 of block 0) and, when u* is hot or the store is plain, marks the newly
+// covered sets of every word and decrements their members: plain ids here, Huffman strings
+// queued for k_dec_big (a cold u* of a Huffman store was handled by k_find_huff).
 HBM_KERNEL(k_apply, SelArgs, 256) {
     const int t = x;
-    __shared__ Tabs tb;
     __shared__ DecCache C;
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
@@ -418,7 +423,6 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
     }
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
     if (r < 0 && A.huff) return;  // the Huffman find step already covered and decremented
-    if (A.huff) load_tabs(A, tb);
     cache_init(C);
     __syncthreads();
     const unsigned lane = lane_id();
@@ -432,12 +436,9 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
         }
         if (!nw) continue;
         if (A.huff) {
-            if ((nw >> lane) & 1ull) {
-                const int64_t j = w * 64 + lane;
-                const uint64_t p0 = (uint64_t)A.bitoff[j], p1 = (uint64_t)A.bitoff[j + 1];
-                if (p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j);
-                else huff_decrement(A, tb, C, A.payload, p0, p1);
-            }
+            // the strings are in device memory: every one goes to k_dec_big, which decodes it
+            // from an LDS copy with the whole wave
+            if ((nw >> lane) & 1ull) queue_big(A, w * 64 + lane);
         } else if (A.raw_off) {
             unsigned long long rest = nw;
             while (rest) {
