@@ -300,7 +300,12 @@ typedef enum hbm_tune_key {
                                      = 1024 on graphs below 2^22 vertices, else 512 */
     HBM_TUNE_LDS_PER_CU = 7,      /* LDS-tier workgroups launched per CU, 1..4, or 0 (default) = 2
                                      on graphs below 2^22 vertices, else 3 */
-    HBM_TUNE_COUNT = 8
+    HBM_TUNE_SPARSE_COUNTS = 8,   /* greedy counts: 0 one per vertex; 1 one per vertex that occurs in
+                                     the store (ids ascending, a vertex-to-slot map; the argmax reads
+                                     the slots and one selection bit per vertex); 2 (default) = 1 on
+                                     graphs of at least 2^22 vertices where the argmax then reads at
+                                     most half as much, else 0.  Exact either way */
+    HBM_TUNE_COUNT = 9
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

@@ -31,8 +31,8 @@ EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hb
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
             "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5,
-        "LDS_THREADS": 6, "LDS_PER_CU": 7}
-TUNE_COUNT = 8
+        "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8}
+TUNE_COUNT = 9
 
 
 class HbmError(RuntimeError):

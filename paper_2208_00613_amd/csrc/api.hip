@@ -448,6 +448,10 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             HBM_REQUIRE(value >= 0 && value <= 4, HBM_EINVAL, "LDS_PER_CU must be in [0, 4]");
             c.lds_per_cu = (int)value;
             break;
+        case HBM_TUNE_SPARSE_COUNTS:
+            HBM_REQUIRE(value >= 0 && value <= 2, HBM_EINVAL, "SPARSE_COUNTS must be 0, 1 or 2");
+            c.sparse_counts = (int)value;
+            break;
         case HBM_TUNE_BLOCK_SETS:
             HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
             c.block_sets = value;
@@ -467,6 +471,7 @@ int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
         case HBM_TUNE_T2_SLOTS: return c.t2_per_cu;
         case HBM_TUNE_LDS_THREADS: return c.lds_threads;
         case HBM_TUNE_LDS_PER_CU: return c.lds_per_cu;
+        case HBM_TUNE_SPARSE_COUNTS: return c.sparse_counts;
         default: return -1;
     }
 }

@@ -161,6 +161,11 @@ struct SelState {
     Buf keys;     // uint64[k]
     Buf partial;  // uint64 per argmax block + a ticket counter
     Buf big;      // uint32: newly covered sets with long strings (+2 counters in front)
+    Buf cand;     // sparse counts: slot -> vertex
+    Buf cpos;     // sparse counts: vertex -> slot
+    Buf csel;     // sparse counts: selection bits over slots
+    Buf sbcnt;    // sparse counts: per-block slot counts and their scan
+    Buf sboff;
     int64_t words_cap = 0;
 };
 
@@ -204,6 +209,7 @@ struct Ctx {
     int t2_per_cu = 4;                   // big-set slots (workgroups) per CU
     int lds_threads = 0;                 // threads of an LDS-tier workgroup (512 or 1024; 0 = by n)
     int lds_per_cu = 0;                  // LDS-tier workgroups launched per CU (0 = by n)
+    int sparse_counts = 2;               // selection counts: 0 dense, 1 sparse slots, 2 by size
     DGraph g;
     Store s;
     Scratch sc;

@@ -58,7 +58,19 @@ struct SelArgs {
     int64_t seg;                  // words per hot-count segment
     const uint8_t *ckb;           // code-boundary slots of the payload
     uint32_t *big;                // [0] sets queued, [1] sets taken, [2..] newly covered long strings
+    // sparse counts (large graphs): only vertices with a nonzero store frequency get a slot, in
+    // ascending id order, and `counts` holds the slots' counts
+    const uint32_t *cand;         // slot -> vertex (null: dense, counts[v])
+    const int32_t *cpos;          // vertex -> slot (read for vertices that have one only)
+    uint32_t *csel;               // selection bits over slots
+    const int64_t *ncand;         // number of slots (device)
 };
+
+// The count of vertex v (every decremented vertex is a member of some set, so it has a slot
+// when the counts are sparse).
+__device__ __forceinline__ uint32_t *cnt_ptr(const SelArgs &A, uint32_t v) {
+    return A.cpos ? &A.counts[A.cpos[v]] : &A.counts[v];
+}
 
 // Exact argmax over counts, stage 1: each block writes the best key of its slice to
 // partial[block]; the consumer kernels of the same iteration reduce the partials
@@ -69,13 +81,74 @@ HBM_KERNEL(k_sel_init, SelArgs, 256) {
     const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     const int64_t sw = ((int64_t)A.n + 31) / 32;
-    for (int64_t v = tid; v < A.n; v += nthr) A.counts[v] = A.hist ? A.hist[v] : 0u;
+    if (A.cpos) {  // sparse: the slot counts were written with the slots
+        const int64_t cw = (*A.ncand + 31) / 32;
+        for (int64_t w = tid; w < cw; w += nthr) A.csel[w] = 0u;
+    } else {
+        for (int64_t v = tid; v < A.n; v += nthr) A.counts[v] = A.hist ? A.hist[v] : 0u;
+    }
     for (int64_t v = tid; v < sw; v += nthr) A.selmask[v] = 0u;
     for (int64_t w = tid; w < A.words; w += nthr) A.covered[w] = 0ull;
     for (int64_t i = tid; i < A.k; i += nthr) A.keys[i] = 0ull;
 }
 
 constexpr int AM_UNROLL = 4;
+
+// Sparse counts: the slots' keys, and for every vertex without a slot (count 0 forever) the
+// key of the lowest unselected id, (0 + 1) << 32 | ~id: a vertex of count 0 can only win as the
+// lowest unselected id, and where that vertex has a slot its own key is at least as large.
+__device__ unsigned long long argmax_sparse(const SelArgs &A, int64_t tid, int64_t nthr) {
+    unsigned long long best = 0;
+    const int64_t m = *A.ncand;
+    const int64_t m4 = m >> 2;
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
+    const uint4 *i4 = reinterpret_cast<const uint4 *>(A.cand);
+    for (int64_t q0 = tid; q0 < m4; q0 += nthr * AM_UNROLL) {
+        uint4 c[AM_UNROLL], id[AM_UNROLL];
+        uint32_t smw[AM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < AM_UNROLL; u++) {
+            const int64_t q = q0 + (int64_t)u * nthr;
+            if (q < m4) {
+                c[u] = c4[q];
+                id[u] = i4[q];
+                smw[u] = A.csel[q >> 3];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < AM_UNROLL; u++) {
+            const int64_t q = q0 + (int64_t)u * nthr;
+            if (q >= m4) break;
+            const uint32_t sm = smw[u] >> ((q & 7) * 4);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const uint32_t cr = r == 0 ? c[u].x : r == 1 ? c[u].y : r == 2 ? c[u].z : c[u].w;
+                const uint32_t vr = r == 0 ? id[u].x : r == 1 ? id[u].y : r == 2 ? id[u].z : id[u].w;
+                const unsigned long long key =
+                    ((sm >> r) & 1u) ? 0ull : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~vr);
+                best = key > best ? key : best;
+            }
+        }
+    }
+    for (int64_t i = m4 * 4 + tid; i < m; i += nthr) {
+        const bool sel = (A.csel[i >> 5] >> (i & 31)) & 1u;
+        const unsigned long long key =
+            sel ? 0ull : (((unsigned long long)A.counts[i] + 1ull) << 32) | (unsigned long long)(~A.cand[i]);
+        best = key > best ? key : best;
+    }
+    const int64_t sw = ((int64_t)A.n + 31) / 32;
+    for (int64_t w = tid; w < sw; w += nthr) {
+        uint32_t free_bits = ~A.selmask[w];
+        const int64_t left = (int64_t)A.n - w * 32;
+        if (left < 32) free_bits &= (1u << left) - 1u;  // no vertex past n
+        if (free_bits) {
+            const uint32_t v = (uint32_t)(w * 32) + (uint32_t)(__ffs(free_bits) - 1);
+            const unsigned long long key = (1ull << 32) | (unsigned long long)(~v);
+            best = key > best ? key : best;
+        }
+    }
+    return best;
+}
 
 HBM_KERNEL(k_argmax, SelArgs, 256) {
     const int t = x;
@@ -84,8 +157,8 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     for (int64_t w = tid; w < A.words; w += nthr) A.newly[w] = 0ull;
     if (A.big && tid < 2) A.big[tid] = 0u;
-    unsigned long long best = 0;
-    const int64_t n4 = A.n >> 2;
+    unsigned long long best = A.cpos ? argmax_sparse(A, tid, nthr) : 0ull;
+    const int64_t n4 = A.cpos ? 0 : A.n >> 2;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
     // AM_UNROLL independent 16-byte loads in flight per thread: the pass is bound by HBM, and
     // one outstanding load per wave would leave it latency-bound
@@ -116,7 +189,7 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
             }
         }
     }
-    for (int64_t v = n4 * 4 + tid; v < A.n; v += nthr) {
+    for (int64_t v = A.cpos ? A.n : n4 * 4 + tid; v < A.n; v += nthr) {
         const bool sel = (A.selmask[v >> 5] >> (v & 31)) & 1u;
         const unsigned long long key =
             sel ? 0ull : (((unsigned long long)A.counts[v] + 1ull) << 32) | (unsigned long long)(~(uint32_t)v);
@@ -246,7 +319,7 @@ __device__ __forceinline__ void cache_init(DecCache &C) {
     }
 }
 
-__device__ __forceinline__ void cache_dec(DecCache &C, uint32_t *counts, uint32_t v) {
+__device__ __forceinline__ void cache_dec(DecCache &C, const SelArgs &A, uint32_t v) {
     const uint32_t h = (v * 0x9E3779B1u) >> (32 - 10);
     uint32_t x = C.id[h];
     if (x == 0xFFFFFFFFu) {
@@ -254,13 +327,13 @@ __device__ __forceinline__ void cache_dec(DecCache &C, uint32_t *counts, uint32_
         x = old == 0xFFFFFFFFu ? v : old;
     }
     if (x == v) atomicAdd(&C.cnt[h], 1u);
-    else atomicSub(&counts[v], 1u);
+    else atomicSub(cnt_ptr(A, v), 1u);
 }
 
 // after a __syncthreads: push the cached decrements to device memory
-__device__ __forceinline__ void cache_flush(DecCache &C, uint32_t *counts) {
+__device__ __forceinline__ void cache_flush(DecCache &C, const SelArgs &A) {
     for (int i = threadIdx.x; i < CC_SLOTS; i += blockDim.x)
-        if (C.cnt[i]) atomicSub(&counts[C.id[i]], C.cnt[i]);
+        if (C.cnt[i]) atomicSub(cnt_ptr(A, C.id[i]), C.cnt[i]);
 }
 
 __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, const uint32_t *buf, uint64_t pos,
@@ -269,9 +342,9 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, co
     for (uint32_t q = 0; q < nesc; q++) {
         const uint32_t v = peek32(buf, pos) >> (32 - A.wbits);
         pos += A.wbits;
-        cache_dec(C, A.counts, v);
+        cache_dec(C, A, v);
     }
-    while (pos < end) cache_dec(C, A.counts, dec_code(A, tb, buf, pos));
+    while (pos < end) cache_dec(C, A, dec_code(A, tb, buf, pos));
 }
 
 // A newly covered set whose string is long: its members are decremented by k_dec_big.
@@ -405,7 +478,7 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         wave_sync();
     }
     __syncthreads();
-    cache_flush(C, A.counts);
+    cache_flush(C, A);
 }
 
 // Records u* (bit 0 of block 0) and, when u* is hot or the store is plain, marks the newly
@@ -419,6 +492,10 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
     if (bid == 0 && threadIdx.x == 0) {
         atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
+        if (A.cpos && A.hist[u] > 0) {  // u has a slot
+            const int32_t p = A.cpos[u];
+            atomicOr(&A.csel[p >> 5], 1u << (p & 31));
+        }
         A.keys[t] = key;
     }
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
@@ -446,12 +523,12 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
                 rest &= rest - 1;
                 const int64_t j = w * 64 + b;
                 const int64_t e = A.raw_off[j + 1];
-                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A.counts, (uint32_t)A.raw_mem[i]);
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A, (uint32_t)A.raw_mem[i]);
             }
         }
     }
     __syncthreads();
-    cache_flush(C, A.counts);
+    cache_flush(C, A);
 }
 
 // Members of the queued long strings, one wave per string: the escaped ids have fixed width,
@@ -484,7 +561,7 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
         const uint64_t ce = (uint64_t)A.bitoff[j + 1];
         const uint32_t nesc = read_gamma(A.payload, pos) - 1;
         for (uint32_t q = lane; q < nesc; q += WAVE)
-            cache_dec(C, A.counts, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W));
+            cache_dec(C, A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W));
         const uint64_t cs = pos + (uint64_t)nesc * W;
         // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
         const uint64_t m0 = cs / CK_SLOT + 1;
@@ -510,13 +587,13 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
             if (sg < nseg) {
                 uint64_t pp = p - wlo * 32;
                 const uint64_t ee = e - wlo * 32;
-                while (pp < ee) cache_dec(C, A.counts, dec_code(A, tb, stage[wv], pp));
+                while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage[wv], pp));
             }
             wave_sync();
         }
     }
     __syncthreads();
-    cache_flush(C, A.counts);
+    cache_flush(C, A);
 }
 
 // hot counts -= popcount(row AND newly): block b covers hot ranks [256 (b mod hx), +256)
@@ -532,16 +609,103 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
         const unsigned long long nwv = A.newly[w];
         if (nwv && h < A.nhot) acc += __popcll(A.bitmap[w * (int64_t)A.nhot + h] & nwv);
     }
-    if (acc) atomicSub(&A.counts[A.hot[h]], acc);
+    if (acc) atomicSub(cnt_ptr(A, (uint32_t)A.hot[h]), acc);
 }
 
 void select_free(Ctx &c) {
     SelState &S = c.sel;
-    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big}) buf_free(c, *b);
+    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big, &S.cand, &S.cpos, &S.csel,
+                   &S.sbcnt, &S.sboff})
+        buf_free(c, *b);
     S.words_cap = 0;
 }
 
 namespace {
+
+// ---------------------------------------------------------------- sparse count slots
+// The vertices with a nonzero store frequency, ascending: per block of SL_SPAN vertices a
+// count, an exclusive scan of the counts (its last entry is the number of slots, left on the
+// device for the kernels), then each block writes its slots in order: the vertex, the
+// vertex's slot, and the slot's starting count.
+constexpr int SL_T = 256, SL_ITEMS = 16, SL_SPAN = SL_T * SL_ITEMS;
+
+__global__ __launch_bounds__(SL_T) void k_slot_count(const uint32_t *hist, int32_t n, uint32_t *bcnt) {
+    __shared__ uint32_t ws[SL_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SL_SPAN;
+    uint32_t c = 0;
+    for (int i = 0; i < SL_ITEMS; i++) {
+        const int64_t v = base + (int64_t)i * SL_T + threadIdx.x;
+        if (v < n && hist[v]) c++;
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < SL_T / WAVE; w++) t += ws[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(SL_T) void k_slot_write(const uint32_t *hist, int32_t n, const int64_t *boff,
+                                                     uint32_t *cand, int32_t *cpos, uint32_t *ccnt) {
+    __shared__ uint32_t ws[SL_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SL_SPAN;
+    const int wv = threadIdx.x / WAVE;
+    int64_t at = boff[blockIdx.x];
+    for (int i = 0; i < SL_ITEMS; i++) {
+        const int64_t v = base + (int64_t)i * SL_T + threadIdx.x;
+        const uint32_t h = v < n ? hist[v] : 0u;
+        const uint32_t f = h ? 1u : 0u;
+        const uint32_t inc = wave_incl_scan(f);
+        if (lane_id() == WAVE - 1) ws[wv] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int x = 0; x < SL_T / WAVE; x++) {
+            if (x < wv) before += ws[x];
+            tot += ws[x];
+        }
+        if (f) {
+            const int64_t p = at + before + inc - 1;
+            cand[p] = (uint32_t)v;
+            cpos[v] = (int32_t)p;
+            ccnt[p] = h;
+        }
+        at += tot;
+        __syncthreads();
+    }
+}
+
+// Build the slots of context c on the root stream (SPARSE_COUNTS 1), or, by default, when the
+// graph is large and the slots few enough for the argmax to read at most half of what dense
+// counts cost (8 bytes per slot and a bit per vertex against 4 bytes per vertex).  Returns the
+// number of slots, or -1 for dense counts.
+static int64_t build_slots(Ctx &root, Ctx &c) {
+    const int32_t n = c.g.n;
+    if (c.sparse_counts == 0 || !c.s.hist.p || c.s.nsets == 0) return -1;
+    if (c.sparse_counts == 2 && n < (1 << 22)) return -1;
+    SelState &S = c.sel;
+    const int64_t nblk = ((int64_t)n + SL_SPAN - 1) / SL_SPAN;
+    buf_grow(c, S.sbcnt, (size_t)(nblk + 1) * 4, false);
+    buf_grow(c, S.sboff, (size_t)(nblk + 1) * 8, false);
+    const hipStream_t st = root.stream;
+    HBM_HIP(hipMemsetAsync(S.sbcnt.as<uint32_t>() + nblk, 0, 4, st));  // the scan's last input
+    k_slot_count<<<(unsigned)nblk, SL_T, 0, st>>>(c.s.hist.as<uint32_t>(), n, S.sbcnt.as<uint32_t>());
+    HBM_HIP(hipGetLastError());
+    scan_u32_to_i64(root, S.sbcnt.as<uint32_t>(), S.sboff.as<int64_t>(), nblk + 1, 0);
+    int64_t m = 0;
+    HBM_HIP(hipMemcpyAsync(&m, S.sboff.as<int64_t>() + nblk, 8, hipMemcpyDeviceToHost, st));
+    HBM_HIP(hipStreamSynchronize(st));
+    if (c.sparse_counts == 2 && 8 * m + n / 8 >= 2 * (int64_t)n) return -1;
+    buf_grow(c, S.cand, (size_t)std::max<int64_t>(m, 1) * 4, false);
+    buf_grow(c, S.cpos, (size_t)n * 4, false);
+    buf_grow(c, S.csel, (size_t)((m + 31) / 32 + 1) * 4, false);
+    buf_grow(c, S.counts, (size_t)std::max<int64_t>(m, 1) * 4, false);
+    k_slot_write<<<(unsigned)nblk, SL_T, 0, st>>>(c.s.hist.as<uint32_t>(), n, S.sboff.as<int64_t>(),
+                                                   S.cand.as<uint32_t>(), S.cpos.as<int32_t>(), S.counts.as<uint32_t>());
+    HBM_HIP(hipGetLastError());
+    return m;
+}
 
 // Per-job launch geometry and algorithmic bytes of one selection iteration.
 struct SelJob {
@@ -558,7 +722,8 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     const int64_t T = s.nsets;
     const int64_t words = (T + 63) / 64;
     const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256 * AM_UNROLL, (int64_t)root.num_cus * 8);
-    buf_grow(c, S.counts, (size_t)n * 4, false);
+    const int64_t m = build_slots(root, c);  // -1: dense counts
+    if (m < 0) buf_grow(c, S.counts, (size_t)n * 4, false);
     buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
     buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
     buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
@@ -571,6 +736,10 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     A.words = words;
     A.n = n;
     A.counts = S.counts.as<uint32_t>();
+    A.cand = m >= 0 ? S.cand.as<uint32_t>() : nullptr;
+    A.cpos = m >= 0 ? S.cpos.as<int32_t>() : nullptr;
+    A.csel = m >= 0 ? S.csel.as<uint32_t>() : nullptr;
+    A.ncand = m >= 0 ? S.sboff.as<int64_t>() + (((int64_t)n + SL_SPAN - 1) / SL_SPAN) : nullptr;
     A.selmask = S.selmask.as<uint32_t>();
     A.covered = S.covered.as<unsigned long long>();
     A.newly = S.newly.as<unsigned long long>();
@@ -615,7 +784,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
     // reads and writes the covered and newly words (and the hot row when u* is hot).
-    J.b_arg = 4.0 * n + 4.0 * ((n + 31) / 32) + 8.0 * words;
+    J.b_arg = (m >= 0 ? 8.0 * m + m / 8.0 : 4.0 * n) + 4.0 * ((n + 31) / 32) + 8.0 * words;
     J.b_find = huff ? (double)((s.nbits + 7) / 8) + 16.0 * T : 4.0 * A.nraw;
     J.b_apply = 24.0 * words;
     return J;

@@ -337,12 +337,13 @@ def test_tuning_invariance(orc, ctx, tier1, budget, block, queue, lds):
 
 
 # ---------------------------------------------------------------- argmax edge cases
-@pytest.mark.parametrize("n,m,enc,k", [(1000, 6000, "NONE", 1000), (5003, 40000, "HUFFMAN", 300),
+@pytest.mark.parametrize("n,m,enc,k", [(1000, 6000, "NONE", 1000), (5003, 40000, "HUFFMAN", 5003),
                                        (9001, 90000, "HOT_BITMAP", 200), (9001, 90000, "HUFFMAN_HOT_BITMAP", 64)])
 def test_argmax_ragged_and_exhaustive(orc, ctx, n, m, enc, k):
     """Greedy seeds equal the oracle's, ties to the lowest id included, where n leaves a
     count tail past the last 4-vertex group (5003, 9001) and where k = n selects every
-    vertex, down to those of count 0."""
+    vertex, down to those of count 0; with dense counts and with sparse slots (vertices
+    outside the store win only as the lowest unselected id)."""
     _say("argmax edge cases", n, m, enc, k)
     g = G.erdos_renyi(n, m, seed=n)
     ctx.hbm_load_graph(g.n, g.row_ptr, g.dst, g.w, model="IC", prob="EDGE")
@@ -352,5 +353,7 @@ def test_argmax_ragged_and_exhaustive(orc, ctx, n, m, enc, k):
     og = _ograph(orc, g, "IC", "EDGE")
     st = orc.sample_store(og, 7, theta)
     os_, og_, oc = orc.greedy(st, g.n, k)
-    seeds, gains, cov = ctx.hbm_select_seeds(k)
-    assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
+    for sparse in (0, 1):
+        ctx.hbm_set_tuning("SPARSE_COUNTS", sparse)
+        seeds, gains, cov = ctx.hbm_select_seeds(k)
+        assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc, f"SPARSE_COUNTS={sparse}"
