@@ -166,6 +166,8 @@ struct SelState {
     Buf csel;     // sparse counts: selection bits over slots
     Buf sbcnt;    // sparse counts: per-block slot counts and their scan
     Buf sboff;
+    Buf slut;     // sparse counts: decode LUT and symbol table over slots
+    Buf ssym;
     int64_t words_cap = 0;
 };
 

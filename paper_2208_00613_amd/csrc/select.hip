@@ -66,11 +66,10 @@ struct SelArgs {
     const int64_t *ncand;         // number of slots (device)
 };
 
-// The count of vertex v (every decremented vertex is a member of some set, so it has a slot
-// when the counts are sparse).
-__device__ __forceinline__ uint32_t *cnt_ptr(const SelArgs &A, uint32_t v) {
-    return A.cpos ? &A.counts[A.cpos[v]] : &A.counts[v];
-}
+// Index into `counts` of vertex v (every decremented vertex is a member of some set, so it
+// has a slot when the counts are sparse).  Decoded Huffman symbols are already such indices:
+// with sparse counts the decode tables name slots instead of vertices.
+__device__ __forceinline__ uint32_t ckey(const SelArgs &A, uint32_t v) { return A.cpos ? (uint32_t)A.cpos[v] : v; }
 
 // Exact argmax over counts, stage 1: each block writes the best key of its slice to
 // partial[block]; the consumer kernels of the same iteration reduce the partials
@@ -319,6 +318,7 @@ __device__ __forceinline__ void cache_init(DecCache &C) {
     }
 }
 
+// v: an index into A.counts (see ckey)
 __device__ __forceinline__ void cache_dec(DecCache &C, const SelArgs &A, uint32_t v) {
     const uint32_t h = (v * 0x9E3779B1u) >> (32 - 10);
     uint32_t x = C.id[h];
@@ -327,13 +327,13 @@ __device__ __forceinline__ void cache_dec(DecCache &C, const SelArgs &A, uint32_
         x = old == 0xFFFFFFFFu ? v : old;
     }
     if (x == v) atomicAdd(&C.cnt[h], 1u);
-    else atomicSub(cnt_ptr(A, v), 1u);
+    else atomicSub(&A.counts[v], 1u);
 }
 
 // after a __syncthreads: push the cached decrements to device memory
 __device__ __forceinline__ void cache_flush(DecCache &C, const SelArgs &A) {
     for (int i = threadIdx.x; i < CC_SLOTS; i += blockDim.x)
-        if (C.cnt[i]) atomicSub(cnt_ptr(A, C.id[i]), C.cnt[i]);
+        if (C.cnt[i]) atomicSub(&A.counts[C.id[i]], C.cnt[i]);
 }
 
 __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, const uint32_t *buf, uint64_t pos,
@@ -342,7 +342,7 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, co
     for (uint32_t q = 0; q < nesc; q++) {
         const uint32_t v = peek32(buf, pos) >> (32 - A.wbits);
         pos += A.wbits;
-        cache_dec(C, A, v);
+        cache_dec(C, A, ckey(A, v));
     }
     while (pos < end) cache_dec(C, A, dec_code(A, tb, buf, pos));
 }
@@ -523,7 +523,7 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
                 rest &= rest - 1;
                 const int64_t j = w * 64 + b;
                 const int64_t e = A.raw_off[j + 1];
-                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A, (uint32_t)A.raw_mem[i]);
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A, ckey(A, (uint32_t)A.raw_mem[i]));
             }
         }
     }
@@ -561,7 +561,7 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
         const uint64_t ce = (uint64_t)A.bitoff[j + 1];
         const uint32_t nesc = read_gamma(A.payload, pos) - 1;
         for (uint32_t q = lane; q < nesc; q += WAVE)
-            cache_dec(C, A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W));
+            cache_dec(C, A, ckey(A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W)));
         const uint64_t cs = pos + (uint64_t)nesc * W;
         // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
         const uint64_t m0 = cs / CK_SLOT + 1;
@@ -609,13 +609,13 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
         const unsigned long long nwv = A.newly[w];
         if (nwv && h < A.nhot) acc += __popcll(A.bitmap[w * (int64_t)A.nhot + h] & nwv);
     }
-    if (acc) atomicSub(cnt_ptr(A, (uint32_t)A.hot[h]), acc);
+    if (acc) atomicSub(&A.counts[ckey(A, (uint32_t)A.hot[h])], acc);
 }
 
 void select_free(Ctx &c) {
     SelState &S = c.sel;
     for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big, &S.cand, &S.cpos, &S.csel,
-                   &S.sbcnt, &S.sboff})
+                   &S.sbcnt, &S.sboff, &S.slut, &S.ssym})
         buf_free(c, *b);
     S.words_cap = 0;
 }
@@ -674,6 +674,19 @@ __global__ __launch_bounds__(SL_T) void k_slot_write(const uint32_t *hist, int32
         at += tot;
         __syncthreads();
     }
+}
+
+// Decode tables over slots: the LUT's direct entries and the canonical symbol table name slots
+// instead of vertices (every coded vertex occurs in the warm-up sets, so it has a slot).
+__global__ void k_slot_tables(const uint32_t *lut, const int32_t *symtab, int64_t nsym, const int32_t *cpos,
+                              uint32_t *slut, int32_t *ssym) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < (1 << LUT_BITS); i += nthr) {
+        const uint32_t e = lut[i];
+        slut[i] = (e & 31u) ? ((uint32_t)cpos[e >> 5] << 5) | (e & 31u) : e;
+    }
+    for (int64_t i = tid; i < nsym; i += nthr) ssym[i] = cpos[symtab[i]];
 }
 
 // Build the slots of context c on the root stream (SPARSE_COUNTS 1), or, by default, when the
@@ -758,6 +771,17 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     A.symtab = s.symtab.as<int32_t>();
     A.lens = s.lens.as<uint8_t>();
     A.lut = s.lut.as<uint32_t>();
+    if (huff && T > 0 && m >= 0) {  // decode straight to slots
+        const int64_t nsym = std::max<int64_t>(s.cb.nsym, 1);
+        buf_grow(c, S.slut, ((size_t)1 << LUT_BITS) * 4, false);
+        buf_grow(c, S.ssym, (size_t)nsym * 4, false);
+        k_slot_tables<<<grid_for(std::max<int64_t>(nsym, 1 << LUT_BITS), 256, 1024), 256, 0, root.stream>>>(
+            s.lut.as<uint32_t>(), s.symtab.as<int32_t>(), s.cb.nsym, S.cpos.as<int32_t>(), S.slut.as<uint32_t>(),
+            S.ssym.as<int32_t>());
+        HBM_HIP(hipGetLastError());
+        A.lut = S.slut.as<uint32_t>();
+        A.symtab = S.ssym.as<int32_t>();
+    }
     A.codes = s.codes.as<uint32_t>();
     A.minlen = s.cb.minlen;
     A.wbits = s.cb.wbits;
