@@ -394,13 +394,33 @@ HBM_KERNEL(k_find_raw, SelArgs, 256) {
     }
 }
 
+// Copy nw words from device memory to a wave's LDS buffer with ST_UNROLL loads in flight per
+// lane (one outstanding load per lane would leave the copy latency-bound).
+constexpr int ST_UNROLL = 8;
+__device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *src, uint64_t nw) {
+    const unsigned lane = lane_id();
+    for (uint64_t q0 = lane; q0 < nw; q0 += (uint64_t)WAVE * ST_UNROLL) {
+        uint32_t v[ST_UNROLL];
+#pragma unroll
+        for (int u = 0; u < ST_UNROLL; u++) {
+            const uint64_t q = q0 + (uint64_t)u * WAVE;
+            v[u] = q < nw ? src[q] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < ST_UNROLL; u++) {
+            const uint64_t q = q0 + (uint64_t)u * WAVE;
+            if (q < nw) dst[q] = v[u];
+        }
+    }
+}
+
 // Huffman strings (Alg. 2's DecodeFind), one wave per 64-set word and one lane per set:
 // a partial decode that stops at u* (a codeless u* is sought among the escaped ids, which
 // come first and ascending; a coded u* is matched by its canonical code and the scan ends
-// at the first larger code).  A set holding u* is marked covered and its members are
-// decremented at once (a long string is queued for k_dec_big, which spreads it over a
-// wave).  The word's strings are contiguous: they are copied to LDS with coalesced loads
-// first (when they fit).  Each wave loads the next word's covered mask and bit offsets
+// at the first larger code).  A set holding u* is marked covered; its members are
+// decremented at once by the lane when its string is short and staged, else the string is
+// queued for k_dec_big, which spreads it over a wave.  The word's strings are contiguous:
+// they are copied to LDS with coalesced loads first (when they fit).  Each wave loads the next word's covered mask and bit offsets
 // before decoding the current one, and the grid is sized to stay resident.
 constexpr int STAGE_WORDS = 1024;
 
@@ -451,7 +471,7 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         const uint32_t *buf = A.payload;
         uint64_t off = 0;
         if (staged) {
-            for (uint64_t q = lane; q < nw; q += WAVE) stage[wv][q] = A.payload[wlo + q];
+            stage_words(stage[wv], A.payload + wlo, nw);
             wave_sync();
             buf = stage[wv];
             off = wlo * 32;
@@ -582,7 +602,7 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
             const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
             const uint64_t wlo = lo >> 5;
             const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
-            for (uint64_t q = lane; q < nw; q += WAVE) stage[wv][q] = A.payload[wlo + q];
+            stage_words(stage[wv], A.payload + wlo, nw);
             wave_sync();
             if (sg < nseg) {
                 uint64_t pp = p - wlo * 32;
