@@ -34,6 +34,7 @@ constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 struct SampleArgs {
     const int64_t *in_ptr;
     const int32_t *in_src;
+    const uint4 *in_rec;    // IC: per in-edge {source, its in-edge range, its WC threshold}
     const uint32_t *thr;
     const uint32_t *guide;  // LT cut-point index
     int32_t n;
@@ -148,17 +149,19 @@ __device__ __forceinline__ uint32_t lt_pick(const SampleArgs &a, uint32_t cur, u
 }
 
 // ---------------------------------------------------------------------------- IC tier 1
+// The queue keeps each member's in-edge range and WC threshold beside it (from the in-edge
+// record that found it), so expanding a level reads no device memory before its Philox calls.
 template <int HB>
 struct IcT1Lds {
     static constexpr int HC = 1 << HB;
     static constexpr int QC = HC / 2;
     uint32_t h[HC];
     uint32_t q[QC];
+    uint32_t qe0[QC];
+    uint32_t qe1[QC];
+    uint32_t qt[QC];
     uint16_t qs[QC];
     uint32_t sP[WAVE];
-    uint32_t sE0[WAVE];
-    uint32_t sE1[WAVE];
-    uint32_t sT[WAVE];
     uint32_t cnt;
     uint32_t ovf;
 };
@@ -190,6 +193,9 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                 uint32_t hs = hash32(root, HB);
                 S.h[hs] = root;
                 S.q[0] = root;
+                S.qe0[0] = (uint32_t)a.in_ptr[root];
+                S.qe1[0] = (uint32_t)a.in_ptr[root + 1];
+                S.qt[0] = a.wc ? a.thr[root] : 0u;
                 S.qs[0] = (uint16_t)hs;
                 S.cnt = 1;
                 S.ovf = 0;
@@ -201,13 +207,11 @@ __device__ void ic_t1_body(const SampleArgs &a) {
             bool ovf = false;
             while (head < qsize) {
                 const uint32_t nbat = qsize - head < (uint32_t)WAVE ? qsize - head : (uint32_t)WAVE;
-                uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
+                uint32_t e0 = 0, e1 = 0, ng = 0;
                 if (lane < nbat) {
-                    const uint32_t v = S.q[head + lane];
-                    e0 = (uint32_t)a.in_ptr[v];
-                    e1 = (uint32_t)a.in_ptr[v + 1];
+                    e0 = S.qe0[head + lane];
+                    e1 = S.qe1[head + lane];
                     ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
-                    if (a.wc) tv = a.thr[v];
                 }
                 const uint32_t P = wave_incl_scan(ng);
                 const uint32_t G = __shfl(P, WAVE - 1, WAVE);
@@ -221,10 +225,8 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                     s_edges += wave_sum(e1 - e0);
                 }
                 S.sP[lane] = P;
-                S.sE0[lane] = e0;
-                S.sE1[lane] = e1;
-                S.sT[lane] = tv;
                 wave_sync();
+                const uint32_t hb = head;  // the batch's queue entries: hb + vertex index
                 head += nbat;
                 uint32_t i = 0;  // vertex of this lane's group: searched only when g leaves it
                 for (uint32_t base = 0; base < G; base += WAVE) {
@@ -232,12 +234,12 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                     if (g < G) {
                         if (S.sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(S.sP, i + 1, (uint32_t)WAVE, g);
                         const uint32_t excl = i ? S.sP[i - 1] : 0u;
-                        const uint32_t E0 = S.sE0[i], E1 = S.sE1[i];
+                        const uint32_t E0 = S.qe0[hb + i], E1 = S.qe1[hb + i];
                         const uint32_t grp = (E0 >> 2) + (g - excl);
                         const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
                         uint4 t4;
                         if (a.wc) {
-                            const uint32_t T = S.sT[i];
+                            const uint32_t T = S.qt[hb + i];
                             t4 = make_uint4(T, T, T, T);
                         } else {
                             t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
@@ -254,7 +256,8 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                                     S.ovf = 1;
                                     continue;
                                 }
-                                const uint32_t u = (uint32_t)a.in_src[e];
+                                const uint4 r = a.in_rec[e];
+                                const uint32_t u = r.x;
                                 uint32_t hs = hash32(u, HB);
                                 for (;;) {
                                     const uint32_t old = atomicCAS(&S.h[hs], EMPTY, u);
@@ -262,6 +265,9 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                                         const uint32_t p = atomicAdd(&S.cnt, 1u);
                                         if (p < (uint32_t)L::QC) {
                                             S.q[p] = u;
+                                            S.qe0[p] = r.y;
+                                            S.qe1[p] = r.z;
+                                            S.qt[p] = r.w;
                                             S.qs[p] = (uint16_t)hs;
                                         } else {
                                             S.ovf = 1;
@@ -598,6 +604,7 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
 // (hash of 16384 slots, 112 KB, one 1024-thread workgroup per CU), and only sets beyond that
 // reach the device-bitmap tier.  The hash never holds more than CAP + NT keys.
 constexpr int T2L_CAP = 2048;
+constexpr int T2L_CAP_REGULAR = T2L_CAP;
 constexpr int T2L_HASH_BITS = 13;
 constexpr int T2X_CAP = 8192;
 constexpr int T2X_HASH_BITS = 14;
@@ -610,18 +617,25 @@ struct T2LArgs {
     int ovf_cw;          // control word counting them
 };
 
+// META: the queue keeps each member's in-edge range and WC threshold beside it, taken from the
+// in-edge record that found it, so a level's expansion reads no device memory before its Philox
+// calls (the regular capacity; the extra-large one has no LDS left for it and loads the ranges).
 template <int NT, int CAP, int HBITS>
 __device__ void big_lds_body(const T2LArgs &t) {
     constexpr int T2L_HASH = 1 << HBITS;
     constexpr int T2L_HASH_BITS = HBITS;
     constexpr int T2L_CAP = CAP;
+    constexpr bool META = CAP == T2L_CAP_REGULAR;
     const SampleArgs &a = t.a;
     __shared__ uint32_t h[T2L_HASH];
     __shared__ uint32_t q[T2L_CAP];
+    __shared__ uint32_t qe0[META ? T2L_CAP : 1];
+    __shared__ uint32_t qe1[META ? T2L_CAP : 1];
+    __shared__ uint32_t qt[META ? T2L_CAP : 1];
     __shared__ uint32_t sP[NT];
-    __shared__ uint32_t sE0[NT];
-    __shared__ uint32_t sE1[NT];
-    __shared__ uint32_t sT[NT];
+    __shared__ uint32_t sE0[META ? 1 : NT];
+    __shared__ uint32_t sE1[META ? 1 : NT];
+    __shared__ uint32_t sT[META ? 1 : NT];
     __shared__ uint32_t wsum[NT / WAVE];
     __shared__ uint32_t qn;
     __shared__ uint32_t item;
@@ -646,6 +660,11 @@ __device__ void big_lds_body(const T2LArgs &t) {
         if (threadIdx.x == 0) {
             h[hash32(root, T2L_HASH_BITS)] = root;
             q[0] = root;
+            if constexpr (META) {
+                qe0[0] = (uint32_t)a.in_ptr[root];
+                qe1[0] = (uint32_t)a.in_ptr[root + 1];
+                qt[0] = a.wc ? a.thr[root] : 0u;
+            }
             qn = 1;
             ovf = 0;
         }
@@ -656,17 +675,28 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
                 uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
                 if (threadIdx.x < cn) {
-                    const uint32_t v = q[c0 + threadIdx.x];
-                    e0 = (uint32_t)a.in_ptr[v];
-                    e1 = (uint32_t)a.in_ptr[v + 1];
+                    if constexpr (META) {
+                        e0 = qe0[c0 + threadIdx.x];
+                        e1 = qe1[c0 + threadIdx.x];
+                    } else {
+                        const uint32_t v = q[c0 + threadIdx.x];
+                        e0 = (uint32_t)a.in_ptr[v];
+                        e1 = (uint32_t)a.in_ptr[v + 1];
+                        if (a.wc) tv = a.thr[v];
+                    }
                     ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
-                    if (a.wc) tv = a.thr[v];
                 }
                 const uint32_t P = block_incl_scan(ng, wsum);
                 sP[threadIdx.x] = P;
-                sE0[threadIdx.x] = e0;
-                sE1[threadIdx.x] = e1;
-                sT[threadIdx.x] = tv;
+                if constexpr (!META) {
+                    sE0[threadIdx.x] = e0;
+                    sE1[threadIdx.x] = e1;
+                    sT[threadIdx.x] = tv;
+                }
+                // the batch's ranges and thresholds, by vertex index within the batch
+                const uint32_t *bE0 = META ? qe0 + c0 : sE0;
+                const uint32_t *bE1 = META ? qe1 + c0 : sE1;
+                const uint32_t *bT = META ? qt + c0 : sT;
                 __syncthreads();
                 const uint32_t G = sP[NT - 1];
                 if (a.dctr) {
@@ -680,12 +710,12 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 for (uint32_t g = threadIdx.x; g < G; g += NT) {
                     if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
                     const uint32_t excl = i ? sP[i - 1] : 0u;
-                    const uint32_t E0 = sE0[i], E1 = sE1[i];
+                    const uint32_t E0 = bE0[i], E1 = bE1[i];
                     const uint32_t grp = (E0 >> 2) + (g - excl);
                     const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
                     uint4 t4;
                     if (a.wc) {
-                        const uint32_t T = sT[i];
+                        const uint32_t T = bT[i];
                         t4 = make_uint4(T, T, T, T);
                     } else {
                         t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
@@ -702,14 +732,25 @@ __device__ void big_lds_body(const T2LArgs &t) {
                                 ovf = 1;
                                 continue;
                             }
-                            const uint32_t u = (uint32_t)a.in_src[e];
+                            uint4 r;
+                            if constexpr (META) r = a.in_rec[e];
+                            else r.x = (uint32_t)a.in_src[e];
+                            const uint32_t u = r.x;
                             uint32_t hs = hash32(u, T2L_HASH_BITS);
                             for (;;) {
                                 const uint32_t old = atomicCAS(&h[hs], EMPTY, u);
                                 if (old == EMPTY) {
                                     const uint32_t p = atomicAdd(&qn, 1u);
-                                    if (p < (uint32_t)T2L_CAP) q[p] = u;
-                                    else ovf = 1;
+                                    if (p < (uint32_t)T2L_CAP) {
+                                        q[p] = u;
+                                        if constexpr (META) {
+                                            qe0[p] = r.y;
+                                            qe1[p] = r.z;
+                                            qt[p] = r.w;
+                                        }
+                                    } else {
+                                        ovf = 1;
+                                    }
                                     break;
                                 }
                                 if (old == u) break;
@@ -1092,6 +1133,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         SampleArgs &a = A[i];
         a.in_ptr = c.g.in_ptr.as<int64_t>();
         a.in_src = c.g.in_src.as<int32_t>();
+        a.in_rec = c.g.model == HBM_IC ? c.g.in_rec.as<uint4>() : nullptr;
         a.thr = c.g.thr.as<uint32_t>();
         a.guide = c.g.guide.as<uint32_t>();
         a.n = c.g.n;

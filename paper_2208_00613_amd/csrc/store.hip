@@ -1128,8 +1128,9 @@ void store_extend(Ctx &c, int64_t theta, uint64_t seed) {
     extend_stores(c, std::vector<Ctx *>{&c}, std::vector<int64_t>{theta}, std::vector<uint64_t>{seed});
 }
 
-// sum of x[0, n) into *out (added with one atomic per wave; *out starts at zero)
+// sum of x[0, n) into *out (one atomic per workgroup; *out starts at zero)
 __global__ __launch_bounds__(256) void k_sum_u32(const uint32_t *x, int64_t n, unsigned long long *out) {
+    __shared__ unsigned long long ws[256 / WAVE];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
     unsigned long long t = 0;
@@ -1141,7 +1142,13 @@ __global__ __launch_bounds__(256) void k_sum_u32(const uint32_t *x, int64_t n, u
     }
     for (int64_t i = n4 * 4 + tid; i < n; i += nthr) t += x[i];
     t = wave_sum(t);
-    if (lane_id() == 0 && t) atomicAdd(out, t);
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int w = 0; w < 256 / WAVE; w++) b += ws[w];
+        if (b) atomicAdd(out, b);
+    }
 }
 
 void store_stats(Ctx &c, hbm_store_stats *o) {
@@ -1170,7 +1177,7 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     if (s.hist.p && s.nsets) {
         buf_grow(c, s.mtmp, 8, true);
         buf_zero(c, s.mtmp, 0, 8);
-        k_sum_u32<<<grid_for(((int64_t)c.g.n + 3) / 4, 256, (int64_t)c.num_cus * 4), 256, 0, c.stream>>>(
+        k_sum_u32<<<grid_for(((int64_t)c.g.n + 3) / 4, 256 * 8, (int64_t)c.num_cus), 256, 0, c.stream>>>(
             s.hist.as<uint32_t>(), c.g.n, s.mtmp.as<unsigned long long>());
         HBM_HIP(hipGetLastError());
         unsigned long long t = 0;
