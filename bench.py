@@ -64,7 +64,7 @@ SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_block_xl", "i
                    "lt_sample_wave", "lt_sample_block", "sample_huge")
 
 
-def roofline(kstats, model, prob):
+def roofline(kstats, model, prob, workload):
     """Roofline of the kernel with the largest total time in one profiled step."""
     k = max(kstats, key=lambda r: r["total_ms"])
     avg_ms = k["total_ms"] / max(k["launches"], 1)
@@ -79,7 +79,7 @@ def roofline(kstats, model, prob):
         achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = traffic_for(k["name"])
+    out["traffic"] = traffic_for(k["name"], workload)
     out["kernel"] = k["name"]
     out["launches_per_step"] = k["launches"]
     out["avg_launch_ms"] = avg_ms
@@ -137,7 +137,7 @@ def traffic_probe(args):
     ctx.close()
 
 
-def traffic_summarize(fetch_csv, write_csv, out_path):
+def traffic_summarize(fetch_csv, write_csv, out_path, workload):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel from two rocprofv3 --pmc runs,
     each scaled by the reading of the 1 GiB copy; writes HBM bytes per launch per profile name."""
     import csv
@@ -172,15 +172,16 @@ def traffic_summarize(fetch_csv, write_csv, out_path):
             "python $GRAFT_REPO_ROOT/bench.py --traffic-probe",
             "python bench.py --traffic-summarize gpurun_out/pmc_fetch/f_counter_collection.csv "
             "gpurun_out/pmc_write/w_counter_collection.csv"]
-    out = {"commands": cmds, "workload": "bench.py default workload, one IMM step",
+    out = {"commands": cmds, "workload": "bench.py default workload, one IMM step", "workload_key": workload,
            "csrc_digest": csrc_digest(), "copy_kernel": ck[:80], "fetch_scale": f_scale, "write_scale": w_scale,
            "unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "kernels": kernels}
     json.dump(out, open(out_path, "w"), indent=1)
     print(json.dumps(out))
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
+def traffic_for(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels and
+    on this workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -188,7 +189,7 @@ def traffic_for(kernel):
         t = json.load(open(path))
     except ValueError:
         return None
-    if t.get("csrc_digest") != csrc_digest():
+    if t.get("csrc_digest") != csrc_digest() or t.get("workload_key") != workload:
         return None
     return t.get("kernels", {}).get(kernel)
 
@@ -299,7 +300,7 @@ def main_c4(args, P, torch, insts, graphs):
                    "eps": [0.5, 0.3]},
         "imm_s": cmp_["batched_s"], "batched_vs_plain": cmp_,
         "phase_ms": {"sample_encode": out[0][2]["t_sample_ms"], "select": out[0][2]["t_select_ms"]},
-        "roofline": roofline(kstats, "IC", "WC"),
+        "roofline": roofline(kstats, "IC", "WC", args.workload),
         "kernels": sorted(({"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3)}
                            for r in kstats), key=lambda r: -r["ms"])[:8],
     }
@@ -437,7 +438,7 @@ def main():
                     help="c5: arrival rates as fractions of the measured single-query service rate")
     args = ap.parse_args()
     if args.traffic_summarize:
-        return traffic_summarize(*args.traffic_summarize, os.path.join(ROOT, "profiles", "traffic.json"))
+        return traffic_summarize(*args.traffic_summarize, os.path.join(ROOT, "profiles", "traffic.json"), args.workload)
     if args.traffic_probe:
         return traffic_probe(args)
     if args.gpus != 1:
@@ -514,7 +515,7 @@ def main():
     ctx.hbm_imm(k, eps, l, seed)
     kstats = ctx.hbm_profile_read()
     ctx.hbm_profile(False)
-    out["roofline"] = roofline(kstats, c["model"], c["prob"])
+    out["roofline"] = roofline(kstats, c["model"], c["prob"], args.workload)
     out["kernels"] = sorted(({"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3)}
                              for r in kstats), key=lambda r: -r["ms"])[:8]
     if not args.no_cpu_baseline:
