@@ -420,9 +420,12 @@ __device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *src, 
 // at the first larger code).  A set holding u* is marked covered; its members are
 // decremented at once by the lane when its string is short and staged, else the string is
 // queued for k_dec_big, which spreads it over a wave.  The word's strings are contiguous:
-// they are copied to LDS with coalesced loads first (when they fit).  Each wave loads the next word's covered mask and bit offsets
-// before decoding the current one, and the grid is sized to stay resident.
-constexpr int STAGE_WORDS = 1024;
+// they are copied to LDS with coalesced loads first (when they fit).  Each wave loads the
+// next word's covered mask and bit offsets before decoding the current one, and the grid is
+// sized to stay resident.  The search is bound by decode latency, so residency matters more
+// than staging: with a stage of 256 words a block needs about 21 KB of LDS and seven blocks
+// (the register limit) fit a CU.
+constexpr int STAGE_WORDS = 256;
 
 HBM_KERNEL(k_find_huff, SelArgs, 256) {
     __shared__ Tabs tb;
@@ -820,7 +823,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     J.huff = huff;
     J.g_arg = g_arg;
     if (T == 0) J.g_find = 0;
-    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 4);  // resident: 4 blocks per CU
+    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 7);  // resident: 7 blocks per CU
     else J.g_find = A.nraw > 0 ? grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4) : 0;
     J.g_apply = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * nseg) : 0;
