@@ -289,7 +289,7 @@ typedef enum hbm_tune_key {
                                      to a workgroup of its own; 0 = no limit.  Default 4096 */
     HBM_TUNE_BLOCK_SETS = 2,      /* RR sets sampled per block (scratch index size), >= 1024.
                                      Default 2^21 */
-    HBM_TUNE_LT_PATH = 3,         /* LT walk length kept in LDS by one lane: 128 (default) or 256;
+    HBM_TUNE_LT_PATH = 3,         /* LT walk length kept in LDS by one lane: 32 (default), 64, 128 or 256;
                                      longer walks move to device memory */
     HBM_TUNE_T2_QUEUE = 4,        /* queue entries of a big-set slot (>= 64, default 2^20); a set with
                                      more members is redone by a few slots with full-size queues */

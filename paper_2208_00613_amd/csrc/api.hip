@@ -274,7 +274,7 @@ hbm_status hbm_autotune(hbm_ctx *const *ctxs, int32_t count, const hbm_query *qu
             {HBM_TUNE_T2_SLOTS, {2, 3, 4}, true},
             {HBM_TUNE_LDS_THREADS, {512, 1024}, ic},
             {HBM_TUNE_LDS_PER_CU, {2, 3}, ic},
-            {HBM_TUNE_LT_PATH, {128, 256}, lt},
+            {HBM_TUNE_LT_PATH, {32, 64, 128}, lt},
         };
         timed();  // warm-up: allocations at the current settings
         double best = timed();
@@ -418,7 +418,8 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             c.ic_t1_budget = value;
             break;
         case HBM_TUNE_LT_PATH:
-            HBM_REQUIRE(value == 128 || value == 256, HBM_EINVAL, "LT_PATH must be 128 or 256");
+            HBM_REQUIRE(value == 32 || value == 64 || value == 128 || value == 256, HBM_EINVAL,
+                        "LT_PATH must be 32, 64, 128 or 256");
             c.lt_lw = (int)value;
             break;
         case HBM_TUNE_T2_QUEUE:

@@ -206,7 +206,7 @@ struct Ctx {
     int ic_tier1 = 1;
     int64_t ic_t1_budget = 4096;
     int64_t block_sets = int64_t(1) << 21;
-    int lt_lw = 128;
+    int lt_lw = 32;
     int64_t t2_cap = int64_t(8) << 30;  // device bytes for big-set slots (bitmap + queue each)
     int64_t t2_queue = int64_t(1) << 20; // queue entries of a big-set slot
     int t2_per_cu = 4;                   // big-set slots (workgroups) per CU

@@ -1194,11 +1194,15 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     int s1b = lt.empty() ? -1 : prof_begin(root, "lt_sample_lane");
     glaunch(root, lt, ltb, 0,
             [&](const SampleArgs &a, unsigned g) {
-                if (lw == 128) k_lt_t1<128><<<g, WAVE, 0, st>>>(a);
+                if (lw == 32) k_lt_t1<32><<<g, WAVE, 0, st>>>(a);
+                else if (lw == 64) k_lt_t1<64><<<g, WAVE, 0, st>>>(a);
+                else if (lw == 128) k_lt_t1<128><<<g, WAVE, 0, st>>>(a);
                 else k_lt_t1<256><<<g, WAVE, 0, st>>>(a);
             },
             [&](const SampleArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
-                if (lw == 128) k_lt_t1_g<128><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+                if (lw == 32) k_lt_t1_g<32><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+                else if (lw == 64) k_lt_t1_g<64><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
+                else if (lw == 128) k_lt_t1_g<128><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
                 else k_lt_t1_g<256><<<g, WAVE, 0, st>>>(GroupArgs<SampleArgs>{d, b, cnt, x});
             });
     HBM_HIP(hipGetLastError());

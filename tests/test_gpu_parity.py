@@ -207,16 +207,18 @@ def test_sets_and_seeds_rmat(orc, ctx, model, prob, scale, theta):
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
 
 
-@pytest.mark.parametrize("queue", [1 << 20, 300])
-def test_lt_long_walks_all_tiers(orc, ctx, queue):
-    """A directed path with weight 1: walk length = root id + 1, crossing every LT tier
-    (with a 300-entry big-set queue, walks beyond it go through the huge-set pass)."""
-    _say("lt long walks, big-set queue", queue)
+@pytest.mark.parametrize("queue,lw", [(1 << 20, 32), (300, 32), (1 << 20, 64), (1 << 20, 256)])
+def test_lt_long_walks_all_tiers(orc, ctx, queue, lw):
+    """A directed path with weight 1: walk length = root id + 1, crossing every LT tier at
+    each lane path length (with a 300-entry big-set queue, walks beyond it go through the
+    huge-set pass)."""
+    _say("lt long walks, big-set queue", queue, "lane path", lw)
     n = 5000
     g = G._csr_from_pairs(n, np.arange(n - 1), np.arange(1, n))
     g = G.with_weights(g, np.ones(g.m, dtype=np.float32))
     ctx.load_synth(g, "LT", "EDGE")
     ctx.hbm_set_tuning("T2_QUEUE", queue)
+    ctx.hbm_set_tuning("LT_PATH", lw)
     ctx.hbm_set_encoding("NONE")
     ctx.hbm_sample_rr(400, 9)
     og = _ograph(orc, g, "LT", "EDGE")
