@@ -64,6 +64,7 @@ struct SelArgs {
     const int32_t *cpos;          // vertex -> slot (read for vertices that have one only)
     uint32_t *csel;               // selection bits over slots
     const int64_t *ncand;         // number of slots (device)
+    unsigned long long *pbits;    // profiling: payload bits decoded by k_dec_big (else null)
 };
 
 // Index into `counts` of vertex v (every decremented vertex is a member of some set, so it
@@ -574,45 +575,68 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
     const int wv = threadIdx.x / WAVE;
     const uint32_t W = (uint32_t)A.wbits;
     const uint32_t nq = A.big[0];
-    for (;;) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(&A.big[1], 1u);
-        it = __shfl(it, 0, WAVE);
-        if (it >= nq) break;
-        const int64_t j = A.big[2 + it];
-        uint64_t pos = (uint64_t)A.bitoff[j];
-        const uint64_t ce = (uint64_t)A.bitoff[j + 1];
-        const uint32_t nesc = read_gamma(A.payload, pos) - 1;
-        for (uint32_t q = lane; q < nesc; q += WAVE)
-            cache_dec(C, A, ckey(A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W)));
-        const uint64_t cs = pos + (uint64_t)nesc * W;
-        // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
-        const uint64_t m0 = cs / CK_SLOT + 1;
-        const uint64_t m1 = ce > 0 ? (ce - 1) / CK_SLOT : 0;
-        const uint64_t nseg = m1 >= m0 ? m1 - m0 + 2 : 1;
-        auto seg_start = [&](uint64_t sg) -> uint64_t {
-            if (sg == 0) return cs;
-            if (sg >= nseg) return ce;
-            const uint64_t b = (m0 + sg - 1) * CK_SLOT + A.ckb[m0 + sg - 1];
-            return b < ce ? b : ce;
-        };
-        for (uint64_t g0 = 0; g0 < nseg; g0 += WAVE) {
-            const uint64_t sg = g0 + lane;
-            const uint64_t p = seg_start(sg), e = seg_start(sg + 1);
-            // bits of the 64 intervals: [start of g0, end of the group's last interval)
-            const uint64_t lo = __shfl((unsigned long long)p, 0, WAVE);
-            const uint64_t gl = g0 + WAVE < nseg ? g0 + WAVE : nseg;
-            const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
-            const uint64_t wlo = lo >> 5;
-            const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
-            stage_words(stage[wv], A.payload + wlo, nw);
-            wave_sync();
-            if (sg < nseg) {
-                uint64_t pp = p - wlo * 32;
-                const uint64_t ee = e - wlo * 32;
-                while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage[wv], pp));
+    // queue entries are dealt to the waves in turn (entry e to wave e mod nwaves); a wave loads
+    // the set ids and bit offsets of up to 64 of its entries at once, then decodes them in turn
+    const uint64_t nwaves = (uint64_t)nblk * (blockDim.x / WAVE);
+    const uint64_t gw = (uint64_t)bid * (blockDim.x / WAVE) + (uint64_t)wv;
+    for (uint64_t r0 = gw; r0 < nq; r0 += nwaves * WAVE) {
+        const uint64_t myit = r0 + (uint64_t)lane * nwaves;
+        int64_t jm = 0;
+        uint64_t b0 = 0, b1 = 0;
+        if (myit < nq) {
+            jm = (int64_t)A.big[2 + myit];
+            b0 = (uint64_t)A.bitoff[jm];
+            b1 = (uint64_t)A.bitoff[jm + 1];
+        }
+        unsigned long long have = __ballot(myit < nq);
+        while (have) {
+            const int src = __ffsll((long long)have) - 1;
+            have &= have - 1;
+            uint64_t pos = (uint64_t)__shfl((unsigned long long)b0, src, WAVE);
+            const uint64_t ce = (uint64_t)__shfl((unsigned long long)b1, src, WAVE);
+            if (A.pbits && lane == 0) atomicAdd(A.pbits, (unsigned long long)(ce - pos));
+            // gamma(nesc + 1) from one three-word window (the code has 2L + 1 <= 63 bits)
+            uint32_t nesc;
+            {
+                const uint64_t w = pos >> 5;
+                const uint32_t sh = (uint32_t)(pos & 31);
+                const uint64_t hi = ((uint64_t)A.payload[w] << 32) | A.payload[w + 1];
+                const uint64_t win = sh ? (hi << sh) | (A.payload[w + 2] >> (32 - sh)) : hi;
+                const uint32_t L = __clzll((long long)win);
+                nesc = (uint32_t)(win >> (63 - 2 * L)) - 1;
+                pos += 2 * (uint64_t)L + 1;
             }
-            wave_sync();
+            for (uint32_t q = lane; q < nesc; q += WAVE)
+                cache_dec(C, A, ckey(A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W)));
+            const uint64_t cs = pos + (uint64_t)nesc * W;
+            // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
+            const uint64_t m0 = cs / CK_SLOT + 1;
+            const uint64_t m1 = ce > 0 ? (ce - 1) / CK_SLOT : 0;
+            const uint64_t nseg = m1 >= m0 ? m1 - m0 + 2 : 1;
+            auto seg_start = [&](uint64_t sg) -> uint64_t {
+                if (sg == 0) return cs;
+                if (sg >= nseg) return ce;
+                const uint64_t b = (m0 + sg - 1) * CK_SLOT + A.ckb[m0 + sg - 1];
+                return b < ce ? b : ce;
+            };
+            for (uint64_t g0 = 0; g0 < nseg; g0 += WAVE) {
+                const uint64_t sg = g0 + lane;
+                const uint64_t p = seg_start(sg), e = seg_start(sg + 1);
+                // bits of the 64 intervals: [start of g0, end of the group's last interval)
+                const uint64_t lo = __shfl((unsigned long long)p, 0, WAVE);
+                const uint64_t gl = g0 + WAVE < nseg ? g0 + WAVE : nseg;
+                const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
+                const uint64_t wlo = lo >> 5;
+                const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
+                stage_words(stage[wv], A.payload + wlo, nw);
+                wave_sync();
+                if (sg < nseg) {
+                    uint64_t pp = p - wlo * 32;
+                    const uint64_t ee = e - wlo * 32;
+                    while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage[wv], pp));
+                }
+                wave_sync();
+            }
         }
     }
     __syncthreads();
@@ -776,6 +800,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     A.cpos = m >= 0 ? S.cpos.as<int32_t>() : nullptr;
     A.csel = m >= 0 ? S.csel.as<uint32_t>() : nullptr;
     A.ncand = m >= 0 ? S.sboff.as<int64_t>() + (((int64_t)n + SL_SPAN - 1) / SL_SPAN) : nullptr;
+    A.pbits = root.prof.on ? prof_counters(root) + DC_EDGES : nullptr;
     A.selmask = S.selmask.as<uint32_t>();
     A.covered = S.covered.as<unsigned long long>();
     A.newly = S.newly.as<unsigned long long>();
@@ -956,6 +981,7 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
     };
     HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
     HBM_HIP(hipGetLastError());
+    int ps_big = -1;  // profiling: a dec_big launch, credited with the bits all of them decoded
     for (int t = 0; t < kmax; t++) {
         int ps = prof_begin(root, "argmax");
         HBM_SEL_LAUNCH(P_ALL_ARG, k_argmax, t);
@@ -977,6 +1003,7 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
             ps = prof_begin(root, "dec_big");
             HBM_SEL_LAUNCH(P_BIG, k_dec_big, t);
             prof_end(root, ps);
+            if (ps >= 0) ps_big = ps;
         }
         if (active(P_HOT, t)) {
             ps = prof_begin(root, "dec_hot");
@@ -986,6 +1013,11 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
     }
 #undef HBM_SEL_LAUNCH
     HBM_HIP(hipGetLastError());
+    if (ps_big >= 0) {
+        unsigned long long ctr[DC_COUNT];
+        prof_read_counters(root, ctr);
+        prof_add(root, ps_big, (double)ctr[DC_EDGES] / 8.0, 0.0);  // algorithmic bytes: the strings read
+    }
     std::vector<unsigned long long> keys((size_t)koff[N]);
     HBM_HIP(hipMemcpyAsync(keys.data(), root.bkeys.p, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
     HBM_HIP(hipEventRecord(e1, st));
