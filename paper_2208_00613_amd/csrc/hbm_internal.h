@@ -242,9 +242,11 @@ void store_free(Ctx &c);
 void store_extend(Ctx &c, int64_t theta, uint64_t seed);
 void extend_stores(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
                    const std::vector<uint64_t> &seed);
-// One block of progress for every job towards theta[i] (a warm-up block while the job's
-// codebook is not built yet): cap[i] >= 0 bounds the job's sets in this step (empty: no
-// bound).  st[i] is EBUDGET when the job's store went over its context budget.
+// One block of progress for every job towards theta[i]: cap[i] >= 0 bounds the sets the
+// job stores in this step (empty or negative: no bound).  While a job's codebook is not
+// built, a block that may be stored and covers sets [0, W) builds it from those W sets
+// and is stored whole; any other warm-up block counts frequencies only, up to set W.
+// st[i] is EBUDGET when the job's store went over its context budget.
 void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &theta,
                  const std::vector<uint64_t> &seed, const std::vector<int64_t> &cap, std::vector<hbm_status> &st);
 int64_t store_bytes(const Ctx &c);

@@ -138,7 +138,9 @@ void imm_sample_step(Ctx &root, const std::vector<ImmJob *> &jobs, const std::ve
     for (size_t i = 0; i < jobs.size(); i++) {
         ImmJob *J = jobs[i];
         if (!imm_sampling(*J)) continue;
-        if (!cap.empty() && cap[i] == 0) continue;
+        const Store &S = J->c->s;
+        const bool warming = S.enc != HBM_ENC_NONE && !S.model_ready;
+        if (!cap.empty() && cap[i] == 0 && !warming) continue;  // warm-up blocks store nothing
         sj.push_back(J);
         sc.push_back(J->c);
         th.push_back(J->target);

@@ -289,14 +289,19 @@ bool hbm_server::step(std::vector<hbm::Slot *> live) {
                 moves = true;  // ready to select
                 continue;
             }
-            if (c.s.enc != HBM_ENC_NONE && !c.s.model_ready) {
-                moves = true;  // warm-up blocks only count frequencies
-                continue;
-            }
             const int64_t want = std::min<int64_t>(J.target - c.s.nsets, root.block_sets);
             const double bps = est_bps(*live[i]);
             const int64_t allow = room > 0 ? (int64_t)std::min(room / bps, 9.0e18) : 0;
             int64_t cp = std::min(want, allow);
+            if (c.s.enc != HBM_ENC_NONE && !c.s.model_ready) {
+                // a warm-up block runs whatever the room; its sets are stored (after the model
+                // is built from the first W of them) only when the cap covers the warm-up
+                if (c.s.wcur > 0 || cp < c.s.W) cp = 0;
+                cap[i] = cp;
+                room -= (double)cp * bps;
+                moves = true;
+                continue;
+            }
             if (cp < std::min<int64_t>(want, 4096)) cp = 0;  // wait for room rather than crawl
             cap[i] = cp;
             room -= (double)cp * bps;

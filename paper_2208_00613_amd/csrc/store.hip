@@ -1030,16 +1030,22 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
         std::vector<size_t> idx;
         std::vector<int64_t> j0, nb, done;
         std::vector<uint64_t> sd;
-        std::vector<char> warm;
+        std::vector<char> warm, fuse;
         for (size_t i = 0; i < N; i++) {
             Ctx &c = *J[i];
             extend_prepare(root, c, theta[i], seed[i]);
             Store &s = c.s;
             if (s.nsets >= theta[i]) continue;
             const bool w = s.enc != HBM_ENC_NONE && !s.model_ready;
-            const int64_t from = w ? s.wcur : s.nsets, to = w ? s.W : theta[i];
-            int64_t b = std::min<int64_t>({to - from, root.block_sets, c.sc.bcap});
-            if (!cap.empty() && cap[i] >= 0) b = std::min<int64_t>(b, cap[i]);
+            const int64_t lim = (!cap.empty() && cap[i] >= 0) ? cap[i] : INT64_MAX;
+            const int64_t from = w ? s.wcur : s.nsets;
+            int64_t b = std::min<int64_t>({theta[i] - from, root.block_sets, c.sc.bcap, lim});
+            // A fresh warm-up whose block may be stored whole and covers sets [0, W) counts
+            // the frequencies of those W sets, builds the model and then encodes the whole
+            // block with it: the warm-up sets are sampled once.  Otherwise a warm-up block
+            // holds sets [wcur, W) only; it stores nothing, so the cap does not bound it.
+            const bool f = w && s.wcur == 0 && b >= s.W;
+            if (w && !f) b = std::min<int64_t>({s.W - s.wcur, root.block_sets, c.sc.bcap});
             if (b <= 0) continue;
             idx.push_back(i);
             jobs.push_back(&c);
@@ -1047,13 +1053,14 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
             nb.push_back(b);
             sd.push_back(seed[i]);
             warm.push_back(w);
+            fuse.push_back(f);
         }
         if (!jobs.empty()) sample_blocks(root, jobs, j0, nb, sd, done);
         // warm-up blocks: frequencies of sets [0, W) only
         std::vector<HistArgs> ha;
         std::vector<uint32_t> hb;
         std::vector<Ctx *> ajobs;
-        std::vector<int64_t> aj0, adone;
+        std::vector<int64_t> aj0, adone, wn(jobs.size(), 0);
         for (size_t q = 0; q < jobs.size(); q++) {
             Ctx &c = *jobs[q];
             if (done[q] == 0) {  // the first set did not fit the arena: retry with twice the room
@@ -1061,8 +1068,9 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
                 continue;
             }
             if (warm[q]) {
-                ha.push_back(HistArgs{block_view(c, done[q]), c.s.warm.as<uint32_t>()});
-                hb.push_back(grid_for(done[q] * WAVE, 256, 65536));
+                wn[q] = std::min<int64_t>(done[q], c.s.W - c.s.wcur);  // the block's warm-up sets lead it
+                ha.push_back(HistArgs{block_view(c, wn[q]), c.s.warm.as<uint32_t>()});
+                hb.push_back(grid_for(wn[q] * WAVE, 256, 65536));
             } else {
                 if (c.s.enc == HBM_ENC_NONE) record_warm_sizes(c, j0[q], done[q]);
                 ajobs.push_back(&c);
@@ -1075,11 +1083,16 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
         for (size_t q = 0; q < jobs.size(); q++) {
             Ctx &c = *jobs[q];
             if (!warm[q] || !done[q]) continue;
-            record_warm_sizes(c, j0[q], done[q]);
-            c.s.wcur += done[q];
+            record_warm_sizes(c, j0[q], wn[q]);
+            c.s.wcur += wn[q];
             if (c.s.wcur >= c.s.W) {
                 characterize(c.s, c.g.n);
                 build_model(c);
+                if (fuse[q]) {  // sets [0, done) are still in the arena
+                    ajobs.push_back(&c);
+                    aj0.push_back(j0[q]);
+                    adone.push_back(done[q]);
+                }
             }
         }
         if (!ajobs.empty()) append_blocks(root, ajobs, aj0, adone);
