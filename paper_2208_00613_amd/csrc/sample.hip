@@ -618,8 +618,12 @@ struct T2LArgs {
 };
 
 // META: the queue keeps each member's in-edge range and WC threshold beside it, taken from the
-// in-edge record that found it, so a level's expansion reads no device memory before its Philox
-// calls (the regular capacity; the extra-large one has no LDS left for it and loads the ranges).
+// in-edge record that found it, and the offset of its first Philox group among the set's
+// groups, reserved with its queue slot by one 64-bit LDS atomic (members << 32 | groups), so a
+// level reads no device memory before its Philox calls and needs no prefix sum (the regular
+// capacity; the extra-large one has no LDS left for it, loads the ranges and scans per batch).
+// Live in-edges of a level are listed in LDS and inserted after its Philox loop, so that their
+// records load together.
 template <int NT, int CAP, int HBITS>
 __device__ void big_lds_body(const T2LArgs &t) {
     constexpr int T2L_HASH = 1 << HBITS;
@@ -632,12 +636,17 @@ __device__ void big_lds_body(const T2LArgs &t) {
     __shared__ uint32_t qe0[META ? T2L_CAP : 1];
     __shared__ uint32_t qe1[META ? T2L_CAP : 1];
     __shared__ uint32_t qt[META ? T2L_CAP : 1];
-    __shared__ uint32_t sP[NT];
+    __shared__ uint32_t qg[META ? T2L_CAP : 1];
+    __shared__ unsigned long long qpack;  // META: members << 32 | their Philox groups
+    __shared__ uint32_t sP[META ? 1 : NT];
     __shared__ uint32_t sE0[META ? 1 : NT];
     __shared__ uint32_t sE1[META ? 1 : NT];
     __shared__ uint32_t sT[META ? 1 : NT];
-    __shared__ uint32_t wsum[NT / WAVE];
-    __shared__ uint32_t qn;
+    __shared__ uint32_t wsum[META ? 1 : NT / WAVE];
+    constexpr uint32_t LIVE_CAP = META ? NT : 2 * NT;
+    __shared__ uint32_t live[LIVE_CAP];
+    __shared__ uint32_t nlive[2];  // by level parity: one is cleared while the other is read
+    __shared__ uint32_t qn;        // members (the extra-large pass)
     __shared__ uint32_t item;
     __shared__ int ovf;
     __shared__ unsigned long long s_at;
@@ -646,6 +655,67 @@ __device__ void big_lds_body(const T2LArgs &t) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < T2L_HASH; i += NT) h[i] = EMPTY;
+    auto members = [&]() -> uint32_t {
+        if constexpr (META) return (uint32_t)(qpack >> 32);
+        else return qn;
+    };
+    // member u found over in-edge e: into the hash and, if new, the queue.  A full queue sends
+    // the set on and stops inserting, so the hash never holds more than T2L_CAP + NT keys (one
+    // insert per thread in flight).
+    auto insert_edge = [&](uint32_t e) {
+        if (members() >= (uint32_t)T2L_CAP) {
+            ovf = 1;
+            return;
+        }
+        uint4 r;
+        if constexpr (META) r = a.in_rec[e];
+        else r.x = (uint32_t)a.in_src[e];
+        const uint32_t u = r.x;
+        uint32_t hs = hash32(u, T2L_HASH_BITS);
+        for (;;) {
+            const uint32_t old = atomicCAS(&h[hs], EMPTY, u);
+            if (old == EMPTY) {
+                uint32_t p;
+                if constexpr (META) {
+                    const uint32_t ng = r.z > r.y ? ((r.z - 1) >> 2) - (r.y >> 2) + 1 : 0;
+                    const unsigned long long o = atomicAdd(&qpack, (1ull << 32) | ng);
+                    p = (uint32_t)(o >> 32);
+                    if (p < (uint32_t)T2L_CAP) {
+                        qe0[p] = r.y;
+                        qe1[p] = r.z;
+                        qt[p] = r.w;
+                        qg[p] = (uint32_t)o;
+                    }
+                } else {
+                    p = atomicAdd(&qn, 1u);
+                }
+                if (p < (uint32_t)T2L_CAP) q[p] = u;
+                else ovf = 1;
+                return;
+            }
+            if (old == u) return;
+            hs = (hs + 1) & (T2L_HASH - 1);
+        }
+    };
+    // Philox call for group g of the member with range [E0, E1), group offset gs and threshold
+    // T (WC), and the live in-edges among its four slots
+    auto expand_group = [&](uint32_t jlo, uint32_t jhi, uint32_t g, uint32_t gs, uint32_t E0, uint32_t E1,
+                            uint32_t T, uint32_t &nl) {
+        const uint32_t grp = (E0 >> 2) + (g - gs);
+        const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
+        const uint4 t4 = a.wc ? make_uint4(T, T, T, T) : *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
+        const uint32_t eb = grp * 4;
+#pragma unroll
+        for (uint32_t qq = 0; qq < 4; qq++) {
+            const uint32_t e = eb + qq;
+            if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
+                if (a.dctr) atomicAdd(&s_ctr[DC_LIVE], 1ull);
+                const uint32_t p = atomicAdd(&nl, 1u);
+                if (p < LIVE_CAP) live[p] = e;
+                else insert_edge(e);  // the list is full: insert at once
+            }
+        }
+    };
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) item = (uint32_t)atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
@@ -661,109 +731,95 @@ __device__ void big_lds_body(const T2LArgs &t) {
             h[hash32(root, T2L_HASH_BITS)] = root;
             q[0] = root;
             if constexpr (META) {
-                qe0[0] = (uint32_t)a.in_ptr[root];
-                qe1[0] = (uint32_t)a.in_ptr[root + 1];
+                const uint32_t e0 = (uint32_t)a.in_ptr[root], e1 = (uint32_t)a.in_ptr[root + 1];
+                qe0[0] = e0;
+                qe1[0] = e1;
                 qt[0] = a.wc ? a.thr[root] : 0u;
+                qg[0] = 0;
+                qpack = (1ull << 32) | (e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0u);
+            } else {
+                qn = 1;
             }
-            qn = 1;
+            nlive[0] = nlive[1] = 0;
             ovf = 0;
         }
         __syncthreads();
-        uint32_t head = 0, tail = 1;
-        while (head < tail && !ovf) {
-            for (uint32_t c0 = head; c0 < tail; c0 += NT) {
-                const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
-                uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
-                if (threadIdx.x < cn) {
-                    if constexpr (META) {
-                        e0 = qe0[c0 + threadIdx.x];
-                        e1 = qe1[c0 + threadIdx.x];
-                    } else {
+        if constexpr (META) {
+            // level [head, tail): its groups are [qg[head], the group total), every member's
+            // group found by a search of qg only when a thread's group leaves its member
+            uint32_t head = 0;
+            for (uint32_t lev = 0;; lev ^= 1) {
+                const unsigned long long pk = qpack;  // the previous level's inserts are done
+                const uint32_t m = (uint32_t)(pk >> 32);
+                const uint32_t tail = m < (uint32_t)T2L_CAP ? m : (uint32_t)T2L_CAP;
+                if (ovf || head >= tail) break;
+                const uint32_t gb = qg[head], ge = (uint32_t)pk;
+                if (a.dctr) {
+                    if (threadIdx.x == 0) {
+                        s_ctr[DC_PHILOX] += ge - gb;
+                        s_ctr[DC_EXPANDED] += tail - head;
+                    }
+                    for (uint32_t x = head + threadIdx.x; x < tail; x += NT)
+                        atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(qe1[x] - qe0[x]));
+                }
+                uint32_t i = head;
+                uint32_t iend = head + 1 < tail ? qg[head + 1] : ge;  // member i's groups end
+                for (uint32_t g = gb + threadIdx.x; g < ge; g += NT) {
+                    if (iend <= g) {
+                        i = upper_bound_dev<uint32_t, uint32_t>(qg, i + 1, tail, g) - 1;
+                        iend = i + 1 < tail ? qg[i + 1] : ge;
+                    }
+                    expand_group(jlo, jhi, g, qg[i], qe0[i], qe1[i], qt[i], nlive[lev]);
+                }
+                __syncthreads();
+                const uint32_t nl = nlive[lev] < LIVE_CAP ? nlive[lev] : LIVE_CAP;
+                for (uint32_t x = threadIdx.x; x < nl; x += NT) insert_edge(live[x]);
+                if (threadIdx.x == 0) nlive[lev ^ 1] = 0;
+                __syncthreads();
+                head = tail;
+            }
+        } else {
+            uint32_t head = 0, tail = 1;
+            while (head < tail && !ovf) {
+                for (uint32_t c0 = head; c0 < tail; c0 += NT) {
+                    const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
+                    uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
+                    if (threadIdx.x < cn) {
                         const uint32_t v = q[c0 + threadIdx.x];
                         e0 = (uint32_t)a.in_ptr[v];
                         e1 = (uint32_t)a.in_ptr[v + 1];
                         if (a.wc) tv = a.thr[v];
+                        ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
                     }
-                    ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
-                }
-                const uint32_t P = block_incl_scan(ng, wsum);
-                sP[threadIdx.x] = P;
-                if constexpr (!META) {
+                    const uint32_t P = block_incl_scan(ng, wsum);
+                    sP[threadIdx.x] = P;
                     sE0[threadIdx.x] = e0;
                     sE1[threadIdx.x] = e1;
                     sT[threadIdx.x] = tv;
-                }
-                // the batch's ranges and thresholds, by vertex index within the batch
-                const uint32_t *bE0 = META ? qe0 + c0 : sE0;
-                const uint32_t *bE1 = META ? qe1 + c0 : sE1;
-                const uint32_t *bT = META ? qt + c0 : sT;
-                __syncthreads();
-                const uint32_t G = sP[NT - 1];
-                if (a.dctr) {
-                    if (threadIdx.x == 0) {
-                        s_ctr[DC_PHILOX] += G;
-                        s_ctr[DC_EXPANDED] += cn;
-                    }
-                    if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
-                }
-                uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
-                for (uint32_t g = threadIdx.x; g < G; g += NT) {
-                    if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
-                    const uint32_t excl = i ? sP[i - 1] : 0u;
-                    const uint32_t E0 = bE0[i], E1 = bE1[i];
-                    const uint32_t grp = (E0 >> 2) + (g - excl);
-                    const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
-                    uint4 t4;
-                    if (a.wc) {
-                        const uint32_t T = bT[i];
-                        t4 = make_uint4(T, T, T, T);
-                    } else {
-                        t4 = *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
-                    }
-                    const uint32_t eb = grp * 4;
-#pragma unroll
-                    for (uint32_t qq = 0; qq < 4; qq++) {
-                        const uint32_t e = eb + qq;
-                        if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
-                            if (a.dctr) atomicAdd(&s_ctr[DC_LIVE], 1ull);
-                            // a full queue: the set moves to k_big; stop inserting so the hash
-                            // never holds more than T2L_CAP + NT keys (one insert per thread in flight)
-                            if (qn >= (uint32_t)T2L_CAP) {
-                                ovf = 1;
-                                continue;
-                            }
-                            uint4 r;
-                            if constexpr (META) r = a.in_rec[e];
-                            else r.x = (uint32_t)a.in_src[e];
-                            const uint32_t u = r.x;
-                            uint32_t hs = hash32(u, T2L_HASH_BITS);
-                            for (;;) {
-                                const uint32_t old = atomicCAS(&h[hs], EMPTY, u);
-                                if (old == EMPTY) {
-                                    const uint32_t p = atomicAdd(&qn, 1u);
-                                    if (p < (uint32_t)T2L_CAP) {
-                                        q[p] = u;
-                                        if constexpr (META) {
-                                            qe0[p] = r.y;
-                                            qe1[p] = r.z;
-                                            qt[p] = r.w;
-                                        }
-                                    } else {
-                                        ovf = 1;
-                                    }
-                                    break;
-                                }
-                                if (old == u) break;
-                                hs = (hs + 1) & (T2L_HASH - 1);
-                            }
+                    if (threadIdx.x == 0) nlive[0] = 0;
+                    __syncthreads();
+                    const uint32_t G = sP[NT - 1];
+                    if (a.dctr) {
+                        if (threadIdx.x == 0) {
+                            s_ctr[DC_PHILOX] += G;
+                            s_ctr[DC_EXPANDED] += cn;
                         }
+                        if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
                     }
+                    uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
+                    for (uint32_t g = threadIdx.x; g < G; g += NT) {
+                        if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
+                        expand_group(jlo, jhi, g, i ? sP[i - 1] : 0u, sE0[i], sE1[i], sT[i], nlive[0]);
+                    }
+                    __syncthreads();
+                    const uint32_t nl = nlive[0] < LIVE_CAP ? nlive[0] : LIVE_CAP;
+                    for (uint32_t x = threadIdx.x; x < nl; x += NT) insert_edge(live[x]);
+                    __syncthreads();
                 }
+                head = tail;
+                tail = qn < (uint32_t)T2L_CAP ? qn : (uint32_t)T2L_CAP;
                 __syncthreads();
             }
-            head = tail;
-            tail = qn < (uint32_t)T2L_CAP ? qn : (uint32_t)T2L_CAP;
-            __syncthreads();
         }
         if (ovf) {
             for (int x = threadIdx.x; x < T2L_HASH; x += NT) h[x] = EMPTY;
@@ -774,7 +830,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
             __syncthreads();
             continue;
         }
-        const uint32_t s = qn;
+        const uint32_t s = members();
         if (threadIdx.x == 0) {
             s_ctr[DC_MEMBERS] += s;
             const unsigned long long at = atomicAdd(&a.ctrl[CW_CURSOR], (unsigned long long)s);
