@@ -52,6 +52,7 @@ struct SampleArgs {
     unsigned long long *dctr;  // work counters (DC_*), or null
     uint32_t *defer2;  // deferred block offsets (tier 2 -> tier 3)
     uint32_t *defer3;  // sets that outgrew a big-set slot's queue (-> the huge pass)
+    uint32_t slice;    // IC tier 1: arena entries each wave owns from the start (0 = none)
 };
 
 __device__ __forceinline__ uint32_t hash32(uint32_t v, int bits) { return (v * 0x9E3779B1u) >> (32 - bits); }
@@ -107,6 +108,7 @@ struct WaveArena {
     uint64_t cur = 0, end = 0;
 };
 constexpr uint64_t ARENA_CHUNK = 4096;
+constexpr uint32_t T1_SLICE = 256;  // arena entries each IC tier-1 wave starts with
 
 // Claim `s` entries for the calling wave (wave-uniform s).  Returns false when the arena is full.
 __device__ __forceinline__ bool arena_claim(WaveArena &A, uint64_t s, const SampleArgs &a, uint64_t &at) {
@@ -155,6 +157,7 @@ template <int HB>
 struct IcT1Lds {
     static constexpr int HC = 1 << HB;
     static constexpr int QC = HC / 2;
+    static constexpr int LC = 256;  // live in-edges of a batch, inserted after its Philox loop
     uint32_t h[HC];
     uint32_t q[QC];
     uint32_t qe0[QC];
@@ -162,12 +165,18 @@ struct IcT1Lds {
     uint32_t qt[QC];
     uint16_t qs[QC];
     uint32_t sP[WAVE];
+    uint32_t live[LC];
     uint32_t cnt;
     uint32_t ovf;
+    uint32_t nlive;
 };
 
+// Sets are dealt to the waves of the launch in turn (wave w takes w, w + W, ...) and each wave
+// starts with its own slice of the arena: same-address device atomics are serialized (about
+// 12 ns each on MI355X), and thousands of waves taking sets or arena space from one counter
+// queue up long enough to hold back the record loads of the sets in flight.
 template <int HB, int WPB>
-__device__ void ic_t1_body(const SampleArgs &a) {
+__device__ void ic_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
     using L = IcT1Lds<HB>;
     __shared__ L lds_all[WPB];
     const unsigned lane = lane_id();
@@ -175,17 +184,44 @@ __device__ void ic_t1_body(const SampleArgs &a) {
     for (int i = lane; i < L::HC; i += WAVE) S.h[i] = EMPTY;
     wave_sync();
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const int step = a.nb >= 65536 ? 8 : 1;
+    const uint64_t gw = (uint64_t)bid * WPB + threadIdx.x / WAVE, nw = (uint64_t)nblk * WPB;
+    // member u found over in-edge e: into the hash and, if new, the queue.  Once the queue is
+    // full the set is redone by tier 2; inserting stops so the table never holds more than
+    // QC + 64 keys (always has free slots).
+    auto insert_edge = [&](uint32_t e) {
+        if (S.cnt >= (uint32_t)L::QC) {
+            S.ovf = 1;
+            return;
+        }
+        const uint4 r = a.in_rec[e];
+        const uint32_t u = r.x;
+        uint32_t hs = hash32(u, HB);
+        for (;;) {
+            const uint32_t old = atomicCAS(&S.h[hs], EMPTY, u);
+            if (old == EMPTY) {
+                const uint32_t p = atomicAdd(&S.cnt, 1u);
+                if (p < (uint32_t)L::QC) {
+                    S.q[p] = u;
+                    S.qe0[p] = r.y;
+                    S.qe1[p] = r.z;
+                    S.qt[p] = r.w;
+                    S.qs[p] = (uint16_t)hs;
+                } else {
+                    S.ovf = 1;
+                }
+                return;
+            }
+            if (old == u) return;
+            hs = (hs + 1) & (L::HC - 1);
+        }
+    };
     WaveArena A;
+    A.cur = gw * a.slice;
+    A.end = A.cur + a.slice;
     // work of completed sets (profiling): Philox calls, expanded vertices, in-edges, live edges, members
     uint64_t c_ph = 0, c_exp = 0, c_edges = 0, c_live = 0, c_mem = 0;
-    for (;;) {
-        uint64_t jb = 0;
-        if (lane == 0) jb = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)step);
-        jb = __shfl(jb, 0, WAVE);
-        if (jb >= (uint64_t)a.nb) break;
-        const uint64_t je = jb + step < (uint64_t)a.nb ? jb + step : (uint64_t)a.nb;
-        for (uint64_t b = jb; b < je; b++) {
+    {
+        for (uint64_t b = gw; b < (uint64_t)a.nb; b += nw) {
             const uint64_t j = (uint64_t)a.j0 + b;
             const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
             const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
@@ -199,6 +235,7 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                 S.qs[0] = (uint16_t)hs;
                 S.cnt = 1;
                 S.ovf = 0;
+                S.nlive = 0;
             }
             wave_sync();
             uint32_t head = 0, qsize = 1;
@@ -250,38 +287,19 @@ __device__ void ic_t1_body(const SampleArgs &a) {
                             const uint32_t e = eb + qq;
                             if (e >= E0 && e < E1 && (pick4(y, qq) >> 8) < pick4(t4, qq)) {
                                 s_live++;
-                                // Once the queue is full the set is redone by tier 2; stop inserting so
-                                // the table never holds more than QC + 64 keys (always has free slots).
-                                if (S.cnt >= (uint32_t)L::QC) {
-                                    S.ovf = 1;
-                                    continue;
-                                }
-                                const uint4 r = a.in_rec[e];
-                                const uint32_t u = r.x;
-                                uint32_t hs = hash32(u, HB);
-                                for (;;) {
-                                    const uint32_t old = atomicCAS(&S.h[hs], EMPTY, u);
-                                    if (old == EMPTY) {
-                                        const uint32_t p = atomicAdd(&S.cnt, 1u);
-                                        if (p < (uint32_t)L::QC) {
-                                            S.q[p] = u;
-                                            S.qe0[p] = r.y;
-                                            S.qe1[p] = r.z;
-                                            S.qt[p] = r.w;
-                                            S.qs[p] = (uint16_t)hs;
-                                        } else {
-                                            S.ovf = 1;
-                                        }
-                                        break;
-                                    }
-                                    if (old == u) break;
-                                    hs = (hs + 1) & (L::HC - 1);
-                                }
+                                // listed: the batch's records then load together
+                                const uint32_t p = atomicAdd(&S.nlive, 1u);
+                                if (p < (uint32_t)L::LC) S.live[p] = e;
+                                else insert_edge(e);  // the list is full: insert at once
                             }
                         }
                     }
                 }
                 wave_sync();
+                const uint32_t nl = S.nlive < (uint32_t)L::LC ? S.nlive : (uint32_t)L::LC;
+                for (uint32_t x = lane; x < nl; x += WAVE) insert_edge(S.live[x]);
+                wave_sync();
+                if (lane == 0) S.nlive = 0;
                 qsize = S.cnt;
                 if (S.ovf || qsize > (uint32_t)L::QC) {
                     ovf = true;
@@ -340,11 +358,12 @@ __device__ void ic_t1_body(const SampleArgs &a) {
 
 template <int HB, int WPB>
 __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1(SampleArgs a) {
-    ic_t1_body<HB, WPB>(a);
+    ic_t1_body<HB, WPB>(a, blockIdx.x, gridDim.x);
 }
 template <int HB, int WPB>
 __global__ __launch_bounds__(WPB *WAVE) void k_ic_t1_g(GroupArgs<SampleArgs> G) {
-    ic_t1_body<HB, WPB>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+    const uint32_t i = group_of(G.boff, G.count, blockIdx.x);
+    ic_t1_body<HB, WPB>(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i]);
 }
 
 // ---------------------------------------------------------------------------- IC tier 2
@@ -1212,7 +1231,6 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = (unsigned long long)nbv[i];
         }
     }
-    ctrl_push(root);
     const hipStream_t st = root.stream;
     const bool profiling = root.prof.on;
     // ---- tier 1
@@ -1228,14 +1246,22 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                 k_iota_u32<<<grid_for(nb, 256, 65536), 256, 0, st>>>(A[i].defer, (uint64_t)nb);
                 continue;
             }
+            const uint32_t nbk = (uint32_t)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)root.num_cus * 8);
+            // arena slices for the waves (a tier-1 set has at most 256 members), when they
+            // take at most half the arena; the rest is claimed from CW_CURSOR beyond them
+            const uint64_t waves = (uint64_t)nbk * WPB;
+            const uint32_t slice = waves * T1_SLICE * 2 <= J[i]->sc.cap ? T1_SLICE : 0u;
+            A[i].slice = slice;
+            root.ctrl_host[i * CW_COUNT + CW_CURSOR] = waves * slice;
             ic.push_back(A[i]);
-            icb.push_back((uint32_t)std::min<int64_t>((nb + WPB - 1) / WPB, (int64_t)root.num_cus * 8));
+            icb.push_back(nbk);
         } else {
             lt.push_back(A[i]);
             ltb.push_back(
                 (uint32_t)std::min<int64_t>((nb + WAVE - 1) / WAVE, (int64_t)root.num_cus * std::max(1, 640 / lw)));
         }
     }
+    ctrl_push(root);
     int s1 = ic.empty() ? -1 : prof_begin(root, "ic_sample_wave");
     glaunch(root, ic, icb, 0, [&](const SampleArgs &a, unsigned g) { k_ic_t1<9, WPB><<<g, WPB * WAVE, 0, st>>>(a); },
             [&](const SampleArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
