@@ -893,9 +893,11 @@ __global__ __launch_bounds__(T2_THREADS) void k_big_g(GroupArgs<T2Args> G) {
 }
 
 // ---------------------------------------------------------------------------- LT tier 1
-// LT_LW: path capacity per lane in LDS (walks longer than this go to tier 2)
+// LT_LW: path capacity per lane in LDS (walks longer than this go to tier 2).  Walks are dealt
+// to the lanes of the launch in turn (lane l takes l, l + L, ...): same-address device atomics
+// are serialized, and a counter refilled by every wave would hold back the walks' loads.
 template <int LT_LW>
-__device__ void lt_t1_body(const SampleArgs &a) {
+__device__ void lt_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
     __shared__ uint32_t path[LT_LW * WAVE];  // path[k * WAVE + lane]
     const unsigned lane = lane_id();
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
@@ -903,28 +905,21 @@ __device__ void lt_t1_body(const SampleArgs &a) {
     bool active = false, exhausted = false;
     uint32_t b = 0, cur = 0, len = 0;
     uint64_t j = 0;
+    uint64_t next = (uint64_t)bid * WAVE + lane;  // this lane's next walk
+    const uint64_t stride = (uint64_t)nblk * WAVE;
     uint64_t c_steps = 0, c_probes = 0, c_mem = 0;  // per lane (profiling)
     for (;;) {
-        // refill idle lanes with one atomic per wave
-        const uint64_t idle = __ballot(!active && !exhausted);
-        if (idle) {
-            const uint32_t want = __popcll(idle);
-            uint64_t base = 0;
-            if (lane == 0) base = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)want);
-            base = __shfl(base, 0, WAVE);
-            if (!active && !exhausted) {
-                const uint32_t rank = __popcll(idle & ((1ull << lane) - 1));
-                const uint64_t bb = base + rank;
-                if (bb < (uint64_t)a.nb) {
-                    b = (uint32_t)bb;
-                    j = (uint64_t)a.j0 + bb;
-                    cur = rr_root(a.seed, j, (uint32_t)a.n);
-                    path[lane] = cur;
-                    len = 1;
-                    active = true;
-                } else {
-                    exhausted = true;
-                }
+        if (!active && !exhausted) {
+            if (next < (uint64_t)a.nb) {
+                b = (uint32_t)next;
+                j = (uint64_t)a.j0 + next;
+                next += stride;
+                cur = rr_root(a.seed, j, (uint32_t)a.n);
+                path[lane] = cur;
+                len = 1;
+                active = true;
+            } else {
+                exhausted = true;
             }
         }
         if (!__ballot(active)) break;
@@ -953,12 +948,16 @@ __device__ void lt_t1_body(const SampleArgs &a) {
                 }
             }
         }
-        if (deferred) {
-            a.pos[b] = POS_DEFER;
-            a.size[b] = 0;
-            const uint64_t d = atomicAdd(&a.ctrl[CW_NDEFER], 1ull);
-            a.defer[d] = b;
-            active = false;
+        // this step's deferred walks join the list with one atomic per wave
+        const uint64_t dm = __ballot(deferred);
+        if (dm) {
+            uint64_t base = 0;
+            if (lane == 0) base = atomicAdd(&a.ctrl[CW_NDEFER], (unsigned long long)__popcll(dm));
+            base = __shfl(base, 0, WAVE);
+            if (deferred) {
+                a.defer[base + __popcll(dm & ((1ull << lane) - 1))] = b;
+                active = false;
+            }
         }
         const uint64_t fin = __ballot(finished);
         if (fin) {
@@ -1007,11 +1006,12 @@ __device__ void lt_t1_body(const SampleArgs &a) {
 
 template <int LT_LW>
 __global__ __launch_bounds__(WAVE) void k_lt_t1(SampleArgs a) {
-    lt_t1_body<LT_LW>(a);
+    lt_t1_body<LT_LW>(a, blockIdx.x, gridDim.x);
 }
 template <int LT_LW>
 __global__ __launch_bounds__(WAVE) void k_lt_t1_g(GroupArgs<SampleArgs> G) {
-    lt_t1_body<LT_LW>(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+    const uint32_t i = group_of(G.boff, G.count, blockIdx.x);
+    lt_t1_body<LT_LW>(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i]);
 }
 
 // ---------------------------------------------------------------------------- LT tier 2
@@ -1025,18 +1025,15 @@ struct Lt2Args {
     uint32_t nlist;
 };
 
-__device__ void lt_wave_body(const Lt2Args &t) {
+// Walks are dealt to the waves of the launch in turn (wave w takes list entries w, w + W, ...).
+__device__ void lt_wave_body(const Lt2Args &t, uint32_t bid, uint32_t nblk) {
     __shared__ uint32_t path[LT2_PC];
     const SampleArgs &a = t.a;
     const unsigned lane = lane_id();
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     WaveArena A;
     uint64_t c_steps = 0, c_probes = 0, c_mem = 0;  // lane 0 (profiling)
-    for (;;) {
-        uint64_t it = 0;
-        if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
-        it = __shfl(it, 0, WAVE);
-        if (it >= t.nlist) break;
+    for (uint64_t it = bid; it < t.nlist; it += nblk) {
         const uint32_t b = t.list[it];
         const uint64_t j = (uint64_t)a.j0 + b;
         uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
@@ -1104,9 +1101,10 @@ __device__ void lt_wave_body(const Lt2Args &t) {
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) { lt_wave_body(t); }
+__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) { lt_wave_body(t, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(WAVE) void k_lt_wave_g(GroupArgs<Lt2Args> G) {
-    lt_wave_body(G.args[group_of(G.boff, G.count, blockIdx.x)]);
+    const uint32_t i = group_of(G.boff, G.count, blockIdx.x);
+    lt_wave_body(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i]);
 }
 
 __global__ void k_iota_u32(uint32_t *p, uint64_t count) {
