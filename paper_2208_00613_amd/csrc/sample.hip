@@ -53,6 +53,7 @@ struct SampleArgs {
     uint32_t *defer2;  // deferred block offsets (tier 2 -> tier 3)
     uint32_t *defer3;  // sets that outgrew a big-set slot's queue (-> the huge pass)
     uint32_t slice;    // IC tier 1: arena entries each wave owns from the start (0 = none)
+    uint32_t deal;     // IC tier 1: sets dealt to the waves in turn (1) or taken from CW_NEXT (0)
 };
 
 __device__ __forceinline__ uint32_t hash32(uint32_t v, int bits) { return (v * 0x9E3779B1u) >> (32 - bits); }
@@ -171,10 +172,12 @@ struct IcT1Lds {
     uint32_t nlive;
 };
 
-// Sets are dealt to the waves of the launch in turn (wave w takes w, w + W, ...) and each wave
-// starts with its own slice of the arena: same-address device atomics are serialized (about
-// 12 ns each on MI355X), and thousands of waves taking sets or arena space from one counter
-// queue up long enough to hold back the record loads of the sets in flight.
+// A launch for one job deals its sets to the waves in turn (wave w takes w, w + W, ...) and
+// gives each wave its own slice of the arena: same-address device atomics are serialized
+// (about 12 ns each on MI355X), and thousands of waves taking sets or arena space from one
+// counter queue up long enough to hold back the record loads of the sets in flight.  A
+// grouped launch (several jobs) takes sets from each job's counter instead, which balances
+// the jobs' waves better there (measured).
 template <int HB, int WPB>
 __device__ void ic_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
     using L = IcT1Lds<HB>;
@@ -221,7 +224,19 @@ __device__ void ic_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
     // work of completed sets (profiling): Philox calls, expanded vertices, in-edges, live edges, members
     uint64_t c_ph = 0, c_exp = 0, c_edges = 0, c_live = 0, c_mem = 0;
     {
-        for (uint64_t b = gw; b < (uint64_t)a.nb; b += nw) {
+        // the set after b (~0: the first): dealt, or from the counter in ranges of `step`
+        const uint64_t step = a.nb >= 65536 ? 8 : 1;
+        uint64_t je = 0;
+        auto take = [&](uint64_t b) -> uint64_t {
+            if (a.deal) return b == ~0ull ? gw : b + nw;
+            if (b != ~0ull && b + 1 < je) return b + 1;
+            uint64_t x = 0;
+            if (lane == 0) x = atomicAdd(&a.ctrl[CW_NEXT], (unsigned long long)step);
+            x = __shfl(x, 0, WAVE);
+            je = x + step < (uint64_t)a.nb ? x + step : (uint64_t)a.nb;
+            return x;
+        };
+        for (uint64_t b = take(~0ull); b < (uint64_t)a.nb; b = take(b)) {
             const uint64_t j = (uint64_t)a.j0 + b;
             const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
             const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
@@ -1025,15 +1040,20 @@ struct Lt2Args {
     uint32_t nlist;
 };
 
-// Walks are dealt to the waves of the launch in turn (wave w takes list entries w, w + W, ...).
-__device__ void lt_wave_body(const Lt2Args &t, uint32_t bid, uint32_t nblk) {
+// Long walks vary widely in length: each wave takes its next walk from a counter (dealing them
+// in turn was measured slower here).
+__device__ void lt_wave_body(const Lt2Args &t) {
     __shared__ uint32_t path[LT2_PC];
     const SampleArgs &a = t.a;
     const unsigned lane = lane_id();
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     WaveArena A;
     uint64_t c_steps = 0, c_probes = 0, c_mem = 0;  // lane 0 (profiling)
-    for (uint64_t it = bid; it < t.nlist; it += nblk) {
+    for (;;) {
+        uint64_t it = 0;
+        if (lane == 0) it = atomicAdd(&a.ctrl[CW_NEXT2], 1ull);
+        it = __shfl(it, 0, WAVE);
+        if (it >= t.nlist) break;
         const uint32_t b = t.list[it];
         const uint64_t j = (uint64_t)a.j0 + b;
         uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
@@ -1101,10 +1121,9 @@ __device__ void lt_wave_body(const Lt2Args &t, uint32_t bid, uint32_t nblk) {
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) { lt_wave_body(t, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(WAVE) void k_lt_wave(Lt2Args t) { lt_wave_body(t); }
 __global__ __launch_bounds__(WAVE) void k_lt_wave_g(GroupArgs<Lt2Args> G) {
-    const uint32_t i = group_of(G.boff, G.count, blockIdx.x);
-    lt_wave_body(G.args[i], blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i]);
+    lt_wave_body(G.args[group_of(G.boff, G.count, blockIdx.x)]);
 }
 
 __global__ void k_iota_u32(uint32_t *p, uint64_t count) {
@@ -1236,6 +1255,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     std::vector<uint32_t> icb, ltb;
     constexpr int WPB = 4;
     const int lw = root.lt_lw;
+    int n_t1 = 0;  // IC jobs whose sets go through tier 1
+    for (size_t i = 0; i < N; i++) n_t1 += nbv[i] > 0 && J[i]->g.model == HBM_IC && root.ic_tier1;
     for (size_t i = 0; i < N; i++) {
         const int64_t nb = nbv[i];
         if (nb <= 0) continue;
@@ -1248,7 +1269,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             // arena slices for the waves (a tier-1 set has at most 256 members), when they
             // take at most half the arena; the rest is claimed from CW_CURSOR beyond them
             const uint64_t waves = (uint64_t)nbk * WPB;
-            const uint32_t slice = waves * T1_SLICE * 2 <= J[i]->sc.cap ? T1_SLICE : 0u;
+            A[i].deal = n_t1 == 1;
+            const uint32_t slice = A[i].deal && waves * T1_SLICE * 2 <= J[i]->sc.cap ? T1_SLICE : 0u;
             A[i].slice = slice;
             root.ctrl_host[i * CW_COUNT + CW_CURSOR] = waves * slice;
             ic.push_back(A[i]);
