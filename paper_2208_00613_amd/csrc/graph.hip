@@ -160,14 +160,18 @@ static uint32_t read_flags(Ctx &c, Buf &flags) {
     return f;
 }
 
-// IC: one 16-byte record per in-edge e of v, {u = in_src[e], u's in-edge range, u's WC
-// threshold (0 for per-edge probabilities)}: a sampler that finds e live learns everything it
-// needs to expand u from this one load, so a BFS level costs one dependent device load.
+// One 16-byte record per in-edge e of v, {u = in_src[e], u's in-edge range, w}: w is u's WC
+// threshold for IC-WC (0 for per-edge probabilities), thr[e] for LT.  An IC sampler that finds
+// e live learns everything it needs to expand u from this one load, so a BFS level costs one
+// dependent device load; an LT walk reads the threshold it compares, the next vertex and that
+// vertex's range in one load, so a step costs the cut-point index read and this one.
 __global__ void k_in_rec(const int32_t *__restrict__ in_src, const int64_t *__restrict__ in_ptr,
-                         const uint32_t *__restrict__ thr_v, int64_t m, uint4 *__restrict__ rec) {
+                         const uint32_t *__restrict__ thr_v, const uint32_t *__restrict__ thr_e, int64_t m,
+                         uint4 *__restrict__ rec) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t u = (uint32_t)in_src[e];
-        rec[e] = make_uint4(u, (uint32_t)in_ptr[u], (uint32_t)in_ptr[u + 1], thr_v ? thr_v[u] : 0u);
+        const uint32_t w = thr_e ? thr_e[e] : thr_v ? thr_v[u] : 0u;
+        rec[e] = make_uint4(u, (uint32_t)in_ptr[u], (uint32_t)in_ptr[u + 1], w);
     }
 }
 
@@ -278,14 +282,13 @@ void graph_load(Ctx &c, int32_t n, int64_t m, const int64_t *row_ptr, const int3
         HBM_HIP(hipGetLastError());
         f = read_flags(c, flags);
         HBM_REQUIRE(f == 0, HBM_EINVAL, flag_text(f));
-        if (model == HBM_IC) {
-            buf_alloc(c, g.in_rec, mm * 16);
-            if (m > 0)
-                k_in_rec<<<grid_for(m, 256, 65536), 256, 0, c.stream>>>(
-                    g.in_src.as<int32_t>(), g.in_ptr.as<int64_t>(),
-                    prob == HBM_PROB_WC ? g.thr.as<uint32_t>() : nullptr, m, g.in_rec.as<uint4>());
-            HBM_HIP(hipGetLastError());
-        }
+        buf_alloc(c, g.in_rec, mm * 16);
+        if (m > 0)
+            k_in_rec<<<grid_for(m, 256, 65536), 256, 0, c.stream>>>(
+                g.in_src.as<int32_t>(), g.in_ptr.as<int64_t>(),
+                model == HBM_IC && prob == HBM_PROB_WC ? g.thr.as<uint32_t>() : nullptr,
+                model == HBM_LT ? g.thr.as<uint32_t>() : nullptr, m, g.in_rec.as<uint4>());
+        HBM_HIP(hipGetLastError());
         if (model == HBM_LT) {
             buf_alloc(c, g.guide, mm * 8);
             k_guide_lt<<<grid_for(n, 64, 65536), 64, 0, c.stream>>>(g.in_ptr.as<int64_t>(), g.thr.as<uint32_t>(), n,

@@ -54,7 +54,7 @@ struct DGraph {
     Buf in_src;  // int32[m]
     Buf thr;     // uint32[m] (IC-EDGE, LT) or uint32[n] (IC-WC)
     Buf guide;   // uint32[2m] LT cut-point index (see graph.hip)
-    Buf in_rec;  // IC: uint32x4 per in-edge {source u, in_ptr[u], in_ptr[u+1], WC threshold of u or 0}
+    Buf in_rec;  // uint32x4 per in-edge {source u, in_ptr[u], in_ptr[u+1], IC: WC threshold of u or 0; LT: thr[e]}
     bool loaded = false;
     bool borrowed = false;  // a copy of another context's graph: never freed here
 };

@@ -34,7 +34,7 @@ constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 struct SampleArgs {
     const int64_t *in_ptr;
     const int32_t *in_src;
-    const uint4 *in_rec;    // IC: per in-edge {source, its in-edge range, its WC threshold}
+    const uint4 *in_rec;    // per in-edge {source, its in-edge range, its WC threshold (IC) or thr[e] (LT)}
     const uint32_t *thr;
     const uint32_t *guide;  // LT cut-point index
     int32_t n;
@@ -135,20 +135,22 @@ __device__ __forceinline__ void mark_ovf(const SampleArgs &a, uint32_t b) {
 
 // LT: the in-edge that vertex `cur` keeps for draw r -- the first e with thr[e] > r, or e1
 // when there is none -- via the cut-point index; *probes counts threshold reads.
-__device__ __forceinline__ uint32_t lt_pick(const SampleArgs &a, uint32_t cur, uint32_t r, uint32_t &e1,
-                                            uint32_t &probes) {
-    const uint32_t e0 = (uint32_t)a.in_ptr[cur];
-    e1 = (uint32_t)a.in_ptr[cur + 1];
-    if (e1 == e0) return e1;
+// LT: the in-edge that a vertex with in-edges [e0, e1) keeps for draw r -- the first e with
+// thr[e] > r -- via the cut-point index, read as its in-edge record (source, the source's
+// in-edge range, thr[e]) so the next step needs no range load; false when it keeps none.
+// *probes counts the index and record reads.
+__device__ __forceinline__ bool lt_step(const SampleArgs &a, uint32_t e0, uint32_t e1, uint32_t r, uint4 &rec,
+                                        uint32_t &probes) {
+    if (e1 == e0) return false;
     const uint32_t d = e1 - e0;
     const uint32_t lb = d > 1 ? min(32 - __clz(d - 1), 24) : 0;
     uint32_t e = a.guide[2 * (uint64_t)e0 + (r >> (24 - lb))];
     probes++;
-    while (e < e1 && a.thr[e] <= r) {
-        e++;
-        probes++;
+    for (; e < e1; e++, probes++) {
+        rec = a.in_rec[e];
+        if (rec.w > r) return true;
     }
-    return e;
+    return false;
 }
 
 // ---------------------------------------------------------------------------- IC tier 1
@@ -559,18 +561,22 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
         } else if (threadIdx.x == 0) {
             // LT walk with an exact visited bitmap
             uint32_t cur = root, len = 1;
+            uint32_t e0 = (uint32_t)a.in_ptr[root], e1 = (uint32_t)a.in_ptr[root + 1];
             for (;;) {
                 const uint4 y = philox10(jlo, jhi, cur, 2u, k0, k1);
                 const uint32_t r = y.x >> 8;
-                uint32_t e1, probes = 0;
-                const uint32_t e = lt_pick(a, cur, r, e1, probes);
+                uint32_t probes = 0;
+                uint4 rec;
+                const bool kept = lt_step(a, e0, e1, r, rec, probes);
                 if (a.dctr) {
                     s_ctr[DC_PHILOX] += 1;
                     s_ctr[DC_EXPANDED] += 1;
                     s_ctr[DC_PROBES] += probes;
                 }
-                if (e == e1) break;
-                const uint32_t s = (uint32_t)a.in_src[e];
+                if (!kept) break;
+                const uint32_t s = rec.x;
+                e0 = rec.y;
+                e1 = rec.z;
                 const uint32_t bit = 1u << (s & 31);
                 if (bm[s >> 5] & bit) break;
                 bm[s >> 5] |= bit;
@@ -918,7 +924,7 @@ __device__ void lt_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     WaveArena A;
     bool active = false, exhausted = false;
-    uint32_t b = 0, cur = 0, len = 0;
+    uint32_t b = 0, cur = 0, len = 0, ce0 = 0, ce1 = 0;  // ce0, ce1: cur's in-edge range
     uint64_t j = 0;
     uint64_t next = (uint64_t)bid * WAVE + lane;  // this lane's next walk
     const uint64_t stride = (uint64_t)nblk * WAVE;
@@ -930,6 +936,8 @@ __device__ void lt_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
                 j = (uint64_t)a.j0 + next;
                 next += stride;
                 cur = rr_root(a.seed, j, (uint32_t)a.n);
+                ce0 = (uint32_t)a.in_ptr[cur];
+                ce1 = (uint32_t)a.in_ptr[cur + 1];
                 path[lane] = cur;
                 len = 1;
                 active = true;
@@ -942,14 +950,15 @@ __device__ void lt_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
         if (active) {
             const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
             const uint32_t r = y.x >> 8;
-            uint32_t e1, probes = 0;
-            const uint32_t e = lt_pick(a, cur, r, e1, probes);
+            uint32_t probes = 0;
+            uint4 rec;
+            const bool kept = lt_step(a, ce0, ce1, r, rec, probes);
             c_steps++;
             c_probes += probes;
-            if (e == e1) {
+            if (!kept) {
                 finished = true;
             } else {
-                const uint32_t s = (uint32_t)a.in_src[e];
+                const uint32_t s = rec.x;
                 bool seen = false;
                 for (uint32_t k = 0; k < len; k++) seen |= path[k * WAVE + lane] == s;
                 if (seen) {
@@ -960,6 +969,8 @@ __device__ void lt_t1_body(const SampleArgs &a, uint32_t bid, uint32_t nblk) {
                     path[len * WAVE + lane] = s;
                     len++;
                     cur = s;
+                    ce0 = rec.y;
+                    ce1 = rec.z;
                 }
             }
         }
@@ -1057,19 +1068,30 @@ __device__ void lt_wave_body(const Lt2Args &t) {
         const uint32_t b = t.list[it];
         const uint64_t j = (uint64_t)a.j0 + b;
         uint32_t cur = rr_root(a.seed, j, (uint32_t)a.n);
-        if (lane == 0) path[0] = cur;
+        uint32_t ce0 = 0, ce1 = 0;  // lane 0: cur's in-edge range
+        if (lane == 0) {
+            path[0] = cur;
+            ce0 = (uint32_t)a.in_ptr[cur];
+            ce1 = (uint32_t)a.in_ptr[cur + 1];
+        }
         uint32_t len = 1;
         bool ok = true;
         for (;;) {
             uint32_t s = 0, stop = 0;
             if (lane == 0) {
                 const uint4 y = philox10((uint32_t)j, (uint32_t)(j >> 32), cur, 2u, k0, k1);
-                uint32_t e1, probes = 0;
-                const uint32_t e = lt_pick(a, cur, y.x >> 8, e1, probes);
+                uint32_t probes = 0;
+                uint4 rec;
+                const bool kept = lt_step(a, ce0, ce1, y.x >> 8, rec, probes);
                 c_steps++;
                 c_probes += probes;
-                if (e == e1) stop = 1;
-                else s = (uint32_t)a.in_src[e];
+                if (!kept) {
+                    stop = 1;
+                } else {
+                    s = rec.x;
+                    ce0 = rec.y;  // used only if the walk goes on to s
+                    ce1 = rec.z;
+                }
             }
             stop = __shfl(stop, 0, WAVE);
             if (stop) break;
@@ -1225,7 +1247,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         SampleArgs &a = A[i];
         a.in_ptr = c.g.in_ptr.as<int64_t>();
         a.in_src = c.g.in_src.as<int32_t>();
-        a.in_rec = c.g.model == HBM_IC ? c.g.in_rec.as<uint4>() : nullptr;
+        a.in_rec = c.g.in_rec.as<uint4>();
         a.thr = c.g.thr.as<uint32_t>();
         a.guide = c.g.guide.as<uint32_t>();
         a.n = c.g.n;
