@@ -1,0 +1,83 @@
+"""CPU checks of bench.py's host logic: the one-GPU rule, the Philox ALU peak, the roofline
+arithmetic and the copy calibration of the HBM traffic counters."""
+
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    import bench as B
+
+    return B
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_philox_peak_from_unit_counts(bench):
+    # 10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32), one lane slot each
+    assert bench.PHILOX_SLOTS == 10 * (2 + 4)
+    assert bench.PHILOX_PEAK_G == pytest.approx(256 * 4 * 16 * 2.4 / 60)
+
+
+def test_roofline_picks_the_dominant_kernel(bench):
+    ks = [
+        {"name": "ic_sample_block", "launches": 4, "total_ms": 2.0, "alg_bytes": 8e6, "alg_ops": 4e8},
+        {"name": "argmax", "launches": 100, "total_ms": 1.0, "alg_bytes": 4e8, "alg_ops": 0.0},
+    ]
+    r = bench.roofline(ks, "IC", "WC", "no-such-workload")
+    # 1e8 Philox calls per 0.5 ms launch
+    assert r["kernel"] == "ic_sample_block" and r["bound"] == "alu"
+    assert r["achieved"] == pytest.approx(1e8 / 0.5e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / bench.PHILOX_PEAK_G)
+    assert r["traffic"] is None  # counters are tied to a workload and a source digest
+    r = bench.roofline(ks[1:], "LT", "EDGE", "no-such-workload")
+    # 4e6 bytes per 10 us launch
+    assert r["bound"] == "hbm" and r["achieved"] == pytest.approx(4e6 / 10e-6 / 1e9)
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, kib in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
+
+
+def test_traffic_calibrated_by_the_copy(bench, tmp_path, capsys):
+    gib_kib = (1 << 30) / 1024.0
+    # the counters read half of the copy's fetched bytes and all of its written bytes
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [
+        ("__amd_rocclr_copyBuffer", gib_kib / 2), ("__amd_rocclr_copyBuffer", 1.0),
+        ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 100.0),
+        ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 300.0),
+        ("void hbm::k_big_lds<1024, 8192, 14>(hbm::T2LArgs)", 7.0),
+        ("void hbm::k_argmax(hbm::SelArgs, int)", 10.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [
+        ("__amd_rocclr_copyBuffer", gib_kib),
+        ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 4.0)])
+    out = tmp_path / "traffic.json"
+    bench.traffic_summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(out), "c2")
+    capsys.readouterr()
+    t = json.load(open(out))
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    k = t["kernels"]
+    # mean of the two regular LDS-tier dispatches, fetched x2, plus written; the extra-large
+    # pass is told apart by its template arguments
+    assert k["ic_sample_block"] == pytest.approx(200.0 * 1024 * 2 + 4.0 * 1024)
+    assert k["ic_sample_block_xl"] == pytest.approx(7.0 * 1024 * 2)
+    assert k["argmax"] == pytest.approx(10.0 * 1024 * 2)
+    assert t["workload_key"] == "c2" and t["csrc_digest"] == bench.csrc_digest()
