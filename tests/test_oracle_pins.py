@@ -450,6 +450,110 @@ def test_imm_approximation_on_tiny_graph(orc):
     assert infl(seeds.tolist()) >= (1 - 1 / math.e - eps) * opt
 
 
+def _tang_params(n, k, eps, l):
+    """lambda' and lambda* of Tang, Shi and Xiao (SIGMOD 2015), written from their definitions by a
+    route of its own: ln C(n, k) from the exact integer binomial (math.comb), l adjusted to
+    l (1 + ln 2 / ln n) so that the whole run fails with probability at most 1/n^l (their
+    Section 3.3), eps' = sqrt(2) eps in the sampling phase, and
+      lambda' = (2 + 2 eps'/3) (ln C(n,k) + l ln n + ln log2 n) n / eps'^2          (phase 1)
+      alpha   = sqrt(l ln n + ln 2),  beta = sqrt((1 - 1/e)(ln C(n,k) + l ln n + ln 2))
+      lambda* = 2 n ((1 - 1/e) alpha + beta)^2 / eps^2                              (phase 2)."""
+    lnn = math.log(n)
+    la = l * (1.0 + math.log(2.0) / lnn)
+    lnc = math.log(math.comb(n, k))
+    ep = math.sqrt(2.0) * eps
+    lam_p = (2.0 + 2.0 * ep / 3.0) * (lnc + la * lnn + math.log(math.log2(n))) * n / ep ** 2
+    e1 = 1.0 - math.exp(-1.0)
+    alpha = math.sqrt(la * lnn + math.log(2.0))
+    beta = math.sqrt(e1 * (lnc + la * lnn + math.log(2.0)))
+    lam_s = 2.0 * n * (e1 * alpha + beta) ** 2 / eps ** 2
+    return lam_p, lam_s
+
+
+@pytest.mark.parametrize("n,k,eps,l", [(1 << 20, 50, 0.5, 1.0), (1 << 23, 100, 0.13, 1.0), (4096, 5, 0.3, 1.0),
+                                       (41_700_000, 200, 0.2, 1.0), (64, 3, 0.7, 2.0)])
+def test_lambda_star_independent(orc, n, k, eps, l):
+    """The oracle's lambda' and lambda* against Tang et al.'s definitions evaluated independently."""
+    prm = orc.imm_params(n, k, eps, l)
+    lam_p, lam_s = _tang_params(n, k, eps, l)
+    assert prm["lambda_prime"] == pytest.approx(lam_p, rel=1e-9)
+    assert prm["lambda_star"] == pytest.approx(lam_s, rel=1e-9)
+    assert prm["eps_prime"] == pytest.approx(math.sqrt(2) * eps, rel=1e-15)
+
+
+def test_lambda_star_eps_scaling(orc):
+    """alpha and beta do not depend on eps, so lambda*(eps/2) = 4 lambda*(eps) exactly (halving eps
+    quarters eps^2 by a power of two; no rounding differs)."""
+    for n, k, eps in [(1 << 20, 50, 0.5), (1 << 23, 100, 0.26), (5000, 7, 0.3)]:
+        a = orc.imm_params(n, k, eps, 1.0)["lambda_star"]
+        b = orc.imm_params(n, k, eps / 2, 1.0)["lambda_star"]
+        assert b == 4.0 * a
+
+
+def _independent_imm_k1(n, sets_of, k_eps_l):
+    """IMM's two phases (Tang et al.) for k = 1, driven independently of the oracle's driver: the
+    RR sets come from `sets_of(theta)`; the greedy pick for k = 1 is the vertex in most sets
+    (lowest id on ties); the stop test of round i is n cov_i / theta_i >= (1 + eps') n / 2^i."""
+    k, eps, l = k_eps_l
+    lam_p, lam_s = _tang_params(n, k, eps, l)
+    ep = math.sqrt(2.0) * eps
+    lb, rounds = 1.0, []
+    i = 1
+    while i <= math.log2(n) - 1:
+        x = n / 2.0 ** i
+        th = math.ceil(lam_p / x)
+        cnt = np.zeros(n, dtype=np.int64)
+        for s in sets_of(th):
+            cnt[s] += 1
+        cov = int(cnt.max())
+        rounds.append((th, cov))
+        if n * cov / th >= (1.0 + ep) * x:
+            lb = n * cov / (th * (1.0 + ep))
+            break
+        i += 1
+    return rounds, lb, math.ceil(lam_s / lb)
+
+
+def test_imm_all_live_star_round_one(orc):
+    """Every edge 0 -> v live: each RR set holds vertex 0, seed {0} covers every set, so the
+    first round passes its test (n >= (1 + eps') n / 2 for eps <= 1/sqrt 2) with
+    LB = n / (1 + sqrt(2) eps) exactly, and theta = ceil(lambda* (1 + sqrt(2) eps) / n)."""
+    n = 2048
+    g = G._csr_from_pairs(n, np.zeros(n - 1, dtype=np.int64), np.arange(1, n))
+    og = orc.Graph(n, g.row_ptr, g.dst, np.ones(g.m, dtype=np.float32), model="IC", prob="EDGE")
+    for eps in (0.5, 0.3, 0.7):
+        seeds, gains, st, store = orc.imm(og, 1, eps, 1.0, 11)
+        ep = math.sqrt(2.0) * eps
+        lam_p, lam_s = _tang_params(n, 1, eps, 1.0)
+        assert st["rounds"] == 1
+        assert st["theta_round"][0] == math.ceil(lam_p / (n / 2))
+        assert st["cov_round"][0] == st["theta_round"][0]
+        assert st["lb"] == pytest.approx(n / (1.0 + ep), rel=1e-12)
+        assert -1e-6 < st["theta_final"] - lam_s * (1.0 + ep) / n < 1.0 + 1e-6
+        assert list(seeds) == [0] and st["coverage"] == st["nsets_final"]
+        assert st["nsets_final"] == max(st["theta_final"], st["theta_round"][0])
+
+
+def test_imm_partial_star_later_round(orc):
+    """Edges 0 -> v live for v < n/8 only: vertex 0 is in the sets rooted below n/8, so the best
+    single seed covers about 1/8 of the sets and the stop test first passes in round 4 for
+    eps = 0.5.  The oracle's rounds, coverage, LB and final theta equal an independent driver's
+    over the oracle's own (separately pinned) RR sets."""
+    n, a = 4096, 4096 // 8
+    g = G._csr_from_pairs(n, np.zeros(a - 1, dtype=np.int64), np.arange(1, a))
+    og = orc.Graph(n, g.row_ptr, g.dst, np.ones(g.m, dtype=np.float32), model="IC", prob="EDGE")
+    seed = 21
+    for eps in (0.5, 0.35):
+        seeds, gains, st, store = orc.imm(og, 1, eps, 1.0, seed)
+        rounds, lb, theta = _independent_imm_k1(n, lambda th: [og.sample(seed, j) for j in range(th)],
+                                                (1, eps, 1.0))
+        assert [(t, c) for t, c in zip(st["theta_round"], st["cov_round"])] == rounds
+        assert st["lb"] == pytest.approx(lb, rel=1e-12)
+        assert abs(st["theta_final"] - theta) <= 1
+        if eps == 0.5:
+            assert st["rounds"] == 4
+
+
 # ---------------------------------------------------------------- Huffman
 def _heap_cost(w):
     import heapq
