@@ -32,7 +32,8 @@ _LIB = os.path.join(_HERE, "_build", "libhbm_oracle.so")
 
 IC, LT = 0, 1
 PROB_EDGE, PROB_WC = 0, 1
-ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3}
+ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3, "BITMAX": 4, "AUTO": 5}
+ENC_NAME = {v: k for k, v in ENC.items()}
 
 _lib = None
 
@@ -76,6 +77,11 @@ def lib():
         L.orc_store_new.restype = P
         L.orc_store_free.argtypes = [P]
         L.orc_store_reset.argtypes = [P]
+        L.orc_store_append_range.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int64]
+        L.orc_scratch_new.restype = P
+        L.orc_scratch_new.argtypes = [C.c_int32]
+        L.orc_scratch_free.argtypes = [P]
+        L.orc_bitmax_select.argtypes = [P, C.c_int32, P, P, P, P]
         L.orc_store_nsets.restype = C.c_int64
         L.orc_store_nsets.argtypes = [P]
         L.orc_store_nmem.restype = C.c_int64
@@ -198,6 +204,11 @@ class Store:
     def extend(self, g: Graph, seed: int, theta: int):
         lib().orc_store_extend(self.h, g.h, seed, theta)
 
+    def append_range(self, g: Graph, seed: int, j0: int, j1: int, scratch: "Scratch" = None):
+        """Append RR sets j0..j1-1 as the next sets (a shard of the index range).  Threads that
+        sample one graph at once each pass a Scratch of their own."""
+        lib().orc_store_append_range(self.h, g.h, scratch.h if scratch else None, seed, j0, j1)
+
     @property
     def nsets(self) -> int:
         return int(lib().orc_store_nsets(self.h))
@@ -219,6 +230,18 @@ class Store:
         d = C.c_double()
         lib().orc_characterize(self.h, n, j0, j1, C.byref(s), C.byref(d))
         return s.value, d.value
+
+
+class Scratch:
+    """Sampling scratch for one thread (a visited flag per vertex and a BFS queue)."""
+
+    def __init__(self, n: int):
+        self.h = lib().orc_scratch_new(n)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_scratch_free(self.h)
+            self.h = None
 
 
 def sample_store(g: Graph, seed: int, theta: int) -> Store:
@@ -316,6 +339,23 @@ class Encoded:
         if getattr(self, "h", None) and _lib is not None:
             _lib.orc_encoded_free(self.h)
             self.h = None
+
+    @property
+    def enc_name(self) -> str:
+        """The encoding in use (AUTO resolves to BITMAX or HUFFMAN)."""
+        return ENC_NAME[self.enc]
+
+    def bitmax_select(self, k: int, want_after: bool = False):
+        """Alg. 3 on the Bitmax bit matrix: seeds, gains, coverage (and the matrix after the
+        k-th subtraction, word-major like ``bitmap``)."""
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        cov = np.zeros(1, dtype=np.uint64)
+        after = np.zeros(self.nwords * self.nhot, dtype=np.uint64) if want_after else None
+        rc = lib().orc_bitmax_select(self.h, k, _p(seeds), _p(gains), _p(cov), _p(after) if want_after else None)
+        if rc:
+            raise ValueError("bitmax_select needs a BITMAX store and 1 <= k <= n")
+        return (seeds, gains, int(cov[0]), after) if want_after else (seeds, gains, int(cov[0]))
 
     def decode_set(self, j: int) -> np.ndarray:
         buf = np.empty(self.n, dtype=np.int32)

@@ -28,7 +28,17 @@
  *               CP array), the warm-up top vertex moved to the front of
  *               each coded string and the other codes in canonical order
  *               (length, then id); hot-vertex bitmap rows (Bitmax encoding
- *               section, restricted to the top fraction of vertices).
+ *               section, restricted to the top fraction of vertices), or a
+ *               row for every vertex (Bitmax proper: an n-row bit matrix
+ *               over the sets, columns padded to a multiple of 64).
+ *   choice      Alg. 1's branch after characterizing the first block (Eq. 2):
+ *               Bitmax when the skewness is negative and the density is
+ *               above 1/32 (the density threshold of the RRR-set
+ *               characterization section), else Huffmax.
+ *   Alg. 3      Bitmax selection on the bit matrix: frequencies are row
+ *               popcounts; after each pick u*, row u* is subtracted from
+ *               every row (v AND (v XOR u*)) and the popcounts are taken
+ *               again.
  *
  * Nothing here is blocked, fused or reordered beyond those definitions.
  */
@@ -46,6 +56,8 @@
 #define ORC_ENC_HUFFMAN 1
 #define ORC_ENC_HOT_BITMAP 2
 #define ORC_ENC_HUFFMAN_HOT_BITMAP 3
+#define ORC_ENC_BITMAX 4 /* every vertex in a bitmap row (the Bitmax encoding section) */
+#define ORC_ENC_AUTO 5   /* Alg. 1: characterize the first block, then Bitmax or Huffmax */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Random123): 10 rounds, key bumped between rounds.         */
@@ -95,9 +107,29 @@ typedef struct orc_graph {
     float *p_edge;   /* IC-EDGE: per in-edge probability */
     float *p_vert;   /* WC: 1/indeg(v) */
     float *cum;      /* LT: running sum of in-weights along each row */
-    uint8_t *visited;
+    uint8_t *visited; /* the graph's own sampling scratch (one caller at a time) */
     int32_t *queue;
 } orc_graph;
+
+/* Sampling scratch of one thread: a visited flag per vertex (all clear between sets) and a
+   BFS queue.  Threads that sample the same graph at once each bring their own. */
+typedef struct orc_scratch {
+    uint8_t *visited;
+    int32_t *queue;
+} orc_scratch;
+
+orc_scratch *orc_scratch_new(int32_t n) {
+    orc_scratch *sc = (orc_scratch *)calloc(1, sizeof(orc_scratch));
+    sc->visited = (uint8_t *)calloc((size_t)n, 1);
+    sc->queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    return sc;
+}
+
+void orc_scratch_free(orc_scratch *sc) {
+    if (!sc) return;
+    free(sc->visited); free(sc->queue);
+    free(sc);
+}
 
 void orc_graph_free(orc_graph *g) {
     if (!g) return;
@@ -172,13 +204,13 @@ int32_t orc_root(int32_t n, uint64_t seed, uint64_t j) {
 }
 
 /* IC: every vertex that reaches the root through live in-edges; plain BFS. */
-static int64_t sample_ic(orc_graph *g, uint64_t seed, uint64_t j, int32_t *out) {
+static int64_t sample_ic(const orc_graph *g, orc_scratch *sc, uint64_t seed, uint64_t j, int32_t *out) {
     int32_t root = orc_root(g->n, seed, j);
     int64_t head = 0, tail = 0;
-    g->queue[tail++] = root;
-    g->visited[root] = 1;
+    sc->queue[tail++] = root;
+    sc->visited[root] = 1;
     while (head < tail) {
-        int32_t v = g->queue[head++];
+        int32_t v = sc->queue[head++];
         uint64_t last_group = UINT64_MAX;
         uint32_t y[4] = {0, 0, 0, 0};
         for (int64_t e = g->in_ptr[v]; e < g->in_ptr[v + 1]; e++) {
@@ -190,27 +222,27 @@ static int64_t sample_ic(orc_graph *g, uint64_t seed, uint64_t j, int32_t *out) 
             float p = g->p_edge ? g->p_edge[e] : g->p_vert[v];
             if (below(y[e & 3], p)) {
                 int32_t u = g->in_src[e];
-                if (!g->visited[u]) {
-                    g->visited[u] = 1;
-                    g->queue[tail++] = u;
+                if (!sc->visited[u]) {
+                    sc->visited[u] = 1;
+                    sc->queue[tail++] = u;
                 }
             }
         }
     }
     for (int64_t i = 0; i < tail; i++) {
-        out[i] = g->queue[i];
-        g->visited[g->queue[i]] = 0;
+        out[i] = sc->queue[i];
+        sc->visited[sc->queue[i]] = 0;
     }
     return tail;
 }
 
 /* LT: reverse walk; at each step the current vertex keeps the first in-edge whose
    cumulative weight exceeds the draw, or none; the walk stops at none or at a repeat. */
-static int64_t sample_lt(orc_graph *g, uint64_t seed, uint64_t j, int32_t *out) {
+static int64_t sample_lt(const orc_graph *g, orc_scratch *sc, uint64_t seed, uint64_t j, int32_t *out) {
     int32_t cur = orc_root(g->n, seed, j);
     int64_t len = 0;
     out[len++] = cur;
-    g->visited[cur] = 1;
+    sc->visited[cur] = 1;
     for (;;) {
         uint32_t y[4];
         draw(seed, j, (uint32_t)cur, 2u, y);
@@ -223,12 +255,12 @@ static int64_t sample_lt(orc_graph *g, uint64_t seed, uint64_t j, int32_t *out) 
         }
         if (pick < 0) break;
         int32_t s = g->in_src[pick];
-        if (g->visited[s]) break;
-        g->visited[s] = 1;
+        if (sc->visited[s]) break;
+        sc->visited[s] = 1;
         out[len++] = s;
         cur = s;
     }
-    for (int64_t i = 0; i < len; i++) g->visited[out[i]] = 0;
+    for (int64_t i = 0; i < len; i++) sc->visited[out[i]] = 0;
     return len;
 }
 
@@ -238,10 +270,15 @@ static int cmp_i32(const void *a, const void *b) {
 }
 
 /* RR set j, ascending; out must hold n entries.  Returns its size. */
-int64_t orc_sample_one(orc_graph *g, uint64_t seed, int64_t j, int32_t *out) {
-    int64_t len = g->model == ORC_IC ? sample_ic(g, seed, (uint64_t)j, out) : sample_lt(g, seed, (uint64_t)j, out);
+static int64_t sample_with(const orc_graph *g, orc_scratch *sc, uint64_t seed, int64_t j, int32_t *out) {
+    int64_t len = g->model == ORC_IC ? sample_ic(g, sc, seed, (uint64_t)j, out) : sample_lt(g, sc, seed, (uint64_t)j, out);
     qsort(out, (size_t)len, sizeof(int32_t), cmp_i32);
     return len;
+}
+
+int64_t orc_sample_one(orc_graph *g, uint64_t seed, int64_t j, int32_t *out) {
+    orc_scratch own = {g->visited, g->queue};
+    return sample_with(g, &own, seed, j, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -301,6 +338,40 @@ int orc_store_extend(orc_store *s, orc_graph *g, uint64_t seed, int64_t theta) {
         s->off[j + 1] = base + len;
     }
     s->nsets = theta;
+    free(buf);
+    return 0;
+}
+
+/* Append RR sets j0..j1-1 as the store's next sets (a shard of the index range: set i
+   of a store filled only this way from j0 is RR set j0 + i).  Results do not depend on
+   how the index range is split, which lets the benchmark time shards on several threads,
+   each with its own scratch `sc` (NULL: the graph's own, for one caller at a time). */
+int orc_store_append_range(orc_store *s, orc_graph *g, orc_scratch *sc, uint64_t seed, int64_t j0, int64_t j1) {
+    if (j1 <= j0) return 0;
+    orc_scratch own = {g->visited, g->queue};
+    if (!sc) sc = &own;
+    int64_t need = s->nsets + (j1 - j0);
+    if (need > s->cap_sets) {
+        int64_t c = s->cap_sets;
+        while (c < need) c *= 2;
+        s->off = (int64_t *)realloc(s->off, sizeof(int64_t) * (size_t)(c + 1));
+        s->cap_sets = c;
+    }
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)g->n);
+    for (int64_t j = j0; j < j1; j++) {
+        int64_t len = sample_with(g, sc, seed, j, buf);
+        int64_t i = s->nsets, base = s->off[i];
+        if (base + len > s->cap_mem) {
+            int64_t c = s->cap_mem;
+            while (c < base + len) c *= 2;
+            s->mem = (int32_t *)realloc(s->mem, sizeof(int32_t) * (size_t)c);
+            s->cap_mem = c;
+        }
+        memcpy(s->mem + base, buf, sizeof(int32_t) * (size_t)len);
+        s->off[i + 1] = base + len;
+        s->nsets = i + 1;
+    }
+    s->seed = seed;
     free(buf);
     return 0;
 }
@@ -615,10 +686,31 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
     e->enc = enc; e->n = n; e->nsets = T; e->W = W;
     e->warm = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     orc_counts(s, n, 0, W, e->warm);
+    if (enc == ORC_ENC_AUTO) {
+        /* Alg. 1: Characterize the first block; Bitmax needs S < 0 and D > 1/32 */
+        double skew = 0.0, dens = 0.0;
+        orc_characterize(s, n, 0, W, &skew, &dens);
+        enc = (skew < 0.0 && dens > 1.0 / 32.0) ? ORC_ENC_BITMAX : ORC_ENC_HUFFMAN;
+        e->enc = enc;
+    }
     int use_hot = (enc == ORC_ENC_HOT_BITMAP || enc == ORC_ENC_HUFFMAN_HOT_BITMAP);
     int use_huff = (enc == ORC_ENC_HUFFMAN || enc == ORC_ENC_HUFFMAN_HOT_BITMAP);
     int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     for (int32_t v = 0; v < n; v++) rank[v] = -1;
+    if (enc == ORC_ENC_BITMAX) {
+        /* the n x nsets bit matrix: row v holds bit j when v is in set j */
+        e->nhot = n;
+        e->hot = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        for (int32_t v = 0; v < n; v++) { e->hot[v] = v; rank[v] = v; }
+        e->nwords = (T + 63) / 64;
+        e->bitmap = (uint64_t *)calloc((size_t)(e->nwords * e->nhot + 1), sizeof(uint64_t));
+        for (int64_t j = 0; j < T; j++)
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
+                e->bitmap[(j / 64) * e->nhot + s->mem[i]] |= 1ull << (j % 64);
+        free(rank);
+        *out = e;
+        return 0;
+    }
     if (use_hot) {
         int64_t want = (int64_t)ceil(hot_frac * (double)n);
         uint64_t min_cnt = (uint64_t)ceil(hot_min_density * (double)W);
@@ -726,6 +818,55 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
     }
     free(rank);
     *out = e;
+    return 0;
+}
+
+/* Alg. 3 on a Bitmax store: h[v] = POPCOUNT(row v); each round picks u* = the unselected
+ * vertex with the largest h (lowest id on ties), then SUBTRACTs row u* from every row
+ * (v AND (v XOR u*)) and recounts h.  Rows whose popcount reaches zero are flagged and
+ * skipped afterwards (deleteVTXflag).  Exactly k picks.  `after` (may be NULL) receives
+ * the matrix once the k-th row has been subtracted. */
+int orc_bitmax_select(const orc_encoded *e, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage,
+                      uint64_t *after) {
+    if (e->enc != ORC_ENC_BITMAX || k < 1 || k > e->n) return 1;
+    int32_t n = e->n;
+    int64_t nw = e->nwords;
+    uint64_t *B = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nw * n + 1));
+    memcpy(B, e->bitmap, sizeof(uint64_t) * (size_t)(nw * n));
+    uint64_t *h = (uint64_t *)calloc((size_t)n, sizeof(uint64_t));
+    uint8_t *del = (uint8_t *)calloc((size_t)n, 1);
+    uint8_t *sel = (uint8_t *)calloc((size_t)n, 1);
+    uint64_t *urow = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nw + 1));
+    for (int32_t v = 0; v < n; v++)
+        for (int64_t w = 0; w < nw; w++) h[v] += (uint64_t)__builtin_popcountll(B[w * n + v]);
+    uint64_t cov = 0;
+    for (int32_t t = 0; t < k; t++) {
+        int32_t best = -1;
+        for (int32_t v = 0; v < n; v++) {
+            if (sel[v]) continue;
+            if (best < 0 || h[v] > h[best]) best = v;
+        }
+        seeds[t] = best;
+        gains[t] = h[best];
+        cov += h[best];
+        sel[best] = 1;
+        for (int64_t w = 0; w < nw; w++) urow[w] = B[w * n + best];
+        for (int32_t v = 0; v < n; v++) {
+            if (del[v]) continue;
+            uint64_t c = 0;
+            for (int64_t w = 0; w < nw; w++) {
+                uint64_t x = B[w * n + v];
+                x = x & (x ^ urow[w]);  /* SUBTRACT */
+                B[w * n + v] = x;
+                c += (uint64_t)__builtin_popcountll(x);
+            }
+            h[v] = c;
+            if (c == 0) del[v] = 1;
+        }
+    }
+    *coverage = cov;
+    if (after) memcpy(after, B, sizeof(uint64_t) * (size_t)(nw * n));
+    free(B); free(h); free(del); free(sel); free(urow);
     return 0;
 }
 

@@ -735,3 +735,127 @@ def test_in_csr_sorted(orc):
     fwd = set(zip(g.src().tolist(), g.dst.tolist()))
     rev = {(int(u), v) for v in range(g.n) for u in src[ptr[v]:ptr[v + 1]]}
     assert fwd == rev
+
+
+def test_append_range_shards_equal_the_store(orc):
+    """Shards of the index range, appended to stores of their own, concatenate to the store
+    a plain extend builds (the benchmark times the oracle this way on several threads)."""
+    from synth import graphs as G
+
+    g = G.erdos_renyi(300, 2400, seed=4, p_hi=0.4)
+    og = orc.Graph(g.n, g.row_ptr, g.dst, g.w, model="IC", prob="EDGE")
+    whole = orc.sample_store(og, 9, 1000)
+    woff, wmem = whole.arrays()
+    parts = []
+    for j0, j1 in ((0, 137), (137, 600), (600, 1000)):
+        s = orc.Store()
+        s.append_range(og, 9, j0, j1)
+        off, mem = s.arrays()
+        assert s.nsets == j1 - j0
+        assert np.array_equal(off, woff[j0:j1 + 1] - woff[j0])
+        parts.append(mem.copy())
+    assert np.array_equal(np.concatenate(parts), wmem)
+
+
+# ---------------------------------------------------------------- Bitmax (all vertices) and Alg. 1's choice
+def test_bitmax_eq3_rows_and_subtract(orc):
+    """The worked example of Eq. 3 through the all-vertex Bitmax store and Alg. 3: the rows
+    are the printed left matrix; after the first pick (v1) the rows are the printed right
+    matrix."""
+    before, after, first = _eq3()
+    off, mem = _sets_from_rows(before)
+    st = orc.Store.from_sets(off, mem)
+    e = orc.Encoded(st, 5, "BITMAX", W=6)
+    assert e.enc_name == "BITMAX" and e.nhot == 5 and list(e.hot) == [0, 1, 2, 3, 4] and e.nwords == 1
+    for v in range(5):
+        assert [(int(e.bitmap[v]) >> j) & 1 for j in range(6)] == list(before[v])
+    seeds, gains, cov, rows = e.bitmax_select(1, want_after=True)
+    assert seeds[0] == first and gains[0] == before[first].sum() and cov == gains[0]
+    for v in range(5):
+        assert [(int(rows[v]) >> j) & 1 for j in range(6)] == list(after[v])
+
+
+@pytest.mark.parametrize("model", ["IC", "LT"])
+def test_bitmax_round_trip_and_alg3_equals_greedy(orc, model):
+    """decode(encode(R)) == R for the all-vertex bit matrix (column padding to 64 adds no
+    member), and Alg. 3 on the matrix picks exactly the plain greedy's seeds and gains, for
+    every k up to n (zero-gain picks included)."""
+    g = G.rmat(8, seed=11)
+    w = G.lt_weights(g, 5) if model == "LT" else np.full(g.m, 0.2, dtype=np.float32)
+    og = orc.Graph(g.n, g.row_ptr, g.dst, w, model=model, prob="EDGE")
+    st = orc.sample_store(og, 17, 1000)  # 1000 sets: the last word is padded
+    off, mem = st.arrays()
+    e = orc.Encoded(st, g.n, "BITMAX", W=100)
+    assert e.nwords == 16
+    for j in range(st.nsets):
+        assert np.array_equal(e.decode_set(j), mem[off[j]:off[j + 1]])
+    for k in (1, 7, 40, g.n):
+        s1, g1, c1 = e.bitmax_select(k)
+        s2, g2, c2 = orc.greedy(st, g.n, k)
+        assert np.array_equal(s1, s2) and np.array_equal(g1, g2) and c1 == c2
+
+
+def _sizes_store(orc, sizes, n, seed=0):
+    """A store whose sets have the given sizes (members drawn without replacement)."""
+    rng = np.random.default_rng(seed)
+    sets = [np.sort(rng.choice(n, size=int(s), replace=False)).astype(np.int32) for s in sizes]
+    off = np.zeros(len(sets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(x) for x in sets])
+    return orc.Store.from_sets(off, np.concatenate(sets).astype(np.int32))
+
+
+def test_auto_choice_follows_skewness_and_density(orc):
+    """Alg. 1 with the Bitmax encoding paragraph: Bitmax exactly when Eq. 2's skewness of the
+    first block is negative and its density is above 1/32; otherwise Huffmax.  The skewness
+    sign and the density are checked against scipy on the same sizes."""
+    from scipy import stats
+
+    n = 400
+    left = [300] * 90 + [5] * 10         # long left tail: S < 0, D ~ 0.68
+    right = [5] * 90 + [300] * 10        # long right tail: S > 0, D ~ 0.09
+    thin = [12] * 90 + [1] * 10          # S < 0 but D = 0.027 <= 1/32
+    for sizes, want in ((left, "BITMAX"), (right, "HUFFMAN"), (thin, "HUFFMAN")):
+        st = _sizes_store(orc, sizes, n)
+        S, D = st.characterize(n, 0, len(sizes))
+        assert np.sign(S) == np.sign(stats.skew(sizes)) and D == pytest.approx(sum(sizes) / (len(sizes) * n))
+        e = orc.Encoded(st, n, "AUTO", W=len(sizes))
+        assert e.enc_name == want, (S, D)
+        for j in (0, len(sizes) - 1):
+            assert np.array_equal(e.decode_set(j), st.arrays()[1][st.arrays()[0][j]:st.arrays()[0][j + 1]])
+    # the density boundary itself: D exactly 1/32 stays Huffmax (Bitmax needs D > 1/32), one
+    # vertex fewer tips it over
+    sizes = [5] * 15 + [1]
+    for n, want in ((152, "HUFFMAN"), (151, "BITMAX")):
+        st = _sizes_store(orc, sizes, n)
+        S, D = st.characterize(n, 0, len(sizes))
+        assert S < 0 and (D == 1.0 / 32) == (n == 152)
+        assert orc.Encoded(st, n, "AUTO", W=len(sizes)).enc_name == want
+
+
+def test_append_range_threads_with_own_scratch(orc):
+    """Shards sampled at once on several threads, each with its own scratch, are the same sets
+    as one thread's (the sampling scratch is the only mutable state a sample touches)."""
+    import threading
+
+    from synth import graphs as G
+
+    g = G.erdos_renyi(2000, 32000, seed=7, p_hi=0.2)
+    og = orc.Graph(g.n, g.row_ptr, g.dst, g.w, model="IC", prob="EDGE")
+    whole = orc.sample_store(og, 3, 4000)
+    woff, wmem = whole.arrays()
+    parts = [None] * 8
+
+    def work(t):
+        sc = orc.Scratch(g.n)
+        s = orc.Store()
+        s.append_range(og, 3, t * 500, (t + 1) * 500, sc)
+        parts[t] = s
+
+    ts = [threading.Thread(target=work, args=(t,)) for t in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    mems = [p.arrays()[1].copy() for p in parts]
+    assert sum(p.nsets for p in parts) == 4000
+    assert np.array_equal(np.concatenate(mems), wmem)
