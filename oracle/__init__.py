@@ -109,7 +109,8 @@ def lib():
         L.orc_warmup_count.restype = C.c_int64
         L.orc_warmup_count.argtypes = [C.c_double, C.c_int64]
         L.orc_encode.restype = C.c_int
-        L.orc_encode.argtypes = [P, C.c_int32, C.c_int, C.c_int64, C.c_double, C.c_double, C.POINTER(C.c_void_p)]
+        L.orc_encode.argtypes = [P, C.c_int32, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_int,
+                                 C.POINTER(C.c_void_p)]
         L.orc_encoded_free.argtypes = [P]
         L.orc_encoded_info.argtypes = [P, P]
         for nm in ["warm", "hot", "bitmap", "cold_off", "cold_mem", "lens", "codes", "bitoff", "payload"]:
@@ -313,9 +314,13 @@ def warmup_count(frac: float, theta: int) -> int:
 class Encoded:
     """The oracle's encoded store (same layout the GPU library documents)."""
 
-    def __init__(self, store: Store, n: int, enc: str, W: int, hot_frac: float = 0.0, hot_min_density: float = 0.0):
+    def __init__(self, store: Store, n: int, enc: str, W: int, hot_frac: float = 0.0, hot_min_density: float = 0.0,
+                 implicit_roots: bool = False):
         h = C.c_void_p()
-        lib().orc_encode(store.h, n, ENC[enc], W, hot_frac, hot_min_density, C.byref(h))
+        rc = lib().orc_encode(store.h, n, ENC[enc], W, hot_frac, hot_min_density, 1 if implicit_roots else 0,
+                              C.byref(h))
+        if rc:
+            raise ValueError("implicit roots need a sampled store (every set holds its root)")
         self.h = h.value
         info = np.zeros(14, dtype=np.int64)
         lib().orc_encoded_info(self.h, _p(info))

@@ -626,6 +626,8 @@ void orc_canonical_codes(int32_t nsym, const uint8_t *lens, uint32_t *codes) {
 /* ------------------------------------------------------------------------ */
 typedef struct orc_encoded {
     int enc;
+    int implicit_roots;  /* the root of set j is not stored unless it is in a bitmap row */
+    uint64_t seed;       /* the store's seed: root_j = orc_root(n, seed, j) */
     int32_t n;
     int64_t nsets, W;
     uint64_t *warm;      /* warm-up vertex frequencies, n */
@@ -679,11 +681,26 @@ static int floor_log2_u64(uint64_t x) {
  * (and in at least one).  A bitmap row costs one bit per set, a stored id 32 bits per
  * occurrence, so a row pays for itself above density 1/32 (the density threshold of the
  * RRR-set characterization section), here applied vertex by vertex. */
+/* Implicit roots: set j always holds its root (the uniform draw that starts it), which is a
+ * function of (seed, j) alone, so with implicit_roots the root is dropped from the stored
+ * plain ids or Huffman string (a root with a bitmap row keeps its bit) and regenerated when
+ * the set is decoded.  Returns 2 if some set lacks its root (a store not sampled from the
+ * graph). */
 int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_frac, double hot_min_density,
-               orc_encoded **out) {
-    orc_encoded *e = (orc_encoded *)calloc(1, sizeof(orc_encoded));
+               int implicit_roots, orc_encoded **out) {
     int64_t T = s->nsets;
+    if (implicit_roots) {
+        for (int64_t j = 0; j < T; j++) {
+            int32_t r = orc_root(n, s->seed, (uint64_t)j);
+            int has = 0;
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) has |= s->mem[i] == r;
+            if (!has) return 2;
+        }
+    }
+    orc_encoded *e = (orc_encoded *)calloc(1, sizeof(orc_encoded));
     e->enc = enc; e->n = n; e->nsets = T; e->W = W;
+    e->implicit_roots = implicit_roots;
+    e->seed = s->seed;
     e->warm = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
     orc_counts(s, n, 0, W, e->warm);
     if (enc == ORC_ENC_AUTO) {
@@ -737,14 +754,17 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         e->cold_off = (int64_t *)calloc((size_t)T + 1, sizeof(int64_t));
         int64_t total = 0;
         for (int64_t j = 0; j < T; j++) {
-            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) total += rank[s->mem[i]] < 0;
+            int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) total += rank[s->mem[i]] < 0 && s->mem[i] != skip;
             e->cold_off[j + 1] = total;
         }
         e->cold_mem = (int32_t *)malloc(sizeof(int32_t) * (size_t)(total ? total : 1));
         int64_t q = 0;
-        for (int64_t j = 0; j < T; j++)
+        for (int64_t j = 0; j < T; j++) {
+            int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
-                if (rank[s->mem[i]] < 0) e->cold_mem[q++] = s->mem[i];
+                if (rank[s->mem[i]] < 0 && s->mem[i] != skip) e->cold_mem[q++] = s->mem[i];
+        }
     } else {
         /* codebook over the non-hot vertices seen in the warm-up block */
         uint64_t *wt = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
@@ -762,9 +782,10 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         e->bitoff = (int64_t *)calloc((size_t)T + 1, sizeof(int64_t));
         for (int64_t j = 0; j < T; j++) {
             uint64_t nesc = 0, bits = 0;
+            int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] >= 0) continue;
+                if (rank[v] >= 0 || v == skip) continue;
                 if (e->lens[v]) bits += e->lens[v];
                 else nesc++;
             }
@@ -778,9 +799,10 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         for (int64_t j = 0; j < T; j++) {
             uint64_t pos = (uint64_t)e->bitoff[j];
             uint64_t nesc = 0;
+            int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] < 0 && e->lens[v] == 0) nesc++;
+                if (rank[v] < 0 && e->lens[v] == 0 && v != skip) nesc++;
             }
             /* Elias gamma of nesc+1 */
             int L = floor_log2_u64(nesc + 1);
@@ -790,7 +812,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             /* verbatim ids of codeless members, ascending */
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] < 0 && e->lens[v] == 0) {
+                if (rank[v] < 0 && e->lens[v] == 0 && v != skip) {
                     put_bits(e->payload, pos, (uint32_t)v, e->wbits);
                     pos += (uint64_t)e->wbits;
                 }
@@ -800,7 +822,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
                order, i.e. by (code length, id), which is ascending left-justified code value */
             int has_front = 0;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
-                if (s->mem[i] == e->ustar_enc) has_front = 1;
+                if (s->mem[i] == e->ustar_enc && s->mem[i] != skip) has_front = 1;
             if (has_front) {
                 put_bits(e->payload, pos, e->codes[e->ustar_enc], e->lens[e->ustar_enc]);
                 pos += e->lens[e->ustar_enc];
@@ -809,7 +831,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             for (int clen = 1; clen <= 32; clen++)
                 for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                     int32_t v = s->mem[i];
-                    if (rank[v] >= 0 || e->lens[v] != clen || v == e->ustar_enc) continue;
+                    if (rank[v] >= 0 || e->lens[v] != clen || v == e->ustar_enc || v == skip) continue;
                     put_bits(e->payload, pos, e->codes[v], e->lens[v]);
                     pos += e->lens[v];
                     e->n_coded++;
@@ -926,6 +948,12 @@ int64_t orc_decode_set(const orc_encoded *e, int64_t j, int32_t *out) {
             out[len++] = sym;
         }
         if (pos != end) return -1;
+    }
+    if (e->implicit_roots) {  /* the root, unless its bitmap row already gave it */
+        int32_t r = orc_root(e->n, e->seed, (uint64_t)j);
+        int in_row = 0;
+        for (int32_t q = 0; q < e->nhot; q++) in_row |= e->hot[q] == r;
+        if (!in_row) out[len++] = r;
     }
     qsort(out, (size_t)len, sizeof(int32_t), cmp_i32);
     return len;

@@ -859,3 +859,49 @@ def test_append_range_threads_with_own_scratch(orc):
     mems = [p.arrays()[1].copy() for p in parts]
     assert sum(p.nsets for p in parts) == 4000
     assert np.array_equal(np.concatenate(mems), wmem)
+
+
+# ---------------------------------------------------------------- implicit roots
+@pytest.mark.parametrize("model", ["IC", "LT"])
+@pytest.mark.parametrize("enc", ["NONE", "HUFFMAN", "HOT_BITMAP", "HUFFMAN_HOT_BITMAP", "BITMAX"])
+def test_implicit_roots_round_trip_and_saving(orc, model, enc):
+    """Every set holds its root, a function of (seed, j): dropping it from the stored part and
+    regenerating it on decode gives back every set, and saves exactly the root's own cost in
+    each set where it is not in a bitmap row (4 bytes as a plain id; its code, or its escape
+    and the longer escape count, in a Huffman string)."""
+    g = G.rmat(9, seed=12)
+    w = G.lt_weights(g, 6) if model == "LT" else None
+    og = orc.Graph(g.n, g.row_ptr, g.dst, w, model=model, prob="EDGE" if model == "LT" else "WC")
+    st = orc.sample_store(og, 23, 3000)
+    off, mem = st.arrays()
+    ex = orc.Encoded(st, g.n, enc, W=300, hot_frac=0.02)
+    im = orc.Encoded(st, g.n, enc, W=300, hot_frac=0.02, implicit_roots=True)
+    for j in range(0, 3000, 7):
+        assert np.array_equal(im.decode_set(j), mem[off[j]:off[j + 1]])
+    roots = np.array([orc.root(g.n, 23, j) for j in range(3000)])
+    hot = set(ex.hot.tolist()) if ex.nhot else set()
+    cold = np.array([r not in hot for r in roots])
+    if enc in ("NONE", "HOT_BITMAP"):
+        assert ex.cold_off[-1] - im.cold_off[-1] == cold.sum()
+    elif enc == "BITMAX":
+        assert cold.sum() == 0 and np.array_equal(ex.bitmap, im.bitmap)
+    else:
+        gam = lambda x: 2 * int(np.floor(np.log2(x))) + 1
+        saved = 0
+        for j in range(3000):
+            r = int(roots[j])
+            if not cold[j]:
+                continue
+            if ex.lens[r]:
+                saved += int(ex.lens[r])
+            else:
+                nesc = sum(1 for v in mem[off[j]:off[j + 1]] if v not in hot and ex.lens[v] == 0)
+                saved += ex.wbits + gam(nesc + 1) - gam(nesc)
+        assert ex.payload_bits - im.payload_bits == saved
+
+
+def test_implicit_roots_need_sampled_sets(orc):
+    off = np.array([0, 2, 3], dtype=np.int64)
+    st = orc.Store.from_sets(off, np.array([1, 2, 0], dtype=np.int32))
+    with pytest.raises(ValueError):
+        orc.Encoded(st, 4, "NONE", W=2, implicit_roots=True)
