@@ -1,29 +1,34 @@
 #!/usr/bin/env python
-"""Benchmark: full IMM on one MI355X, one JSON line.
+"""Benchmark: memory-efficient IMM on one MI355X, one JSON line.
 
-A step is one complete IMM run (hbm_imm): estimation rounds with RR-set
-sampling, hot-bitmap encoding and k-seed greedy selection each, then the final
-sampling and selection.  Default workload (c2): R-MAT scale 20 (a=.57, b=.19,
-c=.19, 16 * 2^20 samples, self-loops and duplicates removed), IC with weighted
-cascade probabilities, eps=0.5, l=1, k=50, hot bitmap for the top 1% of
-vertices by frequency in the first 10% of sets, Philox seed 42.  The graph is
-loaded into HBM before timing; the timed region holds only hbm_imm calls.
+Default (--workload all): the headline is the largest configuration that fits one
+GPU, the Chung-Lu digraph shaped like twitter7 (41.7M vertices, ~1.44B edges,
+exponent 2.2, weighted cascade) with Huffman + density-gated hot-bitmap stores.
+A step is one complete IMM query on it (estimation rounds of sampling, encoding
+and greedy selection, then the final round), drawn from the serving stream
+(k ~ U{10..200}, eps in {.5, .2}, l = 1, seed 1000 + q); --warmup queries run
+untimed, then --steps queries are timed back to back with the graph resident in
+HBM.  value = final RR sets of the timed queries / their time.  The same line
+carries the serving loop at 0.5/0.8/1.0x the measured service rate (p50/p99,
+served == alone), the roofline of the dominant kernel over a profiled second
+pass of the timed queries (HBM fraction beside the Philox ALU fraction), peak
+device bytes, the
+oracle on the host's cores (a bounded sample; core count and CPU model), and
+records of the other configurations measured in the same run:
 
-value = RR sets per second of the whole IMM run (final store size / step
-time).  Extra fields report IMM seconds, compressed bytes per RR set, the
-roofline of the dominant kernel, the CPU oracle baseline, and (unless
---no-batched) the batched workload's whole time batched vs plain on the same
-GPU: 256 R-MAT instances of scale U{12..18}, IC-WC + hot bitmap and LT +
-Huffman alternating, k ~ U{5..100}, eps in {.5, .3}.
+  c2  R-MAT scale 20, IC weighted cascade, eps=.5, l=1, k=50, hot bitmap (top
+      1% from a 10% warm-up; also with the 1/32 density gate);
+  c3  R-MAT scale 23, LT, eps=.13, k=100, Huffman (5% warm-up);
+  c4  256 R-MAT instances of scale U{12..18}, IC-WC + hot bitmap and LT +
+      Huffman alternating, k ~ U{5..100}, eps in {.5, .3}: batched vs plain;
+  flat  G(65536, 2^20) with IC p = 0.1 on every edge (a flat-head store), eps=.5,
+      k=50, encoding chosen by Alg. 1 (Bitmax here), and the equal-memory
+      comparison: the same IMM on plain ids capped at the compressed store's
+      device bytes, the rest spilled to pinned host memory.
 
---workload c3: R-MAT scale 23 under LT, eps=.13, k=100, Huffman (5% warm-up).
---workload c4: the batched workload as the main line (value = RR sets/s of
-hbm_imm_batch over all 256 instances).
---workload c5: the serving loop on a Chung-Lu digraph shaped like twitter7
-(41.7M vertices, ~1.44B edges, exponent 2.2, weighted cascade): Poisson
-arrivals of queries (k ~ U{10..200}, eps in {.5, .2}) at fractions of the
-measured single-query service rate, 200 GB store budget; p50/p99 latency,
-throughput, and each served answer against the same query run alone.
+--workload c2|c3|c4|c5|flat runs one configuration as the main line.
+--philox-probe measures the Philox call rate of the samplers' RNG against the
+ALU peak derived from unit counts.
 """
 
 from __future__ import annotations
@@ -42,8 +47,10 @@ sys.path.insert(0, ROOT)
 METRIC = "RR sets/s and IMM end-to-end s (batched vs plain, same GPU); compressed B/RR"
 
 WORKLOADS = {
+    "all": dict(name="imm_chunglu41.7M_1.44Bedges_icwc_huffman-hotbitmap_serving-stream", cfg="c5"),
     "c2": dict(name="imm_ic_wc_rmat20_eps0.5_k50_hotbitmap", cfg="c2"),
     "c3": dict(name="imm_lt_rmat23_eps0.13_k100_huffman", cfg="c3"),
+    "flat": dict(name="imm_flathead_er65536_m1M_ic_p0.1_eps0.5_k50_auto", cfg="flat"),
     "c4": dict(name="imm_batch256_rmat12-18_icwc-hotbitmap_lt-huffman", cfg="c4"),
     "c5": dict(name="serve_chunglu41.7M_1.44Bedges_icwc_huffman-hotbitmap_poisson", cfg="c5"),
 }
@@ -57,30 +64,54 @@ def log(*a):
 HBM_PEAK_GBS = 8000.0
 CUS, SIMDS, LANES, CLOCK_GHZ = 256, 4, 16, 2.4
 # One Philox4x32-10 call as the kernels compile it: 10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32; the
-# key schedule is scalar) = 60 VALU instructions, each one lane slot per lane (a plain loop of calls
-# measured on MI355X reaches 638 G calls/s, 97 % of the bound below).
+# key schedule is scalar) = 60 VALU instructions, each one lane slot per lane (`--philox-probe`
+# measures the call rate of the same device function over the whole chip).
 PHILOX_SLOTS = 60.0
 PHILOX_PEAK_G = CUS * SIMDS * LANES * CLOCK_GHZ / PHILOX_SLOTS  # G calls/s
 SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_block_xl", "ic_sample_bitmap", "lt_sample_lane",
                    "lt_sample_wave", "lt_sample_block", "sample_huge")
+SELECT_KERNELS = ("argmax", "find_raw", "find_huff", "apply", "dec_big", "dec_hot")
+HOST_THREADS_CAP = 16  # the GPU machine's CPU share per GPU
+
+
+def kernel_rates(kstats):
+    """Algorithmic GB/s and its fraction of the HBM peak for every profiled kernel (average over
+    its launches), with the Philox rate of the samplers."""
+    out = []
+    for r in sorted(kstats, key=lambda r: -r["total_ms"]):
+        if r["total_ms"] <= 0:
+            continue
+        gbs = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+        e = {"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3),
+             "alg_gbs": round(gbs, 2), "hbm_frac": round(gbs / HBM_PEAK_GBS, 5)}
+        if r["alg_ops"] > 0:
+            e["gphilox_s"] = round(r["alg_ops"] / (r["total_ms"] * 1e-3) / 1e9, 2)
+            e["alu_frac"] = round(e["gphilox_s"] / PHILOX_PEAK_G, 4)
+        out.append(e)
+    return out
 
 
 def roofline(kstats, model, prob, workload):
-    """Roofline of the kernel with the largest total time in one profiled step."""
+    """Roofline of the kernel with the largest total time in one profiled step: IC samplers against
+    the Philox ALU peak (derived from unit counts and clock), everything else against HBM; the HBM
+    fraction of the algorithmic bytes is given in both cases."""
     k = max(kstats, key=lambda r: r["total_ms"])
     avg_ms = k["total_ms"] / max(k["launches"], 1)
     per_launch_bytes = k["alg_bytes"] / max(k["launches"], 1)
     per_launch_ops = k["alg_ops"] / max(k["launches"], 1)
+    hbm_gbs = per_launch_bytes / (avg_ms * 1e-3) / 1e9
     if k["name"] in SAMPLER_KERNELS and model == "IC":
         # IC sampling does one Philox call per four in-edges of every expanded vertex and moves few
-        # bytes: the integer ALU bounds it (peak derived from unit counts and clock)
+        # bytes: the integer ALU bounds it
         achieved = per_launch_ops / (avg_ms * 1e-3) / 1e9
         out = {"bound": "alu", "achieved": achieved, "peak": PHILOX_PEAK_G, "unit": "Gphilox/s"}
     else:
-        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-        out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        out = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = traffic_for(k["name"], workload)
+    out["hbm_achieved_gbs"] = hbm_gbs
+    out["hbm_frac"] = hbm_gbs / HBM_PEAK_GBS
+    out["traffic"] = counters_for(k["name"], workload, "traffic")
+    out["l2_hit_rate"] = counters_for(k["name"], workload, "l2_hit")
     out["kernel"] = k["name"]
     out["launches_per_step"] = k["launches"]
     out["avg_launch_ms"] = avg_ms
@@ -114,20 +145,54 @@ for _k in ("hist_add", "cold_count", "split", "huff_bits", "huff_write", "argmax
 COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
 
 
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"counters_{'c5' if workload == 'all' else workload}.json")
+
+
+def c5_context(P, torch, want_host=False):
+    """The served Chung-Lu graph, generated on the GPU and loaded into a context (encoding set)."""
+    from synth import graphs as G
+
+    c = G.C5
+    t0 = time.time()
+    rp, dst = G.chung_lu_csr(c["n"], c["avg_deg"], c["gamma"], c["gseed"], c["max_deg"], device="cuda")
+    torch.cuda.synchronize()
+    m = int(dst.numel())
+    log(f"[bench] Chung-Lu n={c['n']} m={m} generated on the GPU ({time.time() - t0:.1f}s)")
+    ctx = P.Context(0)
+    t0 = time.time()
+    ctx.hbm_load_graph(c["n"], rp, dst, None, "IC", "WC")
+    log(f"[bench] Chung-Lu graph loaded ({time.time() - t0:.1f}s)")
+    host = (rp.cpu().numpy(), dst.cpu().numpy()) if want_host else None
+    del rp, dst
+    torch.cuda.empty_cache()
+    ctx.hbm_set_encoding(c["enc"], c["warmup"], c["hot"])
+    ctx.hbm_set_hot_density(c["hot_density"])
+    return ctx, c, m, host
+
+
 def traffic_probe(args):
-    """The workload of the counter runs: one profiled-size IMM step of the chosen workload, then
-    a plain 1 GiB device copy whose counter readings calibrate FETCH_SIZE and WRITE_SIZE."""
+    """The workload of the counter runs: one IMM step of the chosen workload (for the default line:
+    the timed queries of the Chung-Lu stream), then a plain 1 GiB device copy whose counter
+    readings calibrate FETCH_SIZE and WRITE_SIZE."""
     import torch
 
     import paper_2208_00613_amd as P
     from synth import graphs as G
 
-    c = G.CONFIGS[WORKLOADS[args.workload]["cfg"]]
-    g = G.config_graph(WORKLOADS[args.workload]["cfg"])
-    ctx = P.Context(0)
-    ctx.load_synth(g, model=c["model"], prob=c["prob"])
-    ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
-    ctx.hbm_imm(c["k"], c["eps"], c["l"], c["seed"])
+    if args.workload in ("all", "c5"):
+        ctx, c, _, _ = c5_context(P, torch)
+        ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)
+        # the timed queries of the default line (a few of them: counters serialize every dispatch)
+        for q in G.serving_queries(args.warmup + args.steps, seed=c["gseed"], rate=1.0)[args.warmup:]:
+            ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+    else:
+        c = G.CONFIGS[WORKLOADS[args.workload]["cfg"]]
+        g = G.config_graph(WORKLOADS[args.workload]["cfg"])
+        ctx = P.Context(0)
+        ctx.load_synth(g, model=c["model"], prob=c["prob"])
+        ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
+        ctx.hbm_imm(c["k"], c["eps"], c["l"], c["seed"])
     torch.cuda.synchronize()
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -138,86 +203,156 @@ def traffic_probe(args):
     ctx.close()
 
 
-def traffic_summarize(fetch_csv, write_csv, out_path, workload):
-    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per kernel from two rocprofv3 --pmc runs,
-    each scaled by the reading of the 1 GiB copy; writes HBM bytes per launch per profile name."""
+def counters_summarize(fetch_csv, write_csv, l2_csv, workload, out_path=None):
+    """Per-kernel averages from rocprofv3 --pmc runs of the traffic probe: HBM bytes per launch
+    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by the reading of the 1 GiB copy)
+    and the L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS).  Writes profiles/counters_<workload>.json."""
     import csv
     import re
 
-    def per_kernel(path, counter):
+    def per_kernel(path, counter, scale=1.0):
         acc = {}
+        if not path:
+            return acc
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
-            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * scale)
         return acc
 
-    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE", 1024.0), per_kernel(write_csv, "WRITE_SIZE", 1024.0)
+    hit, miss = per_kernel(l2_csv, "TCC_HIT_sum"), per_kernel(l2_csv, "TCC_MISS_sum")
     # the 1 GiB copies are the largest dispatches of the runtime's copy kernel
     copy = [k for k in fetch if re.search(r"copy", k, re.I) and "hbm::" not in k]
     if not copy:
         raise SystemExit("no copy kernel in the counter run")
     ck = max(copy, key=lambda k: max(fetch[k]))
     f_scale, w_scale = COPY_BYTES / max(fetch[ck]), COPY_BYTES / max(write.get(ck, [COPY_BYTES]))
-    kernels = {}
+    traffic, l2 = {}, {}
     mean = lambda v: sum(v) / len(v)
     for prof, sym in PROFILE_KERNELS.items():
         pat = re.compile(r"hbm::" + sym)
         fs = [x for k, v in fetch.items() if pat.search(k) for x in v]
         ws = [x for k, v in write.items() if pat.search(k) for x in v]
         if fs:
-            kernels[prof] = mean(fs) * f_scale + (mean(ws) * w_scale if ws else 0.0)
-    cmds = ["cd /tmp && rocprofv3 --pmc FETCH_SIZE -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o f -- "
-            "python $GRAFT_REPO_ROOT/bench.py --traffic-probe",
-            "cd /tmp && rocprofv3 --pmc WRITE_SIZE -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o w -- "
-            "python $GRAFT_REPO_ROOT/bench.py --traffic-probe",
-            "python bench.py --traffic-summarize gpurun_out/pmc_fetch/f_counter_collection.csv "
-            "gpurun_out/pmc_write/w_counter_collection.csv"]
-    out = {"commands": cmds, "workload": "bench.py default workload, one IMM step", "workload_key": workload,
+            traffic[prof] = mean(fs) * f_scale + (mean(ws) * w_scale if ws else 0.0)
+        hs = sum(x for k, v in hit.items() if pat.search(k) for x in v)
+        ms = sum(x for k, v in miss.items() if pat.search(k) for x in v)
+        if hs + ms > 0:
+            l2[prof] = hs / (hs + ms)
+    wl = "c5" if workload == "all" else workload
+    cmds = [f"cd /tmp && rocprofv3 --pmc {ctr} -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_{tag} -o {tag} -- "
+            f"python $GRAFT_REPO_ROOT/bench.py --traffic-probe --workload {wl}"
+            for ctr, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"), ("TCC_HIT_sum TCC_MISS_sum", "l2"))]
+    cmds.append(f"python bench.py --workload {wl} --counters-summarize gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+                "gpurun_out/pmc_write/write_counter_collection.csv gpurun_out/pmc_l2/l2_counter_collection.csv")
+    out = {"commands": cmds, "workload": WORKLOADS[wl]["name"] + ", one IMM step", "workload_key": wl,
            "csrc_digest": csrc_digest(), "copy_kernel": ck[:80], "fetch_scale": f_scale, "write_scale": w_scale,
-           "unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "kernels": kernels}
-    json.dump(out, open(out_path, "w"), indent=1)
+           "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "traffic": traffic,
+           "l2_hit_unit": "TCC_HIT / (TCC_HIT + TCC_MISS) over the kernel's launches", "l2_hit": l2}
+    json.dump(out, open(out_path or counters_path(wl), "w"), indent=1)
     print(json.dumps(out))
 
 
-def traffic_for(kernel, workload):
-    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels and
-    on this workload."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def counters_for(kernel, workload, what):
+    """A counter figure for a kernel, if taken on the current kernels and on this workload."""
+    path = counters_path(workload)
     if not os.path.exists(path):
         return None
     try:
         t = json.load(open(path))
     except ValueError:
         return None
-    if t.get("csrc_digest") != csrc_digest() or t.get("workload_key") != workload:
+    if t.get("csrc_digest") != csrc_digest():
         return None
-    return t.get("kernels", {}).get(kernel)
+    return t.get(what, {}).get(kernel)
 
 
-def cpu_baseline(g, c, budget_s=12.0):
-    """The oracle, as it is, on a bounded prefix of the same RR-set stream (one core)."""
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity": avail, "cpu_model": model,
+            "threads": max(1, min(HOST_THREADS_CAP, avail))}
+
+
+def oracle_sample_rate(og, seed, budget_s, threads, chunk):
+    """RR sets per second of the oracle sampling shards of one index range on `threads` threads
+    (each shard a store of its own; the C calls release the GIL)."""
+    import threading
+
+    import oracle
+
+    nxt = [0]
+    lock = threading.Lock()
+    stores = []
+    scratch = [oracle.Scratch(og.n) for _ in range(threads)]  # one per thread: the graph's own is not shared
+    t0 = time.perf_counter()
+
+    def work(sc):
+        st = oracle.Store()
+        stores.append(st)
+        while True:
+            with lock:
+                if time.perf_counter() - t0 > budget_s:
+                    return
+                j0 = nxt[0]
+                nxt[0] += chunk
+            st.append_range(og, seed, j0, j0 + chunk, sc)
+
+    ts = [threading.Thread(target=work, args=(sc,)) for sc in scratch]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    secs = time.perf_counter() - t0
+    return nxt[0] / secs, nxt[0], secs
+
+
+def cpu_baseline(og, n, seed, k, t_graph, label, budget_s=8.0, chunk=500):
+    """The oracle as it stands on a bounded sample of the same RR-set stream: one core sampling a
+    prefix then running its greedy over it, and all host cores (up to the GPU machine's share)
+    sampling shards of the index range."""
+    import oracle
+
+    hi = host_info()
+    st = oracle.Store()
+    theta = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s:
+        theta += chunk
+        st.extend(og, seed, theta)
+    t_sample = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    oracle.greedy(st, n, k)
+    t_select = time.perf_counter() - t2
+    del st
+    rate, sets, secs = oracle_sample_rate(og, seed, budget_s, hi["threads"], chunk)
+    return {"value": rate, "unit": "RR sets/s", "cores": hi["threads"], "kind": "oracle",
+            "sample": f"{label}: RR sets 0..{sets - 1} of the seed-{seed} stream sampled in shards of {chunk} on "
+                      f"{hi['threads']} threads ({secs:.1f}s); graph transpose ({t_graph:.1f}s) excluded",
+            "one_core": {"value": theta / (t_sample + t_select), "unit": "RR sets/s",
+                         "sample": f"RR sets 0..{theta - 1} sampled, then greedy k={k} on them",
+                         "seconds": t_sample + t_select},
+            "nproc": hi["nproc"], "affinity": hi["affinity"], "cpu_model": hi["cpu_model"]}
+
+
+def oracle_graph(n, row_ptr, dst, w, model, prob):
     import oracle
 
     oracle.build()
     t0 = time.perf_counter()
-    og = oracle.Graph(g.n, g.row_ptr, g.dst, g.w if c["prob"] == "EDGE" else None, model=c["model"],
-                      prob=c["prob"])
-    t_graph = time.perf_counter() - t0
-    st = oracle.Store()
-    theta, chunk = 0, 1000
-    t1 = time.perf_counter()
-    while time.perf_counter() - t1 < budget_s:
-        theta += chunk
-        st.extend(og, c["seed"], theta)
-    t_sample = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    oracle.greedy(st, g.n, c["k"])
-    t_select = time.perf_counter() - t2
-    return {"value": theta / (t_sample + t_select), "unit": "RR sets/s", "cores": 1, "kind": "oracle",
-            "sample": f"RR sets 0..{theta - 1} of the same seed-{c['seed']} stream sampled, then greedy "
-                      f"k={c['k']} on them; graph transpose ({t_graph:.1f}s) excluded",
-            "seconds": t_sample + t_select}
+    og = oracle.Graph(n, row_ptr, dst, w, model=model, prob=prob)
+    return og, time.perf_counter() - t0
 
 
 def _instance_graph(inst):
@@ -226,20 +361,20 @@ def _instance_graph(inst):
     return G.instance_graph(inst)
 
 
-def batched_graphs(count=256, workers=8):
-    """The batched workload's instances and graphs, generated in a process pool.  Call it
-    before anything touches the GPU: the pool forks."""
-    import concurrent.futures as cf
-
+def _config_graph(name):
     from synth import graphs as G
 
-    insts = G.batched_instances(count=count)
-    t0 = time.time()
-    with cf.ProcessPoolExecutor(workers) as ex:
-        graphs = list(ex.map(_instance_graph, insts, chunksize=4))
-    log(f"[bench] {count} instance graphs generated ({time.time() - t0:.1f}s), "
-        f"{sum(g.m for g in graphs) / 1e6:.1f}M edges in all")
-    return insts, graphs
+    return G.config_graph(name)
+
+
+def start_host_work(pool, names, batched_count):
+    """Graph generation in a process pool (forked before anything touches the GPU)."""
+    from synth import graphs as G
+
+    futs = {nm: pool.submit(_config_graph, nm) for nm in names}
+    insts = G.batched_instances(count=batched_count) if batched_count else None
+    bfuts = [pool.submit(_instance_graph, i) for i in insts] if insts else None
+    return futs, insts, bfuts
 
 
 def batched_setup(P, insts, graphs):
@@ -278,9 +413,32 @@ def batched_vs_plain(P, torch, ctxs, insts, reps=1):
     sets = sum(o[2]["nsets_final"] for o in out)
     store = sum(o[2]["store"]["store_bytes"] for o in out)
     raw = sum(4 * o[2]["store"]["members"] + 8 * (o[2]["nsets_final"] + 1) for o in out)
+    peak = sum(c.hbm_get_memory()[1] for c in ctxs)
     return dict(instances=len(ctxs), tuning=tuning, batched_s=min(tb), plain_s=min(tp), speedup=min(tp) / min(tb),
                 identical_results=bool(same), rr_sets=sets, bytes_per_rr=store / max(sets, 1),
-                raw_bytes_per_rr=raw / max(sets, 1)), out
+                raw_bytes_per_rr=raw / max(sets, 1), peak_device_bytes=peak), out
+
+
+def cpu_baseline_batched(insts, graphs, budget_s=8.0):
+    """The oracle's full IMM, instance after instance in workload order, until the time budget."""
+    import oracle
+
+    oracle.build()
+    t0 = time.perf_counter()
+    sets, done = 0, 0
+    for inst, g in zip(insts, graphs):
+        og = oracle.Graph(g.n, g.row_ptr, g.dst, g.w if inst["prob"] == "EDGE" else None, model=inst["model"],
+                          prob=inst["prob"])
+        _, _, st, _ = oracle.imm(og, inst["k"], inst["eps"], inst["l"], inst["seed"])
+        sets += st["nsets_final"]
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    secs = time.perf_counter() - t0
+    hi = host_info()
+    return {"value": sets / secs, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle IMM of the first {done} of {len(insts)} instances ({sets} RR sets, graph "
+                      f"transposes included)", "seconds": secs, "nproc": hi["nproc"], "cpu_model": hi["cpu_model"]}
 
 
 def main_c4(args, P, torch, insts, graphs):
@@ -302,35 +460,13 @@ def main_c4(args, P, torch, insts, graphs):
         "imm_s": cmp_["batched_s"], "batched_vs_plain": cmp_,
         "phase_ms": {"sample_encode": out[0][2]["t_sample_ms"], "select": out[0][2]["t_select_ms"]},
         "roofline": roofline(kstats, "IC", "WC", args.workload),
-        "kernels": sorted(({"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3)}
-                           for r in kstats), key=lambda r: -r["ms"])[:8],
+        "kernels": kernel_rates(kstats)[:10],
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_batched(insts, graphs)
     print(json.dumps(res), flush=True)
     for c in ctxs:
         c.close()
-
-
-def cpu_baseline_batched(insts, graphs, budget_s=12.0):
-    """The oracle's full IMM, instance after instance in workload order, until the time budget."""
-    import oracle
-
-    oracle.build()
-    t0 = time.perf_counter()
-    sets, done = 0, 0
-    for inst, g in zip(insts, graphs):
-        og = oracle.Graph(g.n, g.row_ptr, g.dst, g.w if inst["prob"] == "EDGE" else None, model=inst["model"],
-                          prob=inst["prob"])
-        _, _, st, _ = oracle.imm(og, inst["k"], inst["eps"], inst["l"], inst["seed"])
-        sets += st["nsets_final"]
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    secs = time.perf_counter() - t0
-    return {"value": sets / secs, "unit": "RR sets/s", "cores": 1, "kind": "oracle",
-            "sample": f"full oracle IMM of the first {done} of {len(insts)} instances ({sets} RR sets, graph "
-                      f"transposes included)", "seconds": secs}
 
 
 def pct(xs, q):
@@ -352,40 +488,13 @@ def serve_level(P, ctx, queries, budget, max_active):
     return res, st
 
 
-def main_c5(args, P, torch):
-    """The serving loop on the Chung-Lu graph: Poisson arrivals at fractions of the measured
-    single-query service rate; p50/p99 latency, throughput, and served == alone."""
+def serving_levels(P, ctx, c, alone, svc, nq, loads):
+    """Poisson arrivals of the first nq stream queries at fractions of the service rate; each
+    served answer against the same query alone."""
     from synth import graphs as G
 
-    wl = WORKLOADS["c5"]
-    c = G.C5
-    t0 = time.time()
-    rp, dst = G.chung_lu_csr(c["n"], c["avg_deg"], c["gamma"], c["gseed"], c["max_deg"], device="cuda")
-    torch.cuda.synchronize()
-    m = int(dst.numel())
-    log(f"[bench] Chung-Lu n={c['n']} m={m} generated on the GPU ({time.time() - t0:.1f}s)")
-    ctx = P.Context(0)
-    ctx.hbm_load_graph(c["n"], rp, dst, None, "IC", "WC")
-    del rp, dst
-    torch.cuda.empty_cache()
-    ctx.hbm_set_encoding(c["enc"], c["warmup"], c["hot"])
-    ctx.hbm_set_hot_density(c["hot_density"])
-    ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)  # short steps: arrivals join within a block's time
-    nq = args.queries
-    base = G.serving_queries(nq, seed=c["gseed"], rate=1.0)
-    # alone: every query of the stream on its own (service times, reference answers)
-    alone = {}
-    t_alone = []
-    for q in base:
-        t1 = time.perf_counter()
-        s_, g_, st = ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
-        t_alone.append(time.perf_counter() - t1)
-        alone[q["q"]] = (s_, g_, st)
-    svc = float(np.mean(t_alone))
-    log(f"[bench] {nq} queries alone: mean service {svc:.3f}s, max {max(t_alone):.3f}s")
-    levels = {}
-    identical = True
-    for load in args.loads:
+    levels, identical = {}, True
+    for load in loads:
         qs = G.serving_queries(nq, seed=c["gseed"], rate=load / svc)
         res, st = serve_level(P, ctx, qs, c["budget"], 16)
         lat = [r["t_done_ms"] - r["t_submit_ms"] for r in res]
@@ -395,137 +504,309 @@ def main_c5(args, P, torch):
                           for r, q in zip(res, qs))
         identical &= same
         sets = sum(r["stats"]["nsets_final"] for r in res if r["status"] == "OK")
-        levels[str(load)] = dict(rate_qps=load / svc, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
+        levels[str(load)] = dict(rate_qps=load / svc, queries=nq, p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
                                  mean_ms=float(np.mean(lat)), makespan_s=span, queries_per_s=nq / span,
                                  rr_sets_per_s=sets / span, served_equals_alone=bool(same),
                                  peak_active=st["peak_active"], preemptions=st["preemptions"],
                                  peak_store_bytes=st["peak_store_bytes"], steps=st["steps"])
         log(f"[bench] load {load}: p50 {levels[str(load)]['p50_ms']:.0f} ms p99 {levels[str(load)]['p99_ms']:.0f} ms "
             f"{nq / span:.2f} q/s peak_active {st['peak_active']} same={same}")
-    top = levels[str(max(args.loads))]
-    sets_alone = sum(a[2]["nsets_final"] for a in alone.values())
-    stores = [a[2]["store"] for a in alone.values()]
-    res_line = {
-        "metric": METRIC, "value": top["rr_sets_per_s"], "unit": "RR sets/s", "n_gpus": 1, "steps": nq,
-        "warmup": 0, "ms_per_step": top["makespan_s"] * 1e3 / nq, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded Chung-Lu digraph; no public dataset)",
-        "config": {"workload": wl["name"], "n": c["n"], "m": m, "gamma": c["gamma"], "model": "IC", "prob": "WC",
-                   "k": "U{10..200}", "eps": [0.5, 0.2], "queries": nq, "arrivals": "Poisson",
-                   "loads": list(args.loads), "store_budget_bytes": c["budget"], "encoding": c["enc"],
-                   "hot_min_density": c["hot_density"]},
-        "alone": {"mean_service_s": svc, "max_service_s": max(t_alone), "rr_sets_per_s": sets_alone / sum(t_alone)},
-        "levels": levels, "served_equals_alone": bool(identical),
-        "bytes_per_rr": sum(s_["store_bytes"] for s_ in stores) / max(sets_alone, 1),
-        "raw_bytes_per_rr": sum(4 * s_["members"] + 8 * (s_["nsets"] + 1) for s_ in stores) / max(sets_alone, 1),
+    return levels, identical
+
+
+def c5_record(args, P, torch, with_host):
+    """The headline: IMM queries of the serving stream on the Chung-Lu graph, timed back to back
+    alone; then a profiled pass over the same queries, peak bytes, the serving loop at each load."""
+    from synth import graphs as G
+
+    ctx, c, m, host = c5_context(P, torch, want_host=with_host)
+    ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)  # short steps: arrivals join within a block's time
+    W, K = args.warmup, args.steps
+    nq = max(args.queries, W + K)
+    stream = G.serving_queries(nq, seed=c["gseed"], rate=1.0)
+    alone = {}
+    for q in stream[:W]:
+        alone[q["q"]] = ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+    ctx.hbm_get_memory(reset_peak=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in stream[W:W + K]:
+        alone[q["q"]] = ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    _, peak = ctx.hbm_get_memory()
+    timed = [alone[q["q"]][2] for q in stream[W:W + K]]
+    sets = sum(st["nsets_final"] for st in timed)
+    log(f"[bench] {K} timed queries alone: {secs:.3f}s, {sets} RR sets")
+    t_alone = []
+    for q in stream[W + K:]:
+        t1 = time.perf_counter()
+        alone[q["q"]] = ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+        t_alone.append(time.perf_counter() - t1)
+    svc = (secs + sum(t_alone)) / (K + len(t_alone))
+    # one profiled pass over the same K queries: per-kernel HIP-event times and algorithmic work
+    ctx.hbm_profile(True)
+    for q in stream[W:W + K]:
+        ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+    kstats = ctx.hbm_profile_read()
+    ctx.hbm_profile(False)
+    levels, identical = serving_levels(P, ctx, c, alone, svc, args.queries, args.loads)
+    stores = [st["store"] for st in timed]
+    rec = {
+        "value": sets / secs, "ms_per_step": secs * 1e3 / K, "imm_s_mean": secs / K,
+        "config": {"workload": WORKLOADS["all"]["name"], "n": c["n"], "m": m, "gamma": c["gamma"], "model": "IC",
+                   "prob": "WC", "k": "U{10..200}", "eps": [0.5, 0.2], "l": 1.0, "timed_queries": K,
+                   "warmup_queries": W, "query_seeds": f"1000+q, q = {W}..{W + K - 1}", "encoding": c["enc"],
+                   "hot_frac": c["hot"], "hot_min_density": c["hot_density"], "warmup_frac": c["warmup"],
+                   "store_budget_bytes": c["budget"]},
+        "rr_sets": sets, "theta_final_range": [min(st["theta_final"] for st in timed),
+                                               max(st["theta_final"] for st in timed)],
+        "bytes_per_rr": sum(s_["store_bytes"] for s_ in stores) / max(sets, 1),
+        "raw_bytes_per_rr": sum(4 * s_["members"] + 8 * (s_["nsets"] + 1) for s_ in stores) / max(sets, 1),
+        "payload_bits_per_occurrence": sum(s_["payload_bits"] for s_ in stores) / max(
+            sum(s_["members"] for s_ in stores), 1),
+        "peak_device_bytes": peak,
+        "phase_ms_mean": {"sample_encode": float(np.mean([st["t_sample_ms"] for st in timed])),
+                          "select": float(np.mean([st["t_select_ms"] for st in timed]))},
+        "profiled": f"a second pass over the {K} timed queries with per-launch HIP events",
+        "roofline": roofline(kstats, "IC", "WC", "all"),
+        "kernels": kernel_rates(kstats)[:12],
+        "serving": {"levels": levels, "served_equals_alone": bool(identical), "mean_service_s": svc},
     }
-    print(json.dumps(res_line), flush=True)
+    return ctx, c, rec, host
+
+
+def imm_record(P, torch, g, c, wl_key, steps, warmup, density_gate=False, equal_memory=False):
+    """Full IMM on one R-MAT configuration: timed steps, one profiled step, B/RR, peak bytes."""
+    ctx = P.Context(0)
+    ctx.load_synth(g, model=c["model"], prob=c["prob"])
+    ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
+    torch.cuda.synchronize()
+    k, eps, l, seed = c["k"], c["eps"], c["l"], c["seed"]
+    for i in range(warmup):
+        _, _, st = ctx.hbm_imm(k, eps, l, seed)
+        log(f"[bench] {wl_key} warmup {i}: {st['t_total_ms']:.1f} ms, theta={st['nsets_final']}")
+    ctx.hbm_get_memory(reset_peak=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        seeds, gains, st = ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    _, peak = ctx.hbm_get_memory()
+    nsets = st["nsets_final"]
+    store = st["store"]
+    rec = {
+        "value": nsets / (ms / 1e3), "ms_per_step": ms, "imm_s": ms / 1e3, "steps": steps, "warmup": warmup,
+        "config": {"workload": WORKLOADS[wl_key]["name"], "n": g.n, "m": g.m, "model": c["model"], "prob": c["prob"],
+                   "k": k, "eps": eps, "l": l, "encoding": c["enc"], "seed": seed},
+        "theta_final": st["theta_final"], "nsets": nsets, "rounds": st["rounds"], "coverage": st["coverage"],
+        "influence": st["influence"],
+        "bytes_per_rr": store["store_bytes"] / max(nsets, 1),
+        "raw_bytes_per_rr": (4 * store["members"] + 8 * (nsets + 1)) / max(nsets, 1),
+        "skewness": store["skewness"], "density": store["density"], "encoding_used": store["encoding"],
+        "peak_device_bytes": peak,
+        "phase_ms": {"sample_encode": st["t_sample_ms"], "select": st["t_select_ms"]},
+    }
+    ctx.hbm_profile(True)
+    ctx.hbm_imm(k, eps, l, seed)
+    kstats = ctx.hbm_profile_read()
+    ctx.hbm_profile(False)
+    rec["roofline"] = roofline(kstats, c["model"], c["prob"], wl_key)
+    rec["kernels"] = kernel_rates(kstats)[:10]
+    if density_gate:
+        # the same IMM with the hot set gated at density 1/32 (a row only where it is the smaller form)
+        ctx.hbm_set_hot_density(1.0 / 32)
+        ctx.hbm_imm(k, eps, l, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s2, g2, st2 = ctx.hbm_imm(k, eps, l, seed)
+        t_g = time.perf_counter() - t0
+        rec["density_gate_1_32"] = {
+            "bytes_per_rr": st2["store"]["store_bytes"] / max(st2["nsets_final"], 1), "imm_s": t_g,
+            "nhot": st2["store"]["nhot"], "same_seeds": bool(np.array_equal(s2, seeds) and np.array_equal(g2, gains))}
+    if equal_memory:
+        rec["equal_memory"] = equal_memory_leg(P, torch, ctx, c, seeds, gains, rec)
     ctx.close()
+    return rec
+
+
+def equal_memory_leg(P, torch, ctx, c, seeds, gains, rec):
+    """The Evaluation section's equal-memory comparison on one GPU: the same IMM with a plain-id
+    store that may keep on the device only as many bytes as the compressed store took; the rest
+    of its ids spill to pinned host memory, read over the bus by the selection kernels."""
+    k, eps, l, seed = c["k"], c["eps"], c["l"], c["seed"]
+    cap = int(rec["bytes_per_rr"] * rec["nsets"])
+    ctx.hbm_set_encoding("NONE")
+    ctx.hbm_set_spill(cap)
+    ctx.hbm_imm(k, eps, l, seed)  # warm-up (allocations, host part)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s2, g2, st2 = ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    t_spill = time.perf_counter() - t0
+    raw_bytes = st2["store"]["store_bytes"]
+    ctx.hbm_set_spill(0)
+    ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s3, g3, st3 = ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
+    return {"compressed_store_bytes": cap, "compressed_imm_s": rec["imm_s"],
+            "compressed_encoding": rec.get("encoding_used"),
+            "plain_store_bytes": raw_bytes, "plain_device_bytes_cap": cap,
+            "plain_spilled_bytes": max(0, raw_bytes - cap), "plain_spilled_imm_s": t_spill,
+            "plain_all_on_device_imm_s": t_dev,
+            "speedup_compressed_vs_spilled": t_spill / rec["imm_s"],
+            "same_seeds": bool(np.array_equal(s2, seeds) and np.array_equal(g2, gains)
+                               and np.array_equal(s3, seeds) and np.array_equal(g3, gains))}
+
+
+def philox_probe(P, torch):
+    """The samplers' Philox device function over the whole chip, against the ALU peak."""
+    ctx = P.Context(0)
+    blocks, calls = CUS * 8, 4096
+    ctx.hbm_bench_philox(64, blocks)
+    best = None
+    for _ in range(5):
+        ms, chk = ctx.hbm_bench_philox(calls, blocks)
+        best = ms if best is None else min(best, ms)
+    g = blocks * 256 * calls / (best * 1e-3) / 1e9
+    ctx.close()
+    return {"metric": "Philox4x32-10 calls/s", "value": g, "unit": "G calls/s", "peak": PHILOX_PEAK_G,
+            "frac": g / PHILOX_PEAK_G, "blocks": blocks, "threads_per_block": 256, "calls_per_thread": calls,
+            "kernel_ms": best, "checksum": chk,
+            "peak_derivation": f"{CUS} CU x {SIMDS} SIMD x {LANES} lanes x {CLOCK_GHZ} GHz / {PHILOX_SLOTS:.0f} "
+                               "VALU slots per call"}
+
+
+def main_all(args, P, torch, pool, futs, insts, bfuts):
+    """The default line: the Chung-Lu headline, with the c2, c3 and c4 records of the same run."""
+    from synth import graphs as G
+
+    ctx, c, rec, host = c5_record(args, P, torch, with_host=not args.no_cpu_baseline)
+    out = {"metric": METRIC, "value": rec["value"], "unit": "RR sets/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": rec["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic (seeded Chung-Lu digraph shaped like twitter7, R-MAT; no public dataset)"}
+    out.update({k: v for k, v in rec.items() if k not in ("value", "ms_per_step")})
+    ctx.close()
+    if host is not None:
+        rp_h, dst_h = host
+        og, t_graph = oracle_graph(c["n"], rp_h, dst_h, None, "IC", "WC")
+        del rp_h, dst_h
+        hq = G.serving_queries(args.warmup + 1, seed=c["gseed"], rate=1.0)[args.warmup]
+        out["cpu_baseline"] = cpu_baseline(og, c["n"], hq["seed"], hq["k"], t_graph,
+                                           f"Chung-Lu query k={hq['k']} eps={hq['eps']}")
+        del og
+        log("[bench] c5 oracle baseline done")
+    others = {}
+    for key, steps, warm in (("c2", 10, 2), ("c3", 3, 1), ("flat", 3, 1)):
+        t0 = time.time()
+        g = futs[key].result()
+        log(f"[bench] graph {key} ready ({time.time() - t0:.1f}s wait)")
+        cc = G.CONFIGS[key]
+        others[key] = imm_record(P, torch, g, cc, key, steps, warm, density_gate=(key == "c2"),
+                                 equal_memory=(key == "flat"))
+        if not args.no_cpu_baseline and key != "flat":
+            og, t_graph = oracle_graph(g.n, g.row_ptr, g.dst, g.w if cc["prob"] == "EDGE" else None, cc["model"],
+                                       cc["prob"])
+            others[key]["cpu_baseline"] = cpu_baseline(og, g.n, cc["seed"], cc["k"], t_graph, key, budget_s=5.0)
+            del og
+        del g
+        log(f"[bench] {key}: {others[key]['ms_per_step']:.1f} ms per IMM")
+    graphs = [f.result() for f in bfuts]
+    pool.shutdown()
+    ctxs = batched_setup(P, insts, graphs)
+    others["c4"], _ = batched_vs_plain(P, torch, ctxs, insts, reps=1)
+    others["c4"]["workload"] = WORKLOADS["c4"]["name"]
+    for c4 in ctxs:
+        c4.close()
+    out["configs"] = others
+    out["batched_vs_plain"] = others["c4"]
+    print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="all", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain summary of the c2 line")
-    ap.add_argument("--queries", type=int, default=24, help="c5: queries per load level")
+    ap.add_argument("--no-batched", action="store_true", help="c2 line: skip the batched-vs-plain summary")
+    ap.add_argument("--queries", type=int, default=64, help="serving: queries per load level")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8, 1.0],
+                    help="serving: arrival rates as fractions of the measured single-query service rate")
+    ap.add_argument("--philox-probe", action="store_true",
+                    help="measure the Philox call rate of the samplers' RNG and exit")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the workload of the counter runs (one IMM, then a 1 GiB copy) and exit")
-    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn two rocprofv3 --pmc counter files into profiles/traffic.json and exit")
-    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 1.0],
-                    help="c5: arrival rates as fractions of the measured single-query service rate")
+    ap.add_argument("--counters-summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "L2_CSV"),
+                    help="turn three rocprofv3 --pmc counter files into profiles/counters_<workload>.json")
     args = ap.parse_args()
-    if args.traffic_summarize:
-        return traffic_summarize(*args.traffic_summarize, os.path.join(ROOT, "profiles", "traffic.json"), args.workload)
-    if args.traffic_probe:
-        return traffic_probe(args)
+    if args.counters_summarize:
+        return counters_summarize(*args.counters_summarize, args.workload)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.traffic_probe:
+        return traffic_probe(args)
+
+    import concurrent.futures as cf
+
+    pool = futs = insts = bfuts = None
+    if args.workload == "all":
+        pool = cf.ProcessPoolExecutor(8)
+        futs, insts, bfuts = start_host_work(pool, ["c2", "c3", "flat"], 256)
+    elif args.workload == "c4" or (args.workload == "c2" and not args.no_batched):
+        pool = cf.ProcessPoolExecutor(8)
+        _, insts, bfuts = start_host_work(pool, [], 256)
 
     import torch
 
     import paper_2208_00613_amd as P
     from synth import graphs as G
 
-    batched = None
-    if args.workload == "c4" or (args.workload == "c2" and not args.no_batched):
-        batched = batched_graphs()
+    if args.philox_probe:
+        print(json.dumps(philox_probe(P, torch)), flush=True)
+        return
+    if args.workload == "all":
+        return main_all(args, P, torch, pool, futs, insts, bfuts)
     if args.workload == "c4":
-        return main_c4(args, P, torch, *batched)
+        graphs = [f.result() for f in bfuts]
+        pool.shutdown()
+        return main_c4(args, P, torch, insts, graphs)
     if args.workload == "c5":
-        return main_c5(args, P, torch)
+        ctx, c, rec, host = c5_record(args, P, torch, with_host=False)
+        ctx.close()
+        out = {"metric": METRIC, "unit": "RR sets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+               "data": "synthetic (seeded Chung-Lu digraph; no public dataset)"}
+        out.update(rec)
+        print(json.dumps(out), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     c = G.CONFIGS[wl["cfg"]]
     t0 = time.time()
     g = G.config_graph(wl["cfg"])
     log(f"[bench] graph {g.name}: n={g.n} m={g.m} ({time.time() - t0:.1f}s)")
-    ctx = P.Context(0)
-    ctx.load_synth(g, model=c["model"], prob=c["prob"])
-    ctx.hbm_set_encoding(c["enc"], c.get("warmup", 0.1), c.get("hot", 0.01))
-    torch.cuda.synchronize()
-    log("[bench] graph resident in HBM")
-
-    k, eps, l, seed = c["k"], c["eps"], c["l"], c["seed"]
-    for i in range(args.warmup):
-        seeds, gains, st = ctx.hbm_imm(k, eps, l, seed)
-        log(f"[bench] warmup {i}: {st['t_total_ms']:.1f} ms, theta={st['nsets_final']}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        seeds, gains, st = ctx.hbm_imm(k, eps, l, seed)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    st = stats[-1]
-    nsets = st["nsets_final"]
-    store = st["store"]
-    out = {
-        "metric": METRIC,
-        "value": nsets / (ms / 1e3),
-        "unit": "RR sets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic (seeded R-MAT; no public dataset)",
-        "config": {"workload": wl["name"], "n": g.n, "m": g.m, "model": c["model"], "prob": c["prob"],
-                   "k": k, "eps": eps, "l": l, "encoding": c["enc"], "seed": seed},
-        "imm_s": ms / 1e3,
-        "theta_final": st["theta_final"],
-        "nsets": nsets,
-        "rounds": st["rounds"],
-        "coverage": st["coverage"],
-        "influence": st["influence"],
-        "bytes_per_rr": store["store_bytes"] / max(nsets, 1),
-        "raw_bytes_per_rr": (4 * store["members"] + 8 * (nsets + 1)) / max(nsets, 1),
-        "phase_ms": {"sample_encode": st["t_sample_ms"], "select": st["t_select_ms"]},
-    }
-    # one profiled step: per-kernel event times on the library's stream, algorithmic work
-    ctx.hbm_profile(True)
-    ctx.hbm_imm(k, eps, l, seed)
-    kstats = ctx.hbm_profile_read()
-    ctx.hbm_profile(False)
-    out["roofline"] = roofline(kstats, c["model"], c["prob"], args.workload)
-    out["kernels"] = sorted(({"name": r["name"], "launches": r["launches"], "ms": round(r["total_ms"], 3)}
-                             for r in kstats), key=lambda r: -r["ms"])[:8]
+    rec = imm_record(P, torch, g, c, args.workload, args.steps, args.warmup, density_gate=(args.workload == "c2"),
+                     equal_memory=(args.workload == "flat"))
+    out = {"metric": METRIC, "unit": "RR sets/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded R-MAT; no public dataset)"}
+    out.update(rec)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, c)
-    ctx.close()
+        og, t_graph = oracle_graph(g.n, g.row_ptr, g.dst, g.w if c["prob"] == "EDGE" else None, c["model"], c["prob"])
+        out["cpu_baseline"] = cpu_baseline(og, g.n, c["seed"], c["k"], t_graph, args.workload)
     if args.workload == "c2" and not args.no_batched:
-        # the batched form on its own workload, same GPU (256 instances, batched vs plain)
-        ctxs = batched_setup(P, *batched)
-        out["batched_vs_plain"], _ = batched_vs_plain(P, torch, ctxs, batched[0], reps=1)
+        graphs = [f.result() for f in bfuts]
+        pool.shutdown()
+        ctxs = batched_setup(P, insts, graphs)
+        out["batched_vs_plain"], _ = batched_vs_plain(P, torch, ctxs, insts, reps=1)
         out["batched_vs_plain"]["workload"] = WORKLOADS["c4"]["name"]
         for c4 in ctxs:
             c4.close()

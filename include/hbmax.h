@@ -57,12 +57,20 @@ typedef enum hbm_prob { HBM_PROB_EDGE = 0, HBM_PROB_WC = 1 } hbm_prob;
    copies of codeless vertices.  HOT_BITMAP: the top fraction of vertices by
    warm-up frequency go to bitmap rows (Bitmax restricted to hot vertices),
    the rest are kept as plain ids.  HUFFMAN_HOT_BITMAP: hot rows plus Huffman
-   coding of the remaining vertices. */
+   coding of the remaining vertices.  BITMAX: the Bitmax encoding section's
+   dense bit matrix, one row of ceil(theta / 64) words for every vertex (set j
+   is bit j of each row; the padding bits stay zero), selection by Alg. 3.
+   AUTO: Alg. 1's choice after characterizing the warm-up block with Eq. 2:
+   BITMAX when the skewness is negative and the density is above 1/32 (the
+   RRR-set characterization section's threshold), else HUFFMAN;
+   hbm_store_stats.encoding reports the choice. */
 typedef enum hbm_enc {
     HBM_ENC_NONE = 0,
     HBM_ENC_HUFFMAN = 1,
     HBM_ENC_HOT_BITMAP = 2,
-    HBM_ENC_HUFFMAN_HOT_BITMAP = 3
+    HBM_ENC_HUFFMAN_HOT_BITMAP = 3,
+    HBM_ENC_BITMAX = 4,
+    HBM_ENC_AUTO = 5
 } hbm_enc;
 
 typedef struct hbm_ctx hbm_ctx;
@@ -81,7 +89,7 @@ typedef struct hbm_store_stats {
     int64_t nsets;          /* RR sets held (theta) */
     int64_t members;        /* total vertex occurrences */
     int64_t warmup_sets;    /* W: sets in the warm-up block */
-    int32_t encoding;       /* hbm_enc */
+    int32_t encoding;       /* hbm_enc in use (AUTO resolves to BITMAX or HUFFMAN once the warm-up is done) */
     int32_t nhot;           /* hot vertices with bitmap rows */
     int32_t alphabet;       /* vertices with a Huffman code */
     int32_t max_code_len;   /* longest code, bits */
@@ -89,7 +97,7 @@ typedef struct hbm_store_stats {
     int32_t escape_bits;    /* width of a verbatim id */
     int64_t escapes;        /* codeless occurrences copied verbatim */
     uint64_t payload_bits;  /* Huffman stream bits */
-    int64_t index_bytes;    /* per-set offsets (Huffman: + one code-boundary byte per 1024 payload bits) */
+    int64_t index_bytes;    /* per-set offsets (Huffman: + one code-boundary byte per 256 payload bits) */
     int64_t bitmap_bytes;   /* hot rows */
     int64_t raw_bytes;      /* plain ids (NONE / cold part of HOT_BITMAP) */
     int64_t codebook_bytes; /* lengths + symbol table + hot list */
@@ -132,7 +140,10 @@ hbm_status hbm_set_budget(hbm_ctx *ctx, int64_t store_bytes);
 
 /* ---------------------------------------------------------------- graph */
 
-/* Load G = (V, E, w) given as a FORWARD CSR in device memory:
+/* Load G = (V, E, w) (the Influence Maximization Problem subsection of the
+ * Background: a directed graph with edge weights, under the IC or LT model;
+ * RR sets are walked on its transpose, as the RR-set definition of the RIS
+ * subsection states) given as a FORWARD CSR in device memory:
  *   row_ptr  int64[n+1]  out-edge offsets, row_ptr[0] = 0, non-decreasing, row_ptr[n] = m
  *   dst      int32[m]    target of each out-edge
  *   w        float32[m]  weight of each out-edge, or NULL when prob == HBM_PROB_WC
@@ -158,7 +169,11 @@ hbm_status hbm_load_graph(hbm_ctx *ctx, int32_t n, int64_t m, const int64_t *row
  * hot set come from its vertex frequencies and are never rebuilt.  hot_frac:
  * the hot set is the ceil(hot_frac * n) vertices with the highest warm-up
  * frequency (ties to the lower id; vertices never seen are excluded).
- * Resets the store.  HBM_EINVAL for fractions outside (0, 1] where used. */
+ * hot_frac is ignored by BITMAX and AUTO.
+ * Resets the store.  HBM_EINVAL for fractions outside (0, 1] where used, and for
+ * a Huffman encoding (or AUTO) on a graph of 2^27 or more vertices (the decode tables pack
+ * a vertex id and a code length into 32 bits; hbm_load_graph refuses such a graph
+ * while a Huffman encoding is set). */
 hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, double hot_frac);
 
 /* Density gate of the hot set: a vertex qualifies only if it is in at least
@@ -169,7 +184,32 @@ hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, doubl
  * plain top-fraction rule).  Resets the store.  HBM_EINVAL outside [0, 1]. */
 hbm_status hbm_set_hot_density(hbm_ctx *ctx, double min_density);
 
-/* Make the store hold RR sets j = 0 .. theta-1 under `seed`.  Appends when the
+/* Implicit roots: every RR set holds its root, and root_j is a pure function of
+ * (seed, j) (the first Philox draw of set j), so with on = 1 a store leaves the root
+ * out of the set's plain ids or Huffman string and regenerates it wherever the set
+ * is decoded, searched or decremented; a root with a bitmap row keeps its bit (and
+ * a BITMAX store is unchanged).  Saves the root's cost in every set (4 bytes as a
+ * plain id, its code or escape in a Huffman string); results are unchanged.
+ * Default 0.  Resets the store.  HBM_EINVAL unless on is 0 or 1. */
+hbm_status hbm_set_implicit_roots(hbm_ctx *ctx, int32_t on);
+
+/* Spill of plain ids to host memory (the equal-memory comparison of the
+ * Evaluation section, where an uncompressed store that outgrows memory spills to
+ * slower storage): with device_bytes > 0, a store that keeps plain ids (NONE, and
+ * the cold part of HOT_BITMAP) holds at most floor(device_bytes / 16) * 4 of them in
+ * device memory; the rest go to pinned host memory (hipHostMalloc, mapped and
+ * coherent) that the sampling, selection and decode kernels read and write over
+ * the bus.  Results are
+ * unchanged; only where the ids live, and so the speed, differs.  0 (default) keeps
+ * every id on the device.  Huffman and bitmap parts never spill.  Resets the store.
+ * HBM_EINVAL for device_bytes < 0 or in [1, 15]. */
+hbm_status hbm_set_spill(hbm_ctx *ctx, int64_t device_bytes);
+
+/* RIS sampling (the RIS, IMM and Ripples subsection of the Background: each RR
+ * set is the set of vertices that reach a uniformly random root over live edges)
+ * followed by Alg. 1's encoding of every block (the first block is the warm-up
+ * that fixes the codebook and hot set).
+ * Make the store hold RR sets j = 0 .. theta-1 under `seed`.  Appends when the
  * seed matches and theta grows; a different seed, or a smaller theta, resets
  * the store first.  HBM_ESTATE without a graph; HBM_EINVAL if theta < 0 or
  * theta >= 2^31.  Sets are added in blocks; HBM_EBUDGET (the store went over
@@ -305,7 +345,15 @@ typedef enum hbm_tune_key {
                                      the slots and one selection bit per vertex); 2 (default) = 1 on
                                      graphs of at least 2^22 vertices where the argmax then reads at
                                      most half as much, else 0.  Exact either way */
-    HBM_TUNE_COUNT = 9
+    HBM_TUNE_SELECT_GRAPH = 9,    /* 1: the greedy's k-iteration launch sequence (every instance of a
+                                     batch) runs as a HIP graph: its launches read their arguments
+                                     from a descriptor buffer and use grids that depend only on the
+                                     store's shape (k, encoding, graph size), so a graph captured the
+                                     first time a shape occurs is replayed for every later selection
+                                     of that shape (up to 16 shapes kept per driving context).
+                                     0 (default): launched kernel by kernel.  Not used while
+                                     profiling */
+    HBM_TUNE_COUNT = 10
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);
@@ -341,6 +389,20 @@ hbm_status hbm_profile(hbm_ctx *ctx, int32_t enable);
 
 /* Copy up to `cap` entries into host `out`; *count gets the number available. */
 hbm_status hbm_profile_read(hbm_ctx *ctx, hbm_kernel_stat *out, int32_t cap, int32_t *count);
+
+/* Device memory held by the context (graph, store, sampling and selection scratch,
+ * descriptors): *bytes_now
+ * now, *bytes_peak the most at any moment since creation or the last reset.  The
+ * paper's memory tables report peak memory; this is the device-side figure.
+ * reset_peak != 0 sets the peak to the current bytes after reading it. */
+hbm_status hbm_get_memory(hbm_ctx *ctx, int64_t *bytes_now, int64_t *bytes_peak, int32_t reset_peak);
+
+/* Throughput probe of the RNG the samplers use (Philox4x32-10, the same device
+ * function): `blocks` workgroups of 256 threads each draw calls_per_thread outputs
+ * (even, >= 2) from counters of their own.  *ms gets the kernel time (HIP events on
+ * the context's stream), *checksum a sum of the outputs (the same for the same
+ * arguments).  Calls per second = blocks * 256 * calls_per_thread / ms * 1e3. */
+hbm_status hbm_bench_philox(hbm_ctx *ctx, int64_t calls_per_thread, int32_t blocks, double *ms, uint32_t *checksum);
 
 /* ---------------------------------------------------------------- inspection */
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -20,7 +21,7 @@ HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EBUDGET, HBM_EDEVICE, HBM_ESTATE = range(6)
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBUDGET", 4: "EDEVICE", 5: "ESTATE"}
 HBM_IC, HBM_LT = 0, 1
 HBM_PROB_EDGE, HBM_PROB_WC = 0, 1
-ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3}
+ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3, "BITMAX": 4, "AUTO": 5}
 ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uint32), "COUNTS": (3, np.uint32),
           "WARM": (4, np.uint32), "HOT": (5, np.int32), "BITMAP": (6, np.uint64), "RAW_OFF": (7, np.int64),
           "RAW_MEM": (8, np.int32), "LENS": (9, np.uint8), "CODES": (10, np.uint32), "BITOFF": (11, np.int64),
@@ -29,10 +30,11 @@ EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hb
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
             "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_set_hot_density", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
-            "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune"]
+            "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune",
+            "hbm_get_memory", "hbm_bench_philox", "hbm_set_spill", "hbm_set_implicit_roots"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5,
-        "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8}
-TUNE_COUNT = 9
+        "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8, "SELECT_GRAPH": 9}
+TUNE_COUNT = 10
 
 
 class HbmError(RuntimeError):
@@ -83,6 +85,48 @@ class ServeInfo(C.Structure):
                 ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("error", C.c_char * 128)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """hbm_allocator: device memory callbacks the library calls on the calling thread."""
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Backs a context's device memory with PyTorch's caching allocator (on the context's
+    stream).  ``fail_after`` (for tests) makes the n-th and later requests return NULL until it
+    is reset to None."""
+
+    def __init__(self, device: int, stream):
+        import torch
+
+        self._torch = torch
+        self.device, self.stream = device, stream
+        self.fail_after = None
+        self.requests = 0
+        self.live = {}
+
+        def _alloc(nbytes, _user):
+            self.requests += 1
+            if self.fail_after is not None and self.requests >= self.fail_after:
+                return None
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except RuntimeError:
+                return None
+            self.live[p] = int(nbytes)
+            return p
+
+        def _release(ptr, _user):
+            if ptr and self.live.pop(ptr, None) is not None:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._fa, self._fr = _ALLOC_FN(_alloc), _RELEASE_FN(_release)  # kept alive with the context
+        self.struct = Allocator(self._fa, self._fr, None)
+
+
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "failed", "preemptions", "steps",
                                          "peak_active", "peak_store_bytes", "active", "queued")]
@@ -111,8 +155,12 @@ def lib():
         "hbm_load_graph": ([P, I32, I64, P, P, P, C.c_int, C.c_int], C.c_int),
         "hbm_set_encoding": ([P, C.c_int, D, D], C.c_int),
         "hbm_set_hot_density": ([P, D], C.c_int),
+        "hbm_set_spill": ([P, I64], C.c_int),
+        "hbm_set_implicit_roots": ([P, I32], C.c_int),
         "hbm_sample_rr": ([P, I64, U64], C.c_int),
         "hbm_select_seeds": ([P, I32, P, P, P], C.c_int),
+        "hbm_get_memory": ([P, C.POINTER(I64), C.POINTER(I64), I32], C.c_int),
+        "hbm_bench_philox": ([P, I64, I32, C.POINTER(D), C.POINTER(C.c_uint32)], C.c_int),
         "hbm_imm": ([P, I32, D, D, U64, P, P, C.POINTER(ImmStats)], C.c_int),
         "hbm_get_rr": ([P, I64, P, I64, C.POINTER(I64)], C.c_int),
         "hbm_dump_sets": ([P, I64, I64, P, P, I64, C.POINTER(I64)], C.c_int),
@@ -144,9 +192,11 @@ def _ptr(a: np.ndarray):
 
 
 class Context:
-    """One hbm_ctx on a HIP device, issuing work on a torch stream."""
+    """One hbm_ctx on a HIP device, issuing work on a torch stream.  Device memory comes from
+    PyTorch's caching allocator (allocator="torch", the default) or from hipMalloc
+    (allocator=None)."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, allocator="torch"):
         import torch
 
         self._torch = torch
@@ -157,7 +207,9 @@ class Context:
         self.stream = stream
         self.device = device
         h = C.c_void_p()
-        st = L.hbm_create(C.byref(h), device, C.c_void_p(stream.cuda_stream), None)
+        self.allocator = TorchAllocator(device, stream) if allocator == "torch" else None
+        ap = C.c_void_p(C.addressof(self.allocator.struct)) if self.allocator else None
+        st = L.hbm_create(C.byref(h), device, C.c_void_p(stream.cuda_stream), ap)
         if st != HBM_OK:
             raise HbmError(st, "hbm_create failed")
         self.h = h
@@ -169,7 +221,9 @@ class Context:
             lib().hbm_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # the allocator callbacks cannot run any more: leave it to the OS
+            return
         try:
             self.close()
         except Exception:
@@ -194,6 +248,16 @@ class Context:
         self._check(lib().hbm_profile_read(self.h, arr, cnt.value, C.byref(cnt)))
         return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
                      alg_bytes=arr[i].alg_bytes, alg_ops=arr[i].alg_ops) for i in range(cnt.value)]
+
+    def hbm_get_memory(self, reset_peak: bool = False):
+        now, peak = C.c_int64(), C.c_int64()
+        self._check(lib().hbm_get_memory(self.h, C.byref(now), C.byref(peak), 1 if reset_peak else 0))
+        return now.value, peak.value
+
+    def hbm_bench_philox(self, calls_per_thread: int, blocks: int):
+        ms, chk = C.c_double(), C.c_uint32()
+        self._check(lib().hbm_bench_philox(self.h, int(calls_per_thread), int(blocks), C.byref(ms), C.byref(chk)))
+        return ms.value, chk.value
 
     def hbm_set_tuning(self, key: str, value: int):
         self._check(lib().hbm_set_tuning(self.h, TUNE[key], int(value)))
@@ -234,6 +298,12 @@ class Context:
     def hbm_set_encoding(self, enc="NONE", warmup_frac=0.1, hot_frac=0.01):
         self._check(lib().hbm_set_encoding(self.h, ENC[enc] if isinstance(enc, str) else int(enc),
                                            float(warmup_frac), float(hot_frac)))
+
+    def hbm_set_implicit_roots(self, on: bool):
+        self._check(lib().hbm_set_implicit_roots(self.h, 1 if on else 0))
+
+    def hbm_set_spill(self, device_bytes: int):
+        self._check(lib().hbm_set_spill(self.h, int(device_bytes)))
 
     def hbm_set_hot_density(self, min_density: float):
         self._check(lib().hbm_set_hot_density(self.h, float(min_density)))

@@ -89,22 +89,50 @@ hbm_status hbm_set_budget(hbm_ctx *ctx, int64_t bytes) {
     });
 }
 
+// The Huffman decode tables pack a vertex id and a code length into one 32-bit word
+// (id << 5 | length), so Huffman encodings take graphs of fewer than 2^27 vertices.
+static bool huff_enc(int enc) { return hbm::enc_huff(enc) || enc == HBM_ENC_AUTO; }
+constexpr int32_t HUFF_MAX_N = 1 << 27;
+
 hbm_status hbm_load_graph(hbm_ctx *ctx, int32_t n, int64_t m, const int64_t *row_ptr, const int32_t *dst,
                           const float *w, hbm_model model, hbm_prob prob) {
-    return guard(ctx, [&](Ctx &c) { hbm::graph_load(c, n, m, row_ptr, dst, w, (int)model, (int)prob); });
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(!(huff_enc(c.s.enc_req) && n >= HUFF_MAX_N), HBM_EINVAL,
+                    "Huffman encodings need n < 2^27 (decode tables pack id << 5 | length)");
+        hbm::graph_load(c, n, m, row_ptr, dst, w, (int)model, (int)prob);
+    });
 }
 
 hbm_status hbm_set_encoding(hbm_ctx *ctx, hbm_enc enc, double warmup_frac, double hot_frac) {
     return guard(ctx, [&](Ctx &c) {
-        HBM_REQUIRE(enc >= HBM_ENC_NONE && enc <= HBM_ENC_HUFFMAN_HOT_BITMAP, HBM_EINVAL, "unknown encoding");
+        HBM_REQUIRE(enc >= HBM_ENC_NONE && enc <= HBM_ENC_AUTO, HBM_EINVAL, "unknown encoding");
         if (enc != HBM_ENC_NONE)
             HBM_REQUIRE(warmup_frac > 0.0 && warmup_frac <= 1.0, HBM_EINVAL, "warmup_frac must be in (0, 1]");
         if (enc == HBM_ENC_HOT_BITMAP || enc == HBM_ENC_HUFFMAN_HOT_BITMAP)
             HBM_REQUIRE(hot_frac > 0.0 && hot_frac <= 1.0, HBM_EINVAL, "hot_frac must be in (0, 1]");
+        HBM_REQUIRE(!(huff_enc((int)enc) && c.g.loaded && c.g.n >= HUFF_MAX_N), HBM_EINVAL,
+                    "Huffman encodings need n < 2^27 (decode tables pack id << 5 | length)");
+        c.s.enc_req = (int)enc;
         hbm::store_reset(c);
-        c.s.enc = (int)enc;
         c.s.warmup_frac = warmup_frac > 0.0 ? warmup_frac : 0.1;
         c.s.hot_frac = hot_frac;
+    });
+}
+
+hbm_status hbm_set_implicit_roots(hbm_ctx *ctx, int32_t on) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(on == 0 || on == 1, HBM_EINVAL, "on must be 0 or 1");
+        hbm::store_reset(c);
+        c.s.implicit_roots = on != 0;
+    });
+}
+
+hbm_status hbm_set_spill(hbm_ctx *ctx, int64_t device_bytes) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(device_bytes >= 0, HBM_EINVAL, "device_bytes must be >= 0");
+        HBM_REQUIRE(device_bytes == 0 || device_bytes >= 16, HBM_EINVAL, "device_bytes must be 0 or >= 16");
+        hbm::store_reset(c);
+        c.s.spill_cap = device_bytes;
     });
 }
 
@@ -132,6 +160,25 @@ hbm_status hbm_select_seeds(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *g
         std::memcpy(seeds, s.data(), (size_t)k * 4);
         std::memcpy(gains, g.data(), (size_t)k * 8);
         *coverage = cov;
+    });
+}
+
+hbm_status hbm_get_memory(hbm_ctx *ctx, int64_t *bytes_now, int64_t *bytes_peak, int32_t reset_peak) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(bytes_now && bytes_peak, HBM_EINVAL, "null output");
+        *bytes_now = c.mem_now;
+        *bytes_peak = c.mem_peak;
+        if (reset_peak) c.mem_peak = c.mem_now;
+    });
+}
+
+hbm_status hbm_bench_philox(hbm_ctx *ctx, int64_t calls_per_thread, int32_t blocks, double *ms, uint32_t *checksum) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(ms && checksum, HBM_EINVAL, "null output");
+        uint32_t sum = 0;
+        const double t = hbm::philox_probe(c, calls_per_thread, blocks, &sum);
+        *ms = t;
+        *checksum = sum;
     });
 }
 
@@ -370,7 +417,7 @@ hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_
     return guard(ctx, [&](Ctx &c) {
         HBM_REQUIRE(bytes, HBM_EINVAL, "null bytes");
         const hbm::Store &s = c.s;
-        const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
+        const bool huff = hbm::enc_huff(s.enc), raw = hbm::enc_raw(s.enc);
         const void *src = nullptr;
         int64_t nb = 0;
         const int64_t n = c.g.n, T = s.nsets;
@@ -385,8 +432,8 @@ hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_
             case HBM_A_WARM: src = s.warm.p; nb = (s.warm.p && s.model_ready) ? n * 4 : 0; break;
             case HBM_A_HOT: src = s.hot.p; nb = (int64_t)s.nhot * 4; break;
             case HBM_A_BITMAP: src = s.bitmap.p; nb = s.nhot ? ((T + 63) / 64) * s.nhot * 8 : 0; break;
-            case HBM_A_RAW_OFF: src = s.raw_off.p; nb = (!huff && T) ? (T + 1) * 8 : 0; break;
-            case HBM_A_RAW_MEM: src = s.raw_mem.p; nb = (!huff && T) ? s.raw_count * 4 : 0; break;
+            case HBM_A_RAW_OFF: src = s.raw_off.p; nb = (raw && T) ? (T + 1) * 8 : 0; break;
+            case HBM_A_RAW_MEM: src = s.raw_mem.p; nb = (raw && T) ? s.raw_count * 4 : 0; break;
             case HBM_A_LENS: src = s.lens.p; nb = (huff && s.model_ready) ? n : 0; break;
             case HBM_A_CODES: src = s.codes.p; nb = (huff && s.model_ready) ? n * 4 : 0; break;
             case HBM_A_BITOFF: src = s.bitoff.p; nb = (huff && T) ? (T + 1) * 8 : 0; break;
@@ -397,8 +444,11 @@ hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_
         HBM_REQUIRE(nb <= cap_bytes, HBM_EINVAL, "buffer too small");
         if (nb > 0) {
             HBM_REQUIRE(src && host_out, HBM_EINVAL, "array not present");
-            HBM_HIP(hipMemcpyAsync(host_out, src, (size_t)nb, hipMemcpyDeviceToHost, c.stream));
+            int64_t dev_nb = nb;
+            if (what == HBM_A_RAW_MEM && s.raw_split < s.raw_count) dev_nb = s.raw_split * 4;  // spilled
+            HBM_HIP(hipMemcpyAsync(host_out, src, (size_t)dev_nb, hipMemcpyDeviceToHost, c.stream));
             HBM_HIP(hipStreamSynchronize(c.stream));
+            if (dev_nb < nb) std::memcpy((char *)host_out + dev_nb, s.raw_host_h, (size_t)(nb - dev_nb));
         }
     });
 }
@@ -453,6 +503,10 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             HBM_REQUIRE(value >= 0 && value <= 2, HBM_EINVAL, "SPARSE_COUNTS must be 0, 1 or 2");
             c.sparse_counts = (int)value;
             break;
+        case HBM_TUNE_SELECT_GRAPH:
+            HBM_REQUIRE(value == 0 || value == 1, HBM_EINVAL, "SELECT_GRAPH must be 0 or 1");
+            c.select_graph = (int)value;
+            break;
         case HBM_TUNE_BLOCK_SETS:
             HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
             c.block_sets = value;
@@ -473,6 +527,7 @@ int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
         case HBM_TUNE_LDS_THREADS: return c.lds_threads;
         case HBM_TUNE_LDS_PER_CU: return c.lds_per_cu;
         case HBM_TUNE_SPARSE_COUNTS: return c.sparse_counts;
+        case HBM_TUNE_SELECT_GRAPH: return c.select_graph;
         default: return -1;
     }
 }

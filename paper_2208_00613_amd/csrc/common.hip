@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "hbm_device.h"
 #include "hbm_internal.h"
 
 namespace hbm {
@@ -21,11 +22,14 @@ static void *raw_alloc(Ctx &c, size_t bytes) {
             throw Error{HBM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
         }
     }
+    c.mem_now += (int64_t)bytes;
+    c.mem_peak = std::max(c.mem_peak, c.mem_now);
     return p;
 }
 
-static void raw_free(Ctx &c, void *p) {
+static void raw_free(Ctx &c, void *p, size_t bytes) {
     if (!p) return;
+    c.mem_now -= (int64_t)(bytes ? bytes : 256);
     if (c.has_alloc) {
         // the caller's allocator may recycle the block on another stream: finish our work first
         (void)hipStreamSynchronize(c.stream);
@@ -37,7 +41,7 @@ static void raw_free(Ctx &c, void *p) {
 }
 
 void buf_free(Ctx &c, Buf &b) {
-    raw_free(c, b.p);
+    raw_free(c, b.p, b.bytes);
     b.p = nullptr;
     b.bytes = 0;
 }
@@ -56,7 +60,7 @@ void buf_grow(Ctx &c, Buf &b, size_t bytes, bool keep) {
     if (keep && b.p && b.bytes) {
         hipError_t e = hipMemcpyAsync(np, b.p, b.bytes, hipMemcpyDeviceToDevice, c.stream);
         if (e != hipSuccess) {
-            raw_free(c, np);
+            raw_free(c, np, cap);
             throw Error{HBM_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)};
         }
         // new tail must read as zero for buffers that are OR-ed into
@@ -64,7 +68,7 @@ void buf_grow(Ctx &c, Buf &b, size_t bytes, bool keep) {
     } else {
         HBM_HIP(hipMemsetAsync(np, 0, cap, c.stream));
     }
-    raw_free(c, b.p);
+    raw_free(c, b.p, b.bytes);
     b.p = np;
     b.bytes = cap;
 }
@@ -130,6 +134,49 @@ void stage_free(Ctx &root) {
     if (root.hstage) (void)hipHostFree(root.hstage);
     root.hstage = nullptr;
     root.stage_pos = 0;
+}
+
+// ------------------------------------------------------------------ Philox throughput probe
+// Each thread draws `calls` Philox4x32-10 outputs from counters of its own (two independent
+// chains per iteration, so the products of one can issue under the other's xors), and the
+// outputs are folded into one checksum word so no call can be dropped by the compiler.  Every
+// counter word differs from lane to lane, as in the samplers (a counter word shared by the
+// wave would let the compiler move part of the first round to the scalar unit).
+__global__ __launch_bounds__(256) void k_philox_probe(int64_t calls, uint32_t k0, uint32_t k1, uint32_t *out) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t1 = tid * 0x9E3779B9u, t2 = tid * 0x85EBCA6Bu, t3 = tid * 0xC2B2AE35u;
+    uint32_t acc = 0;
+    for (int64_t i = 0; i < calls; i += 2) {
+        const uint32_t lo = (uint32_t)i, hi = (uint32_t)(i >> 32);
+        // both multiplied words change with i, so no product of the first round is loop-invariant
+        const uint4 a = philox10(lo ^ t1, tid, lo ^ t2, hi ^ t3, k0, k1);
+        const uint4 b = philox10((lo + 1u) ^ t1, tid, (lo + 1u) ^ t2, hi ^ t3, k0, k1);
+        acc += (a.x ^ a.y ^ a.z ^ a.w) + (b.x ^ b.y ^ b.z ^ b.w);
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane_id() == 0) atomicAdd(out, acc);
+}
+
+double philox_probe(Ctx &c, int64_t calls, int32_t blocks, uint32_t *checksum) {
+    HBM_REQUIRE(calls >= 2 && calls % 2 == 0, HBM_EINVAL, "calls must be even and >= 2");
+    HBM_REQUIRE(blocks >= 1, HBM_EINVAL, "blocks must be >= 1");
+    buf_grow(c, c.tails, 256, false);
+    uint32_t *out = c.tails.as<uint32_t>();
+    buf_zero(c, c.tails, 0, 4);
+    hipEvent_t e0, e1;
+    HBM_HIP(hipEventCreate(&e0));
+    HBM_HIP(hipEventCreate(&e1));
+    HBM_HIP(hipEventRecord(e0, c.stream));
+    k_philox_probe<<<(unsigned)blocks, 256, 0, c.stream>>>(calls, 0x2545F491u, 0x9E3779B9u, out);
+    HBM_HIP(hipGetLastError());
+    HBM_HIP(hipEventRecord(e1, c.stream));
+    HBM_HIP(hipMemcpyAsync(checksum, out, 4, hipMemcpyDeviceToHost, c.stream));
+    HBM_HIP(hipStreamSynchronize(c.stream));
+    float ms = 0;
+    HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return (double)ms;
 }
 
 // ------------------------------------------------------------------ profiler

@@ -128,6 +128,21 @@ __device__ __forceinline__ uint32_t group_of(const uint32_t *boff, uint32_t coun
     return lo;
 }
 
+// The root a store leaves out of set j under implicit roots (~0u: every member is stored).
+__device__ __forceinline__ uint32_t dropped_root(int implicit, uint64_t seed, uint64_t j, uint32_t n) {
+    return implicit ? rr_root(seed, j, n) : 0xFFFFFFFFu;
+}
+
+// Plain ids of a store: [0, split) in device memory, [split, ...) in pinned host memory that
+// the GPU reads over the bus (split is a multiple of 4, so 16-byte loads never straddle it).
+__device__ __forceinline__ int32_t raw_id(const int32_t *dev, const int32_t *host, int64_t split, int64_t i) {
+    return i < split ? dev[i] : host[i - split];
+}
+__device__ __forceinline__ uint4 raw_id4(const int32_t *dev, const int32_t *host, int64_t split, int64_t q) {
+    const int64_t i = q * 4;
+    return i < split ? reinterpret_cast<const uint4 *>(dev)[q] : reinterpret_cast<const uint4 *>(host + (i - split))[0];
+}
+
 #define HBM_KERNEL(NAME, ARGS, THREADS)                                                              \
     __device__ void NAME##_body(const ARGS &A, uint32_t bid, uint32_t nblk, int x);                  \
     __global__ __launch_bounds__(THREADS) void NAME(ARGS A, int x) { NAME##_body(A, blockIdx.x, gridDim.x, x); } \

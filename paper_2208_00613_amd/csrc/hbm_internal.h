@@ -77,10 +77,17 @@ struct Codebook {
     int32_t minlen = 0;
 };
 
+// What an encoding stores: Huffman strings; plain (cold) ids with per-set offsets; bitmap rows.
+inline bool enc_huff(int e) { return e == HBM_ENC_HUFFMAN || e == HBM_ENC_HUFFMAN_HOT_BITMAP; }
+inline bool enc_raw(int e) { return e == HBM_ENC_NONE || e == HBM_ENC_HOT_BITMAP; }
+inline bool enc_rows(int e) { return e == HBM_ENC_HOT_BITMAP || e == HBM_ENC_HUFFMAN_HOT_BITMAP || e == HBM_ENC_BITMAX; }
+
 struct Store {
-    int enc = HBM_ENC_NONE;
+    int enc_req = HBM_ENC_NONE;  // as requested (AUTO until the warm-up decides)
+    int enc = HBM_ENC_NONE;      // in use
     double warmup_frac = 0.1, hot_frac = 0.01;
     double hot_min_density = 0.0;  // a hot vertex is in at least this fraction of warm-up sets
+    bool implicit_roots = false;   // set j's root is regenerated from (seed, j), not stored
     bool has_seed = false;
     uint64_t seed = 0;
     int64_t nsets = 0;
@@ -99,8 +106,16 @@ struct Store {
     int64_t bm_words = 0;
     // raw (cold) ids
     Buf raw_off;   // int64[nsets+1]
-    Buf raw_mem;   // int32[]
+    Buf raw_mem;   // int32[]: ids [0, raw_split) in device memory
     int64_t raw_count = 0;
+    // spill of plain ids to pinned host memory: with spill_cap > 0 the device keeps the first
+    // raw_split = floor(spill_cap / 16) * 4 ids and ids from raw_split on live in raw_host
+    // (mapped, read by the kernels over the bus); spill_cap == 0 keeps every id on the device
+    int64_t spill_cap = 0;
+    int64_t raw_split = INT64_MAX;
+    int32_t *raw_host = nullptr;    // device address of the host part
+    int32_t *raw_host_h = nullptr;  // its host address
+    size_t raw_host_cap = 0;        // ids
     // Huffman
     Codebook cb;
     Buf lens;      // uint8[n]
@@ -213,6 +228,18 @@ struct Ctx {
     int lds_threads = 0;                 // threads of an LDS-tier workgroup (512 or 1024; 0 = by n)
     int lds_per_cu = 0;                  // LDS-tier workgroups launched per CU (0 = by n)
     int sparse_counts = 2;               // selection counts: 0 dense, 1 sparse slots, 2 by size
+    int select_graph = 0;                // greedy launches replayed from a captured HIP graph
+    hipStream_t cap_stream = nullptr;    // the stream the greedy is captured on
+    // instantiated greedy graphs by launch shape (most recently used last), and the selection
+    // descriptors they read: a device buffer at a fixed address with a pinned host mirror
+    struct SelGraph {
+        std::vector<uint64_t> shape;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<SelGraph> sel_graphs;
+    Buf sel_desc;
+    void *sel_hdesc = nullptr;
+    size_t sel_hdesc_bytes = 0;
     DGraph g;
     Store s;
     Scratch sc;
@@ -230,6 +257,8 @@ struct Ctx {
     Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)
     // timing of the last operations (ms)
     double t_sample = 0, t_encode = 0, t_select = 0;
+    // device bytes this context holds now, and the most since creation or the last peak reset
+    int64_t mem_now = 0, mem_peak = 0;
 };
 
 // ------------------------------------------------------------------ host entry points of each part
@@ -261,12 +290,17 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                    const std::vector<int64_t> &nb, const std::vector<uint64_t> &seed, std::vector<int64_t> &done);
 void ensure_scratch(Ctx &c, size_t entries, int64_t bcap);
 
+// Philox throughput probe: `calls` Philox4x32-10 calls per thread over the whole chip
+// (independent counters, results folded into a checksum); returns kernel milliseconds.
+double philox_probe(Ctx &c, int64_t calls, int32_t blocks, uint32_t *checksum);
+
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
 // greedy selection for several jobs at once (root drives the launches)
 void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
                   std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
                   std::vector<uint64_t> &coverage);
 void select_free(Ctx &c);
+void raw_host_free(Ctx &c);  // the pinned host part of a spilled plain-id store
 
 // profiler: prof_begin records the start event of a launch (returns -1 when off),
 // prof_end the stop event; prof_set fills in work that is known only later.

@@ -10,13 +10,17 @@
 //            If u* is hot its bitmap row gives the newly covered sets directly
 //            (Eq. 3: row AND NOT covered).  Otherwise every uncovered set is
 //            searched for u*: binary search in plain ids, or a partial decode
-//            of the Huffman string that stops at u* or at the first larger id
-//            (Alg. 2's DecodeFind; ids after the front element are ascending).
+//            of the Huffman string (Alg. 2's DecodeFind) that stops at u* or at
+//            the first code above u*'s: after the escaped ids and the front
+//            element the codes follow canonical (length, id) order, i.e.
+//            ascending left-justified code value.
 //            The plain / coded members of newly covered sets are decremented.
 //   hot    : counts of hot vertices drop by popcount(row AND newly), word by
 //            word (Alg. 3's SUBTRACT and POPCOUNT, applied to the change only).
 // Counts are exact 32-bit integers (the paper's float frequencies are not exact
 // beyond 2^24).  The store itself is never modified.
+#include <cstring>
+
 #include "hbm_device.h"
 #include "hbm_internal.h"
 
@@ -37,6 +41,10 @@ struct SelArgs {
     const unsigned long long *bitmap;
     const int64_t *raw_off;
     const int32_t *raw_mem;
+    const int32_t *raw_host;  // plain ids from raw_split on (a spilled store)
+    int64_t raw_split;
+    int implicit;             // implicit roots: set j's root (if not in a bitmap row) is not stored
+    uint64_t seed;            // the store's seed (root_j = rr_root(seed, j, n))
     int huff;
     const int64_t *bitoff;
     const uint32_t *payload;
@@ -66,6 +74,14 @@ struct SelArgs {
     const int64_t *ncand;         // number of slots (device)
     unsigned long long *pbits;    // profiling: payload bits decoded by k_dec_big (else null)
 };
+
+// The root a store with implicit roots left out of set j (a root with a bitmap row is in its
+// row), or ~0u.
+__device__ __forceinline__ uint32_t lost_root(const SelArgs &A, int64_t j) {
+    if (!A.implicit) return 0xFFFFFFFFu;
+    const uint32_t r = rr_root(A.seed, (uint64_t)j, (uint32_t)A.n);
+    return (A.hot_rank && A.hot_rank[r] >= 0) ? 0xFFFFFFFFu : r;
+}
 
 // Index into `counts` of vertex v (every decremented vertex is a member of some set, so it
 // has a slot when the counts are sparse).  Decoded Huffman symbols are already such indices:
@@ -368,16 +384,15 @@ HBM_KERNEL(k_find_raw, SelArgs, 256) {
     const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     const int64_t n4 = A.nraw >> 2;
-    const uint4 *m4 = reinterpret_cast<const uint4 *>(A.raw_mem);
     for (int64_t q = tid; q <= n4; q += nthr) {
         uint32_t x[4];
         int cnt = 4;
         if (q < n4) {
-            const uint4 m = m4[q];
+            const uint4 m = raw_id4(A.raw_mem, A.raw_host, A.raw_split, q);
             x[0] = m.x; x[1] = m.y; x[2] = m.z; x[3] = m.w;
         } else {
             cnt = (int)(A.nraw - n4 * 4);
-            for (int r = 0; r < cnt; r++) x[r] = (uint32_t)A.raw_mem[n4 * 4 + r];
+            for (int r = 0; r < cnt; r++) x[r] = (uint32_t)raw_id(A.raw_mem, A.raw_host, A.raw_split, n4 * 4 + r);
         }
         for (int r = 0; r < cnt; r++) {
             if (x[r] != u) continue;
@@ -391,6 +406,13 @@ HBM_KERNEL(k_find_raw, SelArgs, 256) {
             }
             const unsigned long long bit = 1ull << (lo & 63);
             if (!(A.covered[lo >> 6] & bit)) atomicOr(&A.newly[lo >> 6], bit);
+        }
+    }
+    if (A.implicit) {  // sets whose root, not stored, is u* (u* is cold here)
+        for (int64_t j = tid; j < A.T; j += nthr) {
+            if (rr_root(A.seed, (uint64_t)j, (uint32_t)A.n) != u) continue;
+            const unsigned long long bit = 1ull << (j & 63);
+            if (!(A.covered[j >> 6] & bit)) atomicOr(&A.newly[j >> 6], bit);
         }
     }
 }
@@ -482,10 +504,12 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         }
         bool found = false;
         uint64_t p0 = 0, p1 = 0;
+        uint32_t lroot = 0xFFFFFFFFu;
         if ((live >> lane) & 1ull) {
             p0 = bo - off;
             p1 = bnext - off;
-            found = huff_contains(A, tb, buf, p0, p1, u, ustar_len, ustar_code, fe_len, fe_code);
+            lroot = lost_root(A, j0 + lane);
+            found = lroot == u || huff_contains(A, tb, buf, p0, p1, u, ustar_len, ustar_code, fe_len, fe_code);
         }
         const unsigned long long nwm = __ballot(found);
         if (lane == 0 && nwm) {
@@ -497,7 +521,10 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
             // would be one dependent load per code in this lane): a whole wave decrements it
             // later from an LDS copy
             if (!staged || p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j0 + lane);
-            else huff_decrement(A, tb, C, buf, p0, p1);
+            else {
+                huff_decrement(A, tb, C, buf, p0, p1);
+                if (lroot != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, lroot));
+            }
         }
         wave_sync();
     }
@@ -547,7 +574,12 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
                 rest &= rest - 1;
                 const int64_t j = w * 64 + b;
                 const int64_t e = A.raw_off[j + 1];
-                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE) cache_dec(C, A, ckey(A, (uint32_t)A.raw_mem[i]));
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE)
+                    cache_dec(C, A, ckey(A, (uint32_t)raw_id(A.raw_mem, A.raw_host, A.raw_split, i)));
+                if (A.implicit && lane == 0) {
+                    const uint32_t r = lost_root(A, j);
+                    if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
+                }
             }
         }
     }
@@ -594,6 +626,11 @@ HBM_KERNEL(k_dec_big, SelArgs, 256) {
             have &= have - 1;
             uint64_t pos = (uint64_t)__shfl((unsigned long long)b0, src, WAVE);
             const uint64_t ce = (uint64_t)__shfl((unsigned long long)b1, src, WAVE);
+            const int64_t js = (int64_t)__shfl((unsigned long long)jm, src, WAVE);  // the string's set
+            if (A.implicit && lane == 0) {  // the set's root, left out of its string
+                const uint32_t r = lost_root(A, js);
+                if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
+            }
             if (A.pbits && lane == 0) atomicAdd(A.pbits, (unsigned long long)(ce - pos));
             // gamma(nesc + 1) from one three-word window (the code has 2L + 1 <= 63 bits)
             uint32_t nesc;
@@ -660,6 +697,14 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
 }
 
 void select_free(Ctx &c) {
+    for (auto &g : c.sel_graphs) (void)hipGraphExecDestroy(g.exec);
+    c.sel_graphs.clear();
+    if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+    c.cap_stream = nullptr;
+    buf_free(c, c.sel_desc);
+    if (c.sel_hdesc) (void)hipHostFree(c.sel_hdesc);
+    c.sel_hdesc = nullptr;
+    c.sel_hdesc_bytes = 0;
     SelState &S = c.sel;
     for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big, &S.cand, &S.cpos, &S.csel,
                    &S.sbcnt, &S.sboff, &S.slut, &S.ssym})
@@ -775,42 +820,62 @@ struct SelJob {
     double b_arg, b_find, b_apply;
 };
 
-SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
+// Selection state in caller-provided device memory (dense counts, no profiling); sizes
+// as sel_fixed_layout computes them.
+struct SelBufs {
+    uint32_t *counts, *selmask, *big;
+    unsigned long long *covered, *newly, *partial, *keys;
+};
+
+static unsigned argmax_blocks(const Ctx &root, int32_t n) {
+    return grid_for(((int64_t)n + 3) / 4, 256 * AM_UNROLL, (int64_t)root.num_cus * 8);
+}
+
+// gfix: grids that depend only on the graph and the store's shape (a graph of launches captured
+// once then serves stores of any size: every selection kernel strides over its work)
+SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const SelBufs *fixed = nullptr,
+                bool gfix = false) {
     Store &s = c.s;
     SelState &S = c.sel;
     const int32_t n = c.g.n;
     const int64_t T = s.nsets;
     const int64_t words = (T + 63) / 64;
-    const unsigned g_arg = grid_for(((int64_t)n + 3) / 4, 256 * AM_UNROLL, (int64_t)root.num_cus * 8);
-    const int64_t m = build_slots(root, c);  // -1: dense counts
-    if (m < 0) buf_grow(c, S.counts, (size_t)n * 4, false);
-    buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
-    buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
-    buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
-    buf_grow(c, S.partial, (size_t)g_arg * 8, false);
-    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    if (huff && T > 0) buf_grow(c, S.big, (size_t)(T + 2) * 4, false);
+    const unsigned g_arg = argmax_blocks(root, n);
+    const bool huff = enc_huff(s.enc), raw = enc_raw(s.enc);
+    const int64_t m = fixed ? -1 : build_slots(root, c);  // -1: dense counts
+    if (!fixed) {
+        if (m < 0) buf_grow(c, S.counts, (size_t)n * 4, false);
+        buf_grow(c, S.selmask, ((size_t)n + 31) / 32 * 4, false);
+        buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
+        buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
+        buf_grow(c, S.partial, (size_t)g_arg * 8, false);
+        if (huff && T > 0) buf_grow(c, S.big, (size_t)(T + 2) * 4, false);
+    }
     SelJob J{};
     SelArgs &A = J.A;
     A.T = T;
     A.words = words;
     A.n = n;
-    A.counts = S.counts.as<uint32_t>();
+    A.counts = fixed ? fixed->counts : S.counts.as<uint32_t>();
     A.cand = m >= 0 ? S.cand.as<uint32_t>() : nullptr;
     A.cpos = m >= 0 ? S.cpos.as<int32_t>() : nullptr;
     A.csel = m >= 0 ? S.csel.as<uint32_t>() : nullptr;
     A.ncand = m >= 0 ? S.sboff.as<int64_t>() + (((int64_t)n + SL_SPAN - 1) / SL_SPAN) : nullptr;
-    A.pbits = root.prof.on ? prof_counters(root) + DC_EDGES : nullptr;
-    A.selmask = S.selmask.as<uint32_t>();
-    A.covered = S.covered.as<unsigned long long>();
-    A.newly = S.newly.as<unsigned long long>();
+    A.pbits = root.prof.on && !fixed ? prof_counters(root) + DC_EDGES : nullptr;
+    A.selmask = fixed ? fixed->selmask : S.selmask.as<uint32_t>();
+    A.covered = fixed ? fixed->covered : S.covered.as<unsigned long long>();
+    A.newly = fixed ? fixed->newly : S.newly.as<unsigned long long>();
     A.keys = keys;
     A.nhot = s.nhot;
     A.hot = s.hot.as<int32_t>();
     A.hot_rank = s.nhot ? s.hot_rank.as<int32_t>() : nullptr;
     A.bitmap = s.bitmap.as<unsigned long long>();
-    A.raw_off = huff ? nullptr : s.raw_off.as<int64_t>();
-    A.raw_mem = huff ? nullptr : s.raw_mem.as<int32_t>();
+    A.raw_off = raw ? s.raw_off.as<int64_t>() : nullptr;  // BITMAX: every member is in a row
+    A.raw_mem = raw ? s.raw_mem.as<int32_t>() : nullptr;
+    A.raw_host = s.raw_host;
+    A.raw_split = s.raw_split;
+    A.implicit = s.implicit_roots && s.enc != HBM_ENC_BITMAX;
+    A.seed = s.seed;
     A.huff = huff && T > 0;
     A.bitoff = s.bitoff.as<int64_t>();
     A.payload = s.payload.as<uint32_t>();
@@ -834,12 +899,12 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     A.minlen = s.cb.minlen;
     A.wbits = s.cb.wbits;
     A.ustar_enc = s.cb.ustar_enc;
-    A.nraw = huff ? 0 : s.raw_count;
-    A.partial = S.partial.as<unsigned long long>();
+    A.nraw = raw ? s.raw_count : 0;
+    A.partial = fixed ? fixed->partial : S.partial.as<unsigned long long>();
     A.nparts = (int32_t)g_arg;
     A.hist = T > 0 ? s.hist.as<uint32_t>() : nullptr;
     A.ckb = s.ckb.as<uint8_t>();
-    A.big = huff && T > 0 ? S.big.as<uint32_t>() : nullptr;
+    A.big = huff && T > 0 ? (fixed ? fixed->big : S.big.as<uint32_t>()) : nullptr;
     A.k = k;
     A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
@@ -848,11 +913,12 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys) {
     J.huff = huff;
     J.g_arg = g_arg;
     if (T == 0) J.g_find = 0;
-    else if (huff) J.g_find = grid_for(words, 4, (int64_t)root.num_cus * 7);  // resident: 7 blocks per CU
-    else J.g_find = A.nraw > 0 ? grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4) : 0;
-    J.g_apply = grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
-    J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * nseg) : 0;
-    J.g_big = A.big ? grid_for(T, 256, (int64_t)root.num_cus * 3) : 0;  // idle blocks leave at once
+    else if (huff) J.g_find = gfix ? (uint32_t)root.num_cus * 7 : grid_for(words, 4, (int64_t)root.num_cus * 7);  // resident: 7 blocks per CU
+    else J.g_find = A.nraw > 0 ? (gfix ? (uint32_t)root.num_cus * 4 : grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4)) : 0;
+    J.g_apply = gfix ? (uint32_t)root.num_cus * 2 : grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
+    // hot counts: segments past the words in use find no word to read
+    J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * (gfix ? std::max<int64_t>(1, 4096 / A.hx) : nseg)) : 0;
+    J.g_big = A.big ? (gfix ? (uint32_t)root.num_cus * 3 : grid_for(T, 256, (int64_t)root.num_cus * 3)) : 0;  // idle blocks leave at once
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
     // reads and writes the covered and newly words (and the hot row when u* is hot).
@@ -874,9 +940,11 @@ struct Plan {
 
 }  // namespace
 
-void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
-                  std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
-                  std::vector<uint64_t> &coverage) {
+// fixed != null (one job only): the selection state and keys live in the given device memory,
+// and nothing is allocated, timed or profiled.
+static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
+                       std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
+                       std::vector<uint64_t> &coverage, const SelBufs *fixed) {
     const size_t N = C.size();
     seeds.assign(N, {});
     gains.assign(N, {});
@@ -890,14 +958,19 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         kmax = std::max(kmax, k[i]);
         koff[i + 1] = koff[i] + k[i];
     }
+    HBM_REQUIRE(!fixed || N == 1, HBM_EINVAL, "internal: fixed selection state serves one job");
     stage_reset(root);
-    hipEvent_t e0, e1;
-    HBM_HIP(hipEventCreate(&e0));
-    HBM_HIP(hipEventCreate(&e1));
-    HBM_HIP(hipEventRecord(e0, root.stream));
-    buf_grow(root, root.bkeys, (size_t)koff[N] * 8, false);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!fixed) {
+        HBM_HIP(hipEventCreate(&e0));
+        HBM_HIP(hipEventCreate(&e1));
+        HBM_HIP(hipEventRecord(e0, root.stream));
+        buf_grow(root, root.bkeys, (size_t)koff[N] * 8, false);
+    }
+    unsigned long long *dkeys = fixed ? fixed->keys : root.bkeys.as<unsigned long long>();
+    const bool graph = root.select_graph && !fixed && !root.prof.on;
     std::vector<SelJob> J(N);
-    for (size_t i = 0; i < N; i++) J[i] = plan_job(root, *C[i], k[i], root.bkeys.as<unsigned long long>() + koff[i]);
+    for (size_t i = 0; i < N; i++) J[i] = plan_job(root, *C[i], k[i], dkeys + koff[i], fixed, graph);
 
     // job order: k descending (stable on the index)
     std::vector<size_t> order(N);
@@ -922,18 +995,20 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
             case P_RAW: return J[i].g_find;
             case P_HOT: return J[i].g_hot;
             case P_BIG: return J[i].g_big;
-            default: return grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
+            default: return graph ? 1024u : grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
         }
     };
-    // one upload of every plan's descriptors and block offsets
+    // one upload of every plan's descriptors and block offsets (graph mode: always, into a
+    // buffer at a fixed address that the captured launches read)
     std::vector<char> host;
     std::vector<size_t> aoff(NPLAN), boff_off(NPLAN);
     auto align = [&]() { host.resize((host.size() + 255) & ~size_t(255)); };
+    const bool grouped = N > 1 || graph;
     for (int p = 0; p < NPLAN; p++) {
         Plan &P = plans[p];
         P.boff.assign(P.jobs.size() + 1, 0);
         for (size_t q = 0; q < P.jobs.size(); q++) P.boff[q + 1] = P.boff[q] + blocks(p, P.jobs[q]);
-        if (N == 1) continue;
+        if (!grouped) continue;
         align();
         aoff[p] = host.size();
         for (size_t i : P.jobs) {
@@ -945,14 +1020,31 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         const char *b = reinterpret_cast<const char *>(P.boff.data());
         host.insert(host.end(), b, b + P.boff.size() * 4);
     }
-    if (N > 1) {
-        char *d = (char *)stage_upload(root, host.data(), host.size());
+    if (grouped) {
+        char *d = nullptr;
+        if (graph) {
+            // the previous selection's graph has finished (selections end with a synchronisation),
+            // so the descriptors may be rewritten in place
+            if (root.sel_hdesc_bytes < host.size()) {
+                const size_t cap = std::max<size_t>(host.size() * 2, size_t(64) << 10);
+                buf_alloc(root, root.sel_desc, cap);
+                if (root.sel_hdesc) (void)hipHostFree(root.sel_hdesc);
+                root.sel_hdesc = nullptr;
+                root.sel_hdesc_bytes = 0;
+                HBM_HIP(hipHostMalloc(&root.sel_hdesc, cap, hipHostMallocDefault));
+                root.sel_hdesc_bytes = cap;
+            }
+            std::memcpy(root.sel_hdesc, host.data(), host.size());
+            HBM_HIP(hipMemcpyAsync(root.sel_desc.p, root.sel_hdesc, host.size(), hipMemcpyHostToDevice, root.stream));
+            d = root.sel_desc.as<char>();
+        } else {
+            d = (char *)stage_upload(root, host.data(), host.size());
+        }
         for (int p = 0; p < NPLAN; p++) {
             plans[p].dargs = reinterpret_cast<const SelArgs *>(d + aoff[p]);
             plans[p].dboff = reinterpret_cast<const uint32_t *>(d + boff_off[p]);
         }
     }
-    const hipStream_t st = root.stream;
     // number of jobs of plan p still running at iteration t
     auto active = [&](int p, int t) -> uint32_t {
         const Plan &P = plans[p];
@@ -964,12 +1056,13 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         }
         return lo;
     };
+    hipStream_t st = root.stream;
 #define HBM_SEL_LAUNCH(PLAN, KERNEL, T_)                                                                  \
     do {                                                                                                \
         const Plan &P_ = plans[PLAN];                                                                   \
         const uint32_t cnt_ = active(PLAN, T_);                                                         \
         if (cnt_ && P_.boff[cnt_]) {                                                                    \
-            if (N == 1) KERNEL<<<P_.boff[1], 256, 0, st>>>(J[P_.jobs[0]].A, T_);                         \
+            if (!grouped) KERNEL<<<P_.boff[1], 256, 0, st>>>(J[P_.jobs[0]].A, T_);                      \
             else KERNEL##_g<<<P_.boff[cnt_], 256, 0, st>>>(GroupArgs<SelArgs>{P_.dargs, P_.dboff, cnt_, T_}); \
         }                                                                                               \
     } while (0)
@@ -979,37 +1072,84 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         for (uint32_t q = 0; q < cnt; q++) b += J[plans[p].jobs[q]].*f;
         return b;
     };
-    HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
-    HBM_HIP(hipGetLastError());
+    auto prof_begin = [&](Ctx &r, const char *name) { return fixed ? -1 : hbm::prof_begin(r, name); };
     int ps_big = -1;  // profiling: a dec_big launch, credited with the bits all of them decoded
-    for (int t = 0; t < kmax; t++) {
-        int ps = prof_begin(root, "argmax");
-        HBM_SEL_LAUNCH(P_ALL_ARG, k_argmax, t);
-        prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_ARG, t, &SelJob::b_arg) : 0);
-        if (active(P_HUFF, t)) {
-            ps = prof_begin(root, "find_huff");
-            HBM_SEL_LAUNCH(P_HUFF, k_find_huff, t);
-            prof_end(root, ps, ps >= 0 ? bytes_of(P_HUFF, t, &SelJob::b_find) : 0);
+    auto launch_all = [&]() {
+        HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
+        for (int t = 0; t < kmax; t++) {
+            int ps = prof_begin(root, "argmax");
+            HBM_SEL_LAUNCH(P_ALL_ARG, k_argmax, t);
+            prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_ARG, t, &SelJob::b_arg) : 0);
+            if (active(P_HUFF, t)) {
+                ps = prof_begin(root, "find_huff");
+                HBM_SEL_LAUNCH(P_HUFF, k_find_huff, t);
+                prof_end(root, ps, ps >= 0 ? bytes_of(P_HUFF, t, &SelJob::b_find) : 0);
+            }
+            if (active(P_RAW, t)) {
+                ps = prof_begin(root, "find_raw");
+                HBM_SEL_LAUNCH(P_RAW, k_find_raw, t);
+                prof_end(root, ps, ps >= 0 ? bytes_of(P_RAW, t, &SelJob::b_find) : 0);
+            }
+            ps = prof_begin(root, "apply");
+            HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
+            prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
+            if (active(P_BIG, t)) {
+                ps = prof_begin(root, "dec_big");
+                HBM_SEL_LAUNCH(P_BIG, k_dec_big, t);
+                prof_end(root, ps);
+                if (ps >= 0) ps_big = ps;
+            }
+            if (active(P_HOT, t)) {
+                ps = prof_begin(root, "dec_hot");
+                HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
+                prof_end(root, ps);
+            }
         }
-        if (active(P_RAW, t)) {
-            ps = prof_begin(root, "find_raw");
-            HBM_SEL_LAUNCH(P_RAW, k_find_raw, t);
-            prof_end(root, ps, ps >= 0 ? bytes_of(P_RAW, t, &SelJob::b_find) : 0);
+    };
+    if (!graph) {
+        launch_all();
+    } else {
+        // The k-iteration launch sequence as a HIP graph.  Its launches read their arguments from
+        // the descriptor buffer, and the grids depend only on the store's shape, so one graph
+        // serves every selection of that shape: captured on first use, replayed afterwards.
+        std::vector<uint64_t> shape{(uint64_t)N, (uint64_t)(uintptr_t)root.sel_desc.p, (uint64_t)kmax};
+        for (int p = 0; p < NPLAN; p++) {
+            shape.push_back((uint64_t)plans[p].jobs.size());
+            for (size_t q = 0; q < plans[p].jobs.size(); q++) shape.push_back((uint64_t)k[plans[p].jobs[q]]);
+            for (uint32_t b : plans[p].boff) shape.push_back(b);
         }
-        ps = prof_begin(root, "apply");
-        HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
-        prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
-        if (active(P_BIG, t)) {
-            ps = prof_begin(root, "dec_big");
-            HBM_SEL_LAUNCH(P_BIG, k_dec_big, t);
-            prof_end(root, ps);
-            if (ps >= 0) ps_big = ps;
+        size_t hit = root.sel_graphs.size();
+        for (size_t i = 0; i < root.sel_graphs.size(); i++)
+            if (root.sel_graphs[i].shape == shape) hit = i;
+        if (hit == root.sel_graphs.size()) {
+            if (!root.cap_stream) HBM_HIP(hipStreamCreate(&root.cap_stream));
+            HBM_HIP(hipStreamBeginCapture(root.cap_stream, hipStreamCaptureModeRelaxed));
+            st = root.cap_stream;
+            launch_all();
+            st = root.stream;
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(root.cap_stream, &g);
+            if (ec != hipSuccess || !g) {
+                (void)hipGetLastError();
+                throw Error{HBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec)};
+            }
+            Ctx::SelGraph sg;
+            sg.shape = std::move(shape);
+            const hipError_t e = hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) throw Error{HBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+            constexpr size_t GRAPH_CACHE = 16;
+            if (root.sel_graphs.size() >= GRAPH_CACHE) {
+                (void)hipGraphExecDestroy(root.sel_graphs.front().exec);
+                root.sel_graphs.erase(root.sel_graphs.begin());
+            }
+            root.sel_graphs.push_back(std::move(sg));
+        } else if (hit + 1 != root.sel_graphs.size()) {  // most recently used last
+            Ctx::SelGraph sg = std::move(root.sel_graphs[hit]);
+            root.sel_graphs.erase(root.sel_graphs.begin() + (ptrdiff_t)hit);
+            root.sel_graphs.push_back(std::move(sg));
         }
-        if (active(P_HOT, t)) {
-            ps = prof_begin(root, "dec_hot");
-            HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
-            prof_end(root, ps);
-        }
+        HBM_HIP(hipGraphLaunch(root.sel_graphs.back().exec, root.stream));
     }
 #undef HBM_SEL_LAUNCH
     HBM_HIP(hipGetLastError());
@@ -1019,13 +1159,17 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         prof_add(root, ps_big, (double)ctr[DC_EDGES] / 8.0, 0.0);  // algorithmic bytes: the strings read
     }
     std::vector<unsigned long long> keys((size_t)koff[N]);
-    HBM_HIP(hipMemcpyAsync(keys.data(), root.bkeys.p, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
-    HBM_HIP(hipEventRecord(e1, st));
-    HBM_HIP(hipEventSynchronize(e1));
+    HBM_HIP(hipMemcpyAsync(keys.data(), dkeys, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
     float ms = 0;
-    HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (fixed) {
+        HBM_HIP(hipStreamSynchronize(st));
+    } else {
+        HBM_HIP(hipEventRecord(e1, st));
+        HBM_HIP(hipEventSynchronize(e1));
+        HBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
     for (size_t i = 0; i < N; i++) {
         C[i]->t_select += ms;
         seeds[i].resize((size_t)k[i]);
@@ -1040,6 +1184,12 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
         }
         coverage[i] = cov;
     }
+}
+
+void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int32_t> &k,
+                  std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
+                  std::vector<uint64_t> &coverage) {
+    select_run(root, C, k, seeds, gains, coverage, nullptr);
 }
 
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {

@@ -82,6 +82,7 @@ struct hbm_server {
     int32_t max_active = 1;
     int enc = HBM_ENC_NONE;
     double warmup_frac = 0.1, hot_frac = 0.01, hot_min_density = 0.0;
+    bool implicit_roots = false;
     hbm::DGraph graph;  // borrowed from the graph context
     std::chrono::steady_clock::time_point t0;
 
@@ -236,7 +237,8 @@ void hbm_server::admit_locked() {
         }
         Ctx &c = *s->c;
         c.budget = budget;
-        c.s.enc = enc;
+        c.s.enc_req = c.s.enc = enc;
+        c.s.implicit_roots = implicit_roots;
         c.s.warmup_frac = warmup_frac;
         c.s.hot_frac = hot_frac;
         c.s.hot_min_density = hot_min_density;
@@ -463,6 +465,7 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     }
     s->rootL.device = g.device;
     s->rootL.num_cus = g.num_cus;
+    s->rootL.select_graph = g.select_graph;  // the selector thread drives the greedy launches
     if (hipStreamCreateWithFlags(&s->rootL.stream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipStreamDestroy(s->root.stream);
         delete s;
@@ -470,10 +473,11 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     }
     s->budget = store_budget;
     s->max_active = max_active;
-    s->enc = g.s.enc;
+    s->enc = g.s.enc_req;
     s->warmup_frac = g.s.warmup_frac;
     s->hot_frac = g.s.hot_frac;
     s->hot_min_density = g.s.hot_min_density;
+    s->implicit_roots = g.s.implicit_roots;
     s->graph = g.g;
     s->graph.borrowed = true;
     s->t0 = std::chrono::steady_clock::now();
@@ -521,6 +525,8 @@ void hbm_server_destroy(hbm_server *s) {
         }
     }
     try {
+        hbm::select_free(s->root);
+        hbm::select_free(s->rootL);
         for (hbm::Buf *b : {&s->root.scan_tmp, &s->root.ctrl_arena, &s->root.tails, &s->root.bkeys,
                             &s->root.dctr})
             hbm::buf_free(s->root, *b);

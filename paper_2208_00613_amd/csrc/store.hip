@@ -22,6 +22,7 @@
 //             swap-to-front of the Huffmax encoding section), the rest ascending.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "hbm_device.h"
@@ -60,9 +61,14 @@ struct SplitArgs {
     int64_t j0;
     const int64_t *off;           // raw offsets of the block's sets (null: bitmap only)
     int32_t *raw;
+    int32_t *raw_host;            // ids from raw_split on (spilled store), else unused
+    int64_t raw_split;
     unsigned long long *bitmap;
     int32_t nhot;
     uint32_t *cnt;                // per-set plain-id counts (cold_count output)
+    int implicit;                 // implicit roots: a set's root is not written as a plain id
+    uint64_t seed;
+    uint32_t n;
 };
 HBM_KERNEL(k_cold_count, SplitArgs, 256) {
     const BlockView &bv = A.bv;
@@ -74,9 +80,13 @@ HBM_KERNEL(k_cold_count, SplitArgs, 256) {
     for (uint64_t b = wave; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         uint32_t c = s;
-        if (hot_rank) {
+        if (hot_rank || A.implicit) {
+            const uint32_t root = dropped_root(A.implicit, A.seed, (uint64_t)A.j0 + b, A.n);
             c = 0;
-            for (uint32_t i = lane; i < s; i += WAVE) c += hot_rank[bv.mem[p + i]] < 0;
+            for (uint32_t i = lane; i < s; i += WAVE) {
+                const uint32_t v = bv.mem[p + i];
+                c += (!hot_rank || hot_rank[v] < 0) && v != root;
+            }
             c = wave_sum(c);
         }
         if (lane == 0) out[b] = c;
@@ -100,6 +110,7 @@ HBM_KERNEL(k_split, SplitArgs, 256) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         const int64_t o = off ? off[b] : 0;
         const uint64_t j = (uint64_t)j0 + b;
+        const uint32_t root = dropped_root(A.implicit, A.seed, j, A.n);
         uint32_t written = 0;
         for (uint32_t base = 0; base < s; base += WAVE) {
             const uint32_t i = base + lane;
@@ -109,9 +120,13 @@ HBM_KERNEL(k_split, SplitArgs, 256) {
                 v = bv.mem[p + i];
                 if (hot_rank) r = hot_rank[v];
             }
-            const bool cold = i < s && r < 0;
+            const bool cold = i < s && r < 0 && v != root;
             const uint64_t m = __ballot(cold);
-            if (cold && raw) raw[o + written + __popcll(m & ((1ull << lane) - 1))] = (int32_t)v;
+            if (cold && raw) {
+                const int64_t at = o + written + __popcll(m & ((1ull << lane) - 1));
+                if (at < A.raw_split) raw[at] = (int32_t)v;
+                else A.raw_host[at - A.raw_split] = (int32_t)v;
+            }
             written += __popcll(m);
             if (i < s && r >= 0) atomicOr(&bitmap[(j >> 6) * (uint64_t)nhot + r], 1ull << (j & 63));
         }
@@ -125,6 +140,10 @@ struct HuffEnc {
     const int32_t *hot_rank;  // may be null
     int32_t ustar;
     int32_t wbits;
+    int implicit;             // implicit roots: a set's root is not coded
+    uint64_t seed;
+    int64_t j0;               // set index of the block's first set
+    uint32_t n;
 };
 struct HuffArgs {
     BlockView bv;
@@ -149,11 +168,12 @@ HBM_KERNEL(k_huff_bits, HuffArgs, 256) {
     const uint64_t nw = (uint64_t)nblk * (blockDim.x / WAVE);
     for (uint64_t b = bid * (uint64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
+        const uint32_t root = dropped_root(h.implicit, h.seed, (uint64_t)h.j0 + b, h.n);
         uint64_t bits = 0;
         uint32_t nesc = 0, front = 0;
         for (uint32_t i = lane; i < s; i += WAVE) {
             const uint32_t v = bv.mem[p + i];
-            if (h.hot_rank && h.hot_rank[v] >= 0) continue;
+            if ((h.hot_rank && h.hot_rank[v] >= 0) || v == root) continue;
             const uint32_t L = h.lens[v];
             if (L) bits += L;
             else nesc++;
@@ -208,6 +228,7 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
     uint64_t esc_local = 0;
     for (uint64_t b = bid * (uint64_t)(blockDim.x / WAVE) + wv; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
+        const uint32_t root = dropped_root(h.implicit, h.seed, (uint64_t)h.j0 + b, h.n);
         const uint32_t meta = A.meta[b];
         const uint32_t nesc = meta & 0x7FFFFFFFu;
         const bool has_front = meta >> 31;
@@ -227,7 +248,7 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
         auto code_of = [&](uint32_t i, uint32_t &v, bool &esc) -> uint32_t {
             v = bv.mem[p + i];
             esc = false;
-            if (h.hot_rank && h.hot_rank[v] >= 0) return 0u;
+            if ((h.hot_rank && h.hot_rank[v] >= 0) || v == root) return 0u;
             const uint32_t len = h.lens[v];
             esc = len == 0;
             return (int32_t)v == h.ustar ? 0u : len;
@@ -303,6 +324,12 @@ struct DecodeView {
     const unsigned long long *bitmap;
     const int64_t *raw_off;
     const int32_t *raw_mem;
+    const int32_t *raw_host;
+    int64_t raw_split;
+    int implicit;            // implicit roots: the root is regenerated unless its row holds it
+    uint64_t seed;
+    uint32_t n;
+    const int32_t *hot_rank;
     const int64_t *bitoff;
     const uint32_t *payload;
     const uint64_t *lim;    // [34]
@@ -334,7 +361,7 @@ __device__ uint32_t decode_set(const DecodeView &d, int64_t j, int32_t *out) {
     }
     if (d.raw_off) {
         for (int64_t i = d.raw_off[j]; i < d.raw_off[j + 1]; i++) {
-            if (out) out[c] = d.raw_mem[i];
+            if (out) out[c] = raw_id(d.raw_mem, d.raw_host, d.raw_split, i);
             c++;
         }
     } else if (d.bitoff) {
@@ -353,6 +380,13 @@ __device__ uint32_t decode_set(const DecodeView &d, int64_t j, int32_t *out) {
         while (pos < end) {
             const uint32_t v = decode_code(d, pos);
             if (out) out[c] = (int32_t)v;
+            c++;
+        }
+    }
+    if (d.implicit) {
+        const uint32_t r = rr_root(d.seed, (uint64_t)j, d.n);
+        if (!d.nhot || d.hot_rank[r] < 0) {
+            if (out) out[c] = (int32_t)r;
             c++;
         }
     }
@@ -390,9 +424,15 @@ static DecodeView make_view(Ctx &c) {
     d.nhot = s.nhot;
     d.hot = s.hot.as<int32_t>();
     d.bitmap = s.bitmap.as<unsigned long long>();
-    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    d.raw_off = huff ? nullptr : s.raw_off.as<int64_t>();
-    d.raw_mem = huff ? nullptr : s.raw_mem.as<int32_t>();
+    const bool huff = enc_huff(s.enc), raw = enc_raw(s.enc);
+    d.raw_off = raw ? s.raw_off.as<int64_t>() : nullptr;
+    d.raw_mem = raw ? s.raw_mem.as<int32_t>() : nullptr;
+    d.raw_host = s.raw_host;
+    d.raw_split = s.raw_split;
+    d.implicit = s.implicit_roots && s.enc != HBM_ENC_BITMAX;
+    d.seed = s.seed;
+    d.n = (uint32_t)c.g.n;
+    d.hot_rank = s.nhot ? s.hot_rank.as<int32_t>() : nullptr;
     d.bitoff = huff ? s.bitoff.as<int64_t>() : nullptr;
     d.payload = s.payload.as<uint32_t>();
     d.lim = s.cbtab.as<uint64_t>();
@@ -405,6 +445,7 @@ static DecodeView make_view(Ctx &c) {
 
 void store_reset(Ctx &c) {
     Store &s = c.s;
+    s.enc = s.enc_req;  // AUTO decides again from the next warm-up block
     s.has_seed = false;
     s.nsets = 0;
     s.W = 0;
@@ -428,6 +469,7 @@ void store_reset(Ctx &c) {
 
 void store_free(Ctx &c) {
     Store &s = c.s;
+    raw_host_free(c);
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
                    &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp})
         buf_free(c, *b);
@@ -444,9 +486,8 @@ void store_free(Ctx &c) {
 int64_t store_bytes(const Ctx &c) {
     const Store &s = c.s;
     int64_t b = 0;
-    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    if (huff) b += (s.nsets + 1) * 8 + (int64_t)((s.nbits + 7) / 8) + (int64_t)(s.nbits / CK_SLOT + 1);
-    else b += (s.nsets + 1) * 8 + s.raw_count * 4;
+    if (enc_huff(s.enc)) b += (s.nsets + 1) * 8 + (int64_t)((s.nbits + 7) / 8) + (int64_t)(s.nbits / CK_SLOT + 1);
+    else if (enc_raw(s.enc)) b += (s.nsets + 1) * 8 + s.raw_count * 4;
     b += s.bm_words * (int64_t)s.nhot * 8;
     return b;
 }
@@ -570,6 +611,12 @@ __global__ __launch_bounds__(NZ_T) void k_nz_write(const uint32_t *warm, int32_t
     }
 }
 
+// p[i] = i for i < count (the all-vertex row list and rank of a BITMAX store)
+__global__ void k_iota_i32(int32_t *p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -630,6 +677,19 @@ static void build_model(Ctx &c) {
     Store &s = c.s;
     const int32_t n = c.g.n;
     const hipStream_t st = c.stream;
+    if (s.enc == HBM_ENC_AUTO)  // Alg. 1's branch on the warm-up block's Eq. 2 figures
+        s.enc = (s.skew < 0.0 && s.density > 1.0 / 32.0) ? HBM_ENC_BITMAX : HBM_ENC_HUFFMAN;
+    if (s.enc == HBM_ENC_BITMAX) {
+        // the Bitmax encoding section's n-row bit matrix: vertex v owns row v
+        s.nhot = n;
+        buf_alloc(c, s.hot, (size_t)n * 4);
+        buf_grow(c, s.hot_rank, (size_t)n * 4, false);
+        k_iota_i32<<<fill_grid(n), 256, 0, st>>>(s.hot.as<int32_t>(), n);
+        k_iota_i32<<<fill_grid(n), 256, 0, st>>>(s.hot_rank.as<int32_t>(), n);
+        HBM_HIP(hipGetLastError());
+        s.model_ready = true;
+        return;
+    }
     // the warm-up's symbols in ascending id order: every choice below is a total order
     // over (count, id), so it matches a scan over all n vertices
     std::vector<uint32_t> ids, wcnt;
@@ -837,36 +897,90 @@ static void gather_tails(Ctx &root, const std::vector<const int64_t *> &src, std
                 KERNEL##_g<<<g_, THREADS, 0, (ROOT).stream>>>(GroupArgs<ATYPE>{d_, b_, c_, x_});              \
             })
 
+// Room for `total` plain ids: on the device, or with a spill cap the first raw_split ids on the
+// device and the rest in pinned host memory (grown by copying once the stream is idle).
+static void raw_grow(Ctx &c, int64_t total) {
+    Store &s = c.s;
+    if (s.spill_cap <= 0) {
+        s.raw_split = INT64_MAX;
+        buf_grow(c, s.raw_mem, (size_t)std::max<int64_t>(total, 1) * 4, true);
+        return;
+    }
+    s.raw_split = (s.spill_cap / 16) * 4;
+    buf_grow(c, s.raw_mem, (size_t)std::max<int64_t>(std::min(total, s.raw_split), 4) * 4, true);
+    const int64_t nh = total - s.raw_split;
+    if (nh <= 0 || (size_t)nh <= s.raw_host_cap) return;
+    size_t cap = std::max<size_t>(s.raw_host_cap * 2, size_t(1) << 20);
+    while (cap < (size_t)nh) cap *= 2;
+    void *p = nullptr;
+    HBM_HIP(hipHostMalloc(&p, cap * 4, hipHostMallocMapped | hipHostMallocCoherent));
+    HBM_HIP(hipStreamSynchronize(c.stream));  // earlier blocks' ids are written
+    if (s.raw_host_h) {
+        const int64_t have = std::max<int64_t>(0, s.raw_count - s.raw_split);
+        std::memcpy(p, s.raw_host_h, (size_t)have * 4);
+        (void)hipHostFree(s.raw_host_h);
+        s.raw_host = s.raw_host_h = nullptr;
+        s.raw_host_cap = 0;
+    }
+    void *dp = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(&dp, p, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(p);
+        throw Error{HBM_EDEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e)};
+    }
+    s.raw_host_h = (int32_t *)p;
+    s.raw_host = (int32_t *)dp;
+    s.raw_host_cap = cap;
+}
+
+void raw_host_free(Ctx &c) {
+    Store &s = c.s;
+    if (!s.raw_host_h) return;
+    (void)hipStreamSynchronize(c.stream);
+    (void)hipHostFree(s.raw_host_h);
+    s.raw_host = s.raw_host_h = nullptr;
+    s.raw_host_cap = 0;
+}
+
 // Append sets [j0[i], j0[i] + done[i]) of every job from its scratch arena to its store
-// (UpdateHistogram, then the job's encoding), one grouped launch per step.
+// (the job's encoding, then UpdateHistogram), one grouped launch per step.  Every allocation
+// comes before the first write into the store and the histogram is updated last, so a failed
+// allocation leaves each store as it was (nsets, histogram and encoded parts agree).
 static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &j0,
                           const std::vector<int64_t> &done) {
     const size_t N = J.size();
-    std::vector<HistArgs> ha;
-    std::vector<uint32_t> hb;
-    for (size_t i = 0; i < N; i++) {
-        ha.push_back(HistArgs{block_view(*J[i], done[i]), J[i]->s.hist.as<uint32_t>()});
-        hb.push_back(grid_for(done[i] * WAVE, 256, 65536));
-    }
-    {
-        const int ps = prof_begin(root, "hist_add");
-        HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
-        prof_end(root, ps);
-    }
-    HBM_HIP(hipGetLastError());
-    // plain-id jobs and Huffman jobs
-    std::vector<size_t> P, H;
+    // plain-id jobs, Huffman jobs and all-vertex bitmap jobs
+    std::vector<size_t> P, H, B;
     for (size_t i = 0; i < N; i++) {
         Store &s = J[i]->s;
-        const bool hot = s.enc == HBM_ENC_HOT_BITMAP || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-        const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
         const int64_t new_sets = j0[i] + done[i];
-        if (hot) {
+        if (enc_rows(s.enc)) {
             const int64_t words = (new_sets + 63) / 64;
             buf_grow(*J[i], s.bitmap, (size_t)std::max<int64_t>(words * s.nhot, 1) * 8, true);
             s.bm_words = words;
         }
-        (huff ? H : P).push_back(i);
+        if (enc_huff(s.enc)) H.push_back(i);
+        else if (enc_raw(s.enc)) P.push_back(i);
+        else B.push_back(i);
+    }
+    if (!B.empty()) {  // BITMAX: every member sets its bit in its own vertex's row
+        std::vector<SplitArgs> sa;
+        std::vector<uint32_t> sb;
+        for (size_t i : B) {
+            Store &s = J[i]->s;
+            SplitArgs a{};
+            a.bv = block_view(*J[i], done[i]);
+            a.hot_rank = s.hot_rank.as<int32_t>();
+            a.j0 = j0[i];
+            a.bitmap = s.bitmap.as<unsigned long long>();
+            a.nhot = s.nhot;
+            sa.push_back(a);
+            sb.push_back(grid_for(done[i] * WAVE, 256, 65536));
+        }
+        const int ps = prof_begin(root, "split");
+        HBM_GLAUNCH(root, sa, sb, 0, k_split, 256, SplitArgs);
+        prof_end(root, ps);
+        HBM_HIP(hipGetLastError());
     }
     if (!P.empty()) {
         std::vector<SplitArgs> sa;
@@ -884,6 +998,9 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             a.bitmap = s.bitmap.as<unsigned long long>();
             a.nhot = s.nhot;
             a.cnt = c.sc.cnt.as<uint32_t>();
+            a.implicit = s.implicit_roots;
+            a.seed = s.seed;
+            a.n = (uint32_t)c.g.n;
             sa.push_back(a);
             sb.push_back(grid_for(done[i] * WAVE, 256, 65536));
         }
@@ -903,8 +1020,10 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
         gather_tails(root, tail, total);
         for (size_t q = 0; q < P.size(); q++) {
             Ctx &c = *J[P[q]];
-            buf_grow(c, c.s.raw_mem, (size_t)std::max<int64_t>(total[q], 1) * 4, true);
+            raw_grow(c, total[q]);
             sa[q].raw = c.s.raw_mem.as<int32_t>();
+            sa[q].raw_host = c.s.raw_host;
+            sa[q].raw_split = c.s.raw_split;
             sa[q].bitmap = c.s.bitmap.as<unsigned long long>();
             c.s.raw_count = total[q];
         }
@@ -926,7 +1045,7 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             HuffArgs a{};
             a.bv = block_view(c, done[i]);
             a.h = HuffEnc{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
-                          s.cb.ustar_enc, s.cb.wbits};
+                          s.cb.ustar_enc, s.cb.wbits, s.implicit_roots, s.seed, j0[i], (uint32_t)c.g.n};
             a.bits = c.sc.aux.as<uint64_t>();
             a.meta = c.sc.cnt.as<uint32_t>();
             a.bitoff = s.bitoff.as<int64_t>() + j0[i];
@@ -983,6 +1102,18 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
         HBM_HIP(hipStreamSynchronize(root.stream));
         for (size_t i : H) J[i]->s.escapes += (int64_t)esc[i * CW_COUNT + CW_SUM];
     }
+    std::vector<HistArgs> ha;
+    std::vector<uint32_t> hb;
+    for (size_t i = 0; i < N; i++) {
+        ha.push_back(HistArgs{block_view(*J[i], done[i]), J[i]->s.hist.as<uint32_t>()});
+        hb.push_back(grid_for(done[i] * WAVE, 256, 65536));
+    }
+    {
+        const int ps = prof_begin(root, "hist_add");
+        HBM_GLAUNCH(root, ha, hb, 0, k_hist_add, 256, HistArgs);
+        prof_end(root, ps);
+    }
+    HBM_HIP(hipGetLastError());
     for (size_t i = 0; i < N; i++) J[i]->s.nsets = j0[i] + done[i];
 }
 
@@ -1087,7 +1218,14 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
             c.s.wcur += wn[q];
             if (c.s.wcur >= c.s.W) {
                 characterize(c.s, c.g.n);
-                build_model(c);
+                try {
+                    build_model(c);
+                } catch (...) {  // e.g. ENOMEM: the warm-up starts over at the next request
+                    c.s.wcur = 0;
+                    c.s.warm_sizes.clear();
+                    c.s.enc = c.s.enc_req;
+                    throw;
+                }
                 if (fuse[q]) {  // sets [0, done) are still in the arena
                     ajobs.push_back(&c);
                     aj0.push_back(j0[q]);
@@ -1177,10 +1315,10 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     o->escape_bits = s.cb.wbits;
     o->escapes = s.escapes;
     o->payload_bits = s.nbits;
-    const bool huff = s.enc == HBM_ENC_HUFFMAN || s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP;
-    o->index_bytes = s.nsets ? (s.nsets + 1) * 8 + (huff ? (int64_t)(s.nbits / CK_SLOT + 1) : 0) : 0;
+    const bool huff = enc_huff(s.enc), raw = enc_raw(s.enc);
+    o->index_bytes = s.nsets && (huff || raw) ? (s.nsets + 1) * 8 + (huff ? (int64_t)(s.nbits / CK_SLOT + 1) : 0) : 0;
     o->bitmap_bytes = s.bm_words * (int64_t)s.nhot * 8;
-    o->raw_bytes = huff ? 0 : s.raw_count * 4;
+    o->raw_bytes = raw ? s.raw_count * 4 : 0;
     o->codebook_bytes = huff ? (int64_t)c.g.n + (int64_t)s.cb.nsym * 4 + 68 * 8 : 0;
     if (s.nhot) o->codebook_bytes += (int64_t)s.nhot * 4;
     o->store_bytes = store_bytes(c);

@@ -10,6 +10,9 @@ benchmark configurations name:
                    seeded label permutation, self-loops and duplicates removed;
 * ``chung_lu``     power-law digraph (exponent gamma) drawn source by source,
                    shaped like twitter7 (41.7M vertices, ~1.47B edges);
+* ``flat_head``    G(n, m) with one constant IC probability: RR sets with a flat
+                   head (negative skewness, high density), like the paper's
+                   Bitmax graphs;
 * ``lt_weights``   U(0,1) float32 in-weights rescaled so every vertex's in-weights
                    sum to at most 1 (rows whose sum exceeds 1 are divided by it).
 
@@ -83,6 +86,17 @@ def erdos_renyi(n: int, m: int, seed: int, p_hi: float = 0.1) -> Graph:
     p = (rng.random(m, dtype=np.float32) * np.float32(p_hi)).astype(np.float32)
     g = _csr_from_pairs(n, u, v, p, name=f"er_n{n}_m{m}_s{seed}")
     assert g.m == m
+    return g
+
+
+def flat_head(n: int, m: int, p: float, seed: int) -> Graph:
+    """Directed G(n, m) with one constant IC probability p on every edge: with mean live
+    in-degree (m / n) * p well above 1 most roots reach a giant in-component, so RR-set
+    sizes have a flat head and a short left tail (negative Eq. 2 skewness, density far
+    above 1/32), the shape the paper reports for its Bitmax graphs."""
+    g = erdos_renyi(n, m, seed=seed)
+    g.w = np.full(g.m, p, dtype=np.float32)
+    g.name = f"flat_n{n}_m{m}_p{p}_s{seed}"
     return g
 
 
@@ -263,6 +277,10 @@ CONFIGS = {
     # IMM under IC weighted cascade on R-MAT scale 20, eps=.5, l=1, k=50, hot bitmap 1% from 10% warm-up
     "c2": dict(kind="rmat", scale=20, gseed=2, model="IC", prob="WC", eps=0.5, l=1.0, k=50, seed=42,
                enc="HOT_BITMAP", warmup=0.10, hot=0.01),
+    # flat-head IC (Bitmax-shaped): G(65536, 2^20) with p = 0.1 on every edge, eps=.5, k=50,
+    # encoding chosen by Alg. 1 from a 10% warm-up
+    "flat": dict(kind="flat", n=65536, m=1 << 20, p=0.1, gseed=6, model="IC", prob="EDGE", eps=0.5, l=1.0, k=50,
+                 seed=42, enc="AUTO", warmup=0.10, hot=0.01),
     # IMM under LT on R-MAT scale 23, eps=.13, k=100, Huffman from 5% warm-up
     "c3": dict(kind="rmat", scale=23, gseed=3, model="LT", prob="EDGE", eps=0.13, l=1.0, k=100, seed=42,
                enc="HUFFMAN", warmup=0.05, hot=0.0),
@@ -291,6 +309,8 @@ def config_graph(name: str, scale_override: Optional[int] = None) -> Graph:
     c = CONFIGS[name]
     if c["kind"] == "er":
         return erdos_renyi(c["n"], c["m"], seed=c["gseed"])
+    if c["kind"] == "flat":
+        return flat_head(c["n"], c["m"], c["p"], seed=c["gseed"])
     scale = scale_override if scale_override is not None else c["scale"]
     g = rmat(scale, seed=c["gseed"])
     if c["model"] == "LT":

@@ -69,15 +69,35 @@ def test_traffic_calibrated_by_the_copy(bench, tmp_path, capsys):
     _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [
         ("__amd_rocclr_copyBuffer", gib_kib),
         ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 4.0)])
-    out = tmp_path / "traffic.json"
-    bench.traffic_summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(out), "c2")
+    _counter_csv(tmp_path / "l2.csv", "TCC_HIT_sum", [("void hbm::k_argmax(hbm::SelArgs, int)", 30.0),
+                                                      ("void hbm::k_argmax(hbm::SelArgs, int)", 50.0)])
+    with open(tmp_path / "l2.csv", "a", newline="") as f:
+        csv.writer(f).writerow(["void hbm::k_argmax(hbm::SelArgs, int)", "TCC_MISS_sum", 20.0])
+    out = tmp_path / "counters.json"
+    bench.counters_summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "l2.csv"), "c2",
+                             str(out))
     capsys.readouterr()
     t = json.load(open(out))
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
-    k = t["kernels"]
+    k = t["traffic"]
     # mean of the two regular LDS-tier dispatches, fetched x2, plus written; the extra-large
     # pass is told apart by its template arguments
     assert k["ic_sample_block"] == pytest.approx(200.0 * 1024 * 2 + 4.0 * 1024)
     assert k["ic_sample_block_xl"] == pytest.approx(7.0 * 1024 * 2)
     assert k["argmax"] == pytest.approx(10.0 * 1024 * 2)
+    assert t["l2_hit"] == {"argmax": pytest.approx(80.0 / 100.0)}
     assert t["workload_key"] == "c2" and t["csrc_digest"] == bench.csrc_digest()
+
+
+def test_roofline_reports_hbm_fraction_beside_alu(bench):
+    ks = [{"name": "ic_sample_block", "launches": 2, "total_ms": 1.0, "alg_bytes": 8e6, "alg_ops": 4e8}]
+    r = bench.roofline(ks, "IC", "WC", "no-such-workload")
+    # 4e6 bytes per 0.5 ms launch = 8 GB/s = 0.001 of 8 TB/s
+    assert r["hbm_achieved_gbs"] == pytest.approx(8.0) and r["hbm_frac"] == pytest.approx(0.001)
+    rates = bench.kernel_rates(ks)
+    assert rates[0]["hbm_frac"] == pytest.approx(0.001) and rates[0]["gphilox_s"] == pytest.approx(400.0)
+
+
+def test_host_info_caps_threads(bench):
+    h = bench.host_info()
+    assert 1 <= h["threads"] <= bench.HOST_THREADS_CAP and h["nproc"] >= 1

@@ -2,9 +2,10 @@
 twitter7 (41.7M vertices, ~1.44B edges, exponent 2.2, weighted cascade), Huffman
 + density-gated hot bitmap.
 
-* One IMM query: the theta schedule against the closed form, a random sample of
-  RR sets against the oracle one by one, the warm-up counts against the oracle's
-  warm-up sets, and the oracle's greedy replayed over the GPU's decoded store.
+* Two IMM queries (k=10, eps=.5 and k=120, eps=.2): the theta schedule and the
+  final theta against the closed form, 10^4 random RR sets against the oracle one
+  by one, the warm-up counts against the oracle's warm-up sets, and the oracle's
+  greedy replayed over the GPU's decoded store.
 * Served queries (arriving together and later) equal the same queries alone.
 """
 
@@ -55,9 +56,19 @@ def served(P):
     ctx.close()
 
 
-def test_c5_query_parity(orc, P, served):
-    ctx, c, rp_h, dst_h = served
-    k, eps, seed = 10, 0.5, 1000
+@pytest.fixture(scope="module")
+def c5_oracle(orc, served):
+    _, c, rp_h, dst_h = served
+    t0 = time.time()
+    og = orc.Graph(c["n"], rp_h, dst_h, None, model="IC", prob="WC")
+    _say("oracle in-CSR built", round(time.time() - t0, 1), "s")
+    return og
+
+
+@pytest.mark.parametrize("k,eps,seed", [(10, 0.5, 1000), (120, 0.2, 1007)])
+def test_c5_query_parity(orc, P, served, c5_oracle, k, eps, seed):
+    ctx, c, _, _ = served
+    og = c5_oracle
     _say("c5 IMM k", k, "eps", eps, "seed", seed)
     seeds, gains, st = ctx.hbm_imm(k, eps, 1.0, seed)
     T = st["nsets_final"]
@@ -66,17 +77,27 @@ def test_c5_query_parity(orc, P, served):
     assert st["lambda_prime"] == prm["lambda_prime"] and st["lambda_star"] == prm["lambda_star"]
     for i, th in enumerate(st["theta_round"], start=1):
         assert th == int(np.ceil(prm["lambda_prime"] / (n / 2.0 ** i)))
-    t0 = time.time()
-    og = orc.Graph(n, rp_h, dst_h, None, model="IC", prob="WC")
-    _say("oracle in-CSR built", round(time.time() - t0, 1), "s; theta", T)
-    rng = np.random.default_rng(11)
-    for j in np.unique(np.concatenate([rng.integers(0, T, 300), [0, T - 1]])):
+    # the final theta from the GPU's last-round coverage by the closed form (Tang et al.'s LB)
+    r = st["rounds"]
+    th_r, cov_r = st["theta_round"][r - 1], st["cov_round"][r - 1]
+    x = n / 2.0 ** r
+    ep = np.sqrt(2.0) * eps
+    if n * cov_r / th_r >= (1.0 + ep) * x:
+        assert st["lb"] == n * cov_r / (th_r * (1.0 + ep))
+    assert st["theta_final"] == int(np.ceil(prm["lambda_star"] / st["lb"]))
+    # 10^4 random RR indices regenerated one by one by the oracle
+    _say("c5 theta", T, "- 10^4 sampled sets against the oracle")
+    rng = np.random.default_rng(11 + seed)
+    for j in np.unique(np.concatenate([rng.integers(0, T, 10_000), [0, T - 1]])):
         assert np.array_equal(ctx.hbm_get_rr(int(j)), og.sample(seed, int(j))), f"set {j}"
     W = orc.warmup_count(c["warmup"], st["theta_round"][0])
     warm = orc.sample_store(og, seed, W).counts(n)
     assert np.array_equal(ctx.hbm_export("WARM").astype(np.uint64), warm)
+    # the oracle's greedy replayed over the GPU's decoded canonical store
     off, mem = ctx.hbm_dump_sets(0, T)
+    _say("c5 store dumped:", T, "sets,", int(off[-1]), "members; oracle greedy replay")
     os_, og_, oc = orc.greedy_sets(off, mem, n, k)
+    del off, mem
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == oc
 
 

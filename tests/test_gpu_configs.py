@@ -4,10 +4,10 @@
   10% warm-up): the oracle runs the whole IMM too, so every round's theta and
   coverage, LB, the seeds, gains and coverage are compared exactly, and the
   encoded store is compared word by word.
-* R-MAT scale 23, LT, eps=0.13, k=100, Huffman (5% warm-up): the oracle recomputes
-  a random sample of RR sets one by one, and its own greedy is replayed over the
-  GPU's decoded store; the codebook, warm-up counts and theta schedule are
-  compared exactly.
+* R-MAT scale 23, LT, eps=0.13, k=100, Huffman (5% warm-up): the oracle runs the
+  whole IMM as well; every round's theta and coverage, LB, theta_final, the seeds,
+  gains and coverage, every decoded set of the final store, the warm-up counts,
+  the code lengths and Eq. 2's skewness and density are compared.
 """
 
 import sys
@@ -61,13 +61,17 @@ def test_c2_full_imm_parity(orc, P):
         assert np.array_equal(ctx.hbm_export("RAW_OFF"), e.cold_off)
         assert np.array_equal(ctx.hbm_export("RAW_MEM"), e.cold_mem)
         assert np.array_equal(ctx.hbm_export("COUNTS").astype(np.uint64), store.counts(g.n))
+        ss = ctx.hbm_get_store_stats()
+        sk, de = store.characterize(g.n, 0, W)
+        assert ss["warmup_sets"] == W
+        assert abs(ss["skewness"] - sk) <= 1e-9 * max(1.0, abs(sk)) and abs(ss["density"] - de) <= 1e-12 * de
     finally:
         ctx.close()
 
 
-def test_c3_sampled_parity_and_greedy_replay(orc, P):
+def test_c3_full_imm_parity(orc, P):
     c = G.CONFIGS["c3"]
-    _say("c3: R-MAT 23 LT eps .13 k 100 Huffman, seed 42")
+    _say("c3 full IMM: R-MAT 23 LT eps .13 k 100 Huffman, seed 42 (oracle IMM too)")
     g = G.config_graph("c3")
     ctx = P.Context(0)
     try:
@@ -75,27 +79,31 @@ def test_c3_sampled_parity_and_greedy_replay(orc, P):
         ctx.hbm_set_encoding(c["enc"], c["warmup"], c["hot"])
         seeds, gains, st = ctx.hbm_imm(c["k"], c["eps"], c["l"], c["seed"])
         T = st["nsets_final"]
-        prm = orc.imm_params(g.n, c["k"], c["eps"], c["l"])
-        assert st["lambda_prime"] == prm["lambda_prime"] and st["lambda_star"] == prm["lambda_star"]
-        for i, th in enumerate(st["theta_round"], start=1):
-            assert th == int(np.ceil(prm["lambda_prime"] / (g.n / 2.0 ** i)))
         og = orc.Graph(g.n, g.row_ptr, g.dst, g.w, model="LT", prob="EDGE")
-        # sampled sets, one by one
-        rng = np.random.default_rng(7)
-        idx = np.unique(np.concatenate([rng.integers(0, T, 3000), [0, T - 1]]))
-        for j in idx:
-            assert np.array_equal(ctx.hbm_get_rr(int(j)), og.sample(c["seed"], int(j))), f"set {j}"
-        # warm-up counts and codebook from the oracle's warm-up sets
+        _say("c3 oracle IMM, GPU theta", T)
+        os_, og_, ost, store = orc.imm(og, c["k"], c["eps"], c["l"], c["seed"])
+        assert st["lambda_prime"] == ost["lambda_prime"] and st["lambda_star"] == ost["lambda_star"]
+        assert st["theta_round"] == ost["theta_round"]
+        assert st["cov_round"] == ost["cov_round"]
+        assert st["lb"] == ost["lb"] and st["theta_final"] == ost["theta_final"]
+        assert T == ost["nsets_final"]
+        assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == ost["coverage"]
+        # every set of the final store, decoded from the Huffman strings
+        ooff, omem = store.arrays()
+        for j0 in range(0, T, 200_000):
+            j1 = min(T, j0 + 200_000)
+            off, mem = ctx.hbm_dump_sets(j0, j1)
+            assert np.array_equal(off, ooff[j0:j1 + 1] - ooff[j0]), f"set sizes differ in [{j0},{j1})"
+            assert np.array_equal(mem, omem[ooff[j0]:ooff[j1]]), f"set members differ in [{j0},{j1})"
+        # warm-up counts, codebook and Eq. 2 over the oracle's warm-up sets
         W = orc.warmup_count(c["warmup"], st["theta_round"][0])
-        ws = orc.sample_store(og, c["seed"], W)
-        warm = ws.counts(g.n)
+        warm = store.counts(g.n, 0, W)
         assert np.array_equal(ctx.hbm_export("WARM").astype(np.uint64), warm)
         assert np.array_equal(ctx.hbm_export("LENS"), orc.huffman_lengths(warm))
-        # the oracle's greedy over the GPU's decoded store reproduces the GPU's selection
-        off, mem = ctx.hbm_dump_sets(0, T)
-        os_, og_, oc = orc.greedy_sets(off, mem, g.n, c["k"])
-        assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == oc
-        assert np.array_equal(ctx.hbm_export("COUNTS").astype(np.uint64),
-                              np.bincount(mem, minlength=g.n).astype(np.uint64))
+        ss = ctx.hbm_get_store_stats()
+        sk, de = store.characterize(g.n, 0, W)
+        assert ss["warmup_sets"] == W
+        assert abs(ss["skewness"] - sk) <= 1e-9 * max(1.0, abs(sk)) and abs(ss["density"] - de) <= 1e-12 * de
+        assert np.array_equal(ctx.hbm_export("COUNTS").astype(np.uint64), store.counts(g.n))
     finally:
         ctx.close()

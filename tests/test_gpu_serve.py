@@ -2,7 +2,8 @@
 
 Queries of different k and eps arrive while others run; each answer must be the
 one hbm_imm gives alone on the same graph (seeds, gains, coverage, theta
-schedule), bit for bit, whatever the mix, the admission order or preemptions.
+schedule), bit for bit, whatever the mix, the admission order or preemptions;
+two served answers are also checked against the oracle's own IMM.
 """
 
 import sys
@@ -66,7 +67,7 @@ def _same(res, ref):
     assert res["stats"]["store"]["store_bytes"] == st["store"]["store_bytes"]
 
 
-def test_mix_equals_alone(P, graph_ctx, alone):
+def test_mix_equals_alone(orc, P, graph_ctx, alone):
     c, _ = graph_ctx
     _say("serve: staggered arrivals, budget 4 GB, 4 slots")
     srv = P.Server(c, store_budget=4 << 30, max_active=4)
@@ -76,15 +77,27 @@ def test_mix_equals_alone(P, graph_ctx, alone):
             tickets[srv.hbm_server_submit(*q)] = q
             if i % 2 == 1:
                 time.sleep(0.02)  # later arrivals join running ones
+        served = {}
         for t, q in tickets.items():
             r = srv.hbm_server_poll(t, wait=True)
             _say("query", q, "latency ms", round(r["t_done_ms"] - r["t_submit_ms"], 2))
             _same(r, alone[q])
+            served[q] = r
         st = srv.hbm_server_get_stats()
         assert st["completed"] == len(QUERIES) and st["failed"] == 0 and st["active"] == 0
         assert st["peak_active"] >= 2  # queries did overlap
     finally:
         srv.close()
+    # served answers straight against the oracle's full IMM on the same graph
+    g = graph_ctx[1]
+    og = orc.Graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
+    for q in (QUERIES[1], QUERIES[5]):
+        _say("oracle IMM for served query", q)
+        os_, og_, ost, _ = orc.imm(og, *q)
+        r = served[q]
+        assert np.array_equal(r["seeds"], os_) and np.array_equal(r["gains"], og_)
+        assert r["stats"]["coverage"] == ost["coverage"] and r["stats"]["theta_round"] == ost["theta_round"]
+        assert r["stats"]["lb"] == ost["lb"] and r["stats"]["nsets_final"] == ost["nsets_final"]
 
 
 def test_budget_preemption_keeps_results(P, graph_ctx, alone):

@@ -46,3 +46,11 @@ def test_batched_instances():
     assert len(insts) == 256
     assert {i["model"] for i in insts[::2]} == {"IC"} and {i["model"] for i in insts[1::2]} == {"LT"}
     assert all(12 <= i["scale"] <= 18 and 5 <= i["k"] <= 100 and i["eps"] in (0.5, 0.3) for i in insts)
+
+
+def test_flat_head_graph_is_constant_p():
+    g = G.flat_head(2048, 32768, 0.1, seed=2)
+    _check_csr(g)
+    assert g.m == 32768 and g.w.dtype == np.float32 and (g.w == np.float32(0.1)).all()
+    g2 = G.config_graph("flat")
+    assert g2.n == 65536 and g2.m == 1 << 20 and (g2.w == np.float32(0.1)).all()
