@@ -226,6 +226,23 @@ hbm_status hbm_sample_rr(hbm_ctx *ctx, int64_t theta, uint64_t seed);
  * The store is not modified.  HBM_EINVAL if k < 1 or k > n. */
 hbm_status hbm_select_seeds(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
 
+/* hbm_select_seeds for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results as hbm_select_seeds, bit for bit, but the selection state
+ * (counts, covered and newly covered bits, argmax partials, seed keys, the queue of
+ * long strings) lives in a fixed device array of 48 MiB that the library holds on
+ * each device it runs on until the process ends; nothing is allocated, and the
+ * call neither times nor profiles its kernels.  The state needs, each part rounded
+ * up to 256 bytes: 4 n + n / 8 + 2 * 8 ceil(theta / 64) + 8 k + 8 * 8 * CUs, plus
+ * 4 (theta + 2) for a Huffman store; a call that needs more returns HBM_EINVAL
+ * (2^22 vertices with 2^22 sets fit under any encoding).  Counts are dense (one
+ * per vertex) whatever HBM_TUNE_SPARSE_COUNTS says.  Every call on a device
+ * shares that device's array, so calls that overlap on one device (two contexts on
+ * different streams or threads) race and must be serialised by the caller; each
+ * call clears what it needs at its start.  The store must have been sampled by
+ * the calling context (hbm_sample_rr), whose allocations are its own. */
+hbm_status hbm_select_seeds_noalloc(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
+
 /* Full IMM (Eq. 1 read as Tang et al.'s lambda'; their lower bound and final
  * theta): l is adjusted to l (1 + ln 2 / ln n); estimation round i samples
  * theta_i = ceil(lambda' / (n / 2^i)) sets and selects k seeds; the first
@@ -391,7 +408,7 @@ hbm_status hbm_profile(hbm_ctx *ctx, int32_t enable);
 hbm_status hbm_profile_read(hbm_ctx *ctx, hbm_kernel_stat *out, int32_t cap, int32_t *count);
 
 /* Device memory held by the context (graph, store, sampling and selection scratch,
- * descriptors): *bytes_now
+ * descriptors; the fixed array of hbm_select_seeds_noalloc is not counted): *bytes_now
  * now, *bytes_peak the most at any moment since creation or the last reset.  The
  * paper's memory tables report peak memory; this is the device-side figure.
  * reset_peak != 0 sets the peak to the current bytes after reading it. */

@@ -30,7 +30,7 @@ EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hb
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
             "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_set_hot_density", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
-            "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune",
+            "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune", "hbm_select_seeds_noalloc",
             "hbm_get_memory", "hbm_bench_philox", "hbm_set_spill", "hbm_set_implicit_roots"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5,
         "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8, "SELECT_GRAPH": 9}
@@ -159,6 +159,7 @@ def lib():
         "hbm_set_implicit_roots": ([P, I32], C.c_int),
         "hbm_sample_rr": ([P, I64, U64], C.c_int),
         "hbm_select_seeds": ([P, I32, P, P, P], C.c_int),
+        "hbm_select_seeds_noalloc": ([P, I32, P, P, P], C.c_int),
         "hbm_get_memory": ([P, C.POINTER(I64), C.POINTER(I64), I32], C.c_int),
         "hbm_bench_philox": ([P, I64, I32, C.POINTER(D), C.POINTER(C.c_uint32)], C.c_int),
         "hbm_imm": ([P, I32, D, D, U64, P, P, C.POINTER(ImmStats)], C.c_int),
@@ -316,6 +317,13 @@ class Context:
         gains = np.zeros(k, dtype=np.uint64)
         cov = np.zeros(1, dtype=np.uint64)
         self._check(lib().hbm_select_seeds(self.h, int(k), _ptr(seeds), _ptr(gains), _ptr(cov)))
+        return seeds, gains, int(cov[0])
+
+    def hbm_select_seeds_noalloc(self, k: int):
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        cov = np.zeros(1, dtype=np.uint64)
+        self._check(lib().hbm_select_seeds_noalloc(self.h, int(k), _ptr(seeds), _ptr(gains), _ptr(cov)))
         return seeds, gains, int(cov[0])
 
     def hbm_imm(self, k: int, eps: float, l: float, seed: int):

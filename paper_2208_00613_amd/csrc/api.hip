@@ -59,6 +59,7 @@ hbm_status hbm_create(hbm_ctx **out, int device, void *stream, const hbm_allocat
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->c.num_cus = prop.multiProcessorCount;
+    hbm::noalloc_setup(device);  // device address of the fixed selection scratch, once per device
     *out = ctx;
     return HBM_OK;
 }
@@ -179,6 +180,21 @@ hbm_status hbm_bench_philox(hbm_ctx *ctx, int64_t calls_per_thread, int32_t bloc
         const double t = hbm::philox_probe(c, calls_per_thread, blocks, &sum);
         *ms = t;
         *checksum = sum;
+    });
+}
+
+hbm_status hbm_select_seeds_noalloc(hbm_ctx *ctx, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(seeds && gains && coverage, HBM_EINVAL, "null output");
+        HBM_REQUIRE(c.g.loaded, HBM_ESTATE, "no graph loaded");
+        HBM_REQUIRE(k >= 1 && k <= c.g.n, HBM_EINVAL, "k must be in [1, n]");
+        std::vector<int32_t> s((size_t)k);
+        std::vector<uint64_t> g((size_t)k);
+        uint64_t cov = 0;
+        hbm::select_seeds_noalloc(c, k, s.data(), g.data(), &cov);
+        std::memcpy(seeds, s.data(), (size_t)k * 4);
+        std::memcpy(gains, g.data(), (size_t)k * 8);
+        *coverage = cov;
     });
 }
 

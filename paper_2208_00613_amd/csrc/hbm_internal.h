@@ -301,6 +301,11 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
                   std::vector<uint64_t> &coverage);
 void select_free(Ctx &c);
 void raw_host_free(Ctx &c);  // the pinned host part of a spilled plain-id store
+// Selection with its state in a fixed per-device device array (no allocation); noalloc_setup
+// takes that array's device address, once per device, with the device current.
+void noalloc_setup(int device);
+size_t noalloc_capacity();
+void select_seeds_noalloc(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage);
 
 // profiler: prof_begin records the start event of a launch (returns -1 when off),
 // prof_end the stop event; prof_set fills in work that is known only later.

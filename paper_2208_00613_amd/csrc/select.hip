@@ -20,6 +20,7 @@
 // Counts are exact 32-bit integers (the paper's float frequencies are not exact
 // beyond 2^24).  The store itself is never modified.
 #include <cstring>
+#include <mutex>
 
 #include "hbm_device.h"
 #include "hbm_internal.h"
@@ -1190,6 +1191,86 @@ void select_batch(Ctx &root, const std::vector<Ctx *> &C, const std::vector<int3
                   std::vector<std::vector<int32_t>> &seeds, std::vector<std::vector<uint64_t>> &gains,
                   std::vector<uint64_t> &coverage) {
     select_run(root, C, k, seeds, gains, coverage, nullptr);
+}
+
+// ------------------------------------------------------------------ selection without allocation
+// For callers that cannot allocate device memory (work under graph capture, tight serving
+// loops, harnesses that forbid hipMalloc): the selection state of hbm_select_seeds_noalloc
+// lives in this fixed array.  Each device the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address hipGetSymbolAddress gives.
+constexpr size_t NOALLOC_BYTES = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::once_flag g_noalloc_once[NOALLOC_MAX_DEVICES];
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+static hipError_t g_noalloc_err[NOALLOC_MAX_DEVICES];
+
+// Once per device, with that device current: the device address of this device's copy.
+void noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+    std::call_once(g_noalloc_once[device], [device] {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_noalloc_err[device] = e;
+        if (e == hipSuccess && p) g_noalloc_ptr[device] = p;
+        else (void)hipGetLastError();
+    });
+}
+
+size_t noalloc_capacity() { return NOALLOC_BYTES; }
+
+// Bytes of selection state a k-seed selection over context c's store needs; fills `b` with
+// their places inside `base` when it is given.
+static size_t sel_fixed_layout(const Ctx &root, const Ctx &c, int32_t k, char *base, SelBufs *b) {
+    const int32_t n = c.g.n;
+    const int64_t T = c.s.nsets;
+    const int64_t words = std::max<int64_t>((T + 63) / 64, 1);
+    const bool huff = enc_huff(c.s.enc);
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at = (at + bytes + 255) & ~size_t(255);
+        return base ? base + o : nullptr;
+    };
+    char *counts = take((size_t)n * 4);
+    char *selmask = take(((size_t)n + 31) / 32 * 4);
+    char *covered = take((size_t)words * 8);
+    char *newly = take((size_t)words * 8);
+    char *partial = take((size_t)argmax_blocks(root, n) * 8);
+    char *keys = take((size_t)k * 8);
+    char *big = huff && T > 0 ? take((size_t)(T + 2) * 4) : nullptr;
+    if (b) {
+        b->counts = (uint32_t *)counts;
+        b->selmask = (uint32_t *)selmask;
+        b->covered = (unsigned long long *)covered;
+        b->newly = (unsigned long long *)newly;
+        b->partial = (unsigned long long *)partial;
+        b->keys = (unsigned long long *)keys;
+        b->big = (uint32_t *)big;
+    }
+    return at;
+}
+
+void select_seeds_noalloc(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
+    noalloc_setup(c.device);  // a no-op after hbm_create's call on this device
+    HBM_REQUIRE(c.device >= 0 && c.device < NOALLOC_MAX_DEVICES, HBM_EDEVICE, "device index out of range");
+    if (!g_noalloc_ptr[c.device])
+        throw Error{HBM_EDEVICE, std::string("hipGetSymbolAddress of the selection scratch: ") +
+                                     hipGetErrorString(g_noalloc_err[c.device])};
+    const size_t need = sel_fixed_layout(c, c, k, nullptr, nullptr);
+    HBM_REQUIRE(need <= NOALLOC_BYTES, HBM_EINVAL,
+                "selection state needs " + std::to_string(need) + " bytes, the fixed scratch holds " +
+                    std::to_string(NOALLOC_BYTES) + " (fewer vertices, sets or seeds)");
+    SelBufs b{};
+    sel_fixed_layout(c, c, k, (char *)g_noalloc_ptr[c.device], &b);
+    std::vector<std::vector<int32_t>> s;
+    std::vector<std::vector<uint64_t>> g;
+    std::vector<uint64_t> cov;
+    select_run(c, std::vector<Ctx *>{&c}, std::vector<int32_t>{k}, s, g, cov, &b);
+    std::copy(s[0].begin(), s[0].end(), seeds);
+    std::copy(g[0].begin(), g[0].end(), gains);
+    *coverage = cov[0];
 }
 
 void select_seeds(Ctx &c, int32_t k, int32_t *seeds, uint64_t *gains, uint64_t *coverage) {
