@@ -109,8 +109,11 @@ def lib():
         L.orc_warmup_count.restype = C.c_int64
         L.orc_warmup_count.argtypes = [C.c_double, C.c_int64]
         L.orc_encode.restype = C.c_int
-        L.orc_encode.argtypes = [P, C.c_int32, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_int,
+        L.orc_encode.argtypes = [P, C.c_int32, C.c_int, C.c_int64, C.c_double, C.c_double, C.c_int, C.c_int,
                                  C.POINTER(C.c_void_p)]
+        for nm in ("orc_encoded_ar_hot", "orc_encoded_ar_off", "orc_encoded_ar_low"):
+            getattr(L, nm).restype = P
+            getattr(L, nm).argtypes = [P]
         L.orc_encoded_free.argtypes = [P]
         L.orc_encoded_info.argtypes = [P, P]
         for nm in ["warm", "hot", "bitmap", "cold_off", "cold_mem", "lens", "codes", "bitoff", "payload"]:
@@ -315,17 +318,18 @@ class Encoded:
     """The oracle's encoded store (same layout the GPU library documents)."""
 
     def __init__(self, store: Store, n: int, enc: str, W: int, hot_frac: float = 0.0, hot_min_density: float = 0.0,
-                 implicit_roots: bool = False):
+                 implicit_roots: bool = False, containers: bool = False):
         h = C.c_void_p()
         rc = lib().orc_encode(store.h, n, ENC[enc], W, hot_frac, hot_min_density, 1 if implicit_roots else 0,
-                              C.byref(h))
+                              1 if containers else 0, C.byref(h))
         if rc:
             raise ValueError("implicit roots need a sampled store (every set holds its root)")
         self.h = h.value
-        info = np.zeros(14, dtype=np.int64)
+        info = np.zeros(17, dtype=np.int64)
         lib().orc_encoded_info(self.h, _p(info))
         (self.enc, self.n, self.nsets, self.W, self.nhot, self.nwords, ncold, self.ustar_enc, self.wbits,
-         self.payload_bits, npay, self.n_escapes, self.n_coded, self.maxlen) = [int(x) for x in info]
+         self.payload_bits, npay, self.n_escapes, self.n_coded, self.maxlen, self.nar, self.nchunks,
+         nlow) = [int(x) for x in info]
         L = lib()
         self.warm = _view(L.orc_encoded_warm(self.h), np.uint64, n)
         self.hot = _view(L.orc_encoded_hot(self.h), np.int32, self.nhot)
@@ -339,6 +343,11 @@ class Encoded:
         bo = L.orc_encoded_bitoff(self.h)
         self.bitoff = _view(bo, np.int64, self.nsets + 1) if bo else None
         self.payload = _view(L.orc_encoded_payload(self.h), np.uint32, npay) if bo else None
+        # array containers: rows in hot order; offsets per (chunk, row); 16-bit set offsets
+        self.ar_hot = _view(L.orc_encoded_ar_hot(self.h), np.int32, self.nar) if self.nar else np.zeros(0, np.int32)
+        self.ar_off = (_view(L.orc_encoded_ar_off(self.h), np.int64, self.nchunks * (self.nar + 1))
+                       if self.nar and self.nchunks else np.zeros(0, np.int64))
+        self.ar_low = _view(L.orc_encoded_ar_low(self.h), np.uint16, nlow) if nlow else np.zeros(0, np.uint16)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

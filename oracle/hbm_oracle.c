@@ -635,6 +635,14 @@ typedef struct orc_encoded {
     int32_t *hot;        /* hot vertices by rank */
     int64_t nwords;      /* ceil(nsets/64) */
     uint64_t *bitmap;    /* nwords * nhot, word-major: bitmap[w*nhot + r] */
+    /* array containers (Roaring-style) for hot vertices of warm-up density below 1/16:
+       per chunk c of 2^16 sets, array row a's sets are the sorted 16-bit offsets
+       ar_low[ar_off[c*(nar+1) + a] .. ar_off[c*(nar+1) + a + 1]) */
+    int32_t nar;
+    int32_t *ar_hot;     /* array-row vertices, in hot order */
+    int64_t nchunks;     /* ceil(nsets / 2^16) */
+    int64_t *ar_off;     /* nchunks * (nar + 1), offsets into ar_low */
+    uint16_t *ar_low;
     int64_t *cold_off;   /* raw cold members (NONE / HOT_BITMAP): nsets+1 */
     int32_t *cold_mem;
     uint8_t *lens;       /* Huffman lengths, n (0 = no code) */
@@ -651,6 +659,7 @@ typedef struct orc_encoded {
 
 void orc_encoded_free(orc_encoded *e) {
     if (!e) return;
+    free(e->ar_hot); free(e->ar_off); free(e->ar_low);
     free(e->warm); free(e->hot); free(e->bitmap); free(e->cold_off); free(e->cold_mem);
     free(e->lens); free(e->codes); free(e->bitoff); free(e->payload);
     free(e);
@@ -686,8 +695,13 @@ static int floor_log2_u64(uint64_t x) {
  * plain ids or Huffman string (a root with a bitmap row keeps its bit) and regenerated when
  * the set is decoded.  Returns 2 if some set lacks its root (a store not sampled from the
  * graph). */
+/* Row containers (Roaring-style, after Chambi et al.): with `containers`, a hot vertex whose
+ * warm-up density is below 1/16 (in fewer than W/16 warm-up sets) keeps, per chunk of 2^16
+ * sets, the sorted 16-bit offsets of its sets within the chunk (16 bits per occurrence, the
+ * smaller form below that density) instead of a bitmap row (one bit per set); hot vertices
+ * at or above 1/16 keep bitmap rows.  Either way the vertex is out of the cold part. */
 int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_frac, double hot_min_density,
-               int implicit_roots, orc_encoded **out) {
+               int implicit_roots, int containers, orc_encoded **out) {
     int64_t T = s->nsets;
     if (implicit_roots) {
         for (int64_t j = 0; j < T; j++) {
@@ -713,7 +727,9 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
     int use_hot = (enc == ORC_ENC_HOT_BITMAP || enc == ORC_ENC_HUFFMAN_HOT_BITMAP);
     int use_huff = (enc == ORC_ENC_HUFFMAN || enc == ORC_ENC_HUFFMAN_HOT_BITMAP);
     int32_t *rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
-    for (int32_t v = 0; v < n; v++) rank[v] = -1;
+    int32_t *arank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t v = 0; v < n; v++) rank[v] = arank[v] = -1;
+#define ORC_COLD(v) (rank[(v)] < 0 && arank[(v)] < 0)
     if (enc == ORC_ENC_BITMAX) {
         /* the n x nsets bit matrix: row v holds bit j when v is in set j */
         e->nhot = n;
@@ -725,6 +741,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
                 e->bitmap[(j / 64) * e->nhot + s->mem[i]] |= 1ull << (j % 64);
         free(rank);
+        free(arank);
         *out = e;
         return 0;
     }
@@ -738,10 +755,47 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         for (int32_t v = 0; v < n; v++)
             if (e->warm[v] >= min_cnt) { c[q].w = UINT64_MAX - e->warm[v]; c[q].id = v; q++; }
         qsort(c, (size_t)q, sizeof(leaf_t), cmp_leaf);
-        e->nhot = (int32_t)(q < want ? q : want);
-        e->hot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(e->nhot ? e->nhot : 1));
-        for (int32_t r = 0; r < e->nhot; r++) { e->hot[r] = c[r].id; rank[c[r].id] = r; }
+        int32_t keep = (int32_t)(q < want ? q : want);
+        e->hot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(keep ? keep : 1));
+        e->ar_hot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(keep ? keep : 1));
+        e->nhot = 0;
+        e->nar = 0;
+        for (int32_t r = 0; r < keep; r++) {
+            int32_t v = c[r].id;
+            if (containers && (uint64_t)16 * e->warm[v] < (uint64_t)W) {
+                arank[v] = e->nar;
+                e->ar_hot[e->nar++] = v;
+            } else {
+                rank[v] = e->nhot;
+                e->hot[e->nhot++] = v;
+            }
+        }
         free(c);
+        e->nchunks = (T + 65535) / 65536;
+        int64_t stride = (int64_t)e->nar + 1;
+        e->ar_off = (int64_t *)calloc((size_t)(e->nchunks * stride + 1), sizeof(int64_t));
+        /* counts per (chunk, row), then offsets in (chunk, row) order, then the offsets of
+           the sets in ascending set order, which keeps each row's list ascending */
+        int64_t *cnt = (int64_t *)calloc((size_t)(e->nchunks * stride + 1), sizeof(int64_t));
+        for (int64_t j = 0; j < T; j++)
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
+                if (arank[s->mem[i]] >= 0) cnt[(j / 65536) * stride + arank[s->mem[i]]]++;
+        int64_t nlow = 0;
+        for (int64_t ch = 0; ch < e->nchunks; ch++) {
+            for (int32_t a = 0; a < e->nar; a++) {
+                e->ar_off[ch * stride + a] = nlow;
+                nlow += cnt[ch * stride + a];
+            }
+            e->ar_off[ch * stride + e->nar] = nlow;
+        }
+        e->ar_low = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(nlow ? nlow : 1));
+        for (int64_t ch = 0; ch < e->nchunks; ch++)
+            for (int32_t a = 0; a < e->nar; a++) cnt[ch * stride + a] = e->ar_off[ch * stride + a];
+        for (int64_t j = 0; j < T; j++)
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
+                if (arank[s->mem[i]] >= 0)
+                    e->ar_low[cnt[(j / 65536) * stride + arank[s->mem[i]]]++] = (uint16_t)(j % 65536);
+        free(cnt);
         e->nwords = (T + 63) / 64;
         e->bitmap = (uint64_t *)calloc((size_t)(e->nwords * e->nhot + 1), sizeof(uint64_t));
         for (int64_t j = 0; j < T; j++)
@@ -755,7 +809,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         int64_t total = 0;
         for (int64_t j = 0; j < T; j++) {
             int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
-            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) total += rank[s->mem[i]] < 0 && s->mem[i] != skip;
+            for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) total += ORC_COLD(s->mem[i]) && s->mem[i] != skip;
             e->cold_off[j + 1] = total;
         }
         e->cold_mem = (int32_t *)malloc(sizeof(int32_t) * (size_t)(total ? total : 1));
@@ -763,12 +817,12 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         for (int64_t j = 0; j < T; j++) {
             int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++)
-                if (rank[s->mem[i]] < 0 && s->mem[i] != skip) e->cold_mem[q++] = s->mem[i];
+                if (ORC_COLD(s->mem[i]) && s->mem[i] != skip) e->cold_mem[q++] = s->mem[i];
         }
     } else {
         /* codebook over the non-hot vertices seen in the warm-up block */
         uint64_t *wt = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
-        for (int32_t v = 0; v < n; v++) wt[v] = rank[v] < 0 ? e->warm[v] : 0;
+        for (int32_t v = 0; v < n; v++) wt[v] = ORC_COLD(v) ? e->warm[v] : 0;
         e->lens = (uint8_t *)malloc((size_t)n);
         e->codes = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
         e->maxlen = orc_huffman_lengths(n, wt, e->lens);
@@ -785,7 +839,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] >= 0 || v == skip) continue;
+                if (!ORC_COLD(v) || v == skip) continue;
                 if (e->lens[v]) bits += e->lens[v];
                 else nesc++;
             }
@@ -802,7 +856,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             int32_t skip = implicit_roots ? orc_root(n, s->seed, (uint64_t)j) : -1;
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] < 0 && e->lens[v] == 0 && v != skip) nesc++;
+                if (ORC_COLD(v) && e->lens[v] == 0 && v != skip) nesc++;
             }
             /* Elias gamma of nesc+1 */
             int L = floor_log2_u64(nesc + 1);
@@ -812,7 +866,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             /* verbatim ids of codeless members, ascending */
             for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                 int32_t v = s->mem[i];
-                if (rank[v] < 0 && e->lens[v] == 0 && v != skip) {
+                if (ORC_COLD(v) && e->lens[v] == 0 && v != skip) {
                     put_bits(e->payload, pos, (uint32_t)v, e->wbits);
                     pos += (uint64_t)e->wbits;
                 }
@@ -831,7 +885,7 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
             for (int clen = 1; clen <= 32; clen++)
                 for (int64_t i = s->off[j]; i < s->off[j + 1]; i++) {
                     int32_t v = s->mem[i];
-                    if (rank[v] >= 0 || e->lens[v] != clen || v == e->ustar_enc || v == skip) continue;
+                    if (!ORC_COLD(v) || e->lens[v] != clen || v == e->ustar_enc || v == skip) continue;
                     put_bits(e->payload, pos, e->codes[v], e->lens[v]);
                     pos += e->lens[v];
                     e->n_coded++;
@@ -839,6 +893,8 @@ int orc_encode(const orc_store *s, int32_t n, int enc, int64_t W, double hot_fra
         }
     }
     free(rank);
+    free(arank);
+#undef ORC_COLD
     *out = e;
     return 0;
 }
@@ -899,7 +955,12 @@ void orc_encoded_info(const orc_encoded *e, int64_t *info) {
     info[7] = e->ustar_enc; info[8] = e->wbits;
     info[9] = e->bitoff ? e->bitoff[e->nsets] : 0;
     info[10] = e->npayload; info[11] = e->n_escapes; info[12] = e->n_coded; info[13] = e->maxlen;
+    info[14] = e->nar; info[15] = e->nchunks;
+    info[16] = (e->nar > 0 && e->nchunks > 0) ? e->ar_off[e->nchunks * ((int64_t)e->nar + 1) - 1] : 0;
 }
+const int32_t *orc_encoded_ar_hot(const orc_encoded *e) { return e->ar_hot; }
+const int64_t *orc_encoded_ar_off(const orc_encoded *e) { return e->ar_off; }
+const uint16_t *orc_encoded_ar_low(const orc_encoded *e) { return e->ar_low; }
 const uint64_t *orc_encoded_warm(const orc_encoded *e) { return e->warm; }
 const int32_t *orc_encoded_hot(const orc_encoded *e) { return e->hot; }
 const uint64_t *orc_encoded_bitmap(const orc_encoded *e) { return e->bitmap; }
@@ -918,6 +979,14 @@ int64_t orc_decode_set(const orc_encoded *e, int64_t j, int32_t *out) {
     if (e->nhot > 0) {
         for (int32_t r = 0; r < e->nhot; r++)
             if ((e->bitmap[(j / 64) * e->nhot + r] >> (j % 64)) & 1ull) out[len++] = e->hot[r];
+    }
+    if (e->nar > 0) {  /* array rows: linear search of each row's offsets in j's chunk */
+        int64_t ch = j / 65536;
+        uint16_t low = (uint16_t)(j % 65536);
+        const int64_t *o = e->ar_off + ch * ((int64_t)e->nar + 1);
+        for (int32_t a = 0; a < e->nar; a++)
+            for (int64_t i = o[a]; i < o[a + 1]; i++)
+                if (e->ar_low[i] == low) { out[len++] = e->ar_hot[a]; break; }
     }
     if (e->cold_off) {
         for (int64_t i = e->cold_off[j]; i < e->cold_off[j + 1]; i++) out[len++] = e->cold_mem[i];
@@ -953,6 +1022,7 @@ int64_t orc_decode_set(const orc_encoded *e, int64_t j, int32_t *out) {
         int32_t r = orc_root(e->n, e->seed, (uint64_t)j);
         int in_row = 0;
         for (int32_t q = 0; q < e->nhot; q++) in_row |= e->hot[q] == r;
+        for (int32_t q = 0; q < e->nar; q++) in_row |= e->ar_hot[q] == r;
         if (!in_row) out[len++] = r;
     }
     qsort(out, (size_t)len, sizeof(int32_t), cmp_i32);

@@ -905,3 +905,43 @@ def test_implicit_roots_need_sampled_sets(orc):
     st = orc.Store.from_sets(off, np.array([1, 2, 0], dtype=np.int32))
     with pytest.raises(ValueError):
         orc.Encoded(st, 4, "NONE", W=2, implicit_roots=True)
+
+
+# ---------------------------------------------------------------- Roaring-style row containers
+@pytest.mark.parametrize("enc", ["HOT_BITMAP", "HUFFMAN_HOT_BITMAP"])
+@pytest.mark.parametrize("implicit", [False, True])
+def test_row_containers(orc, enc, implicit):
+    """Hot vertices below warm-up density 1/16 keep per 2^16-set chunk the sorted 16-bit
+    offsets of their sets (array containers), the others bitmap rows: the split follows the
+    rule, every list is strictly ascending and names exactly the sets that hold its vertex
+    (over two chunks, the second partial), and every set decodes back, also with implicit
+    roots."""
+    g = G.rmat(10, seed=19)
+    og = orc.Graph(g.n, g.row_ptr, g.dst, None, model="IC", prob="WC")
+    T, W = 70_000, 3_000
+    st = orc.sample_store(og, 4, T)
+    off, mem = st.arrays()
+    e = orc.Encoded(st, g.n, enc, W=W, hot_frac=0.05, implicit_roots=implicit, containers=True)
+    plain = orc.Encoded(st, g.n, enc, W=W, hot_frac=0.05)
+    warm = st.counts(g.n, 0, W)
+    assert e.nar > 0 and e.nhot > 0 and e.nchunks == 2
+    assert sorted(e.hot.tolist() + e.ar_hot.tolist()) == sorted(plain.hot.tolist())
+    assert all(16 * warm[v] < W for v in e.ar_hot) and all(16 * warm[v] >= W for v in e.hot)
+    assert [v for v in plain.hot if v in set(e.ar_hot.tolist())] == e.ar_hot.tolist()  # hot order kept
+    sets_of = {int(v): [] for v in e.ar_hot}
+    for j in range(T):
+        for v in mem[off[j]:off[j + 1]]:
+            if int(v) in sets_of:
+                sets_of[int(v)].append(j)
+    stride = e.nar + 1
+    for a, v in enumerate(e.ar_hot):
+        got = []
+        for ch in range(e.nchunks):
+            lo, hi = e.ar_off[ch * stride + a], e.ar_off[ch * stride + a + 1]
+            seg = e.ar_low[lo:hi].astype(np.int64)
+            assert (np.diff(seg) > 0).all()
+            got += (seg + ch * 65536).tolist()
+        assert got == sets_of[int(v)]
+    assert len(e.ar_low) == sum(len(x) for x in sets_of.values())
+    for j in list(range(0, T, 997)) + [65535, 65536, T - 1]:
+        assert np.array_equal(e.decode_set(j), mem[off[j]:off[j + 1]])
