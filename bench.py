@@ -211,10 +211,13 @@ def counters_summarize(fetch_csv, write_csv, l2_csv, workload, out_path=None):
     import re
 
     def per_kernel(path, counter, scale=1.0):
+        import gzip
+
         acc = {}
         if not path:
             return acc
-        for r in csv.DictReader(open(path)):
+        f = gzip.open(path, "rt") if path.endswith(".gz") else open(path)
+        for r in csv.DictReader(f):
             if r["Counter_Name"] != counter:
                 continue
             acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * scale)
@@ -550,6 +553,21 @@ def c5_record(args, P, torch, with_host):
         ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
     kstats = ctx.hbm_profile_read()
     ctx.hbm_profile(False)
+    # implicit roots, then array rows for the sparse hot vertices, on the first timed query:
+    # B/RR beside the plain store's
+    q0 = stream[W]
+    st_0 = alone[q0["q"]][2]
+    variants = {}
+    for name, setter in (("implicit_roots", ctx.hbm_set_implicit_roots), ("row_containers", ctx.hbm_set_row_containers)):
+        setter(True)
+        s_i, g_i, st_i = ctx.hbm_imm(q0["k"], q0["eps"], q0["l"], q0["seed"])
+        setter(False)
+        variants[name] = {
+            "query": {"k": q0["k"], "eps": q0["eps"], "seed": q0["seed"]},
+            "bytes_per_rr": st_i["store"]["store_bytes"] / st_i["nsets_final"],
+            "plain_bytes_per_rr": st_0["store"]["store_bytes"] / st_0["nsets_final"],
+            "narray": st_i["store"]["narray"], "nhot": st_i["store"]["nhot"],
+            "same_seeds": bool(np.array_equal(s_i, alone[q0["q"]][0]) and np.array_equal(g_i, alone[q0["q"]][1]))}
     levels, identical = serving_levels(P, ctx, c, alone, svc, args.queries, args.loads)
     stores = [st["store"] for st in timed]
     rec = {
@@ -572,8 +590,28 @@ def c5_record(args, P, torch, with_host):
         "roofline": roofline(kstats, "IC", "WC", "all"),
         "kernels": kernel_rates(kstats)[:12],
         "serving": {"levels": levels, "served_equals_alone": bool(identical), "mean_service_s": svc},
+        **variants,
     }
     return ctx, c, rec, host
+
+
+def variant_leg(torch, ctx, c, seeds, gains, rec, setter):
+    """The same IMM with one store option on (implicit roots: each set's root regenerated from
+    Philox, not stored; row containers: array rows for the sparse hot vertices): B/RR and time
+    beside the plain store's, and the seeds (which must not change)."""
+    k, eps, l, seed = c["k"], c["eps"], c["l"], c["seed"]
+    setter(True)
+    ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s2, g2, st2 = ctx.hbm_imm(k, eps, l, seed)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    setter(False)
+    return {"bytes_per_rr": st2["store"]["store_bytes"] / max(st2["nsets_final"], 1),
+            "plain_bytes_per_rr": rec["bytes_per_rr"], "imm_s": t, "plain_imm_s": rec["imm_s"],
+            "narray": st2["store"]["narray"], "nhot": st2["store"]["nhot"],
+            "same_seeds": bool(np.array_equal(s2, seeds) and np.array_equal(g2, gains))}
 
 
 def imm_record(P, torch, g, c, wl_key, steps, warmup, density_gate=False, equal_memory=False):
@@ -625,8 +663,13 @@ def imm_record(P, torch, g, c, wl_key, steps, warmup, density_gate=False, equal_
         rec["density_gate_1_32"] = {
             "bytes_per_rr": st2["store"]["store_bytes"] / max(st2["nsets_final"], 1), "imm_s": t_g,
             "nhot": st2["store"]["nhot"], "same_seeds": bool(np.array_equal(s2, seeds) and np.array_equal(g2, gains))}
+        ctx.hbm_set_hot_density(0.0)
     if equal_memory:
         rec["equal_memory"] = equal_memory_leg(P, torch, ctx, c, seeds, gains, rec)
+    elif c["enc"] != "BITMAX":
+        rec["implicit_roots"] = variant_leg(torch, ctx, c, seeds, gains, rec, ctx.hbm_set_implicit_roots)
+        if c["enc"] in ("HOT_BITMAP", "HUFFMAN_HOT_BITMAP"):
+            rec["row_containers"] = variant_leg(torch, ctx, c, seeds, gains, rec, ctx.hbm_set_row_containers)
     ctx.close()
     return rec
 

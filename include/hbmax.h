@@ -104,6 +104,9 @@ typedef struct hbm_store_stats {
     int64_t store_bytes;    /* index + payload + bitmap + raw (codebook excluded) */
     double skewness;        /* Eq. 2 over the warm-up block */
     double density;         /* Eq. 2 over the warm-up block */
+    int32_t narray;         /* hot vertices with array rows (hbm_set_row_containers) */
+    int64_t array_entries;  /* 16-bit set offsets held by the array rows */
+    int64_t array_bytes;    /* array rows: per-chunk offsets + entries (in store_bytes) */
 } hbm_store_stats;
 
 /* Result details of hbm_imm. */
@@ -192,6 +195,21 @@ hbm_status hbm_set_hot_density(hbm_ctx *ctx, double min_density);
  * plain id, its code or escape in a Huffman string); results are unchanged.
  * Default 0.  Resets the store.  HBM_EINVAL unless on is 0 or 1. */
 hbm_status hbm_set_implicit_roots(hbm_ctx *ctx, int32_t on);
+
+/* Row containers for the hot set (the Roaring-style bitmap compression that the
+ * Huffman Coding and Bitmap Compression background section names): with on = 1, a hot
+ * vertex found in fewer than W/16 of the W warm-up sets gets an ARRAY row instead of a
+ * bitmap row.  The sets are cut into chunks of 2^16 consecutive sets; in each chunk an
+ * array row holds the ascending 16-bit offsets (j mod 2^16) of the chunk's sets that
+ * hold the vertex, 16 bits per occurrence against a bitmap row's one bit per set.
+ * Layout (hbm_export HBM_A_ARR_*): rows in hot order (ARR_HOT); offsets chunk-major,
+ * nar + 1 per chunk, into one entry array (ARR_OFF, ARR_LOW); row a of chunk c is
+ * ARR_LOW[ARR_OFF[c (nar + 1) + a] .. ARR_OFF[c (nar + 1) + a + 1]).  Selection reads
+ * an array row as the list of its sets (u* with an array row marks them; counts of
+ * array rows drop by the entries of newly covered sets).  Affects HOT_BITMAP and
+ * HUFFMAN_HOT_BITMAP only; results are unchanged.  Default 0.  Resets the store.
+ * HBM_EINVAL unless on is 0 or 1. */
+hbm_status hbm_set_row_containers(hbm_ctx *ctx, int32_t on);
 
 /* Spill of plain ids to host memory (the equal-memory comparison of the
  * Evaluation section, where an uncompressed store that outgrows memory spills to
@@ -452,7 +470,10 @@ typedef enum hbm_array {
     HBM_A_LENS = 9,      /* uint8[n]    Huffman code lengths (0 = codeless) */
     HBM_A_CODES = 10,    /* uint32[n]   canonical codes, right-aligned */
     HBM_A_BITOFF = 11,   /* int64[nsets+1] start bit of each set's string */
-    HBM_A_PAYLOAD = 12   /* uint32[]    bit stream, MSB first within each word */
+    HBM_A_PAYLOAD = 12,  /* uint32[]    bit stream, MSB first within each word */
+    HBM_A_ARR_HOT = 13,  /* int32[nar]  vertices with array rows, in hot order */
+    HBM_A_ARR_OFF = 14,  /* int64[ceil(nsets/2^16) * (nar+1)] chunk-major offsets into ARR_LOW */
+    HBM_A_ARR_LOW = 15   /* uint16[]    ascending set offsets (j mod 2^16) per (chunk, row) */
 } hbm_array;
 
 hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_bytes, int64_t *bytes);

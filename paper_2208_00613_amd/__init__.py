@@ -25,13 +25,15 @@ ENC = {"NONE": 0, "HUFFMAN": 1, "HOT_BITMAP": 2, "HUFFMAN_HOT_BITMAP": 3, "BITMA
 ARRAYS = {"IN_PTR": (0, np.int64), "IN_SRC": (1, np.int32), "THRESH": (2, np.uint32), "COUNTS": (3, np.uint32),
           "WARM": (4, np.uint32), "HOT": (5, np.int32), "BITMAP": (6, np.uint64), "RAW_OFF": (7, np.int64),
           "RAW_MEM": (8, np.int32), "LENS": (9, np.uint8), "CODES": (10, np.uint32), "BITOFF": (11, np.int64),
-          "PAYLOAD": (12, np.uint32)}
+          "PAYLOAD": (12, np.uint32), "ARR_HOT": (13, np.int32), "ARR_OFF": (14, np.int64),
+          "ARR_LOW": (15, np.uint16)}
 EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hbm_load_graph", "hbm_set_encoding",
             "hbm_sample_rr", "hbm_select_seeds", "hbm_imm", "hbm_get_rr", "hbm_dump_sets", "hbm_get_store_stats",
             "hbm_export", "hbm_version", "hbm_set_tuning", "hbm_set_hot_density", "hbm_profile", "hbm_profile_read", "hbm_imm_batch",
             "hbm_server_create", "hbm_server_destroy", "hbm_server_last_error", "hbm_server_submit",
             "hbm_server_poll", "hbm_server_get_stats", "hbm_autotune", "hbm_select_seeds_noalloc",
-            "hbm_get_memory", "hbm_bench_philox", "hbm_set_spill", "hbm_set_implicit_roots"]
+            "hbm_get_memory", "hbm_bench_philox", "hbm_set_spill", "hbm_set_implicit_roots",
+            "hbm_set_row_containers"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5,
         "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8, "SELECT_GRAPH": 9}
 TUNE_COUNT = 10
@@ -49,7 +51,8 @@ class StoreStats(C.Structure):
                 ("ustar_enc", C.c_int32), ("escape_bits", C.c_int32), ("escapes", C.c_int64),
                 ("payload_bits", C.c_uint64), ("index_bytes", C.c_int64), ("bitmap_bytes", C.c_int64),
                 ("raw_bytes", C.c_int64), ("codebook_bytes", C.c_int64), ("store_bytes", C.c_int64),
-                ("skewness", C.c_double), ("density", C.c_double)]
+                ("skewness", C.c_double), ("density", C.c_double), ("narray", C.c_int32),
+                ("array_entries", C.c_int64), ("array_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -157,6 +160,7 @@ def lib():
         "hbm_set_hot_density": ([P, D], C.c_int),
         "hbm_set_spill": ([P, I64], C.c_int),
         "hbm_set_implicit_roots": ([P, I32], C.c_int),
+        "hbm_set_row_containers": ([P, I32], C.c_int),
         "hbm_sample_rr": ([P, I64, U64], C.c_int),
         "hbm_select_seeds": ([P, I32, P, P, P], C.c_int),
         "hbm_select_seeds_noalloc": ([P, I32, P, P, P], C.c_int),
@@ -302,6 +306,9 @@ class Context:
 
     def hbm_set_implicit_roots(self, on: bool):
         self._check(lib().hbm_set_implicit_roots(self.h, 1 if on else 0))
+
+    def hbm_set_row_containers(self, on: bool):
+        self._check(lib().hbm_set_row_containers(self.h, 1 if on else 0))
 
     def hbm_set_spill(self, device_bytes: int):
         self._check(lib().hbm_set_spill(self.h, int(device_bytes)))

@@ -128,6 +128,14 @@ hbm_status hbm_set_implicit_roots(hbm_ctx *ctx, int32_t on) {
     });
 }
 
+hbm_status hbm_set_row_containers(hbm_ctx *ctx, int32_t on) {
+    return guard(ctx, [&](Ctx &c) {
+        HBM_REQUIRE(on == 0 || on == 1, HBM_EINVAL, "on must be 0 or 1");
+        hbm::store_reset(c);
+        c.s.containers = on != 0;
+    });
+}
+
 hbm_status hbm_set_spill(hbm_ctx *ctx, int64_t device_bytes) {
     return guard(ctx, [&](Ctx &c) {
         HBM_REQUIRE(device_bytes >= 0, HBM_EINVAL, "device_bytes must be >= 0");
@@ -454,6 +462,9 @@ hbm_status hbm_export(hbm_ctx *ctx, hbm_array what, void *host_out, int64_t cap_
             case HBM_A_CODES: src = s.codes.p; nb = (huff && s.model_ready) ? n * 4 : 0; break;
             case HBM_A_BITOFF: src = s.bitoff.p; nb = (huff && T) ? (T + 1) * 8 : 0; break;
             case HBM_A_PAYLOAD: src = s.payload.p; nb = (huff && T) ? (int64_t)((s.nbits + 31) / 32) * 4 : 0; break;
+            case HBM_A_ARR_HOT: src = s.ar_hot.p; nb = (int64_t)s.nar * 4; break;
+            case HBM_A_ARR_OFF: src = s.ar_off.p; nb = s.nar ? s.ar_chunks * (int64_t)(s.nar + 1) * 8 : 0; break;
+            case HBM_A_ARR_LOW: src = s.ar_low.p; nb = s.nar ? s.ar_entries * 2 : 0; break;
             default: throw Error{HBM_EINVAL, "unknown array"};
         }
         *bytes = nb;

@@ -88,6 +88,7 @@ struct Store {
     double warmup_frac = 0.1, hot_frac = 0.01;
     double hot_min_density = 0.0;  // a hot vertex is in at least this fraction of warm-up sets
     bool implicit_roots = false;   // set j's root is regenerated from (seed, j), not stored
+    bool containers = false;       // hot rows below warm-up density 1/16 as array containers
     bool has_seed = false;
     uint64_t seed = 0;
     int64_t nsets = 0;
@@ -127,6 +128,19 @@ struct Store {
     Buf payload;   // uint32[]
     Buf ckb;       // uint8 per CK_SLOT payload bits: code-boundary slots
     Buf mtmp;      // model building: warm-up symbol lists and their uploads
+    // array containers (Roaring-style): array row a (a hot vertex of warm-up density below
+    // 1/16) keeps, per chunk c of 2^16 sets, the ascending 16-bit offsets of its sets in
+    // ar_low[ar_off[c (nar + 1) + a], ar_off[c (nar + 1) + a + 1]); chunks lie in order
+    int32_t nar = 0;
+    Buf ar_hot;    // int32[nar] array-row vertices, hot order
+    Buf ar_rank;   // int32[n], -1 unless an array row
+    Buf ar_off;    // int64[nchunks * (nar + 1)]
+    Buf ar_low;    // uint16 entries
+    int64_t ar_chunks = 0, ar_entries = 0;
+    int64_t ar_last_start = 0;  // first entry of the last chunk
+    Buf ar_tmp;    // rebuild scratch: per-row counts and offsets
+    Buf ar_keys;   // rebuild scratch: the rebuilt chunk's entries, sorted copy
+    Buf ar_sort;   // rebuild scratch: segmented-sort temporary storage
     uint64_t nbits = 0;
     int64_t escapes = 0;
     double skew = 0.0, density = 0.0;

@@ -74,14 +74,41 @@ struct SelArgs {
     uint32_t *csel;               // selection bits over slots
     const int64_t *ncand;         // number of slots (device)
     unsigned long long *pbits;    // profiling: payload bits decoded by k_dec_big (else null)
+    // array rows (hot vertices of low density): per 2^16-set chunk, each row's sorted 16-bit set
+    // offsets; ar_off is chunk-major with nar + 1 entries per chunk
+    int32_t nar;
+    const int32_t *ar_rank;
+    const int32_t *ar_hot;
+    const int64_t *ar_off;
+    const uint16_t *ar_low;
+    int64_t nchunks;
+    int32_t arx;                  // k_dec_arr blocks per chunk (DA_ROWS rows each)
 };
+
+__device__ __forceinline__ bool in_arr(const SelArgs &A, uint32_t v) { return A.nar && A.ar_rank[v] >= 0; }
 
 // The root a store with implicit roots left out of set j (a root with a bitmap row is in its
 // row), or ~0u.
 __device__ __forceinline__ uint32_t lost_root(const SelArgs &A, int64_t j) {
     if (!A.implicit) return 0xFFFFFFFFu;
     const uint32_t r = rr_root(A.seed, (uint64_t)j, (uint32_t)A.n);
-    return (A.hot_rank && A.hot_rank[r] >= 0) ? 0xFFFFFFFFu : r;
+    return ((A.hot_rank && A.hot_rank[r] >= 0) || in_arr(A, r)) ? 0xFFFFFFFFu : r;
+}
+
+// u* with array row a: its uncovered sets, read off the row's list in every chunk (one wave per
+// chunk at a time), are marked in `newly`; k_apply covers them and decrements their members.
+__device__ void arr_mark(const SelArgs &A, int32_t a, int64_t bid, uint32_t nblk) {
+    const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
+    const unsigned lane = lane_id();
+    for (int64_t ch = bid * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; ch < A.nchunks; ch += nwaves) {
+        const int64_t *o = A.ar_off + ch * (int64_t)(A.nar + 1);
+        const int64_t e = o[a + 1];
+        for (int64_t i = o[a] + lane; i < e; i += WAVE) {
+            const int64_t j = (ch << 16) | (int64_t)A.ar_low[i];
+            const unsigned long long bit = 1ull << (j & 63);
+            if (!(A.covered[j >> 6] & bit)) atomicOr(&A.newly[j >> 6], bit);
+        }
+    }
 }
 
 // Index into `counts` of vertex v (every decremented vertex is a member of some set, so it
@@ -382,6 +409,10 @@ HBM_KERNEL(k_find_raw, SelArgs, 256) {
     unsigned long long key;
     const uint32_t u = ustar_of(A, x, key);
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
+    if (in_arr(A, u)) {
+        arr_mark(A, A.ar_rank[u], bid, nblk);
+        return;
+    }
     const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     const int64_t n4 = A.nraw >> 2;
@@ -461,6 +492,10 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
     unsigned long long key;
     const uint32_t u = ustar_of(A, x, key);
     if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
+    if (in_arr(A, u)) {
+        arr_mark(A, A.ar_rank[u], bid, nblk);
+        return;
+    }
     const uint32_t ustar_len = A.lens[u];
     const uint32_t ustar_code = ustar_len ? A.codes[u] : 0u;
     const uint32_t fe_len = A.ustar_enc >= 0 ? A.lens[A.ustar_enc] : 0u;  // the front code
@@ -551,7 +586,8 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
         A.keys[t] = key;
     }
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
-    if (r < 0 && A.huff) return;  // the Huffman find step already covered and decremented
+    // a cold u*: the Huffman find step already covered and decremented
+    if (r < 0 && A.huff && !in_arr(A, u)) return;
     cache_init(C);
     __syncthreads();
     const unsigned lane = lane_id();
@@ -697,6 +733,43 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
     if (acc) atomicSub(&A.counts[ckey(A, (uint32_t)A.hot[h])], acc);
 }
 
+// array-row counts -= the row's entries whose set is newly covered: work item b takes chunk
+// b / arx and rows [DA_ROWS (b mod arx), +DA_ROWS) of it, one wave per row, with the chunk's
+// 1024 `newly` words in LDS (a chunk with none newly covered is left at once)
+constexpr int DA_ROWS = 256;
+HBM_KERNEL(k_dec_arr, SelArgs, 256) {
+    (void)x;
+    __shared__ unsigned long long nl[1024];
+    const unsigned lane = lane_id();
+    const int64_t items = A.nchunks * (int64_t)A.arx;
+    for (int64_t b = bid; b < items; b += nblk) {
+        const int64_t ch = b / A.arx;
+        const int32_t r0 = (int32_t)(b % A.arx) * DA_ROWS;
+        const int64_t w0 = ch * 1024;
+        const int64_t nwc = A.words - w0 < 1024 ? A.words - w0 : 1024;
+        int mine = 0;
+        for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+            const unsigned long long v = i < nwc ? A.newly[w0 + i] : 0ull;
+            nl[i] = v;
+            mine |= v != 0ull;
+        }
+        if (!__syncthreads_or(mine)) continue;
+        const int64_t *o = A.ar_off + ch * (int64_t)(A.nar + 1);
+        const int32_t r1 = r0 + DA_ROWS < A.nar ? r0 + DA_ROWS : A.nar;
+        for (int32_t a = r0 + (int32_t)(threadIdx.x / WAVE); a < r1; a += (int32_t)(blockDim.x / WAVE)) {
+            uint32_t c = 0;
+            const int64_t e = o[a + 1];
+            for (int64_t i = o[a] + lane; i < e; i += WAVE) {
+                const uint32_t low = A.ar_low[i];
+                c += (uint32_t)(nl[low >> 6] >> (low & 63)) & 1u;
+            }
+            c = wave_sum(c);
+            if (lane == 0 && c) atomicSub(&A.counts[ckey(A, (uint32_t)A.ar_hot[a])], c);
+        }
+        __syncthreads();  // nl is rewritten for the next item
+    }
+}
+
 void select_free(Ctx &c) {
     for (auto &g : c.sel_graphs) (void)hipGraphExecDestroy(g.exec);
     c.sel_graphs.clear();
@@ -817,7 +890,7 @@ static int64_t build_slots(Ctx &root, Ctx &c) {
 struct SelJob {
     SelArgs A;
     bool huff;
-    uint32_t g_arg, g_find, g_apply, g_hot, g_big;
+    uint32_t g_arg, g_find, g_apply, g_hot, g_big, g_arr;
     double b_arg, b_find, b_apply;
 };
 
@@ -907,6 +980,13 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.ckb = s.ckb.as<uint8_t>();
     A.big = huff && T > 0 ? (fixed ? fixed->big : S.big.as<uint32_t>()) : nullptr;
     A.k = k;
+    A.nar = T > 0 ? s.nar : 0;
+    A.ar_rank = s.ar_rank.as<int32_t>();
+    A.ar_hot = s.ar_hot.as<int32_t>();
+    A.ar_off = s.ar_off.as<int64_t>();
+    A.ar_low = s.ar_low.as<uint16_t>();
+    A.nchunks = s.ar_chunks;
+    A.arx = (int32_t)std::max<int64_t>(((int64_t)s.nar + DA_ROWS - 1) / DA_ROWS, 1);
     A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
     A.seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
@@ -915,10 +995,12 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     J.g_arg = g_arg;
     if (T == 0) J.g_find = 0;
     else if (huff) J.g_find = gfix ? (uint32_t)root.num_cus * 7 : grid_for(words, 4, (int64_t)root.num_cus * 7);  // resident: 7 blocks per CU
-    else J.g_find = A.nraw > 0 ? (gfix ? (uint32_t)root.num_cus * 4 : grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4)) : 0;
+    else J.g_find = (A.nraw > 0 || A.implicit || A.nar) ? (gfix ? (uint32_t)root.num_cus * 4 : grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4)) : 0;
     J.g_apply = gfix ? (uint32_t)root.num_cus * 2 : grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
     // hot counts: segments past the words in use find no word to read
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * (gfix ? std::max<int64_t>(1, 4096 / A.hx) : nseg)) : 0;
+    J.g_arr = A.nar ? (gfix ? (uint32_t)root.num_cus * 4
+                            : grid_for(A.nchunks * A.arx, 1, (int64_t)root.num_cus * 16)) : 0;
     J.g_big = A.big ? (gfix ? (uint32_t)root.num_cus * 3 : grid_for(T, 256, (int64_t)root.num_cus * 3)) : 0;  // idle blocks leave at once
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
@@ -977,7 +1059,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     std::vector<size_t> order(N);
     for (size_t i = 0; i < N; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return k[a] > k[b]; });
-    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_BIG, NPLAN };
+    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_BIG, P_ARR, NPLAN };
     Plan plans[NPLAN];
     for (size_t i : order) {
         plans[P_ALL_ARG].jobs.push_back(i);
@@ -987,6 +1069,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
         if (J[i].g_find && !J[i].huff) plans[P_RAW].jobs.push_back(i);
         if (J[i].g_hot) plans[P_HOT].jobs.push_back(i);
         if (J[i].g_big) plans[P_BIG].jobs.push_back(i);
+        if (J[i].g_arr) plans[P_ARR].jobs.push_back(i);
     }
     auto blocks = [&](int p, size_t i) -> uint32_t {
         switch (p) {
@@ -996,6 +1079,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
             case P_RAW: return J[i].g_find;
             case P_HOT: return J[i].g_hot;
             case P_BIG: return J[i].g_big;
+            case P_ARR: return J[i].g_arr;
             default: return graph ? 1024u : grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
         }
     };
@@ -1103,6 +1187,11 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
             if (active(P_HOT, t)) {
                 ps = prof_begin(root, "dec_hot");
                 HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
+                prof_end(root, ps);
+            }
+            if (active(P_ARR, t)) {
+                ps = prof_begin(root, "dec_arr");
+                HBM_SEL_LAUNCH(P_ARR, k_dec_arr, t);
                 prof_end(root, ps);
             }
         }

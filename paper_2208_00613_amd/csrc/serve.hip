@@ -65,7 +65,8 @@ struct Slot {
 void release_store(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp, &s.ar_hot, &s.ar_rank,
+                   &s.ar_off, &s.ar_low, &s.ar_tmp})
         buf_free(c, *b);
     store_reset(c);
 }
@@ -82,7 +83,7 @@ struct hbm_server {
     int32_t max_active = 1;
     int enc = HBM_ENC_NONE;
     double warmup_frac = 0.1, hot_frac = 0.01, hot_min_density = 0.0;
-    bool implicit_roots = false;
+    bool implicit_roots = false, containers = false;
     hbm::DGraph graph;  // borrowed from the graph context
     std::chrono::steady_clock::time_point t0;
 
@@ -239,6 +240,7 @@ void hbm_server::admit_locked() {
         c.budget = budget;
         c.s.enc_req = c.s.enc = enc;
         c.s.implicit_roots = implicit_roots;
+        c.s.containers = containers;
         c.s.warmup_frac = warmup_frac;
         c.s.hot_frac = hot_frac;
         c.s.hot_min_density = hot_min_density;
@@ -478,6 +480,7 @@ hbm_status hbm_server_create(hbm_server **out, hbm_ctx *graph, int64_t store_bud
     s->hot_frac = g.s.hot_frac;
     s->hot_min_density = g.s.hot_min_density;
     s->implicit_roots = g.s.implicit_roots;
+    s->containers = g.s.containers;
     s->graph = g.g;
     s->graph.borrowed = true;
     s->t0 = std::chrono::steady_clock::now();

@@ -20,6 +20,8 @@
 //             fixed-width fields (the CP copies kept in-band), then the canonical
 //             codes of the coded ids, the warm-up top vertex first (the u*
 //             swap-to-front of the Huffmax encoding section), the rest ascending.
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -69,6 +71,7 @@ struct SplitArgs {
     int implicit;                 // implicit roots: a set's root is not written as a plain id
     uint64_t seed;
     uint32_t n;
+    const int32_t *ar_rank;       // array-row members are neither cold nor bitmap bits (may be null)
 };
 HBM_KERNEL(k_cold_count, SplitArgs, 256) {
     const BlockView &bv = A.bv;
@@ -80,12 +83,12 @@ HBM_KERNEL(k_cold_count, SplitArgs, 256) {
     for (uint64_t b = wave; b < (uint64_t)bv.nb; b += nw) {
         const uint32_t p = bv.pos[b], s = bv.size[b];
         uint32_t c = s;
-        if (hot_rank || A.implicit) {
+        if (hot_rank || A.implicit || A.ar_rank) {
             const uint32_t root = dropped_root(A.implicit, A.seed, (uint64_t)A.j0 + b, A.n);
             c = 0;
             for (uint32_t i = lane; i < s; i += WAVE) {
                 const uint32_t v = bv.mem[p + i];
-                c += (!hot_rank || hot_rank[v] < 0) && v != root;
+                c += (!hot_rank || hot_rank[v] < 0) && (!A.ar_rank || A.ar_rank[v] < 0) && v != root;
             }
             c = wave_sum(c);
         }
@@ -120,7 +123,7 @@ HBM_KERNEL(k_split, SplitArgs, 256) {
                 v = bv.mem[p + i];
                 if (hot_rank) r = hot_rank[v];
             }
-            const bool cold = i < s && r < 0 && v != root;
+            const bool cold = i < s && r < 0 && v != root && !(A.ar_rank && A.ar_rank[v] >= 0);
             const uint64_t m = __ballot(cold);
             if (cold && raw) {
                 const int64_t at = o + written + __popcll(m & ((1ull << lane) - 1));
@@ -144,6 +147,7 @@ struct HuffEnc {
     uint64_t seed;
     int64_t j0;               // set index of the block's first set
     uint32_t n;
+    const int32_t *ar_rank;   // array-row members are not coded (may be null)
 };
 struct HuffArgs {
     BlockView bv;
@@ -173,7 +177,7 @@ HBM_KERNEL(k_huff_bits, HuffArgs, 256) {
         uint32_t nesc = 0, front = 0;
         for (uint32_t i = lane; i < s; i += WAVE) {
             const uint32_t v = bv.mem[p + i];
-            if ((h.hot_rank && h.hot_rank[v] >= 0) || v == root) continue;
+            if ((h.hot_rank && h.hot_rank[v] >= 0) || (h.ar_rank && h.ar_rank[v] >= 0) || v == root) continue;
             const uint32_t L = h.lens[v];
             if (L) bits += L;
             else nesc++;
@@ -248,7 +252,7 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
         auto code_of = [&](uint32_t i, uint32_t &v, bool &esc) -> uint32_t {
             v = bv.mem[p + i];
             esc = false;
-            if ((h.hot_rank && h.hot_rank[v] >= 0) || v == root) return 0u;
+            if ((h.hot_rank && h.hot_rank[v] >= 0) || (h.ar_rank && h.ar_rank[v] >= 0) || v == root) return 0u;
             const uint32_t len = h.lens[v];
             esc = len == 0;
             return (int32_t)v == h.ustar ? 0u : len;
@@ -330,6 +334,11 @@ struct DecodeView {
     uint64_t seed;
     uint32_t n;
     const int32_t *hot_rank;
+    int32_t nar;             // array rows (chunk-major offsets, sorted 16-bit set offsets)
+    const int32_t *ar_hot;
+    const int32_t *ar_rank;
+    const int64_t *ar_off;
+    const uint16_t *ar_low;
     const int64_t *bitoff;
     const uint32_t *payload;
     const uint64_t *lim;    // [34]
@@ -359,6 +368,22 @@ __device__ uint32_t decode_set(const DecodeView &d, int64_t j, int32_t *out) {
                 c++;
             }
     }
+    if (d.nar) {  // binary search of each array row's list in j's chunk
+        const int64_t *o = d.ar_off + (j >> 16) * (int64_t)(d.nar + 1);
+        const uint16_t low = (uint16_t)(j & 0xffff);
+        for (int32_t a = 0; a < d.nar; a++) {
+            int64_t lo = o[a], hi = o[a + 1];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (d.ar_low[mid] < low) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < o[a + 1] && d.ar_low[lo] == low) {
+                if (out) out[c] = d.ar_hot[a];
+                c++;
+            }
+        }
+    }
     if (d.raw_off) {
         for (int64_t i = d.raw_off[j]; i < d.raw_off[j + 1]; i++) {
             if (out) out[c] = raw_id(d.raw_mem, d.raw_host, d.raw_split, i);
@@ -385,7 +410,7 @@ __device__ uint32_t decode_set(const DecodeView &d, int64_t j, int32_t *out) {
     }
     if (d.implicit) {
         const uint32_t r = rr_root(d.seed, (uint64_t)j, d.n);
-        if (!d.nhot || d.hot_rank[r] < 0) {
+        if ((!d.nhot || d.hot_rank[r] < 0) && (!d.nar || d.ar_rank[r] < 0)) {
             if (out) out[c] = (int32_t)r;
             c++;
         }
@@ -433,6 +458,11 @@ static DecodeView make_view(Ctx &c) {
     d.seed = s.seed;
     d.n = (uint32_t)c.g.n;
     d.hot_rank = s.nhot ? s.hot_rank.as<int32_t>() : nullptr;
+    d.nar = s.nsets ? s.nar : 0;
+    d.ar_hot = s.ar_hot.as<int32_t>();
+    d.ar_rank = s.ar_rank.as<int32_t>();
+    d.ar_off = s.ar_off.as<int64_t>();
+    d.ar_low = s.ar_low.as<uint16_t>();
     d.bitoff = huff ? s.bitoff.as<int64_t>() : nullptr;
     d.payload = s.payload.as<uint32_t>();
     d.lim = s.cbtab.as<uint64_t>();
@@ -453,6 +483,8 @@ void store_reset(Ctx &c) {
     s.model_ready = false;
     s.members = 0;
     s.nhot = 0;
+    s.nar = 0;
+    s.ar_chunks = s.ar_entries = s.ar_last_start = 0;
     s.bm_words = 0;
     s.raw_count = 0;
     s.nbits = 0;
@@ -471,7 +503,8 @@ void store_free(Ctx &c) {
     Store &s = c.s;
     raw_host_free(c);
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp})
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp, &s.ar_hot, &s.ar_rank,
+                   &s.ar_off, &s.ar_low, &s.ar_tmp, &s.ar_keys, &s.ar_sort})
         buf_free(c, *b);
     Scratch &sc = c.sc;
     for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.t2h_bitmap,
@@ -489,6 +522,7 @@ int64_t store_bytes(const Ctx &c) {
     if (enc_huff(s.enc)) b += (s.nsets + 1) * 8 + (int64_t)((s.nbits + 7) / 8) + (int64_t)(s.nbits / CK_SLOT + 1);
     else if (enc_raw(s.enc)) b += (s.nsets + 1) * 8 + s.raw_count * 4;
     b += s.bm_words * (int64_t)s.nhot * 8;
+    b += s.ar_chunks * (int64_t)(s.nar + 1) * 8 + s.ar_entries * 2;
     return b;
 }
 
@@ -711,18 +745,31 @@ static void build_model(Ctx &c) {
         std::partial_sort(seen.begin(), seen.begin() + keep, seen.end(), [&](size_t a, size_t b) {
             return wcnt[a] != wcnt[b] ? wcnt[a] > wcnt[b] : ids[a] < ids[b];
         });
-        std::vector<uint32_t> hot_ids(std::max<size_t>(keep, 1), 0u);
+        // with containers, a hot vertex below warm-up density 1/16 gets an array row (16 bits
+        // per occurrence beats a bit per set there), the others bitmap rows; hot order is kept
+        std::vector<uint32_t> hot_ids, ar_ids;
         for (size_t r = 0; r < keep; r++) {
-            hot_ids[r] = ids[seen[r]];
+            const bool arr = s.containers && (uint64_t)16 * wcnt[seen[r]] < (uint64_t)s.W;
+            (arr ? ar_ids : hot_ids).push_back(ids[seen[r]]);
             is_hot[seen[r]] = 1;
         }
-        s.nhot = (int32_t)keep;
+        s.nhot = (int32_t)hot_ids.size();
+        s.nar = (int32_t)ar_ids.size();
+        hot_ids.resize(std::max<size_t>(hot_ids.size(), 1), 0u);
         buf_alloc(c, s.hot, hot_ids.size() * 4);
         buf_grow(c, s.hot_rank, (size_t)n * 4, false);
         HBM_HIP(hipMemcpyAsync(s.hot.p, hot_ids.data(), hot_ids.size() * 4, hipMemcpyHostToDevice, st));
         k_fill_i32<<<fill_grid(n), 256, 0, st>>>(s.hot_rank.as<int32_t>(), n, -1);
-        if (keep) k_scatter_rank<<<fill_grid((int64_t)keep), 256, 0, st>>>(s.hot.as<uint32_t>(), (int64_t)keep,
-                                                                        s.hot_rank.as<int32_t>());
+        if (s.nhot) k_scatter_rank<<<fill_grid((int64_t)s.nhot), 256, 0, st>>>(s.hot.as<uint32_t>(), (int64_t)s.nhot,
+                                                                            s.hot_rank.as<int32_t>());
+        if (s.nar) {
+            buf_alloc(c, s.ar_hot, ar_ids.size() * 4);
+            buf_grow(c, s.ar_rank, (size_t)n * 4, false);
+            HBM_HIP(hipMemcpyAsync(s.ar_hot.p, ar_ids.data(), ar_ids.size() * 4, hipMemcpyHostToDevice, st));
+            k_fill_i32<<<fill_grid(n), 256, 0, st>>>(s.ar_rank.as<int32_t>(), n, -1);
+            k_scatter_rank<<<fill_grid((int64_t)s.nar), 256, 0, st>>>(s.ar_hot.as<uint32_t>(), (int64_t)s.nar,
+                                                                      s.ar_rank.as<int32_t>());
+        }
         HBM_HIP(hipGetLastError());
         // the host vector is freed at return: the queued copy must have read it
         HBM_HIP(hipStreamSynchronize(st));
@@ -942,6 +989,194 @@ void raw_host_free(Ctx &c) {
     s.raw_host_cap = 0;
 }
 
+// ------------------------------------------------------------------ array containers
+// A block's sets that fall in chunk ch (block-relative [b0, b1)) add, for every array row, the
+// 16-bit offsets of the sets that hold the row's vertex.  Sets arrive in ascending order, so only
+// the last chunk ever grows: it is rebuilt with each row's old entries followed by the new
+// ones, then every row's list is sorted (the new entries are written in arbitrary order).
+constexpr int AR_CHUNK_BITS = 16;
+struct ArrArgs {
+    BlockView bv;
+    uint64_t b0, b1;             // block-relative sets, all in one chunk
+    int64_t j0;                  // set index of the block's first set
+    int64_t cbase;               // first set of the chunk
+    const int32_t *ar_rank;
+    uint32_t *cnt;               // count pass: new entries per row
+    unsigned long long *cursor;  // write pass: next position per row
+    uint16_t *low;
+};
+
+__global__ __launch_bounds__(256) void k_arr_count(ArrArgs A) {
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+    const unsigned lane = lane_id();
+    for (uint64_t b = A.b0 + wave; b < A.b1; b += nw) {
+        const uint32_t p = A.bv.pos[b], s = A.bv.size[b];
+        for (uint32_t i = lane; i < s; i += WAVE) {
+            const int32_t a = A.ar_rank[A.bv.mem[p + i]];
+            if (a >= 0) atomicAdd(&A.cnt[a], 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_arr_write(ArrArgs A) {
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / WAVE;
+    const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / WAVE;
+    const unsigned lane = lane_id();
+    for (uint64_t b = A.b0 + wave; b < A.b1; b += nw) {
+        const uint32_t p = A.bv.pos[b], s = A.bv.size[b];
+        const uint16_t low = (uint16_t)((uint64_t)A.j0 + b - (uint64_t)A.cbase);
+        for (uint32_t i = lane; i < s; i += WAVE) {
+            const int32_t a = A.ar_rank[A.bv.mem[p + i]];
+            if (a >= 0) A.low[atomicAdd(&A.cursor[a], 1ull)] = low;
+        }
+    }
+}
+
+// per row: total = old + new entries (tot[nar] = 0 closes the scan)
+__global__ void k_arr_tot(const int64_t *old_off, const uint32_t *cnt, uint32_t *tot, int32_t nar) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a <= nar; a += (int64_t)gridDim.x * blockDim.x)
+        tot[a] = a < nar ? cnt[a] + (old_off ? (uint32_t)(old_off[a + 1] - old_off[a]) : 0u) : 0u;
+}
+
+// per row: its old entries (in `keys`, chunk-relative) moved to their new place, the write cursor
+// after them, and the chunk-relative segment start for the sort
+__global__ void k_arr_move(const int64_t *old_off, const int64_t *new_off, int64_t start, const uint16_t *keys,
+                           uint16_t *low, unsigned long long *cursor, uint32_t *rel, int32_t nar) {
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / WAVE;
+    const unsigned lane = lane_id();
+    for (int64_t a = wave; a <= nar; a += nw) {
+        if (lane == 0) rel[a] = (uint32_t)(new_off[a] - start);
+        if (a == nar) continue;
+        const int64_t oc = old_off ? old_off[a + 1] - old_off[a] : 0;
+        for (int64_t i = lane; i < oc; i += WAVE) low[new_off[a] + i] = keys[old_off[a] - start + i];
+        if (lane == 0) cursor[a] = (unsigned long long)(new_off[a] + oc);
+    }
+}
+
+// One chunk's rebuild, planned before any store write: where its entries end and what it needs.
+struct ArrPlan {
+    int64_t ch, b0, b1, start, end;
+    bool existed;
+};
+
+// Layout of ar_tmp: cnt u32[nar + 1] | tot u32[nar + 1] | rel u32[nar + 1] | new_off i64[nar + 1]
+// | cursor u64[nar]
+static size_t ar_tmp_at(int32_t nar, int part) {
+    const size_t u = ((size_t)(nar + 1) * 4 + 255) & ~size_t(255), q = ((size_t)(nar + 1) * 8 + 255) & ~size_t(255);
+    const size_t at[] = {0, u, 2 * u, 3 * u, 3 * u + q, 3 * u + 2 * q};
+    return at[part];
+}
+
+// Counts and offsets of every chunk the block touches, then every allocation the rebuild needs
+// (entries, chunk offsets, scratch, sort space): nothing of the store is written yet.
+static void arr_plan(Ctx &c, int64_t j0, int64_t done, std::vector<ArrPlan> &plans) {
+    Store &s = c.s;
+    plans.clear();
+    if (!s.nar || done <= 0) return;
+    const int32_t nar = s.nar;
+    const hipStream_t st = c.stream;
+    buf_grow(c, s.ar_tmp, ar_tmp_at(nar, 5), false);
+    uint32_t *cnt = (uint32_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 0));
+    uint32_t *tot = (uint32_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 1));
+    int64_t *noff = (int64_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 3));
+    int64_t entries = s.ar_entries, chunks = s.ar_chunks, last_start = s.ar_last_start;
+    const int64_t j1 = j0 + done;
+    for (int64_t ch = j0 >> AR_CHUNK_BITS; ch <= (j1 - 1) >> AR_CHUNK_BITS; ch++) {
+        ArrPlan p;
+        p.ch = ch;
+        p.b0 = std::max<int64_t>(j0, ch << AR_CHUNK_BITS) - j0;
+        p.b1 = std::min<int64_t>(j1, (ch + 1) << AR_CHUNK_BITS) - j0;
+        p.existed = ch < chunks;
+        p.start = p.existed ? last_start : entries;
+        buf_zero(c, s.ar_tmp, ar_tmp_at(nar, 0), (size_t)(nar + 1) * 4);
+        ArrArgs A{};
+        A.bv = block_view(c, done);
+        A.b0 = (uint64_t)p.b0;
+        A.b1 = (uint64_t)p.b1;
+        A.ar_rank = s.ar_rank.as<int32_t>();
+        A.cnt = cnt;
+        k_arr_count<<<grid_for((p.b1 - p.b0) * WAVE, 256, 65536), 256, 0, st>>>(A);
+        const int64_t *old_off = p.existed ? s.ar_off.as<int64_t>() + ch * (int64_t)(nar + 1) : nullptr;
+        k_arr_tot<<<grid_for(nar + 1, 256, 1024), 256, 0, st>>>(old_off, cnt, tot, nar);
+        HBM_HIP(hipGetLastError());
+        scan_u32_to_i64(c, tot, noff, nar + 1, p.start);
+        HBM_HIP(hipMemcpyAsync(&p.end, noff + nar, 8, hipMemcpyDeviceToHost, st));
+        HBM_HIP(hipStreamSynchronize(st));
+        plans.push_back(p);
+        entries = p.end;
+        last_start = p.start;
+        chunks = ch + 1;
+    }
+    // every allocation of the rebuild
+    int64_t span = 0;
+    for (const ArrPlan &p : plans) span = std::max(span, p.end - p.start);
+    buf_grow(c, s.ar_low, (size_t)std::max<int64_t>(entries, 1) * 2 + 64, true);
+    buf_grow(c, s.ar_off, (size_t)chunks * (size_t)(nar + 1) * 8, true);
+    buf_grow(c, s.ar_keys, (size_t)std::max<int64_t>(span, 1) * 2 + 64, false);
+    size_t sort_bytes = 0;
+    HBM_HIP(rocprim::segmented_radix_sort_keys(nullptr, sort_bytes, (const uint16_t *)nullptr, (uint16_t *)nullptr,
+                                               (unsigned int)std::max<int64_t>(span, 1), (unsigned int)nar,
+                                               (const uint32_t *)nullptr, (const uint32_t *)nullptr, 0, 16, st));
+    buf_grow(c, s.ar_sort, std::max<size_t>(sort_bytes, 256), false);
+}
+
+// The rebuild of each planned chunk (no allocation): old entries moved behind their new offsets,
+// new entries written, every row's list sorted, offsets stored.
+static void arr_write(Ctx &c, int64_t j0, int64_t done, const std::vector<ArrPlan> &plans) {
+    Store &s = c.s;
+    const int32_t nar = s.nar;
+    const hipStream_t st = c.stream;
+    uint32_t *cnt = (uint32_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 0));
+    uint32_t *tot = (uint32_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 1));
+    uint32_t *rel = (uint32_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 2));
+    int64_t *noff = (int64_t *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 3));
+    unsigned long long *cursor = (unsigned long long *)(s.ar_tmp.as<char>() + ar_tmp_at(nar, 4));
+    uint16_t *low = s.ar_low.as<uint16_t>();
+    for (const ArrPlan &p : plans) {
+        // offsets again (the plan's scratch was reused chunk by chunk)
+        int64_t *old_off = p.existed ? s.ar_off.as<int64_t>() + p.ch * (int64_t)(nar + 1) : nullptr;
+        buf_zero(c, s.ar_tmp, ar_tmp_at(nar, 0), (size_t)(nar + 1) * 4);
+        ArrArgs A{};
+        A.bv = block_view(c, done);
+        A.b0 = (uint64_t)p.b0;
+        A.b1 = (uint64_t)p.b1;
+        A.j0 = j0;
+        A.cbase = p.ch << AR_CHUNK_BITS;
+        A.ar_rank = s.ar_rank.as<int32_t>();
+        A.cnt = cnt;
+        const unsigned g = grid_for((p.b1 - p.b0) * WAVE, 256, 65536);
+        k_arr_count<<<g, 256, 0, st>>>(A);
+        k_arr_tot<<<grid_for(nar + 1, 256, 1024), 256, 0, st>>>(old_off, cnt, tot, nar);
+        HBM_HIP(hipGetLastError());
+        scan_u32_to_i64(c, tot, noff, nar + 1, p.start);
+        const int64_t old_end = p.existed ? s.ar_entries : p.start;
+        if (old_end > p.start)
+            HBM_HIP(hipMemcpyAsync(s.ar_keys.p, low + p.start, (size_t)(old_end - p.start) * 2,
+                                   hipMemcpyDeviceToDevice, st));
+        k_arr_move<<<grid_for((int64_t)(nar + 1) * WAVE, 256, 4096), 256, 0, st>>>(
+            old_off, noff, p.start, s.ar_keys.as<uint16_t>(), low, cursor, rel, nar);
+        A.cursor = cursor;
+        A.low = low;
+        k_arr_write<<<g, 256, 0, st>>>(A);
+        HBM_HIP(hipGetLastError());
+        const int64_t sz = p.end - p.start;
+        if (sz > 0) {
+            size_t sort_bytes = s.ar_sort.bytes;
+            HBM_HIP(rocprim::segmented_radix_sort_keys(s.ar_sort.p, sort_bytes, low + p.start,
+                                                       s.ar_keys.as<uint16_t>(), (unsigned int)sz, (unsigned int)nar,
+                                                       rel, rel + 1, 0, 16, st));
+            HBM_HIP(hipMemcpyAsync(low + p.start, s.ar_keys.p, (size_t)sz * 2, hipMemcpyDeviceToDevice, st));
+        }
+        HBM_HIP(hipMemcpyAsync(s.ar_off.as<int64_t>() + p.ch * (int64_t)(nar + 1), noff, (size_t)(nar + 1) * 8,
+                               hipMemcpyDeviceToDevice, st));
+        s.ar_entries = p.end;
+        s.ar_last_start = p.start;
+        s.ar_chunks = p.ch + 1;
+    }
+}
+
 // Append sets [j0[i], j0[i] + done[i]) of every job from its scratch arena to its store
 // (the job's encoding, then UpdateHistogram), one grouped launch per step.  Every allocation
 // comes before the first write into the store and the histogram is updated last, so a failed
@@ -949,6 +1184,9 @@ void raw_host_free(Ctx &c) {
 static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64_t> &j0,
                           const std::vector<int64_t> &done) {
     const size_t N = J.size();
+    // array rows: counts, offsets and every allocation before the first store write
+    std::vector<std::vector<ArrPlan>> arr(N);
+    for (size_t i = 0; i < N; i++) arr_plan(*J[i], j0[i], done[i], arr[i]);
     // plain-id jobs, Huffman jobs and all-vertex bitmap jobs
     std::vector<size_t> P, H, B;
     for (size_t i = 0; i < N; i++) {
@@ -1001,6 +1239,7 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             a.implicit = s.implicit_roots;
             a.seed = s.seed;
             a.n = (uint32_t)c.g.n;
+            a.ar_rank = s.nar ? s.ar_rank.as<int32_t>() : nullptr;
             sa.push_back(a);
             sb.push_back(grid_for(done[i] * WAVE, 256, 65536));
         }
@@ -1045,7 +1284,8 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             HuffArgs a{};
             a.bv = block_view(c, done[i]);
             a.h = HuffEnc{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
-                          s.cb.ustar_enc, s.cb.wbits, s.implicit_roots, s.seed, j0[i], (uint32_t)c.g.n};
+                          s.cb.ustar_enc, s.cb.wbits, s.implicit_roots, s.seed, j0[i], (uint32_t)c.g.n,
+                          s.nar ? s.ar_rank.as<int32_t>() : nullptr};
             a.bits = c.sc.aux.as<uint64_t>();
             a.meta = c.sc.cnt.as<uint32_t>();
             a.bitoff = s.bitoff.as<int64_t>() + j0[i];
@@ -1102,6 +1342,12 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
         HBM_HIP(hipStreamSynchronize(root.stream));
         for (size_t i : H) J[i]->s.escapes += (int64_t)esc[i * CW_COUNT + CW_SUM];
     }
+    for (size_t i = 0; i < N; i++)
+        if (!arr[i].empty()) {
+            const int ps = prof_begin(root, "arr_rows");
+            arr_write(*J[i], j0[i], done[i], arr[i]);
+            prof_end(root, ps);
+        }
     std::vector<HistArgs> ha;
     std::vector<uint32_t> hb;
     for (size_t i = 0; i < N; i++) {
@@ -1324,6 +1570,10 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     o->store_bytes = store_bytes(c);
     o->skewness = s.skew;
     o->density = s.density;
+    o->narray = s.nar;
+    o->array_entries = s.ar_entries;
+    o->array_bytes = s.ar_chunks * (int64_t)(s.nar + 1) * 8 + s.ar_entries * 2;
+    if (s.nar) o->codebook_bytes += (int64_t)s.nar * 4;
     // total members = sum of the histogram (reduced on the device; 8 bytes come back)
     if (s.hist.p && s.nsets) {
         buf_grow(c, s.mtmp, 8, true);
