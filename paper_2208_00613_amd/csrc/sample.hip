@@ -737,12 +737,9 @@ __device__ void big_lds_body(const T2LArgs &t) {
             hs = (hs + 1) & (T2L_HASH - 1);
         }
     };
-    // Philox call for group g of the member with range [E0, E1), group offset gs and threshold
-    // T (WC), and the live in-edges among its four slots
-    auto expand_group = [&](uint32_t jlo, uint32_t jhi, uint32_t g, uint32_t gs, uint32_t E0, uint32_t E1,
-                            uint32_t T, uint32_t &nl) {
-        const uint32_t grp = (E0 >> 2) + (g - gs);
-        const uint4 y = philox10(jlo, jhi, grp, 1u, k0, k1);
+    // the live in-edges among the four slots of Philox group grp (words y) of a member with
+    // in-edge range [E0, E1) and threshold T (WC)
+    auto live_of = [&](uint32_t grp, const uint4 &y, uint32_t E0, uint32_t E1, uint32_t T, uint32_t &nl) {
         const uint4 t4 = a.wc ? make_uint4(T, T, T, T) : *reinterpret_cast<const uint4 *>(a.thr + (size_t)grp * 4);
         const uint32_t eb = grp * 4;
 #pragma unroll
@@ -754,6 +751,45 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 if (p < LIVE_CAP) live[p] = e;
                 else insert_edge(e);  // the list is full: insert at once
             }
+        }
+    };
+    // Groups [g, gend) of a level (or batch), one contiguous range per thread: the member of a
+    // group is found once by binary search (mem_of), then by stepping forward (next_member), and
+    // two groups' Philox calls are issued together so that each thread keeps two independent
+    // chains of multiplies in flight.  mem_of(g) -> (member index); member(i, E0, E1, T, first
+    // group) reads a member's range, threshold and first group; mend(i) is its groups' end.
+    auto expand_range = [&](uint32_t jlo, uint32_t jhi, uint32_t g, uint32_t gend, uint32_t i, auto member,
+                            auto mend, uint32_t &nl) {
+        uint32_t E0, E1, T, gs;
+        member(i, E0, E1, T, gs);
+        uint32_t ie = mend(i);
+        for (; g + 1 < gend; g += 2) {
+            while (ie <= g) {
+                ++i;
+                member(i, E0, E1, T, gs);
+                ie = mend(i);
+            }
+            const uint32_t ga = (E0 >> 2) + (g - gs);
+            const uint32_t Ea0 = E0, Ea1 = E1, Ta = T;
+            while (ie <= g + 1) {
+                ++i;
+                member(i, E0, E1, T, gs);
+                ie = mend(i);
+            }
+            const uint32_t gb2 = (E0 >> 2) + (g + 1 - gs);
+            const uint4 ya = philox10(jlo, jhi, ga, 1u, k0, k1);
+            const uint4 yb = philox10(jlo, jhi, gb2, 1u, k0, k1);
+            live_of(ga, ya, Ea0, Ea1, Ta, nl);
+            live_of(gb2, yb, E0, E1, T, nl);
+        }
+        if (g < gend) {
+            while (ie <= g) {
+                ++i;
+                member(i, E0, E1, T, gs);
+                ie = mend(i);
+            }
+            const uint32_t ga = (E0 >> 2) + (g - gs);
+            live_of(ga, philox10(jlo, jhi, ga, 1u, k0, k1), E0, E1, T, nl);
         }
     };
     __syncthreads();
@@ -802,14 +838,21 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     for (uint32_t x = head + threadIdx.x; x < tail; x += NT)
                         atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(qe1[x] - qe0[x]));
                 }
-                uint32_t i = head;
-                uint32_t iend = head + 1 < tail ? qg[head + 1] : ge;  // member i's groups end
-                for (uint32_t g = gb + threadIdx.x; g < ge; g += NT) {
-                    if (iend <= g) {
-                        i = upper_bound_dev<uint32_t, uint32_t>(qg, i + 1, tail, g) - 1;
-                        iend = i + 1 < tail ? qg[i + 1] : ge;
-                    }
-                    expand_group(jlo, jhi, g, qg[i], qe0[i], qe1[i], qt[i], nlive[lev]);
+                // thread t takes groups [gb + t per, + per)
+                const uint32_t per = (ge - gb + NT - 1) / NT;
+                const uint32_t g0 = gb + threadIdx.x * per;
+                const uint32_t g1 = g0 + per < ge ? g0 + per : ge;
+                if (g0 < g1) {
+                    const uint32_t i0 = upper_bound_dev<uint32_t, uint32_t>(qg, head + 1, tail, g0) - 1;
+                    expand_range(
+                        jlo, jhi, g0, g1, i0,
+                        [&](uint32_t i, uint32_t &E0, uint32_t &E1, uint32_t &T, uint32_t &gs) {
+                            E0 = qe0[i];
+                            E1 = qe1[i];
+                            T = qt[i];
+                            gs = qg[i];
+                        },
+                        [&](uint32_t i) { return i + 1 < tail ? qg[i + 1] : ge; }, nlive[lev]);
                 }
                 __syncthreads();
                 const uint32_t nl = nlive[lev] < LIVE_CAP ? nlive[lev] : LIVE_CAP;
@@ -846,10 +889,21 @@ __device__ void big_lds_body(const T2LArgs &t) {
                         }
                         if (e1 > e0) atomicAdd(&s_ctr[DC_EDGES], (unsigned long long)(e1 - e0));
                     }
-                    uint32_t i = 0;  // vertex of this thread's group: searched only when g leaves it
-                    for (uint32_t g = threadIdx.x; g < G; g += NT) {
-                        if (sP[i] <= g) i = upper_bound_dev<uint32_t, uint32_t>(sP, i + 1, cn, g);
-                        expand_group(jlo, jhi, g, i ? sP[i - 1] : 0u, sE0[i], sE1[i], sT[i], nlive[0]);
+                    // thread t takes groups [t per, + per)
+                    const uint32_t per = (G + NT - 1) / NT;
+                    const uint32_t g0 = threadIdx.x * per;
+                    const uint32_t g1 = g0 + per < G ? g0 + per : G;
+                    if (g0 < g1) {
+                        const uint32_t i0 = upper_bound_dev<uint32_t, uint32_t>(sP, 0, cn, g0);
+                        expand_range(
+                            jlo, jhi, g0, g1, i0,
+                            [&](uint32_t i, uint32_t &E0, uint32_t &E1, uint32_t &T, uint32_t &gs) {
+                                E0 = sE0[i];
+                                E1 = sE1[i];
+                                T = sT[i];
+                                gs = i ? sP[i - 1] : 0u;
+                            },
+                            [&](uint32_t i) { return sP[i]; }, nlive[0]);
                     }
                     __syncthreads();
                     const uint32_t nl = nlive[0] < LIVE_CAP ? nlive[0] : LIVE_CAP;

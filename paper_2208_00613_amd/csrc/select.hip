@@ -82,7 +82,7 @@ struct SelArgs {
     const int64_t *ar_off;
     const uint16_t *ar_low;
     int64_t nchunks;
-    int32_t arx;                  // k_dec_arr blocks per chunk (DA_ROWS rows each)
+    int64_t nentries;             // array entries over all chunks
 };
 
 __device__ __forceinline__ bool in_arr(const SelArgs &A, uint32_t v) { return A.nar && A.ar_rank[v] >= 0; }
@@ -733,41 +733,36 @@ HBM_KERNEL(k_dec_hot, SelArgs, 256) {
     if (acc) atomicSub(&A.counts[ckey(A, (uint32_t)A.hot[h])], acc);
 }
 
-// array-row counts -= the row's entries whose set is newly covered: work item b takes chunk
-// b / arx and rows [DA_ROWS (b mod arx), +DA_ROWS) of it, one wave per row, with the chunk's
-// 1024 `newly` words in LDS (a chunk with none newly covered is left at once)
-constexpr int DA_ROWS = 256;
+// array-row counts -= the row's entries whose set is newly covered: one coalesced pass over every
+// chunk's entries, a thread per entry; an entry whose set is newly covered finds its row by a
+// binary search of the chunk's offsets and decrements it through the block's combining cache
+// (most entries are not newly covered, so most threads only read their entry and one word)
 HBM_KERNEL(k_dec_arr, SelArgs, 256) {
     (void)x;
-    __shared__ unsigned long long nl[1024];
-    const unsigned lane = lane_id();
-    const int64_t items = A.nchunks * (int64_t)A.arx;
-    for (int64_t b = bid; b < items; b += nblk) {
-        const int64_t ch = b / A.arx;
-        const int32_t r0 = (int32_t)(b % A.arx) * DA_ROWS;
-        const int64_t w0 = ch * 1024;
-        const int64_t nwc = A.words - w0 < 1024 ? A.words - w0 : 1024;
-        int mine = 0;
-        for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
-            const unsigned long long v = i < nwc ? A.newly[w0 + i] : 0ull;
-            nl[i] = v;
-            mine |= v != 0ull;
-        }
-        if (!__syncthreads_or(mine)) continue;
+    __shared__ DecCache C;
+    cache_init(C);
+    __syncthreads();
+    const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nthr = (int64_t)nblk * blockDim.x;
+    for (int64_t ch = 0; ch < A.nchunks; ch++) {
         const int64_t *o = A.ar_off + ch * (int64_t)(A.nar + 1);
-        const int32_t r1 = r0 + DA_ROWS < A.nar ? r0 + DA_ROWS : A.nar;
-        for (int32_t a = r0 + (int32_t)(threadIdx.x / WAVE); a < r1; a += (int32_t)(blockDim.x / WAVE)) {
-            uint32_t c = 0;
-            const int64_t e = o[a + 1];
-            for (int64_t i = o[a] + lane; i < e; i += WAVE) {
-                const uint32_t low = A.ar_low[i];
-                c += (uint32_t)(nl[low >> 6] >> (low & 63)) & 1u;
+        const int64_t e0 = o[0], e1 = o[A.nar];
+        const unsigned long long *nw = A.newly + (ch << 10);
+        for (int64_t i = e0 + tid; i < e1; i += nthr) {
+            const uint32_t low = A.ar_low[i];
+            if (!((nw[low >> 6] >> (low & 63)) & 1ull)) continue;
+            // row: the last a with o[a] <= i
+            int32_t lo = 0, hi = A.nar - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (o[mid] <= i) lo = mid;
+                else hi = mid - 1;
             }
-            c = wave_sum(c);
-            if (lane == 0 && c) atomicSub(&A.counts[ckey(A, (uint32_t)A.ar_hot[a])], c);
+            cache_dec(C, A, ckey(A, (uint32_t)A.ar_hot[lo]));
         }
-        __syncthreads();  // nl is rewritten for the next item
     }
+    __syncthreads();
+    cache_flush(C, A);
 }
 
 void select_free(Ctx &c) {
@@ -986,7 +981,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.ar_off = s.ar_off.as<int64_t>();
     A.ar_low = s.ar_low.as<uint16_t>();
     A.nchunks = s.ar_chunks;
-    A.arx = (int32_t)std::max<int64_t>(((int64_t)s.nar + DA_ROWS - 1) / DA_ROWS, 1);
+    A.nentries = s.ar_entries;
     A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
     A.seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
@@ -1000,7 +995,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     // hot counts: segments past the words in use find no word to read
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * (gfix ? std::max<int64_t>(1, 4096 / A.hx) : nseg)) : 0;
     J.g_arr = A.nar ? (gfix ? (uint32_t)root.num_cus * 4
-                            : grid_for(A.nchunks * A.arx, 1, (int64_t)root.num_cus * 16)) : 0;
+                            : grid_for(std::max<int64_t>(A.nentries, 1), 256, (int64_t)root.num_cus * 8)) : 0;
     J.g_big = A.big ? (gfix ? (uint32_t)root.num_cus * 3 : grid_for(T, 256, (int64_t)root.num_cus * 3)) : 0;  // idle blocks leave at once
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply

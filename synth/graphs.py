@@ -294,13 +294,18 @@ C5 = dict(n=41_700_000, avg_deg=1_468_365_182 / 41_652_230, gamma=2.2, max_deg=7
           budget=200 * 10 ** 9)
 
 
+QUERY_POOL = 4096
+
+
 def serving_queries(count: int, seed: int = 5, rate: float = 1.0):
     """Poisson arrivals (mean gap 1/rate seconds) of IMM queries: k ~ U{10..200}, eps in
-    {.5, .2}, l = 1, sampling seed 1000 + q."""
+    {.5, .2}, l = 1, sampling seed 1000 + q.  Query q is the same for every count (up to
+    QUERY_POOL queries are drawn, then cut) and every rate (the gaps scale with 1/rate)."""
+    N = max(count, QUERY_POOL)
     rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, size=count)
-    ks = rng.integers(10, 201, size=count)
-    eps = rng.choice(np.array([0.5, 0.2]), size=count)
+    gaps = rng.exponential(1.0 / rate, size=N)[:count]
+    ks = rng.integers(10, 201, size=N)
+    eps = rng.choice(np.array([0.5, 0.2]), size=N)
     t = np.cumsum(gaps) - gaps[0]
     return [dict(q=q, t=float(t[q]), k=int(ks[q]), eps=float(eps[q]), l=1.0, seed=1000 + q) for q in range(count)]
 

@@ -39,6 +39,11 @@ def test_serving_queries():
     t = np.array([q["t"] for q in qs])
     assert (np.diff(t) >= 0).all() and 15 < t[-1] < 50
     assert all(10 <= q["k"] <= 200 and q["eps"] in (0.5, 0.2) for q in qs)
+    # a query does not depend on how many are drawn or on the rate, apart from its arrival
+    for other in (G.serving_queries(5, seed=5, rate=2.0), G.serving_queries(100, seed=5, rate=0.5)):
+        for a, b in zip(qs, other):
+            assert (a["k"], a["eps"], a["seed"]) == (b["k"], b["eps"], b["seed"])
+    assert [q["t"] * 4 for q in qs[:20]] == [q["t"] for q in G.serving_queries(20, seed=5, rate=0.5)]
 
 
 def test_batched_instances():
