@@ -70,7 +70,7 @@ PHILOX_SLOTS = 60.0
 PHILOX_PEAK_G = CUS * SIMDS * LANES * CLOCK_GHZ / PHILOX_SLOTS  # G calls/s
 SAMPLER_KERNELS = ("ic_sample_wave", "ic_sample_block", "ic_sample_block_xl", "ic_sample_bitmap", "lt_sample_lane",
                    "lt_sample_wave", "lt_sample_block", "sample_huge")
-SELECT_KERNELS = ("argmax", "find_raw", "find_huff", "apply", "dec_big", "dec_hot")
+SELECT_KERNELS = ("argmax", "find_raw", "find_huff", "apply", "dec_hot", "dec_arr")
 HOST_THREADS_CAP = 16  # the GPU machine's CPU share per GPU
 
 
@@ -140,7 +140,7 @@ PROFILE_KERNELS = {
     "sample_huge": r"k_big(_g)?\b",
 }
 for _k in ("hist_add", "cold_count", "split", "huff_bits", "huff_write", "argmax", "find_raw", "find_huff", "apply",
-           "dec_big", "dec_hot"):
+           "dec_hot", "dec_arr"):
     PROFILE_KERNELS[_k] = r"k_" + _k + r"(_g)?\b"
 COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
 

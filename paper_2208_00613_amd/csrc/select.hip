@@ -66,14 +66,12 @@ struct SelArgs {
     int32_t hx;                   // hot-count blocks per word segment
     int64_t seg;                  // words per hot-count segment
     const uint8_t *ckb;           // code-boundary slots of the payload
-    uint32_t *big;                // [0] sets queued, [1] sets taken, [2..] newly covered long strings
     // sparse counts (large graphs): only vertices with a nonzero store frequency get a slot, in
     // ascending id order, and `counts` holds the slots' counts
     const uint32_t *cand;         // slot -> vertex (null: dense, counts[v])
     const int32_t *cpos;          // vertex -> slot (read for vertices that have one only)
     uint32_t *csel;               // selection bits over slots
     const int64_t *ncand;         // number of slots (device)
-    unsigned long long *pbits;    // profiling: payload bits decoded by k_dec_big (else null)
     // array rows (hot vertices of low density): per 2^16-set chunk, each row's sorted 16-bit set
     // offsets; ar_off is chunk-major with nar + 1 entries per chunk
     int32_t nar;
@@ -200,7 +198,6 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     const int64_t tid = bid * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nthr = (int64_t)nblk * blockDim.x;
     for (int64_t w = tid; w < A.words; w += nthr) A.newly[w] = 0ull;
-    if (A.big && tid < 2) A.big[tid] = 0u;
     unsigned long long best = A.cpos ? argmax_sparse(A, tid, nthr) : 0ull;
     const int64_t n4 = A.cpos ? 0 : A.n >> 2;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
@@ -392,12 +389,6 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, co
     while (pos < end) cache_dec(C, A, dec_code(A, tb, buf, pos));
 }
 
-// A newly covered set whose string is long: its members are decremented by k_dec_big.
-__device__ __forceinline__ void queue_big(const SelArgs &A, int64_t j) {
-    const uint32_t q = atomicAdd(&A.big[0], 1u);
-    A.big[2 + q] = (uint32_t)j;
-}
-
 __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
     (void)t;
     key = argmax_key(A);
@@ -469,18 +460,76 @@ __device__ __forceinline__ void stage_words(uint32_t *dst, const uint32_t *src, 
     }
 }
 
+// The members of one string [pos, ce) of set js, decremented by the whole wave (js, pos, ce
+// wave-uniform): the escaped ids have fixed width, so each lane takes every 64th; the coded
+// part is cut at the code-boundary slots (one per CK_SLOT bits) and NI lanes decode NI slot
+// intervals at a time from an LDS copy of their bits (`stage`: NI * CK_SLOT / 32 + 4 words).
+template <int NI>
+__device__ void wave_dec_string(const SelArgs &A, const Tabs &tb, DecCache &C, uint32_t *stage, int64_t js,
+                                uint64_t pos, const uint64_t ce) {
+    const unsigned lane = lane_id();
+    const uint32_t W = (uint32_t)A.wbits;
+    if (A.implicit && lane == 0) {  // the set's root, left out of its string
+        const uint32_t r = lost_root(A, js);
+        if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
+    }
+    // gamma(nesc + 1) from one three-word window (the code has 2L + 1 <= 63 bits)
+    uint32_t nesc;
+    {
+        const uint64_t w = pos >> 5;
+        const uint32_t sh = (uint32_t)(pos & 31);
+        const uint64_t hi = ((uint64_t)A.payload[w] << 32) | A.payload[w + 1];
+        const uint64_t win = sh ? (hi << sh) | (A.payload[w + 2] >> (32 - sh)) : hi;
+        const uint32_t L = __clzll((long long)win);
+        nesc = (uint32_t)(win >> (63 - 2 * L)) - 1;
+        pos += 2 * (uint64_t)L + 1;
+    }
+    for (uint32_t q = lane; q < nesc; q += WAVE)
+        cache_dec(C, A, ckey(A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W)));
+    const uint64_t cs = pos + (uint64_t)nesc * W;
+    // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
+    const uint64_t m0 = cs / CK_SLOT + 1;
+    const uint64_t m1 = ce > 0 ? (ce - 1) / CK_SLOT : 0;
+    const uint64_t nseg = m1 >= m0 ? m1 - m0 + 2 : 1;
+    auto seg_start = [&](uint64_t sg) -> uint64_t {
+        if (sg == 0) return cs;
+        if (sg >= nseg) return ce;
+        const uint64_t b = (m0 + sg - 1) * CK_SLOT + A.ckb[m0 + sg - 1];
+        return b < ce ? b : ce;
+    };
+    for (uint64_t g0 = 0; g0 < nseg; g0 += NI) {
+        const uint64_t sg = g0 + (lane < (unsigned)NI ? lane : 0u);
+        const uint64_t p = seg_start(sg), e = seg_start(sg + 1);
+        // bits of the group's intervals: [start of g0, end of the group's last interval)
+        const uint64_t lo = __shfl((unsigned long long)p, 0, WAVE);
+        const uint64_t gl = g0 + NI < nseg ? g0 + NI : nseg;
+        const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
+        const uint64_t wlo = lo >> 5;
+        const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
+        stage_words(stage, A.payload + wlo, nw);
+        wave_sync();
+        if (lane < (unsigned)NI && sg < nseg) {
+            uint64_t pp = p - wlo * 32;
+            const uint64_t ee = e - wlo * 32;
+            while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage, pp));
+        }
+        wave_sync();
+    }
+}
+
 // Huffman strings (Alg. 2's DecodeFind), one wave per 64-set word and one lane per set:
 // a partial decode that stops at u* (a codeless u* is sought among the escaped ids, which
 // come first and ascending; a coded u* is matched by its canonical code and the scan ends
 // at the first larger code).  A set holding u* is marked covered; its members are
-// decremented at once by the lane when its string is short and staged, else the string is
-// queued for k_dec_big, which spreads it over a wave.  The word's strings are contiguous:
+// decremented at once by the lane when its string is short and staged, else, after the
+// word's search, by the whole wave (wave_dec_string, 32 slot intervals at a time).  The word's strings are contiguous:
 // they are copied to LDS with coalesced loads first (when they fit).  Each wave loads the
 // next word's covered mask and bit offsets before decoding the current one, and the grid is
 // sized to stay resident.  The search is bound by decode latency, so residency matters more
 // than staging: with a stage of 256 words a block needs about 21 KB of LDS and seven blocks
 // (the register limit) fit a CU.
-constexpr int STAGE_WORDS = 256;
+constexpr int FH_NI = 32;                                  // slot intervals per pass of a long string
+constexpr int STAGE_WORDS = (FH_NI * CK_SLOT) / 32 + 4;    // 260: also holds FH_NI intervals
 
 HBM_KERNEL(k_find_huff, SelArgs, 256) {
     __shared__ Tabs tb;
@@ -552,28 +601,39 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
             A.newly[w] = nwm;
             A.covered[w] = cov | nwm;
         }
-        if (found) {
-            // a long string, or any string not staged in LDS (decoding it from device memory
-            // would be one dependent load per code in this lane): a whole wave decrements it
-            // later from an LDS copy
-            if (!staged || p1 - p0 > (uint64_t)BIG_BITS) queue_big(A, j0 + lane);
-            else {
-                huff_decrement(A, tb, C, buf, p0, p1);
-                if (lroot != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, lroot));
-            }
+        // a long string, or any string not staged in LDS (decoding it from device memory
+        // would be one dependent load per code in this lane): the whole wave decrements it
+        // below, from LDS copies of its slot intervals
+        const bool wide = found && (!staged || p1 - p0 > (uint64_t)BIG_BITS);
+        if (found && !wide) {
+            huff_decrement(A, tb, C, buf, p0, p1);
+            if (lroot != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, lroot));
         }
-        wave_sync();
+        unsigned long long wm = __ballot(wide);
+        wave_sync();  // the word's staged strings are no longer read
+        while (wm) {
+            const int b = __ffsll((long long)wm) - 1;
+            wm &= wm - 1;
+            const uint64_t ps = (uint64_t)__shfl((unsigned long long)bo, b, WAVE);
+            const uint64_t pe = (uint64_t)__shfl((unsigned long long)bnext, b, WAVE);
+            wave_dec_string<FH_NI>(A, tb, C, stage[wv], j0 + b, ps, pe);
+        }
     }
     __syncthreads();
     cache_flush(C, A);
 }
 
-// Records u* (bit 0 of block 0) and, when u* is hot or the store is plain, marks the newly
-// covered sets of every word and decrements their members: plain ids here, Huffman strings
-// queued for k_dec_big (a cold u* of a Huffman store was handled by k_find_huff).
+// Records u* (bit 0 of block 0) and, when u* has a row (bitmap or array) or the store is
+// plain, marks the newly covered sets of every word and decrements their members: plain ids
+// by the lanes, Huffman strings one at a time by the whole wave (wave_dec_string, 64 slot
+// intervals at a time); a cold u* of a Huffman store was handled by k_find_huff.
+constexpr int AP_NI = WAVE;
+constexpr int AP_STAGE = (AP_NI * CK_SLOT) / 32 + 4;
 HBM_KERNEL(k_apply, SelArgs, 256) {
     const int t = x;
     __shared__ DecCache C;
+    __shared__ Tabs tb;
+    __shared__ uint32_t stage[256 / WAVE][AP_STAGE];
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
@@ -588,6 +648,7 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
     // a cold u*: the Huffman find step already covered and decremented
     if (r < 0 && A.huff && !in_arr(A, u)) return;
+    if (A.huff) load_tabs(A, tb);
     cache_init(C);
     __syncthreads();
     const unsigned lane = lane_id();
@@ -601,9 +662,21 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
         }
         if (!nw) continue;
         if (A.huff) {
-            // the strings are in device memory: every one goes to k_dec_big, which decodes it
-            // from an LDS copy with the whole wave
-            if ((nw >> lane) & 1ull) queue_big(A, w * 64 + lane);
+            // the word's newly covered strings, one at a time by the whole wave
+            const int64_t j0 = w * 64;
+            const int64_t jl = j0 + lane < A.T ? j0 + lane : A.T;
+            const uint64_t bo = (uint64_t)A.bitoff[jl];
+            const uint64_t be = (uint64_t)A.bitoff[(j0 + 64 < A.T ? j0 + 64 : A.T)];
+            uint64_t bnext = (uint64_t)__shfl_down((unsigned long long)bo, 1, WAVE);
+            if (lane == WAVE - 1 || j0 + lane + 1 >= A.T) bnext = be;
+            unsigned long long rest = nw;
+            while (rest) {
+                const int b = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const uint64_t ps = (uint64_t)__shfl((unsigned long long)bo, b, WAVE);
+                const uint64_t pe = (uint64_t)__shfl((unsigned long long)bnext, b, WAVE);
+                wave_dec_string<AP_NI>(A, tb, C, stage[threadIdx.x / WAVE], j0 + b, ps, pe);
+            }
         } else if (A.raw_off) {
             unsigned long long rest = nw;
             while (rest) {
@@ -617,99 +690,6 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
                     const uint32_t r = lost_root(A, j);
                     if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
                 }
-            }
-        }
-    }
-    __syncthreads();
-    cache_flush(C, A);
-}
-
-// Members of the queued long strings, one wave per string: the escaped ids have fixed width,
-// so each lane takes every 64th; the coded part is cut at the code-boundary slots (one per
-// CK_SLOT bits) and the lanes decode 64 slot intervals at a time from an LDS copy of their
-// bits (one interval per lane).
-constexpr int DB_STAGE = (WAVE * CK_SLOT) / 32 + 4;  // words of 64 intervals, +look-ahead
-
-HBM_KERNEL(k_dec_big, SelArgs, 256) {
-    (void)x;
-    // blocks past the queue have nothing to take: leave before any set-up
-    if ((uint64_t)bid * (blockDim.x / WAVE) >= (uint64_t)A.big[0]) return;
-    __shared__ Tabs tb;
-    __shared__ DecCache C;
-    __shared__ uint32_t stage[256 / WAVE][DB_STAGE];
-    load_tabs(A, tb);
-    cache_init(C);
-    __syncthreads();
-    const unsigned lane = lane_id();
-    const int wv = threadIdx.x / WAVE;
-    const uint32_t W = (uint32_t)A.wbits;
-    const uint32_t nq = A.big[0];
-    // queue entries are dealt to the waves in turn (entry e to wave e mod nwaves); a wave loads
-    // the set ids and bit offsets of up to 64 of its entries at once, then decodes them in turn
-    const uint64_t nwaves = (uint64_t)nblk * (blockDim.x / WAVE);
-    const uint64_t gw = (uint64_t)bid * (blockDim.x / WAVE) + (uint64_t)wv;
-    for (uint64_t r0 = gw; r0 < nq; r0 += nwaves * WAVE) {
-        const uint64_t myit = r0 + (uint64_t)lane * nwaves;
-        int64_t jm = 0;
-        uint64_t b0 = 0, b1 = 0;
-        if (myit < nq) {
-            jm = (int64_t)A.big[2 + myit];
-            b0 = (uint64_t)A.bitoff[jm];
-            b1 = (uint64_t)A.bitoff[jm + 1];
-        }
-        unsigned long long have = __ballot(myit < nq);
-        while (have) {
-            const int src = __ffsll((long long)have) - 1;
-            have &= have - 1;
-            uint64_t pos = (uint64_t)__shfl((unsigned long long)b0, src, WAVE);
-            const uint64_t ce = (uint64_t)__shfl((unsigned long long)b1, src, WAVE);
-            const int64_t js = (int64_t)__shfl((unsigned long long)jm, src, WAVE);  // the string's set
-            if (A.implicit && lane == 0) {  // the set's root, left out of its string
-                const uint32_t r = lost_root(A, js);
-                if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
-            }
-            if (A.pbits && lane == 0) atomicAdd(A.pbits, (unsigned long long)(ce - pos));
-            // gamma(nesc + 1) from one three-word window (the code has 2L + 1 <= 63 bits)
-            uint32_t nesc;
-            {
-                const uint64_t w = pos >> 5;
-                const uint32_t sh = (uint32_t)(pos & 31);
-                const uint64_t hi = ((uint64_t)A.payload[w] << 32) | A.payload[w + 1];
-                const uint64_t win = sh ? (hi << sh) | (A.payload[w + 2] >> (32 - sh)) : hi;
-                const uint32_t L = __clzll((long long)win);
-                nesc = (uint32_t)(win >> (63 - 2 * L)) - 1;
-                pos += 2 * (uint64_t)L + 1;
-            }
-            for (uint32_t q = lane; q < nesc; q += WAVE)
-                cache_dec(C, A, ckey(A, peek32(A.payload, pos + (uint64_t)q * W) >> (32 - W)));
-            const uint64_t cs = pos + (uint64_t)nesc * W;
-            // slot intervals: [cs, b(m0)), [b(m0), b(m0 + 1)), ..., [b(m1), ce), b(m) the boundary of slot m
-            const uint64_t m0 = cs / CK_SLOT + 1;
-            const uint64_t m1 = ce > 0 ? (ce - 1) / CK_SLOT : 0;
-            const uint64_t nseg = m1 >= m0 ? m1 - m0 + 2 : 1;
-            auto seg_start = [&](uint64_t sg) -> uint64_t {
-                if (sg == 0) return cs;
-                if (sg >= nseg) return ce;
-                const uint64_t b = (m0 + sg - 1) * CK_SLOT + A.ckb[m0 + sg - 1];
-                return b < ce ? b : ce;
-            };
-            for (uint64_t g0 = 0; g0 < nseg; g0 += WAVE) {
-                const uint64_t sg = g0 + lane;
-                const uint64_t p = seg_start(sg), e = seg_start(sg + 1);
-                // bits of the 64 intervals: [start of g0, end of the group's last interval)
-                const uint64_t lo = __shfl((unsigned long long)p, 0, WAVE);
-                const uint64_t gl = g0 + WAVE < nseg ? g0 + WAVE : nseg;
-                const uint64_t hi = __shfl((unsigned long long)e, (int)(gl - 1 - g0), WAVE);
-                const uint64_t wlo = lo >> 5;
-                const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
-                stage_words(stage[wv], A.payload + wlo, nw);
-                wave_sync();
-                if (sg < nseg) {
-                    uint64_t pp = p - wlo * 32;
-                    const uint64_t ee = e - wlo * 32;
-                    while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage[wv], pp));
-                }
-                wave_sync();
             }
         }
     }
@@ -775,7 +755,7 @@ void select_free(Ctx &c) {
     c.sel_hdesc = nullptr;
     c.sel_hdesc_bytes = 0;
     SelState &S = c.sel;
-    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.big, &S.cand, &S.cpos, &S.csel,
+    for (Buf *b : {&S.counts, &S.selmask, &S.covered, &S.newly, &S.keys, &S.partial, &S.cand, &S.cpos, &S.csel,
                    &S.sbcnt, &S.sboff, &S.slut, &S.ssym})
         buf_free(c, *b);
     S.words_cap = 0;
@@ -885,14 +865,14 @@ static int64_t build_slots(Ctx &root, Ctx &c) {
 struct SelJob {
     SelArgs A;
     bool huff;
-    uint32_t g_arg, g_find, g_apply, g_hot, g_big, g_arr;
+    uint32_t g_arg, g_find, g_apply, g_hot, g_arr;
     double b_arg, b_find, b_apply;
 };
 
 // Selection state in caller-provided device memory (dense counts, no profiling); sizes
 // as sel_fixed_layout computes them.
 struct SelBufs {
-    uint32_t *counts, *selmask, *big;
+    uint32_t *counts, *selmask;
     unsigned long long *covered, *newly, *partial, *keys;
 };
 
@@ -918,7 +898,6 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
         buf_grow(c, S.covered, (size_t)std::max<int64_t>(words, 1) * 8, false);
         buf_grow(c, S.newly, (size_t)std::max<int64_t>(words, 1) * 8, false);
         buf_grow(c, S.partial, (size_t)g_arg * 8, false);
-        if (huff && T > 0) buf_grow(c, S.big, (size_t)(T + 2) * 4, false);
     }
     SelJob J{};
     SelArgs &A = J.A;
@@ -930,7 +909,6 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.cpos = m >= 0 ? S.cpos.as<int32_t>() : nullptr;
     A.csel = m >= 0 ? S.csel.as<uint32_t>() : nullptr;
     A.ncand = m >= 0 ? S.sboff.as<int64_t>() + (((int64_t)n + SL_SPAN - 1) / SL_SPAN) : nullptr;
-    A.pbits = root.prof.on && !fixed ? prof_counters(root) + DC_EDGES : nullptr;
     A.selmask = fixed ? fixed->selmask : S.selmask.as<uint32_t>();
     A.covered = fixed ? fixed->covered : S.covered.as<unsigned long long>();
     A.newly = fixed ? fixed->newly : S.newly.as<unsigned long long>();
@@ -973,7 +951,6 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.nparts = (int32_t)g_arg;
     A.hist = T > 0 ? s.hist.as<uint32_t>() : nullptr;
     A.ckb = s.ckb.as<uint8_t>();
-    A.big = huff && T > 0 ? (fixed ? fixed->big : S.big.as<uint32_t>()) : nullptr;
     A.k = k;
     A.nar = T > 0 ? s.nar : 0;
     A.ar_rank = s.ar_rank.as<int32_t>();
@@ -996,7 +973,6 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * (gfix ? std::max<int64_t>(1, 4096 / A.hx) : nseg)) : 0;
     J.g_arr = A.nar ? (gfix ? (uint32_t)root.num_cus * 4
                             : grid_for(std::max<int64_t>(A.nentries, 1), 256, (int64_t)root.num_cus * 8)) : 0;
-    J.g_big = A.big ? (gfix ? (uint32_t)root.num_cus * 3 : grid_for(T, 256, (int64_t)root.num_cus * 3)) : 0;  // idle blocks leave at once
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
     // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
     // reads and writes the covered and newly words (and the hot row when u* is hot).
@@ -1054,7 +1030,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     std::vector<size_t> order(N);
     for (size_t i = 0; i < N; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return k[a] > k[b]; });
-    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_BIG, P_ARR, NPLAN };
+    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_ARR, NPLAN };
     Plan plans[NPLAN];
     for (size_t i : order) {
         plans[P_ALL_ARG].jobs.push_back(i);
@@ -1063,7 +1039,6 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
         if (J[i].g_find && J[i].huff) plans[P_HUFF].jobs.push_back(i);
         if (J[i].g_find && !J[i].huff) plans[P_RAW].jobs.push_back(i);
         if (J[i].g_hot) plans[P_HOT].jobs.push_back(i);
-        if (J[i].g_big) plans[P_BIG].jobs.push_back(i);
         if (J[i].g_arr) plans[P_ARR].jobs.push_back(i);
     }
     auto blocks = [&](int p, size_t i) -> uint32_t {
@@ -1073,7 +1048,6 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
             case P_HUFF:
             case P_RAW: return J[i].g_find;
             case P_HOT: return J[i].g_hot;
-            case P_BIG: return J[i].g_big;
             case P_ARR: return J[i].g_arr;
             default: return graph ? 1024u : grid_for(std::max<int64_t>({(int64_t)J[i].A.n, J[i].A.words, (int64_t)k[i]}), 256, 1024);
         }
@@ -1153,7 +1127,6 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
         return b;
     };
     auto prof_begin = [&](Ctx &r, const char *name) { return fixed ? -1 : hbm::prof_begin(r, name); };
-    int ps_big = -1;  // profiling: a dec_big launch, credited with the bits all of them decoded
     auto launch_all = [&]() {
         HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
         for (int t = 0; t < kmax; t++) {
@@ -1173,12 +1146,6 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
             ps = prof_begin(root, "apply");
             HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
             prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
-            if (active(P_BIG, t)) {
-                ps = prof_begin(root, "dec_big");
-                HBM_SEL_LAUNCH(P_BIG, k_dec_big, t);
-                prof_end(root, ps);
-                if (ps >= 0) ps_big = ps;
-            }
             if (active(P_HOT, t)) {
                 ps = prof_begin(root, "dec_hot");
                 HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
@@ -1238,11 +1205,6 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     }
 #undef HBM_SEL_LAUNCH
     HBM_HIP(hipGetLastError());
-    if (ps_big >= 0) {
-        unsigned long long ctr[DC_COUNT];
-        prof_read_counters(root, ctr);
-        prof_add(root, ps_big, (double)ctr[DC_EDGES] / 8.0, 0.0);  // algorithmic bytes: the strings read
-    }
     std::vector<unsigned long long> keys((size_t)koff[N]);
     HBM_HIP(hipMemcpyAsync(keys.data(), dkeys, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
     float ms = 0;
@@ -1323,7 +1285,6 @@ static size_t sel_fixed_layout(const Ctx &root, const Ctx &c, int32_t k, char *b
     char *newly = take((size_t)words * 8);
     char *partial = take((size_t)argmax_blocks(root, n) * 8);
     char *keys = take((size_t)k * 8);
-    char *big = huff && T > 0 ? take((size_t)(T + 2) * 4) : nullptr;
     if (b) {
         b->counts = (uint32_t *)counts;
         b->selmask = (uint32_t *)selmask;
@@ -1331,7 +1292,6 @@ static size_t sel_fixed_layout(const Ctx &root, const Ctx &c, int32_t k, char *b
         b->newly = (unsigned long long *)newly;
         b->partial = (unsigned long long *)partial;
         b->keys = (unsigned long long *)keys;
-        b->big = (uint32_t *)big;
     }
     return at;
 }
