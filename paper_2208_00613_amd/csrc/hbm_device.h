@@ -143,12 +143,10 @@ __device__ __forceinline__ uint4 raw_id4(const int32_t *dev, const int32_t *host
     return i < split ? reinterpret_cast<const uint4 *>(dev)[q] : reinterpret_cast<const uint4 *>(host + (i - split))[0];
 }
 
-#define HBM_KERNEL(NAME, ARGS, THREADS) HBM_KERNEL_ATTR(NAME, ARGS, THREADS, )
-// ATTR: extra function attributes of both kernels (e.g. a wave-occupancy target)
-#define HBM_KERNEL_ATTR(NAME, ARGS, THREADS, ATTR)                                                   \
+#define HBM_KERNEL(NAME, ARGS, THREADS)                                                              \
     __device__ void NAME##_body(const ARGS &A, uint32_t bid, uint32_t nblk, int x);                  \
-    __global__ __launch_bounds__(THREADS) ATTR void NAME(ARGS A, int x) { NAME##_body(A, blockIdx.x, gridDim.x, x); } \
-    __global__ __launch_bounds__(THREADS) ATTR void NAME##_g(GroupArgs<ARGS> G) {                    \
+    __global__ __launch_bounds__(THREADS) void NAME(ARGS A, int x) { NAME##_body(A, blockIdx.x, gridDim.x, x); } \
+    __global__ __launch_bounds__(THREADS) void NAME##_g(GroupArgs<ARGS> G) {                         \
         const uint32_t i = group_of(G.boff, G.count, blockIdx.x);                                     \
         const ARGS a_ = G.args[i]; /* uniform: held in scalar registers, not re-read */              \
         NAME##_body(a_, blockIdx.x - G.boff[i], G.boff[i + 1] - G.boff[i], G.x);                      \
