@@ -143,6 +143,7 @@ for _k in ("hist_add", "cold_count", "split", "huff_bits", "huff_write", "argmax
            "dec_hot", "dec_arr"):
     PROFILE_KERNELS[_k] = r"k_" + _k + r"(_g)?\b"
 COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
+PROBE_FLAGS = {"c5": " --warmup 5 --steps 4"}  # the counter runs' queries: the first four timed ones
 
 
 def counters_path(workload):
@@ -186,6 +187,7 @@ def traffic_probe(args):
         # the timed queries of the default line (a few of them: counters serialize every dispatch)
         for q in G.serving_queries(args.warmup + args.steps, seed=c["gseed"], rate=1.0)[args.warmup:]:
             ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
+            log(f"[traffic] query {q['q']} done")
     else:
         c = G.CONFIGS[WORKLOADS[args.workload]["cfg"]]
         g = G.config_graph(WORKLOADS[args.workload]["cfg"])
@@ -244,12 +246,15 @@ def counters_summarize(fetch_csv, write_csv, l2_csv, workload, out_path=None):
         if hs + ms > 0:
             l2[prof] = hs / (hs + ms)
     wl = "c5" if workload == "all" else workload
+    probe = PROBE_FLAGS.get(wl, "")
     cmds = [f"cd /tmp && rocprofv3 --pmc {ctr} -f csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_{tag} -o {tag} -- "
-            f"python $GRAFT_REPO_ROOT/bench.py --traffic-probe --workload {wl}"
+            f"python $GRAFT_REPO_ROOT/bench.py --traffic-probe --workload {wl}{probe}"
             for ctr, tag in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"), ("TCC_HIT_sum TCC_MISS_sum", "l2"))]
-    cmds.append(f"python bench.py --workload {wl} --counters-summarize gpurun_out/pmc_fetch/fetch_counter_collection.csv "
-                "gpurun_out/pmc_write/write_counter_collection.csv gpurun_out/pmc_l2/l2_counter_collection.csv")
-    out = {"commands": cmds, "workload": WORKLOADS[wl]["name"] + ", one IMM step", "workload_key": wl,
+    cmds.append(f"python bench.py --workload {wl} --counters-summarize gpurun_out/pmc_fetch/fetch_counter_collection.csv.gz "
+                "gpurun_out/pmc_write/write_counter_collection.csv.gz gpurun_out/pmc_l2/l2_counter_collection.csv.gz")
+    what = ("queries 5..8 of the serving stream (the first four timed queries of the default line)" if wl == "c5"
+            else "one IMM step")
+    out = {"commands": cmds, "workload": WORKLOADS[wl]["name"] + ", " + what, "workload_key": wl,
            "csrc_digest": csrc_digest(), "copy_kernel": ck[:80], "fetch_scale": f_scale, "write_scale": w_scale,
            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "traffic": traffic,
            "l2_hit_unit": "TCC_HIT / (TCC_HIT + TCC_MISS) over the kernel's launches", "l2_hit": l2}
