@@ -213,26 +213,32 @@ def counters_summarize(fetch_csv, write_csv, l2_csv, workload, out_path=None):
     import re
 
     def per_kernel(path, counter, scale=1.0):
+        """Kernel name -> values in dispatch order, and the last three dispatches (the probe's
+        closing copies) as (name, value)."""
         import gzip
 
-        acc = {}
+        acc, rows = {}, []
         if not path:
-            return acc
+            return acc, rows
         f = gzip.open(path, "rt") if path.endswith(".gz") else open(path)
         for r in csv.DictReader(f):
             if r["Counter_Name"] != counter:
                 continue
-            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * scale)
-        return acc
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * scale))
+        rows.sort()
+        for _, k, v in rows:
+            acc.setdefault(k, []).append(v)
+        return acc, [(k, v) for _, k, v in rows[-3:]]
 
-    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE", 1024.0), per_kernel(write_csv, "WRITE_SIZE", 1024.0)
-    hit, miss = per_kernel(l2_csv, "TCC_HIT_sum"), per_kernel(l2_csv, "TCC_MISS_sum")
-    # the 1 GiB copies are the largest dispatches of the runtime's copy kernel
-    copy = [k for k in fetch if re.search(r"copy", k, re.I) and "hbm::" not in k]
-    if not copy:
-        raise SystemExit("no copy kernel in the counter run")
-    ck = max(copy, key=lambda k: max(fetch[k]))
-    f_scale, w_scale = COPY_BYTES / max(fetch[ck]), COPY_BYTES / max(write.get(ck, [COPY_BYTES]))
+    (fetch, f_last), (write, w_last) = per_kernel(fetch_csv, "FETCH_SIZE", 1024.0), per_kernel(write_csv, "WRITE_SIZE", 1024.0)
+    (hit, _), (miss, _) = per_kernel(l2_csv, "TCC_HIT_sum"), per_kernel(l2_csv, "TCC_MISS_sum")
+    # the probe ends with three 1 GiB device copies: its last three dispatches calibrate the counters
+    names = {k for k, _ in f_last} | {k for k, _ in w_last}
+    if len(f_last) < 3 or len(names) != 1 or "hbm::" in next(iter(names)):
+        raise SystemExit("the counter run does not end with the probe's three copies")
+    ck = next(iter(names))
+    f_scale = COPY_BYTES / float(np.median([v for _, v in f_last]))
+    w_scale = COPY_BYTES / float(np.median([v for _, v in w_last])) if w_last else 1.0
     traffic, l2 = {}, {}
     mean = lambda v: sum(v) / len(v)
     for prof, sym in PROFILE_KERNELS.items():

@@ -267,6 +267,8 @@ struct Ctx {
     size_t stage_pos = 0;                  // bump offset into both
     Buf tails;                             // uint64 per job: gathered totals
     Buf bkeys;                             // uint64 selection keys of every job
+    Buf xmeta;                             // extra-large LDS pass: member records (uint4)
+    Buf pfind;                             // profiling: find_huff's algorithmic bytes (partial sums)
     Prof prof;
     Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)
     // timing of the last operations (ms)

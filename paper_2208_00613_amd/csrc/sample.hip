@@ -655,6 +655,7 @@ struct T2LArgs {
     uint32_t nlist;
     uint32_t *ovf_list;  // where sets that outgrow the LDS queue go
     int ovf_cw;          // control word counting them
+    uint4 *xmeta;        // extra-large pass: CAP member records per workgroup of the launch
 };
 
 // META: the queue keeps each member's in-edge range and WC threshold beside it, taken from the
@@ -695,6 +696,11 @@ __device__ void big_lds_body(const T2LArgs &t) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     if (threadIdx.x < DC_COUNT) s_ctr[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < T2L_HASH; i += NT) h[i] = EMPTY;
+    // extra-large pass: the queue's in-edge records live in device memory (no LDS left for
+    // them), this workgroup's CAP slots of the launch's buffer; a level's batch then reads each
+    // member's range and threshold with one load that the workgroup itself wrote (L2), where it
+    // read the member's in_ptr pair and threshold (two dependent loads from HBM)
+    uint4 *const xm = META ? nullptr : t.xmeta + (size_t)blockIdx.x * (size_t)T2L_CAP;
     auto members = [&]() -> uint32_t {
         if constexpr (META) return (uint32_t)(qpack >> 32);
         else return qn;
@@ -707,9 +713,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
             ovf = 1;
             return;
         }
-        uint4 r;
-        if constexpr (META) r = a.in_rec[e];
-        else r.x = (uint32_t)a.in_src[e];
+        const uint4 r = a.in_rec[e];
         const uint32_t u = r.x;
         uint32_t hs = hash32(u, T2L_HASH_BITS);
         for (;;) {
@@ -728,6 +732,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     }
                 } else {
                     p = atomicAdd(&qn, 1u);
+                    if (p < (uint32_t)T2L_CAP) xm[p] = r;
                 }
                 if (p < (uint32_t)T2L_CAP) q[p] = u;
                 else ovf = 1;
@@ -815,6 +820,8 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 qpack = (1ull << 32) | (e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0u);
             } else {
                 qn = 1;
+                xm[0] = make_uint4(root, (uint32_t)a.in_ptr[root], (uint32_t)a.in_ptr[root + 1],
+                                   a.wc ? a.thr[root] : 0u);
             }
             nlive[0] = nlive[1] = 0;
             ovf = 0;
@@ -868,10 +875,11 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
                     uint32_t e0 = 0, e1 = 0, ng = 0, tv = 0;
                     if (threadIdx.x < cn) {
-                        const uint32_t v = q[c0 + threadIdx.x];
-                        e0 = (uint32_t)a.in_ptr[v];
-                        e1 = (uint32_t)a.in_ptr[v + 1];
-                        if (a.wc) tv = a.thr[v];
+                        // the member's record, written by the insert that found it (or the root's)
+                        const uint4 r = xm[c0 + threadIdx.x];
+                        e0 = r.y;
+                        e1 = r.z;
+                        tv = r.w;
                         ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0;
                     }
                     const uint32_t P = block_incl_scan(ng, wsum);
@@ -1405,7 +1413,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
-            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2});
+            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
             ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
@@ -1460,10 +1468,27 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             const uint64_t nd2 = root.ctrl_host[i * CW_COUNT + CW_NDEFER2];
             if (!nd2) continue;
             root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
-            xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER});
+            xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
             xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));
         }
         if (!xl.empty()) {
+            // member records: T2X_CAP per workgroup of the launch (a grouped launch numbers its
+            // workgroups across all jobs).  One such workgroup fits a CU, so more than two per CU
+            // only queue: the jobs share 2 per CU (at least one each; each job's workgroups take
+            // its sets from its own counter until none is left)
+            uint64_t blocks = 0;
+            for (uint32_t b : xlb) blocks += b;
+            const uint64_t cap = std::max<uint64_t>((uint64_t)root.num_cus * 2, xlb.size());
+            if (blocks > cap) {
+                const uint64_t total = blocks;
+                blocks = 0;
+                for (uint32_t &b : xlb) {
+                    b = (uint32_t)std::max<uint64_t>(1, (uint64_t)b * cap / total);
+                    blocks += b;
+                }
+            }
+            buf_grow(root, root.xmeta, (size_t)blocks * T2X_CAP * sizeof(uint4), false);
+            for (T2LArgs &t : xl) t.xmeta = root.xmeta.as<uint4>();
             ctrl_push(root);
             int sx = prof_begin(root, "ic_sample_block_xl");
             glaunch(root, xl, xlb, 0,

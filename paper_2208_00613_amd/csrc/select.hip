@@ -27,6 +27,8 @@
 
 namespace hbm {
 
+constexpr int PB_SLOTS = 4096;
+
 struct SelArgs {
     int64_t T;       // sets
     int64_t words;   // ceil(T / 64)
@@ -72,6 +74,8 @@ struct SelArgs {
     const int32_t *cpos;          // vertex -> slot (read for vertices that have one only)
     uint32_t *csel;               // selection bits over slots
     const int64_t *ncand;         // number of slots (device)
+    unsigned long long *pbytes;   // profiling: algorithmic bytes find_huff reads, PB_SLOTS
+                                  // partial sums (one per workgroup, modulo), else null
     // array rows (hot vertices of low density): per 2^16-set chunk, each row's sorted 16-bit set
     // offsets; ar_off is chunk-major with nar + 1 entries per chunk
     int32_t nar;
@@ -564,6 +568,7 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         be_n = (uint64_t)A.bitoff[j1];
     };
     if (w < A.words) fetch(w);
+    unsigned long long pacc = 0;  // profiling: this wave's algorithmic bytes
     for (; w < A.words; w += nwaves) {
         const unsigned long long cov = cov_n;
         const uint64_t bo = bo_n, be = be_n;
@@ -571,11 +576,18 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         const int64_t j0 = w * 64;
         const int64_t j1 = j0 + 64 < A.T ? j0 + 64 : A.T;
         const unsigned long long live = (j1 - j0 == 64 ? ~0ull : ((1ull << (j1 - j0)) - 1)) & ~cov;
-        if (!live) continue;
+        if (!live) {
+            pacc += 8;  // the covered word
+            continue;
+        }
         const uint64_t b0 = (uint64_t)__shfl((unsigned long long)bo, 0, WAVE);
         // the next set's start ends this lane's set
         uint64_t bnext = (uint64_t)__shfl_down((unsigned long long)bo, 1, WAVE);
         if (j0 + lane + 1 >= j1) bnext = be;
+        if (A.pbytes) {  // the covered word, and each uncovered set's string and its two offsets
+            const uint32_t bits = wave_sum(((live >> lane) & 1ull) ? (uint32_t)(bnext - bo) : 0u);
+            pacc += 8ull + ((unsigned long long)bits + 7) / 8 + 16ull * __popcll(live);
+        }
         const uint64_t wlo = b0 >> 5;
         const uint64_t nw = ((be + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
         const bool staged = nw <= (uint64_t)STAGE_WORDS;
@@ -619,6 +631,7 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
             wave_dec_string<FH_NI>(A, tb, C, stage[wv], j0 + b, ps, pe);
         }
     }
+    if (A.pbytes && lane == 0 && pacc) atomicAdd(&A.pbytes[blockIdx.x & (PB_SLOTS - 1)], pacc);
     __syncthreads();
     cache_flush(C, A);
 }
@@ -909,6 +922,11 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.cpos = m >= 0 ? S.cpos.as<int32_t>() : nullptr;
     A.csel = m >= 0 ? S.csel.as<uint32_t>() : nullptr;
     A.ncand = m >= 0 ? S.sboff.as<int64_t>() + (((int64_t)n + SL_SPAN - 1) / SL_SPAN) : nullptr;
+    if (root.prof.on && !fixed && huff && !root.pfind.p) {
+        buf_alloc(root, root.pfind, PB_SLOTS * 8);
+        buf_zero(root, root.pfind, 0, PB_SLOTS * 8);
+    }
+    A.pbytes = root.prof.on && !fixed && huff ? root.pfind.as<unsigned long long>() : nullptr;
     A.selmask = fixed ? fixed->selmask : S.selmask.as<uint32_t>();
     A.covered = fixed ? fixed->covered : S.covered.as<unsigned long long>();
     A.newly = fixed ? fixed->newly : S.newly.as<unsigned long long>();
@@ -974,10 +992,11 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     J.g_arr = A.nar ? (gfix ? (uint32_t)root.num_cus * 4
                             : grid_for(std::max<int64_t>(A.nentries, 1), 256, (int64_t)root.num_cus * 8)) : 0;
     // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
-    // (or, for Huffman, the strings of uncovered sets: counted as the whole payload); apply
-    // reads and writes the covered and newly words (and the hot row when u* is hot).
+    // (for Huffman: the covered words and the strings and offsets of the uncovered sets, counted
+    // on the device while profiling); apply reads and writes the covered and newly words (and
+    // the hot row when u* is hot).
     J.b_arg = (m >= 0 ? 8.0 * m + m / 8.0 : 4.0 * n) + 4.0 * ((n + 31) / 32) + 8.0 * words;
-    J.b_find = huff ? (double)((s.nbits + 7) / 8) + 16.0 * T : 4.0 * A.nraw;
+    J.b_find = huff ? 0.0 : 4.0 * A.nraw;
     J.b_apply = 24.0 * words;
     return J;
 }
@@ -1127,6 +1146,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
         return b;
     };
     auto prof_begin = [&](Ctx &r, const char *name) { return fixed ? -1 : hbm::prof_begin(r, name); };
+    int ps_find = -1;  // profiling: a find_huff launch, credited with the bytes all of them read
     auto launch_all = [&]() {
         HBM_SEL_LAUNCH(P_INIT, k_sel_init, 0);
         for (int t = 0; t < kmax; t++) {
@@ -1136,7 +1156,8 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
             if (active(P_HUFF, t)) {
                 ps = prof_begin(root, "find_huff");
                 HBM_SEL_LAUNCH(P_HUFF, k_find_huff, t);
-                prof_end(root, ps, ps >= 0 ? bytes_of(P_HUFF, t, &SelJob::b_find) : 0);
+                prof_end(root, ps, 0);
+                if (ps >= 0) ps_find = ps;
             }
             if (active(P_RAW, t)) {
                 ps = prof_begin(root, "find_raw");
@@ -1205,6 +1226,15 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     }
 #undef HBM_SEL_LAUNCH
     HBM_HIP(hipGetLastError());
+    if (ps_find >= 0) {
+        std::vector<unsigned long long> part(PB_SLOTS);
+        HBM_HIP(hipMemcpyAsync(part.data(), root.pfind.p, PB_SLOTS * 8, hipMemcpyDeviceToHost, root.stream));
+        HBM_HIP(hipStreamSynchronize(root.stream));
+        buf_zero(root, root.pfind, 0, PB_SLOTS * 8);
+        double total = 0;
+        for (unsigned long long v : part) total += (double)v;
+        prof_add(root, ps_find, total, 0.0);
+    }
     std::vector<unsigned long long> keys((size_t)koff[N]);
     HBM_HIP(hipMemcpyAsync(keys.data(), dkeys, (size_t)koff[N] * 8, hipMemcpyDeviceToHost, st));
     float ms = 0;

@@ -51,28 +51,32 @@ def test_roofline_picks_the_dominant_kernel(bench):
 
 def _counter_csv(path, counter, rows):
     with open(path, "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for name, kib in rows:
-            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
+        for i, (name, kib) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
 
 
 def test_traffic_calibrated_by_the_copy(bench, tmp_path, capsys):
     gib_kib = (1 << 30) / 1024.0
-    # the counters read half of the copy's fetched bytes and all of its written bytes
+    # the counters read half of the copy's fetched bytes and all of its written bytes; a larger
+    # copy-named kernel earlier in the run (the graph's generation) must not calibrate them
+    copy = "__amd_rocclr_copyBuffer"
     _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [
-        ("__amd_rocclr_copyBuffer", gib_kib / 2), ("__amd_rocclr_copyBuffer", 1.0),
+        ("void at::native::copy_kernel_impl(...)", 4 * gib_kib), (copy, 1.0),
         ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 100.0),
         ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 300.0),
         ("void hbm::k_big_lds<1024, 8192, 14>(hbm::T2LArgs)", 7.0),
-        ("void hbm::k_argmax(hbm::SelArgs, int)", 10.0)])
+        ("void hbm::k_argmax(hbm::SelArgs, int)", 10.0),
+        (copy, gib_kib / 2 + 3), (copy, gib_kib / 2), (copy, gib_kib / 2 - 3)])
     _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [
-        ("__amd_rocclr_copyBuffer", gib_kib),
-        ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 4.0)])
+        ("void at::native::copy_kernel_impl(...)", 4 * gib_kib),
+        ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 4.0),
+        (copy, gib_kib), (copy, gib_kib), (copy, gib_kib)])
     _counter_csv(tmp_path / "l2.csv", "TCC_HIT_sum", [("void hbm::k_argmax(hbm::SelArgs, int)", 30.0),
                                                       ("void hbm::k_argmax(hbm::SelArgs, int)", 50.0)])
     with open(tmp_path / "l2.csv", "a", newline="") as f:
-        csv.writer(f).writerow(["void hbm::k_argmax(hbm::SelArgs, int)", "TCC_MISS_sum", 20.0])
+        csv.writer(f).writerow([3, "void hbm::k_argmax(hbm::SelArgs, int)", "TCC_MISS_sum", 20.0])
     out = tmp_path / "counters.json"
     bench.counters_summarize(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "l2.csv"), "c2",
                              str(out))
