@@ -100,7 +100,7 @@ typedef struct hbm_store_stats {
     int64_t index_bytes;    /* per-set offsets (Huffman: + one code-boundary byte per 256 payload bits) */
     int64_t bitmap_bytes;   /* hot rows */
     int64_t raw_bytes;      /* plain ids (NONE / cold part of HOT_BITMAP) */
-    int64_t codebook_bytes; /* lengths + symbol table + hot list */
+    int64_t codebook_bytes; /* lengths, packed per-vertex code table (8 B per vertex), symbol table, hot and array lists */
     int64_t store_bytes;    /* index + payload + bitmap + raw (codebook excluded) */
     double skewness;        /* Eq. 2 over the warm-up block */
     double density;         /* Eq. 2 over the warm-up block */

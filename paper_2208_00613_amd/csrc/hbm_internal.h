@@ -121,6 +121,7 @@ struct Store {
     Codebook cb;
     Buf lens;      // uint8[n]
     Buf codes;     // uint32[n]
+    Buf enc8;      // uint64[n]: code | length << 32 | (vertex has a row) << 40, the encoders' one read
     Buf symtab;    // int32[nsym] ids ordered by (length, id)
     Buf cbtab;     // uint64 lim[34], int64 base[34] decode tables
     Buf lut;       // uint32[2^LUT_BITS]: (symbol << 5) | length for codes of <= LUT_BITS bits, else 0

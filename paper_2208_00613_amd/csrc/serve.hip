@@ -66,7 +66,7 @@ void release_store(Ctx &c) {
     Store &s = c.s;
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
                    &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp, &s.ar_hot, &s.ar_rank,
-                   &s.ar_off, &s.ar_low, &s.ar_tmp})
+                   &s.ar_off, &s.ar_low, &s.ar_tmp, &s.ar_keys, &s.ar_sort, &s.enc8})
         buf_free(c, *b);
     store_reset(c);
 }

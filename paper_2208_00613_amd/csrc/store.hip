@@ -138,6 +138,7 @@ HBM_KERNEL(k_split, SplitArgs, 256) {
 
 // ------------------------------------------------------------------ Huffman stream
 struct HuffEnc {
+    const unsigned long long *enc8;  // per vertex: code | length << 32 | (has a row) << 40
     const uint8_t *lens;
     const uint32_t *codes;
     const int32_t *hot_rank;  // may be null
@@ -177,8 +178,9 @@ HBM_KERNEL(k_huff_bits, HuffArgs, 256) {
         uint32_t nesc = 0, front = 0;
         for (uint32_t i = lane; i < s; i += WAVE) {
             const uint32_t v = bv.mem[p + i];
-            if ((h.hot_rank && h.hot_rank[v] >= 0) || (h.ar_rank && h.ar_rank[v] >= 0) || v == root) continue;
-            const uint32_t L = h.lens[v];
+            const unsigned long long e = h.enc8[v];
+            if ((e >> 40) || v == root) continue;  // in a row, or the dropped root
+            const uint32_t L = (uint32_t)(e >> 32);
             if (L) bits += L;
             else nesc++;
             front |= (int32_t)v == h.ustar;
@@ -248,21 +250,24 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
             }
         }
         if (has_front) code_pos += h.lens[h.ustar];
-        // code length of member i in the coded part (0: hot, escaped or the front vertex)
-        auto code_of = [&](uint32_t i, uint32_t &v, bool &esc) -> uint32_t {
+        // code length of member i in the coded part (0: in a row, escaped or the front vertex)
+        // and its code, from one read of the packed table
+        auto code_of = [&](uint32_t i, uint32_t &v, bool &esc, uint32_t &code) -> uint32_t {
             v = bv.mem[p + i];
             esc = false;
-            if ((h.hot_rank && h.hot_rank[v] >= 0) || (h.ar_rank && h.ar_rank[v] >= 0) || v == root) return 0u;
-            const uint32_t len = h.lens[v];
+            const unsigned long long e = h.enc8[v];
+            code = (uint32_t)e;
+            if ((e >> 40) || v == root) return 0u;
+            const uint32_t len = (uint32_t)(e >> 32);
             esc = len == 0;
             return (int32_t)v == h.ustar ? 0u : len;
         };
         if (lane < 33) cls_n[wv][lane] = 0u;
         wave_sync();
         for (uint32_t c0 = 0; c0 < s; c0 += WAVE) {
-            uint32_t v;
+            uint32_t v, code;
             bool esc;
-            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc) : 0u;
+            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc, code) : 0u;
             if (len) atomicAdd(&cls_n[wv][len], 1u);
         }
         wave_sync();
@@ -273,9 +278,9 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
         }
         wave_sync();
         for (uint32_t c0 = 0; c0 < s; c0 += WAVE) {
-            uint32_t v = 0;
+            uint32_t v = 0, code = 0;
             bool esc = false;
-            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc) : 0u;
+            const uint32_t len = c0 + lane < s ? code_of(c0 + lane, v, esc, code) : 0u;
             const unsigned long long em = __ballot(esc);
             if (esc) put_bits(payload, esc_pos + (uint64_t)__popcll(em & below) * h.wbits, v, h.wbits);
             esc_pos += (uint64_t)__popcll(em) * h.wbits;
@@ -295,7 +300,7 @@ HBM_KERNEL(k_huff_write, HuffArgs, 256) {
             }
             if (len) {
                 const uint64_t at = cls_at[wv][len] + (uint64_t)rank * len;
-                put_bits(payload, at, h.codes[v], len);
+                put_bits(payload, at, code, len);
                 mark_slot(A.ckb, at, len);
             }
             wave_sync();
@@ -503,7 +508,7 @@ void store_free(Ctx &c) {
     Store &s = c.s;
     raw_host_free(c);
     for (Buf *b : {&s.hist, &s.warm, &s.hot, &s.hot_rank, &s.bitmap, &s.raw_off, &s.raw_mem, &s.lens, &s.codes,
-                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp, &s.ar_hot, &s.ar_rank,
+                   &s.symtab, &s.cbtab, &s.lut, &s.bitoff, &s.payload, &s.ckb, &s.mtmp, &s.ar_hot, &s.ar_rank, &s.enc8,
                    &s.ar_off, &s.ar_low, &s.ar_tmp, &s.ar_keys, &s.ar_sort})
         buf_free(c, *b);
     Scratch &sc = c.sc;
@@ -663,6 +668,15 @@ __global__ void k_scatter_rank(const uint32_t *ids, int64_t k, int32_t *rank) {
 }
 
 // lens[ids[i]] = len[i], codes[ids[i]] = code[i] (coded vertices)
+// The encoders' packed table: code | length << 32 | (v has a bitmap or array row) << 40.
+__global__ void k_pack_codes(const uint8_t *lens, const uint32_t *codes, const int32_t *hot_rank,
+                             const int32_t *ar_rank, int64_t n, unsigned long long *enc8) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const bool row = (hot_rank && hot_rank[v] >= 0) || (ar_rank && ar_rank[v] >= 0);
+        enc8[v] = (unsigned long long)codes[v] | ((unsigned long long)lens[v] << 32) | ((unsigned long long)row << 40);
+    }
+}
+
 __global__ void k_scatter_codes(const uint32_t *ids, const uint8_t *len, const uint32_t *code, int64_t m,
                                 uint8_t *lens, uint32_t *codes) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
@@ -871,6 +885,12 @@ static void build_model(Ctx &c) {
         HBM_HIP(hipMemcpyAsync(s.symtab.p, symtab.data(), symtab.size() * 4, hipMemcpyHostToDevice, st));
         HBM_HIP(hipMemcpyAsync(s.cbtab.p, tab_lim, 34 * 8, hipMemcpyHostToDevice, st));
         HBM_HIP(hipMemcpyAsync(s.cbtab.as<int64_t>() + 34, tab_base, 34 * 8, hipMemcpyHostToDevice, st));
+        buf_grow(c, s.enc8, (size_t)n * 8, false);
+        k_pack_codes<<<fill_grid(n), 256, 0, st>>>(s.lens.as<uint8_t>(), s.codes.as<uint32_t>(),
+                                                   hot ? s.hot_rank.as<int32_t>() : nullptr,
+                                                   s.nar ? s.ar_rank.as<int32_t>() : nullptr, n,
+                                                   s.enc8.as<unsigned long long>());
+        HBM_HIP(hipGetLastError());
         HBM_HIP(hipStreamSynchronize(st));
     }
     s.model_ready = true;
@@ -1283,7 +1303,8 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             buf_grow(c, s.bitoff, (size_t)(j0[i] + done[i] + 1) * 8, true);
             HuffArgs a{};
             a.bv = block_view(c, done[i]);
-            a.h = HuffEnc{s.lens.as<uint8_t>(), s.codes.as<uint32_t>(), hot ? s.hot_rank.as<int32_t>() : nullptr,
+            a.h = HuffEnc{s.enc8.as<unsigned long long>(), s.lens.as<uint8_t>(), s.codes.as<uint32_t>(),
+                          hot ? s.hot_rank.as<int32_t>() : nullptr,
                           s.cb.ustar_enc, s.cb.wbits, s.implicit_roots, s.seed, j0[i], (uint32_t)c.g.n,
                           s.nar ? s.ar_rank.as<int32_t>() : nullptr};
             a.bits = c.sc.aux.as<uint64_t>();
@@ -1565,7 +1586,7 @@ void store_stats(Ctx &c, hbm_store_stats *o) {
     o->index_bytes = s.nsets && (huff || raw) ? (s.nsets + 1) * 8 + (huff ? (int64_t)(s.nbits / CK_SLOT + 1) : 0) : 0;
     o->bitmap_bytes = s.bm_words * (int64_t)s.nhot * 8;
     o->raw_bytes = raw ? s.raw_count * 4 : 0;
-    o->codebook_bytes = huff ? (int64_t)c.g.n + (int64_t)s.cb.nsym * 4 + 68 * 8 : 0;
+    o->codebook_bytes = huff ? (int64_t)c.g.n * (1 + 8) + (int64_t)s.cb.nsym * 4 + 68 * 8 : 0;
     if (s.nhot) o->codebook_bytes += (int64_t)s.nhot * 4;
     o->store_bytes = store_bytes(c);
     o->skewness = s.skew;
