@@ -1337,7 +1337,7 @@ static void append_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vec
             fa[q].payload = c.s.payload.as<uint32_t>();
             fa[q].ckb = c.s.ckb.as<uint8_t>();
             c.s.nbits = (uint64_t)total[q];
-            if (c.s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP) {
+            if (c.s.enc == HBM_ENC_HUFFMAN_HOT_BITMAP && c.s.nhot > 0) {  // hot bits (none: nothing to set)
                 SplitArgs a{};
                 a.bv = fa[q].bv;
                 a.hot_rank = c.s.hot_rank.as<int32_t>();
