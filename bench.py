@@ -144,6 +144,7 @@ for _k in ("hist_add", "cold_count", "split", "huff_bits", "huff_write", "argmax
     PROFILE_KERNELS[_k] = r"k_" + _k + r"(_g)?\b"
 COPY_BYTES = 1 << 30  # the reference copy kernel of the traffic probe moves 1 GiB each way
 PROBE_FLAGS = {"c5": " --warmup 5 --steps 4"}  # the counter runs' queries: the first four timed ones
+C5_BLOCK_ALONE, C5_BLOCK_SERVING = 1 << 18, 1 << 16  # sets per sampling block on the Chung-Lu graph
 
 
 def counters_path(workload):
@@ -183,7 +184,7 @@ def traffic_probe(args):
 
     if args.workload in ("all", "c5"):
         ctx, c, _, _ = c5_context(P, torch)
-        ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)
+        ctx.hbm_set_tuning("BLOCK_SETS", C5_BLOCK_ALONE)
         # the timed queries of the default line (a few of them: counters serialize every dispatch)
         for q in G.serving_queries(args.warmup + args.steps, seed=c["gseed"], rate=1.0)[args.warmup:]:
             ctx.hbm_imm(q["k"], q["eps"], q["l"], q["seed"])
@@ -534,7 +535,9 @@ def c5_record(args, P, torch, with_host):
     from synth import graphs as G
 
     ctx, c, m, host = c5_context(P, torch, want_host=with_host)
-    ctx.hbm_set_tuning("BLOCK_SETS", 1 << 16)  # short steps: arrivals join within a block's time
+    # queries alone run in blocks of 2^18 sets (fewer tier launches and host round trips); the
+    # serving loop below uses 2^16, so arrivals join within a block's time
+    ctx.hbm_set_tuning("BLOCK_SETS", C5_BLOCK_ALONE)
     W, K = args.warmup, args.steps
     nq = max(args.queries, W + K)
     stream = G.serving_queries(nq, seed=c["gseed"], rate=1.0)
@@ -579,6 +582,7 @@ def c5_record(args, P, torch, with_host):
             "plain_bytes_per_rr": st_0["store"]["store_bytes"] / st_0["nsets_final"],
             "narray": st_i["store"]["narray"], "nhot": st_i["store"]["nhot"],
             "same_seeds": bool(np.array_equal(s_i, alone[q0["q"]][0]) and np.array_equal(g_i, alone[q0["q"]][1]))}
+    ctx.hbm_set_tuning("BLOCK_SETS", C5_BLOCK_SERVING)
     levels, identical = serving_levels(P, ctx, c, alone, svc, args.queries, args.loads)
     stores = [st["store"] for st in timed]
     rec = {
@@ -587,7 +591,8 @@ def c5_record(args, P, torch, with_host):
                    "prob": "WC", "k": "U{10..200}", "eps": [0.5, 0.2], "l": 1.0, "timed_queries": K,
                    "warmup_queries": W, "query_seeds": f"1000+q, q = {W}..{W + K - 1}", "encoding": c["enc"],
                    "hot_frac": c["hot"], "hot_min_density": c["hot_density"], "warmup_frac": c["warmup"],
-                   "store_budget_bytes": c["budget"]},
+                   "store_budget_bytes": c["budget"], "block_sets_alone": C5_BLOCK_ALONE,
+                   "block_sets_serving": C5_BLOCK_SERVING},
         "rr_sets": sets, "theta_final_range": [min(st["theta_final"] for st in timed),
                                                max(st["theta_final"] for st in timed)],
         "bytes_per_rr": sum(s_["store_bytes"] for s_ in stores) / max(sets, 1),
