@@ -120,7 +120,9 @@ typedef struct hbm_imm_stats {
     uint64_t coverage;          /* sets covered by the final seeds */
     double influence;           /* n * coverage / nsets_final */
     double lambda_prime, lambda_star;
-    double t_sample_ms, t_encode_ms, t_select_ms, t_total_ms;
+    double t_sample_ms, t_encode_ms, t_select_ms, t_total_ms;  /* t_encode_ms: building the codebook and
+                                                                  hot set from the warm-up block (host wall
+                                                                  time, part of t_sample_ms) */
     hbm_store_stats store;
 } hbm_imm_stats;
 

@@ -23,6 +23,7 @@
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -567,10 +568,18 @@ static int huffman_lengths_host(const std::vector<std::pair<uint64_t, int32_t>> 
     std::vector<int64_t> up(2 * L - 1);
     std::vector<int32_t> depth(2 * L - 1);
     for (;;) {
-        std::iota(order.begin(), order.end(), 0);
-        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-            return w[a] != w[b] ? w[a] < w[b] : syms[a].second < syms[b].second;
-        });
+        // (weight, id) order: syms come in ascending id order, so a stable sort by weight gives it;
+        // warm-up counts are small integers, so a counting sort does it in linear time
+        const uint64_t mx = *std::max_element(w.begin(), w.end());
+        if (mx <= (uint64_t)std::max<size_t>(4 * L, size_t(1) << 16)) {
+            std::vector<size_t> start((size_t)mx + 2, 0);
+            for (size_t i = 0; i < L; i++) start[(size_t)w[i] + 1]++;
+            for (size_t x = 1; x < start.size(); x++) start[x] += start[x - 1];
+            for (size_t i = 0; i < L; i++) order[start[(size_t)w[i]]++] = i;
+        } else {
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return w[a] < w[b]; });
+        }
         for (size_t i = 0; i < L; i++) wt[i] = w[order[i]];
         size_t leaf = 0, inner = L, made = L;
         auto take = [&]() -> size_t {
@@ -803,11 +812,14 @@ static void build_model(Ctx &c) {
         for (auto &p : syms)
             if (p.first > best) { best = p.first; cb.ustar_enc = p.second; }
         // canonical assignment by (length, id)
+        // (length, id) order: a stable bucket pass by length over the ascending ids
         std::vector<size_t> ord(syms.size());
-        std::iota(ord.begin(), ord.end(), 0);
-        std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-            return L[a] != L[b] ? L[a] < L[b] : syms[a].second < syms[b].second;
-        });
+        {
+            size_t start[34] = {};
+            for (size_t i = 0; i < syms.size(); i++) start[L[i] + 1]++;
+            for (int x = 1; x < 34; x++) start[x] += start[x - 1];
+            for (size_t i = 0; i < syms.size(); i++) ord[start[L[i]]++] = i;
+        }
         std::vector<uint32_t> sym_code(syms.size(), 0), sym_id(std::max<size_t>(syms.size(), 1), 0);
         std::vector<int32_t> symtab(std::max<size_t>(syms.size(), 1), 0);
         uint64_t count[34] = {}, first[34] = {}, firstidx[34] = {};
@@ -1486,7 +1498,9 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
             if (c.s.wcur >= c.s.W) {
                 characterize(c.s, c.g.n);
                 try {
+                    const auto tm0 = std::chrono::steady_clock::now();
                     build_model(c);
+                    c.t_encode += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tm0).count();
                 } catch (...) {  // e.g. ENOMEM: the warm-up starts over at the next request
                     c.s.wcur = 0;
                     c.s.warm_sizes.clear();
