@@ -601,7 +601,8 @@ def c5_record(args, P, torch, with_host):
             sum(s_["members"] for s_ in stores), 1),
         "peak_device_bytes": peak,
         "phase_ms_mean": {"sample_encode": float(np.mean([st["t_sample_ms"] for st in timed])),
-                          "select": float(np.mean([st["t_select_ms"] for st in timed]))},
+                          "select": float(np.mean([st["t_select_ms"] for st in timed])),
+                          "model_of_which": float(np.mean([st["t_encode_ms"] for st in timed]))},
         "profiled": f"a second pass over the {K} timed queries with per-launch HIP events",
         "roofline": roofline(kstats, "IC", "WC", "all"),
         "kernels": kernel_rates(kstats)[:12],
@@ -660,7 +661,8 @@ def imm_record(P, torch, g, c, wl_key, steps, warmup, density_gate=False, equal_
         "raw_bytes_per_rr": (4 * store["members"] + 8 * (nsets + 1)) / max(nsets, 1),
         "skewness": store["skewness"], "density": store["density"], "encoding_used": store["encoding"],
         "peak_device_bytes": peak,
-        "phase_ms": {"sample_encode": st["t_sample_ms"], "select": st["t_select_ms"]},
+        "phase_ms": {"sample_encode": st["t_sample_ms"], "select": st["t_select_ms"],
+                     "model_of_which": st["t_encode_ms"]},
     }
     ctx.hbm_profile(True)
     ctx.hbm_imm(k, eps, l, seed)

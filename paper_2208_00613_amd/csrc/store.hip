@@ -1498,6 +1498,7 @@ void extend_step(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int64
             if (c.s.wcur >= c.s.W) {
                 characterize(c.s, c.g.n);
                 try {
+                    HBM_HIP(hipStreamSynchronize(c.stream));  // the warm-up block is done: time the model alone
                     const auto tm0 = std::chrono::steady_clock::now();
                     build_model(c);
                     c.t_encode += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tm0).count();
