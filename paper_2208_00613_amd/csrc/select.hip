@@ -297,6 +297,52 @@ __device__ __forceinline__ uint32_t dec_code(const SelArgs &A, const Tabs &tb, c
     return (uint32_t)A.symtab[tb.base[L] + (int64_t)(w >> (32 - L))];
 }
 
+// An MSB-first bit reader with a 64-bit window: the next 32 bits are always at the top, and
+// one word is loaded per 32 bits consumed (decoding with peek32 loads two words per code, on
+// the code's dependency chain).  Reads reach at most the word that holds bit pos + 31, as
+// peek32 does.
+struct BitReader {
+    const uint32_t *buf;
+    uint64_t win;    // bits [pos, pos + avail), left-justified
+    uint32_t avail;  // >= 32
+    uint64_t nxt;    // the next word to load
+    __device__ __forceinline__ void init(const uint32_t *b, uint64_t pos) {
+        buf = b;
+        const uint64_t w = pos >> 5;
+        const uint32_t sh = (uint32_t)(pos & 31);
+        win = (((uint64_t)b[w] << 32) | (uint64_t)b[w + 1]) << sh;
+        avail = 64 - sh;
+        nxt = w + 2;
+    }
+    __device__ __forceinline__ uint32_t top() const { return (uint32_t)(win >> 32); }
+    __device__ __forceinline__ void skip(uint32_t n) {  // n <= 32
+        win <<= n;
+        avail -= n;
+        if (avail < 32) {
+            win |= (uint64_t)buf[nxt++] << (32 - avail);
+            avail += 32;
+        }
+    }
+};
+
+// one canonical code from a reader (as dec_code)
+__device__ __forceinline__ uint32_t dec_code_r(const SelArgs &A, const Tabs &tb, BitReader &R, uint64_t &pos) {
+    const uint32_t w = R.top();
+    const uint32_t ent = tb.lut[w >> (32 - LUT_BITS)];
+    uint32_t L, sym;
+    if (ent & 31u) {
+        L = ent & 31u;
+        sym = ent >> 5;
+    } else {
+        L = ent >> 5;  // shortest length a code with this prefix can have
+        while ((uint64_t)w >= tb.lim[L]) L++;
+        sym = (uint32_t)A.symtab[tb.base[L] + (int64_t)(w >> (32 - L))];
+    }
+    R.skip(L);
+    pos += L;
+    return sym;
+}
+
 __device__ __forceinline__ uint32_t read_gamma(const uint32_t *payload, uint64_t &pos) {
     const uint32_t L = __clz(peek32(payload, pos));
     pos += L;
@@ -333,16 +379,20 @@ __device__ bool huff_contains(const SelArgs &A, const Tabs &tb, const uint32_t *
         return false;
     }
     pos += (uint64_t)nesc * A.wbits;
+    if (pos >= end) return false;
     const uint32_t U = ustar_code << (32 - ustar_len);
     bool first = true;
+    BitReader R;
+    R.init(buf, pos);
     while (pos < end) {
-        const uint32_t w = peek32(buf, pos);
+        const uint32_t w = R.top();
         const uint32_t L = code_len(A, tb, w);
         const uint32_t c = w >> (32 - L);
         if (L == ustar_len && c == ustar_code) return true;
         if (!(first && L == fe_len && c == fe_code) && (c << (32 - L)) > U) return false;
         first = false;
         pos += L;
+        R.skip(L);
     }
     return false;
 }
@@ -390,7 +440,10 @@ __device__ void huff_decrement(const SelArgs &A, const Tabs &tb, DecCache &C, co
         pos += A.wbits;
         cache_dec(C, A, ckey(A, v));
     }
-    while (pos < end) cache_dec(C, A, dec_code(A, tb, buf, pos));
+    if (pos >= end) return;
+    BitReader R;
+    R.init(buf, pos);
+    while (pos < end) cache_dec(C, A, dec_code_r(A, tb, R, pos));
 }
 
 __device__ __forceinline__ uint32_t ustar_of(const SelArgs &A, int t, unsigned long long &key) {
@@ -512,10 +565,12 @@ __device__ void wave_dec_string(const SelArgs &A, const Tabs &tb, DecCache &C, u
         const uint64_t nw = ((hi + 31) >> 5) - wlo + 1;  // +1: peek32 reads a word ahead
         stage_words(stage, A.payload + wlo, nw);
         wave_sync();
-        if (lane < (unsigned)NI && sg < nseg) {
+        if (lane < (unsigned)NI && sg < nseg && p < e) {
             uint64_t pp = p - wlo * 32;
             const uint64_t ee = e - wlo * 32;
-            while (pp < ee) cache_dec(C, A, dec_code(A, tb, stage, pp));
+            BitReader R;
+            R.init(stage, pp);
+            while (pp < ee) cache_dec(C, A, dec_code_r(A, tb, R, pp));
         }
         wave_sync();
     }
