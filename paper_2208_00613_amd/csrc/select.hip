@@ -1,24 +1,25 @@
 // select.hip -- greedy max coverage on the (encoded) RR store.
 //
-// k iterations (the Seed Selection paragraph; Alg. 2 / Alg. 3 read as picking
-// exactly k seeds).  Each iteration t runs three kernels on the stream:
-//   argmax : u* = the unselected vertex with the highest count, lowest id on
-//            ties; the 64-bit key (count+1) << 32 | ~id is reduced with atomicMax
-//            into keys[t] (an exact argmax, not the paper's parallel-merge
+// k iterations (the Seed Selection paragraph; Alg. 2 / Alg. 3 read as picking exactly k
+// seeds).  Each iteration t runs, on the stream:
+//   argmax : every block writes the best key (count + 1) << 32 | ~id of its slice (the
+//            unselected vertex with the highest count, lowest id on ties); the next kernels
+//            reduce the partials themselves, so u* is exact (not the paper's parallel-merge
 //            heuristic, which can miss the true maximum);
-//   mark   : one wave per 64 consecutive sets (one word of the covered mask).
-//            If u* is hot its bitmap row gives the newly covered sets directly
-//            (Eq. 3: row AND NOT covered).  Otherwise every uncovered set is
-//            searched for u*: binary search in plain ids, or a partial decode
-//            of the Huffman string (Alg. 2's DecodeFind) that stops at u* or at
-//            the first code above u*'s: after the escaped ids and the front
-//            element the codes follow canonical (length, id) order, i.e.
-//            ascending left-justified code value.
-//            The plain / coded members of newly covered sets are decremented.
-//   hot    : counts of hot vertices drop by popcount(row AND newly), word by
-//            word (Alg. 3's SUBTRACT and POPCOUNT, applied to the change only).
-// Counts are exact 32-bit integers (the paper's float frequencies are not exact
-// beyond 2^24).  The store itself is never modified.
+//   find   : the sets that hold u*, when u* has no bitmap row: a pass over the plain ids
+//            (find_raw), a partial decode of every uncovered set's Huffman string (find_huff,
+//            Alg. 2's DecodeFind: after the escaped ids and the front element the codes
+//            follow canonical (length, id) order, ascending left-justified code value, so
+//            the scan stops at u* or at the first code above u*'s), or u*'s array row read
+//            as a list of sets;
+//   apply  : records u*; when u* has a row or the store is plain, marks the newly covered
+//            sets (Eq. 3: row AND NOT covered) and decrements their stored members (find_huff
+//            already did that for a cold u* of a Huffman store);
+//   hot / array rows : counts of vertices with bitmap rows drop by popcount(row AND newly),
+//            word by word (Alg. 3's SUBTRACT and POPCOUNT, applied to the change only), and
+//            those with array rows by their entries in newly covered sets.
+// Counts are exact 32-bit integers (the paper's float frequencies are not exact beyond
+// 2^24).  The store itself is never modified.
 #include <cstring>
 #include <mutex>
 
