@@ -9,16 +9,16 @@
 // whose running in-weight exceeds (word0 >> 8) / 2^24 of Philox(seed; j, cur,
 // tag 2), or none; the reverse walk stops at none or at a repeated vertex.
 //
-// Tiers.  IC tier 1: one wave per set, visited set in an LDS hash table and the
-// BFS queue in LDS; a frontier batch of up to 64 vertices is flattened into
-// groups of four in-edges (one Philox call each) spread over the lanes.  Sets
-// that outgrow the LDS queue, or whose expansion work passes a budget (sets that
-// reach in-degree hubs), are redone by tier 2: one 512-thread workgroup per set,
-// a visited bitmap over V and a queue in device memory, each level's edge groups
-// spread over all eight waves.  LT tier 1: one lane per
-// walk with the path in an LDS column; lanes refill from a shared counter as
-// their walks end.  Longer walks go to tier 2 (lane per walk, device-memory hash
-// and path), and walks longer still to tier 3 (bitmap over V).
+// Tiers (each takes the sets the previous one gave up on).  IC: a wave per set with its
+// visited set in an LDS hash and its queue in LDS, a frontier batch flattened into groups of
+// four in-edges (one Philox call each) over the lanes, up to a group budget (k_ic_t1); a
+// workgroup per set with an LDS hash and a 2048-member queue that keeps each member's
+// in-edge range, threshold and first Philox group (k_big_lds<., 2048, .>); an extra-large
+// pass of one 1024-thread workgroup per CU with room for 8192 members, their in-edge records
+// in device memory beside it (k_big_lds<1024, 8192, 14>); a workgroup per set with a visited
+// bitmap over V and a bounded device queue (k_big); and, for sets past that queue, slots
+// with full n-entry queues.  LT: a lane per walk with its path in LDS, refilled from a list
+// dealt to the lanes; a wave per walk with a 2048-step LDS path; then k_big and the slots.
 //
 // Every finished set is sorted ascending (its canonical form) and written to a
 // scratch arena; pos[b] / size[b] record where.  Block offsets that found no
