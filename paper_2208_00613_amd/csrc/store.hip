@@ -1,25 +1,35 @@
 // store.hip -- block-based sampling-and-encoding (Alg. 1) into the RR store.
 //
 // A request for sets [nsets, theta) runs in blocks sized to the scratch arena.
-// With an encoding, the first request begins with a warm-up pass over sets
+// With an encoding, the first request begins with a warm-up block over sets
 // [0, W): their vertex frequencies give the hot set and the Huffman codebook
-// (Alg. 1's first block; never rebuilt).  Sets are pure functions of their
-// index, so the warm-up sets are then simply sampled again and encoded like
-// every other block.  After each block the raw members are dropped; only the
+// (Alg. 1's first block; never rebuilt).  When the first block covers [0, W) it
+// is encoded and stored whole once the model is built; otherwise the warm-up
+// sets are pure functions of their index and are sampled again in the blocks
+// that store them.  After each block the raw members are dropped; only the
 // encoded form stays (the "Deallocate R_i" step).
 //
 // Store layouts (device memory):
 //   hist      uint32[n]   frequency of every vertex over all sets (UpdateHistogram)
 //   RAW       raw_off int64[nsets+1], raw_mem int32[]: ascending ids (all of a set,
-//             or its non-hot part under HOT_BITMAP)
+//             or its part without rows under HOT_BITMAP); with a spill cap the ids past
+//             a split point live in pinned host memory
 //   HOT rows  bitmap uint64[ceil(nsets/64) * nhot], word-major: the bit of set j
 //             for hot rank r is bit j%64 of word (j/64)*nhot + r (the Bitmax bit
-//             matrix of its encoding section, restricted to hot vertices)
+//             matrix of its encoding section, restricted to hot vertices; BITMAX
+//             itself is this matrix over all n vertices)
+//   ARRAY rows (optional) per chunk of 2^16 sets, each sparse hot vertex's
+//             ascending 16-bit set offsets: ar_off int64[chunks * (nar + 1)],
+//             ar_low uint16[]
 //   HUFFMAN   bitoff int64[nsets+1]; set j is bits [bitoff[j], bitoff[j+1]) of an
 //             MSB-first stream: Elias-gamma(nesc+1), the nesc codeless ids as
 //             fixed-width fields (the CP copies kept in-band), then the canonical
 //             codes of the coded ids, the warm-up top vertex first (the u*
-//             swap-to-front of the Huffmax encoding section), the rest ascending.
+//             swap-to-front of the Huffmax encoding section), the rest in
+//             canonical (length, id) order, i.e. ascending left-justified value;
+//             ckb uint8 per 256 payload bits: the distance to the next code start
+//   With implicit roots, a root that has no row is left out of its set's stored
+//   part and regenerated from (seed, j).
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include <algorithm>
