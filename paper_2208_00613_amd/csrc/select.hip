@@ -252,13 +252,22 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     }
 }
 
-// Stage 2, run at the start of every consumer block: the key of u* (block-uniform).
+// Stage 2, run at the start of every consumer block: the key of u* (block-uniform).  Each
+// thread issues its PR_N partial reads before it uses any (a loop that uses each read before
+// the next would pay one device-memory latency per step).
+constexpr int PR_N = 8;
 __device__ unsigned long long argmax_key(const SelArgs &A) {
     __shared__ unsigned long long red[1024 / WAVE];
     unsigned long long b = 0;
-    for (int i = threadIdx.x; i < A.nparts; i += blockDim.x) {
-        const unsigned long long x = A.partial[i];
-        b = x > b ? x : b;
+    for (int i0 = threadIdx.x; i0 < A.nparts; i0 += blockDim.x * PR_N) {
+        unsigned long long x[PR_N];
+#pragma unroll
+        for (int r = 0; r < PR_N; r++) {
+            const int i = i0 + r * (int)blockDim.x;
+            x[r] = i < A.nparts ? A.partial[i] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < PR_N; r++) b = x[r] > b ? x[r] : b;
     }
     b = wave_max_u64(b);
     if (lane_id() == 0) red[threadIdx.x / WAVE] = b;
@@ -275,12 +284,25 @@ struct Tabs {
     uint32_t lut[1 << LUT_BITS];
 };
 
+// The decode tables into LDS, PR_N reads in flight per thread (as argmax_key).
 __device__ void load_tabs(const SelArgs &A, Tabs &tb) {
     for (int i = threadIdx.x; i < 34; i += blockDim.x) {
         tb.lim[i] = A.lim[i];
         tb.base[i] = A.base[i];
     }
-    for (int i = threadIdx.x; i < (1 << LUT_BITS); i += blockDim.x) tb.lut[i] = A.lut[i];
+    for (int i0 = threadIdx.x; i0 < (1 << LUT_BITS); i0 += blockDim.x * PR_N) {
+        uint32_t x[PR_N];
+#pragma unroll
+        for (int r = 0; r < PR_N; r++) {
+            const int i = i0 + r * (int)blockDim.x;
+            x[r] = i < (1 << LUT_BITS) ? A.lut[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < PR_N; r++) {
+            const int i = i0 + r * (int)blockDim.x;
+            if (i < (1 << LUT_BITS)) tb.lut[i] = x[r];
+        }
+    }
 }
 
 // one canonical code: the LDS table for short codes, the limit search for long ones.
@@ -595,20 +617,6 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
     __shared__ Tabs tb;
     __shared__ uint32_t stage[256 / WAVE][STAGE_WORDS];
     __shared__ DecCache C;
-    load_tabs(A, tb);
-    cache_init(C);
-    __syncthreads();
-    unsigned long long key;
-    const uint32_t u = ustar_of(A, x, key);
-    if (key == 0 || (A.hot_rank && A.hot_rank[u] >= 0)) return;
-    if (in_arr(A, u)) {
-        arr_mark(A, A.ar_rank[u], bid, nblk);
-        return;
-    }
-    const uint32_t ustar_len = A.lens[u];
-    const uint32_t ustar_code = ustar_len ? A.codes[u] : 0u;
-    const uint32_t fe_len = A.ustar_enc >= 0 ? A.lens[A.ustar_enc] : 0u;  // the front code
-    const uint32_t fe_code = fe_len ? A.codes[A.ustar_enc] : 0u;
     const unsigned lane = lane_id();
     const int wv = threadIdx.x / WAVE;
     const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
@@ -623,7 +631,26 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
         bo_n = (uint64_t)A.bitoff[j0 + lane < j1 ? j0 + lane : j1];
         be_n = (uint64_t)A.bitoff[j1];
     };
+    // the first word's reads, the tables' and the argmax partials' are all in flight together
     if (w < A.words) fetch(w);
+    const uint32_t fe_len = A.ustar_enc >= 0 ? A.lens[A.ustar_enc] : 0u;  // the front code
+    const uint32_t fe_code = fe_len ? A.codes[A.ustar_enc] : 0u;
+    load_tabs(A, tb);
+    cache_init(C);
+    __syncthreads();
+    unsigned long long key;
+    const uint32_t u = ustar_of(A, x, key);
+    // u*'s row rank, code length and code read together (any vertex has a table entry)
+    const uint32_t us = key ? u : 0u;
+    const int32_t hr = A.hot_rank ? A.hot_rank[us] : -1;
+    const uint32_t ustar_len = A.lens[us];
+    const uint32_t ucode = A.codes[us];
+    if (key == 0 || hr >= 0) return;
+    if (in_arr(A, u)) {
+        arr_mark(A, A.ar_rank[u], bid, nblk);
+        return;
+    }
+    const uint32_t ustar_code = ustar_len ? ucode : 0u;
     unsigned long long pacc = 0;  // profiling: this wave's algorithmic bytes
     for (; w < A.words; w += nwaves) {
         const unsigned long long cov = cov_n;
