@@ -191,7 +191,6 @@ struct SelState {
     Buf newly;    // uint64[words]
     Buf keys;     // uint64[k]
     Buf partial;  // uint64 per argmax block + a ticket counter
-    Buf big;      // uint32: newly covered sets with long strings (+2 counters in front)
     Buf cand;     // sparse counts: slot -> vertex
     Buf cpos;     // sparse counts: vertex -> slot
     Buf csel;     // sparse counts: selection bits over slots

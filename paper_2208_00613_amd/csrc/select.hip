@@ -183,7 +183,10 @@ __device__ unsigned long long argmax_sparse(const SelArgs &A, int64_t tid, int64
             sel ? 0ull : (((unsigned long long)A.counts[i] + 1ull) << 32) | (unsigned long long)(~A.cand[i]);
         best = key > best ? key : best;
     }
-    const int64_t sw = ((int64_t)A.n + 31) / 32;
+    // fewer than k vertices are selected before the last pick, so the lowest unselected id is
+    // below k: only the selection words of ids [0, k] need a look
+    const int64_t swn = ((int64_t)A.n + 31) / 32, swk = (int64_t)A.k / 32 + 1;
+    const int64_t sw = swn < swk ? swn : swk;
     for (int64_t w = tid; w < sw; w += nthr) {
         uint32_t free_bits = ~A.selmask[w];
         const int64_t left = (int64_t)A.n - w * 32;
@@ -1074,11 +1077,14 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     J.g_hot = (T > 0 && s.nhot > 0) ? (uint32_t)(A.hx * (gfix ? std::max<int64_t>(1, 4096 / A.hx) : nseg)) : 0;
     J.g_arr = A.nar ? (gfix ? (uint32_t)root.num_cus * 4
                             : grid_for(std::max<int64_t>(A.nentries, 1), 256, (int64_t)root.num_cus * 8)) : 0;
-    // algorithmic bytes: argmax reads every count and selection bit; find reads every plain id
+    // algorithmic bytes: argmax reads every count and selection bit (sparse counts: the slots, and
+    // the selection words of ids [0, k]) and clears the newly words; find reads every plain id
     // (for Huffman: the covered words and the strings and offsets of the uncovered sets, counted
     // on the device while profiling); apply reads and writes the covered and newly words (and
     // the hot row when u* is hot).
-    J.b_arg = (m >= 0 ? 8.0 * m + m / 8.0 : 4.0 * n) + 4.0 * ((n + 31) / 32) + 8.0 * words;
+    J.b_arg = (m >= 0 ? 8.0 * m + m / 8.0 + 4.0 * std::min<int64_t>((n + 31) / 32, k / 32 + 1)
+                      : 4.0 * n + 4.0 * ((n + 31) / 32)) +
+              8.0 * words;
     J.b_find = huff ? 0.0 : 4.0 * A.nraw;
     J.b_apply = 24.0 * words;
     return J;

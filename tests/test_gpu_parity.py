@@ -338,6 +338,27 @@ def test_tuning_invariance(orc, ctx, tier1, budget, block, queue, lds):
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc
 
 
+@pytest.mark.parametrize("enc", ["NONE", "HUFFMAN"])
+def test_argmax_coverage_complete_before_k(orc, ctx, enc):
+    """The store is covered long before the k-th pick: the remaining picks are the lowest
+    unselected ids (count 0), with dense counts and with sparse slots, whose scan for that id
+    looks only at ids below k."""
+    n, theta, k = 3001, 40, 150
+    _say("argmax: coverage complete before k", enc)
+    g = G.erdos_renyi(n, 6000, seed=5)
+    ctx.hbm_load_graph(g.n, g.row_ptr, g.dst, g.w, model="IC", prob="EDGE")
+    ctx.hbm_set_encoding(enc, 0.5, 0.02)
+    ctx.hbm_sample_rr(theta, 3)
+    og = _ograph(orc, g, "IC", "EDGE")
+    st = orc.sample_store(og, 3, theta)
+    os_, og_, oc = orc.greedy(st, g.n, k)
+    assert oc == theta and og_[-1] == 0  # every set covered, the last picks gain nothing
+    for sparse in (0, 1):
+        ctx.hbm_set_tuning("SPARSE_COUNTS", sparse)
+        seeds, gains, cov = ctx.hbm_select_seeds(k)
+        assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and cov == oc, f"SPARSE_COUNTS={sparse}"
+
+
 # ---------------------------------------------------------------- argmax edge cases
 @pytest.mark.parametrize("n,m,enc,k", [(1000, 6000, "NONE", 1000), (5003, 40000, "HUFFMAN", 5003),
                                        (9001, 90000, "HOT_BITMAP", 200), (9001, 90000, "HUFFMAN_HOT_BITMAP", 64)])
