@@ -141,24 +141,24 @@ HBM_KERNEL(k_sel_init, SelArgs, 256) {
 
 constexpr int AM_UNROLL = 4;
 
-// Sparse counts: the slots' keys, and for every vertex without a slot (count 0 forever) the
-// key of the lowest unselected id, (0 + 1) << 32 | ~id: a vertex of count 0 can only win as the
-// lowest unselected id, and where that vertex has a slot its own key is at least as large.
+// Sparse counts: the keys of the slots of count > 0, (count + 1) << 32 | ~slot (slots are in
+// ascending vertex order, so the lowest slot of a count is its lowest vertex; the block maps
+// its best slot to its vertex once), and the key of the lowest unselected id, (0 + 1) << 32 |
+// ~id, for every vertex of count 0: such a vertex can only win as the lowest unselected id,
+// whether it has a slot or not.
 __device__ unsigned long long argmax_sparse(const SelArgs &A, int64_t tid, int64_t nthr) {
     unsigned long long best = 0;
     const int64_t m = *A.ncand;
     const int64_t m4 = m >> 2;
     const uint4 *c4 = reinterpret_cast<const uint4 *>(A.counts);
-    const uint4 *i4 = reinterpret_cast<const uint4 *>(A.cand);
     for (int64_t q0 = tid; q0 < m4; q0 += nthr * AM_UNROLL) {
-        uint4 c[AM_UNROLL], id[AM_UNROLL];
+        uint4 c[AM_UNROLL];
         uint32_t smw[AM_UNROLL];
 #pragma unroll
         for (int u = 0; u < AM_UNROLL; u++) {
             const int64_t q = q0 + (int64_t)u * nthr;
             if (q < m4) {
                 c[u] = c4[q];
-                id[u] = i4[q];
                 smw[u] = A.csel[q >> 3];
             }
         }
@@ -170,17 +170,19 @@ __device__ unsigned long long argmax_sparse(const SelArgs &A, int64_t tid, int64
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const uint32_t cr = r == 0 ? c[u].x : r == 1 ? c[u].y : r == 2 ? c[u].z : c[u].w;
-                const uint32_t vr = r == 0 ? id[u].x : r == 1 ? id[u].y : r == 2 ? id[u].z : id[u].w;
-                const unsigned long long key =
-                    ((sm >> r) & 1u) ? 0ull : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~vr);
+                const uint32_t sr = (uint32_t)(q * 4 + r);
+                const unsigned long long key = (((sm >> r) & 1u) || !cr)
+                                                   ? 0ull
+                                                   : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~sr);
                 best = key > best ? key : best;
             }
         }
     }
     for (int64_t i = m4 * 4 + tid; i < m; i += nthr) {
         const bool sel = (A.csel[i >> 5] >> (i & 31)) & 1u;
+        const uint32_t cr = A.counts[i];
         const unsigned long long key =
-            sel ? 0ull : (((unsigned long long)A.counts[i] + 1ull) << 32) | (unsigned long long)(~A.cand[i]);
+            (sel || !cr) ? 0ull : (((unsigned long long)cr + 1ull) << 32) | (unsigned long long)(~(uint32_t)i);
         best = key > best ? key : best;
     }
     // fewer than k vertices are selected before the last pick, so the lowest unselected id is
@@ -251,6 +253,8 @@ HBM_KERNEL(k_argmax, SelArgs, 256) {
     if (threadIdx.x == 0) {
         unsigned long long b = part[0];
         for (int i = 1; i < (int)(blockDim.x / WAVE); i++) b = part[i] > b ? part[i] : b;
+        // a slot's key (count field >= 2) to its vertex's: same order, as slots ascend with ids
+        if (A.cpos && (b >> 32) >= 2ull) b = (b & 0xFFFFFFFF00000000ull) | (unsigned long long)(~A.cand[~(uint32_t)b]);
         A.partial[bid] = b;
     }
 }
@@ -1082,7 +1086,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     // (for Huffman: the covered words and the strings and offsets of the uncovered sets, counted
     // on the device while profiling); apply reads and writes the covered and newly words (and
     // the hot row when u* is hot).
-    J.b_arg = (m >= 0 ? 8.0 * m + m / 8.0 + 4.0 * std::min<int64_t>((n + 31) / 32, k / 32 + 1)
+    J.b_arg = (m >= 0 ? 4.0 * m + m / 8.0 + 4.0 * std::min<int64_t>((n + 31) / 32, k / 32 + 1)
                       : 4.0 * n + 4.0 * ((n + 31) / 32)) +
               8.0 * words;
     J.b_find = huff ? 0.0 : 4.0 * A.nraw;
