@@ -86,6 +86,8 @@ struct SelArgs {
     const uint16_t *ar_low;
     int64_t nchunks;
     int64_t nentries;             // array entries over all chunks
+    int fused;                    // Huffman store without array rows: k_find_huff also records u*
+                                  // and, for a u* with a bitmap row, does k_apply's work
 };
 
 __device__ __forceinline__ bool in_arr(const SelArgs &A, uint32_t v) { return A.nar && A.ar_rank[v] >= 0; }
@@ -606,6 +608,66 @@ __device__ void wave_dec_string(const SelArgs &A, const Tabs &tb, DecCache &C, u
     }
 }
 
+// u* (key `key`) as the pick of iteration t: its selection bit (and its slot's) and its key
+__device__ __forceinline__ void record_ustar(const SelArgs &A, int t, uint32_t u, unsigned long long key) {
+    atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
+    if (A.cpos && A.hist[u] > 0) {  // u has a slot
+        const int32_t p = A.cpos[u];
+        atomicOr(&A.csel[p >> 5], 1u << (p & 31));
+    }
+    A.keys[t] = key;
+}
+
+// k_apply's pass over the words (u* with bitmap row r, or -1): the newly covered sets are
+// marked and their members decremented, Huffman strings NI slot intervals at a time from the
+// wave's stage (NI * CK_SLOT / 32 + 4 words)
+template <int NI>
+__device__ void apply_words(const SelArgs &A, const Tabs &tb, DecCache &C, uint32_t *stage, int32_t r, int64_t bid,
+                            uint32_t nblk) {
+    const unsigned lane = lane_id();
+    const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
+    for (int64_t w = bid * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
+        const unsigned long long cov = A.covered[w];
+        const unsigned long long nw = (r >= 0 ? A.bitmap[w * (int64_t)A.nhot + r] : A.newly[w]) & ~cov;
+        if (lane == 0) {
+            A.newly[w] = nw;
+            if (nw) A.covered[w] = cov | nw;
+        }
+        if (!nw) continue;
+        if (A.huff) {
+            // the word's newly covered strings, one at a time by the whole wave
+            const int64_t j0 = w * 64;
+            const int64_t jl = j0 + lane < A.T ? j0 + lane : A.T;
+            const uint64_t bo = (uint64_t)A.bitoff[jl];
+            const uint64_t be = (uint64_t)A.bitoff[(j0 + 64 < A.T ? j0 + 64 : A.T)];
+            uint64_t bnext = (uint64_t)__shfl_down((unsigned long long)bo, 1, WAVE);
+            if (lane == WAVE - 1 || j0 + lane + 1 >= A.T) bnext = be;
+            unsigned long long rest = nw;
+            while (rest) {
+                const int b = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const uint64_t ps = (uint64_t)__shfl((unsigned long long)bo, b, WAVE);
+                const uint64_t pe = (uint64_t)__shfl((unsigned long long)bnext, b, WAVE);
+                wave_dec_string<NI>(A, tb, C, stage, j0 + b, ps, pe);
+            }
+        } else if (A.raw_off) {
+            unsigned long long rest = nw;
+            while (rest) {
+                const int b = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const int64_t j = w * 64 + b;
+                const int64_t e = A.raw_off[j + 1];
+                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE)
+                    cache_dec(C, A, ckey(A, (uint32_t)raw_id(A.raw_mem, A.raw_host, A.raw_split, i)));
+                if (A.implicit && lane == 0) {
+                    const uint32_t r = lost_root(A, j);
+                    if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
+                }
+            }
+        }
+    }
+}
+
 // Huffman strings (Alg. 2's DecodeFind), one wave per 64-set word and one lane per set:
 // a partial decode that stops at u* (a codeless u* is sought among the escaped ids, which
 // come first and ascending; a coded u* is matched by its canonical code and the scan ends
@@ -652,7 +714,16 @@ HBM_KERNEL(k_find_huff, SelArgs, 256) {
     const int32_t hr = A.hot_rank ? A.hot_rank[us] : -1;
     const uint32_t ustar_len = A.lens[us];
     const uint32_t ucode = A.codes[us];
-    if (key == 0 || hr >= 0) return;
+    if (key == 0) return;
+    if (A.fused && bid == 0 && threadIdx.x == 0) record_ustar(A, x, u, key);
+    if (hr >= 0) {
+        if (A.fused) {  // k_apply's work, in this launch
+            apply_words<FH_NI>(A, tb, C, stage[wv], hr, bid, nblk);
+            __syncthreads();
+            cache_flush(C, A);
+        }
+        return;
+    }
     if (in_arr(A, u)) {
         arr_mark(A, A.ar_rank[u], bid, nblk);
         return;
@@ -740,62 +811,14 @@ HBM_KERNEL(k_apply, SelArgs, 256) {
     unsigned long long key;
     const uint32_t u = ustar_of(A, t, key);
     if (key == 0) return;  // cannot happen for k <= n: some vertex is always unselected
-    if (bid == 0 && threadIdx.x == 0) {
-        atomicOr(&A.selmask[u >> 5], 1u << (u & 31));
-        if (A.cpos && A.hist[u] > 0) {  // u has a slot
-            const int32_t p = A.cpos[u];
-            atomicOr(&A.csel[p >> 5], 1u << (p & 31));
-        }
-        A.keys[t] = key;
-    }
+    if (bid == 0 && threadIdx.x == 0) record_ustar(A, t, u, key);
     const int32_t r = A.hot_rank ? A.hot_rank[u] : -1;
     // a cold u*: the Huffman find step already covered and decremented
     if (r < 0 && A.huff && !in_arr(A, u)) return;
     if (A.huff) load_tabs(A, tb);
     cache_init(C);
     __syncthreads();
-    const unsigned lane = lane_id();
-    const int64_t nwaves = (int64_t)nblk * (blockDim.x / WAVE);
-    for (int64_t w = bid * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; w < A.words; w += nwaves) {
-        const unsigned long long cov = A.covered[w];
-        const unsigned long long nw = (r >= 0 ? A.bitmap[w * (int64_t)A.nhot + r] : A.newly[w]) & ~cov;
-        if (lane == 0) {
-            A.newly[w] = nw;
-            if (nw) A.covered[w] = cov | nw;
-        }
-        if (!nw) continue;
-        if (A.huff) {
-            // the word's newly covered strings, one at a time by the whole wave
-            const int64_t j0 = w * 64;
-            const int64_t jl = j0 + lane < A.T ? j0 + lane : A.T;
-            const uint64_t bo = (uint64_t)A.bitoff[jl];
-            const uint64_t be = (uint64_t)A.bitoff[(j0 + 64 < A.T ? j0 + 64 : A.T)];
-            uint64_t bnext = (uint64_t)__shfl_down((unsigned long long)bo, 1, WAVE);
-            if (lane == WAVE - 1 || j0 + lane + 1 >= A.T) bnext = be;
-            unsigned long long rest = nw;
-            while (rest) {
-                const int b = __ffsll((long long)rest) - 1;
-                rest &= rest - 1;
-                const uint64_t ps = (uint64_t)__shfl((unsigned long long)bo, b, WAVE);
-                const uint64_t pe = (uint64_t)__shfl((unsigned long long)bnext, b, WAVE);
-                wave_dec_string<AP_NI>(A, tb, C, stage[threadIdx.x / WAVE], j0 + b, ps, pe);
-            }
-        } else if (A.raw_off) {
-            unsigned long long rest = nw;
-            while (rest) {
-                const int b = __ffsll((long long)rest) - 1;
-                rest &= rest - 1;
-                const int64_t j = w * 64 + b;
-                const int64_t e = A.raw_off[j + 1];
-                for (int64_t i = A.raw_off[j] + lane; i < e; i += WAVE)
-                    cache_dec(C, A, ckey(A, (uint32_t)raw_id(A.raw_mem, A.raw_host, A.raw_split, i)));
-                if (A.implicit && lane == 0) {
-                    const uint32_t r = lost_root(A, j);
-                    if (r != 0xFFFFFFFFu) cache_dec(C, A, ckey(A, r));
-                }
-            }
-        }
-    }
+    apply_words<AP_NI>(A, tb, C, stage[threadIdx.x / WAVE], r, bid, nblk);
     __syncthreads();
     cache_flush(C, A);
 }
@@ -1067,6 +1090,9 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     A.ar_low = s.ar_low.as<uint16_t>();
     A.nchunks = s.ar_chunks;
     A.nentries = s.ar_entries;
+    // without array rows no set is marked by one launch and covered by the next, so the find
+    // step can also record u* and cover a bitmap row's sets: one launch less per iteration
+    A.fused = huff && T > 0 && A.nar == 0;
     A.hx = (int32_t)std::max<int64_t>(((int64_t)s.nhot + 255) / 256, 1);
     int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(words, 4096 / A.hx));
     A.seg = std::max<int64_t>(1, (words + nseg - 1) / nseg);
@@ -1142,11 +1168,11 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     std::vector<size_t> order(N);
     for (size_t i = 0; i < N; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return k[a] > k[b]; });
-    enum { P_ALL_ARG, P_ALL_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_ARR, NPLAN };
+    enum { P_ALL_ARG, P_APPLY, P_HUFF, P_RAW, P_HOT, P_INIT, P_ARR, NPLAN };
     Plan plans[NPLAN];
     for (size_t i : order) {
         plans[P_ALL_ARG].jobs.push_back(i);
-        plans[P_ALL_APPLY].jobs.push_back(i);
+        if (!J[i].A.fused) plans[P_APPLY].jobs.push_back(i);
         plans[P_INIT].jobs.push_back(i);
         if (J[i].g_find && J[i].huff) plans[P_HUFF].jobs.push_back(i);
         if (J[i].g_find && !J[i].huff) plans[P_RAW].jobs.push_back(i);
@@ -1156,7 +1182,7 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
     auto blocks = [&](int p, size_t i) -> uint32_t {
         switch (p) {
             case P_ALL_ARG: return J[i].g_arg;
-            case P_ALL_APPLY: return J[i].g_apply;
+            case P_APPLY: return J[i].g_apply;
             case P_HUFF:
             case P_RAW: return J[i].g_find;
             case P_HOT: return J[i].g_hot;
@@ -1257,9 +1283,11 @@ static void select_run(Ctx &root, const std::vector<Ctx *> &C, const std::vector
                 HBM_SEL_LAUNCH(P_RAW, k_find_raw, t);
                 prof_end(root, ps, ps >= 0 ? bytes_of(P_RAW, t, &SelJob::b_find) : 0);
             }
-            ps = prof_begin(root, "apply");
-            HBM_SEL_LAUNCH(P_ALL_APPLY, k_apply, t);
-            prof_end(root, ps, ps >= 0 ? bytes_of(P_ALL_APPLY, t, &SelJob::b_apply) : 0);
+            if (active(P_APPLY, t)) {
+                ps = prof_begin(root, "apply");
+                HBM_SEL_LAUNCH(P_APPLY, k_apply, t);
+                prof_end(root, ps, ps >= 0 ? bytes_of(P_APPLY, t, &SelJob::b_apply) : 0);
+            }
             if (active(P_HOT, t)) {
                 ps = prof_begin(root, "dec_hot");
                 HBM_SEL_LAUNCH(P_HOT, k_dec_hot, t);
