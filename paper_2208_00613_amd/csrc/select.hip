@@ -5,7 +5,8 @@
 //   argmax : every block writes the best key (count + 1) << 32 | ~id of its slice (the
 //            unselected vertex with the highest count, lowest id on ties); the next kernels
 //            reduce the partials themselves, so u* is exact (not the paper's parallel-merge
-//            heuristic, which can miss the true maximum);
+//            heuristic, which can miss the true maximum).  With sparse counts the slots are
+//            keyed by index (they ascend with the ids) and a block maps its best to a vertex;
 //   find   : the sets that hold u*, when u* has no bitmap row: a pass over the plain ids
 //            (find_raw), a partial decode of every uncovered set's Huffman string (find_huff,
 //            Alg. 2's DecodeFind: after the escaped ids and the front element the codes
@@ -14,7 +15,9 @@
 //            as a list of sets;
 //   apply  : records u*; when u* has a row or the store is plain, marks the newly covered
 //            sets (Eq. 3: row AND NOT covered) and decrements their stored members (find_huff
-//            already did that for a cold u* of a Huffman store);
+//            already did that for a cold u* of a Huffman store).  A Huffman store without
+//            array rows needs no apply launch: find_huff records u* and covers a bitmap
+//            row's sets itself;
 //   hot / array rows : counts of vertices with bitmap rows drop by popcount(row AND newly),
 //            word by word (Alg. 3's SUBTRACT and POPCOUNT, applied to the change only), and
 //            those with array rows by their entries in newly covered sets.
