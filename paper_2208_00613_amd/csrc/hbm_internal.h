@@ -166,6 +166,9 @@ struct Scratch {
     int t2h_slots = 0;
     Buf aux;        // uint64 per set (+1): bit lengths
     Buf cnt;        // uint32 per set (+1): plain-id counts
+    Buf spill;      // IC: the levels an LDS-tier set had completed when it outgrew the tier,
+                    // one slot per entry of the extra-large pass's list (records, then headers)
+    uint32_t spill_cap = 0;
 };
 
 // control word indices

@@ -656,6 +656,13 @@ struct T2LArgs {
     uint32_t *ovf_list;  // where sets that outgrow the LDS queue go
     int ovf_cw;          // control word counting them
     uint4 *xmeta;        // extra-large pass: CAP member records per workgroup of the launch
+    // spilled levels (or null): the regular tier writes, for entry d < sp_cap of its overflow
+    // list, the members of the BFS levels it had completed with their in-edge records
+    // (T2L_CAP_REGULAR records from sp_rec + d * T2L_CAP_REGULAR) and sp_hdr[d] = (first
+    // member of the last completed level, members); the extra-large pass resumes entry d there
+    uint4 *sp_rec;
+    uint2 *sp_hdr;
+    uint32_t sp_cap;
 };
 
 // META: the queue keeps each member's in-edge range and WC threshold beside it, taken from the
@@ -808,7 +815,33 @@ __device__ void big_lds_body(const T2LArgs &t) {
         const uint64_t j = (uint64_t)a.j0 + b;
         const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
         const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
-        if (threadIdx.x == 0) {
+        // the extra-large pass resumes a set whose completed levels the regular tier spilled:
+        // members [0, r_n) with their records, level [r_lo, r_n) to expand next
+        uint32_t r_lo = 0, r_n = 1;
+        bool resumed = false;
+        if constexpr (!META) {
+            if (t.sp_rec && it < t.sp_cap) {
+                const uint2 hd = t.sp_hdr[it];
+                r_lo = hd.x;
+                r_n = hd.y;
+                resumed = true;
+            }
+        }
+        if (resumed) {
+            const uint4 *src = t.sp_rec + (size_t)it * T2L_CAP_REGULAR;
+            for (uint32_t x = threadIdx.x; x < r_n; x += NT) {
+                const uint4 r = src[x];
+                q[x] = r.x;
+                xm[x] = r;
+                uint32_t hs = hash32(r.x, T2L_HASH_BITS);
+                while (atomicCAS(&h[hs], EMPTY, r.x) != EMPTY) hs = (hs + 1) & (T2L_HASH - 1);  // ids are distinct
+            }
+            if (threadIdx.x == 0) {
+                qn = r_n;
+                nlive[0] = nlive[1] = 0;
+                ovf = 0;
+            }
+        } else if (threadIdx.x == 0) {
             h[hash32(root, T2L_HASH_BITS)] = root;
             q[0] = root;
             if constexpr (META) {
@@ -827,15 +860,22 @@ __device__ void big_lds_body(const T2LArgs &t) {
             ovf = 0;
         }
         __syncthreads();
+        uint32_t sp_lo = 0, sp_n = 0;  // at an overflow: the last completed level [sp_lo, sp_n)
         if constexpr (META) {
             // level [head, tail): its groups are [qg[head], the group total), every member's
             // group found by a search of qg only when a thread's group leaves its member
-            uint32_t head = 0;
+            uint32_t head = 0, lh = 0;
             for (uint32_t lev = 0;; lev ^= 1) {
                 const unsigned long long pk = qpack;  // the previous level's inserts are done
                 const uint32_t m = (uint32_t)(pk >> 32);
                 const uint32_t tail = m < (uint32_t)T2L_CAP ? m : (uint32_t)T2L_CAP;
-                if (ovf || head >= tail) break;
+                if (ovf || head >= tail) {
+                    // the level [lh, head) overflowed while it was expanded: members [0, head)
+                    // are the levels up to it, all of them complete
+                    sp_lo = lh;
+                    sp_n = head;
+                    break;
+                }
                 const uint32_t gb = qg[head], ge = (uint32_t)pk;
                 if (a.dctr) {
                     if (threadIdx.x == 0) {
@@ -866,10 +906,11 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 for (uint32_t x = threadIdx.x; x < nl; x += NT) insert_edge(live[x]);
                 if (threadIdx.x == 0) nlive[lev ^ 1] = 0;
                 __syncthreads();
+                lh = head;
                 head = tail;
             }
         } else {
-            uint32_t head = 0, tail = 1;
+            uint32_t head = r_lo, tail = r_n;
             while (head < tail && !ovf) {
                 for (uint32_t c0 = head; c0 < tail; c0 += NT) {
                     const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
@@ -928,8 +969,19 @@ __device__ void big_lds_body(const T2LArgs &t) {
             if (threadIdx.x == 0) {
                 const uint64_t d = atomicAdd(&a.ctrl[t.ovf_cw], 1ull);
                 t.ovf_list[d] = b;
+                s_at = d;
             }
             __syncthreads();
+            if constexpr (META) {
+                // the completed levels, for the extra-large pass to resume from
+                const uint64_t d = s_at;
+                if (t.sp_rec && d < (uint64_t)t.sp_cap) {
+                    uint4 *dst = t.sp_rec + (size_t)d * T2L_CAP;
+                    for (uint32_t x = threadIdx.x; x < sp_n; x += NT) dst[x] = make_uint4(q[x], qe0[x], qe1[x], qt[x]);
+                    if (threadIdx.x == 0) t.sp_hdr[d] = make_uint2(sp_lo, sp_n);
+                }
+                __syncthreads();  // q and the records are the next set's
+            }
             continue;
         }
         const uint32_t s = members();
@@ -1242,6 +1294,23 @@ static void ensure_t2(Ctx &c) {
     sc.t2_slots = slots;
 }
 
+// Spill slots of the regular LDS tier (one per entry of the extra-large pass's list, up to
+// SPILL_SLOTS; entries past them start over from the root): T2L_CAP_REGULAR 16-byte records
+// each, then an 8-byte header each.  128 MB at most.
+constexpr uint32_t SPILL_SLOTS = 4096;
+static void ensure_spill(Ctx &c) {
+    Scratch &sc = c.sc;
+    const uint32_t want = (uint32_t)std::min<int64_t>(sc.bcap, SPILL_SLOTS);
+    if (sc.spill_cap >= want) return;
+    buf_alloc(c, sc.spill, (size_t)want * (T2L_CAP_REGULAR * sizeof(uint4) + sizeof(uint2)));
+    sc.spill_cap = want;
+}
+static void set_spill(Ctx &c, T2LArgs &t) {
+    t.sp_cap = c.sc.spill_cap;
+    t.sp_rec = c.sc.spill.as<uint4>();
+    t.sp_hdr = reinterpret_cast<uint2 *>(c.sc.spill.as<char>() + (size_t)t.sp_cap * T2L_CAP_REGULAR * sizeof(uint4));
+}
+
 static void ensure_t2_huge(Ctx &c) {
     Scratch &sc = c.sc;
     if (sc.t2h_slots) return;
@@ -1413,7 +1482,9 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
+            ensure_spill(c);
             lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
+            set_spill(c, lds.back());
             ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
@@ -1469,6 +1540,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             if (!nd2) continue;
             root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
             xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
+            set_spill(c, xl.back());  // as the regular tier wrote it
             xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));
         }
         if (!xl.empty()) {
