@@ -390,7 +390,12 @@ typedef enum hbm_tune_key {
                                      of that shape (up to 16 shapes kept per driving context).
                                      0 (default): launched kernel by kernel.  Not used while
                                      profiling */
-    HBM_TUNE_COUNT = 10
+    HBM_TUNE_SPILL_SLOTS = 10,    /* IC sets that outgrow the LDS tier: how many per sampling block
+                                     (0..4096, default 4096) keep the BFS levels the tier completed
+                                     (32 KB of device memory each, allocated on first use) so the
+                                     extra-large pass goes on from there; the rest start over from
+                                     their root */
+    HBM_TUNE_COUNT = 11
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

@@ -538,6 +538,10 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             HBM_REQUIRE(value >= 1024 && value <= (int64_t(1) << 26), HBM_EINVAL, "BLOCK_SETS out of range");
             c.block_sets = value;
             break;
+        case HBM_TUNE_SPILL_SLOTS:
+            HBM_REQUIRE(value >= 0 && value <= 4096, HBM_EINVAL, "SPILL_SLOTS must be in [0, 4096]");
+            c.spill_slots = value;
+            break;
         default:
             throw Error{HBM_EINVAL, "unknown tuning key"};
     }
@@ -555,6 +559,7 @@ int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
         case HBM_TUNE_LDS_PER_CU: return c.lds_per_cu;
         case HBM_TUNE_SPARSE_COUNTS: return c.sparse_counts;
         case HBM_TUNE_SELECT_GRAPH: return c.select_graph;
+        case HBM_TUNE_SPILL_SLOTS: return c.spill_slots;
         default: return -1;
     }
 }

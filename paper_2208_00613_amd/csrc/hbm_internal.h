@@ -246,6 +246,7 @@ struct Ctx {
     int lds_per_cu = 0;                  // LDS-tier workgroups launched per CU (0 = by n)
     int sparse_counts = 2;               // selection counts: 0 dense, 1 sparse slots, 2 by size
     int select_graph = 0;                // greedy launches replayed from a captured HIP graph
+    int64_t spill_slots = 4096;          // LDS-tier spill slots per sampling block
     hipStream_t cap_stream = nullptr;    // the stream the greedy is captured on
     // instantiated greedy graphs by launch shape (most recently used last), and the selection
     // descriptors they read: a device buffer at a fixed address with a pinned host mirror

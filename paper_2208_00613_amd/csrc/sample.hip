@@ -1294,21 +1294,24 @@ static void ensure_t2(Ctx &c) {
     sc.t2_slots = slots;
 }
 
-// Spill slots of the regular LDS tier (one per entry of the extra-large pass's list, up to
-// SPILL_SLOTS; entries past them start over from the root): T2L_CAP_REGULAR 16-byte records
-// each, then an 8-byte header each.  128 MB at most.
-constexpr uint32_t SPILL_SLOTS = 4096;
+// Spill slots of the regular LDS tier (one per entry of the extra-large pass's list, up to the
+// context's SPILL_SLOTS setting, at most 4096; entries past them start over from the root):
+// T2L_CAP_REGULAR 16-byte records each, then an 8-byte header each (128 MB at most).
+static uint32_t spill_want(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.sc.bcap, c.spill_slots); }
 static void ensure_spill(Ctx &c) {
     Scratch &sc = c.sc;
-    const uint32_t want = (uint32_t)std::min<int64_t>(sc.bcap, SPILL_SLOTS);
+    const uint32_t want = spill_want(c);
     if (sc.spill_cap >= want) return;
     buf_alloc(c, sc.spill, (size_t)want * (T2L_CAP_REGULAR * sizeof(uint4) + sizeof(uint2)));
     sc.spill_cap = want;
 }
 static void set_spill(Ctx &c, T2LArgs &t) {
-    t.sp_cap = c.sc.spill_cap;
-    t.sp_rec = c.sc.spill.as<uint4>();
-    t.sp_hdr = reinterpret_cast<uint2 *>(c.sc.spill.as<char>() + (size_t)t.sp_cap * T2L_CAP_REGULAR * sizeof(uint4));
+    const Scratch &sc = c.sc;
+    t.sp_cap = std::min(sc.spill_cap, spill_want(c));
+    t.sp_rec = t.sp_cap ? sc.spill.as<uint4>() : nullptr;
+    t.sp_hdr = t.sp_cap ? reinterpret_cast<uint2 *>(sc.spill.as<char>() +
+                                                    (size_t)sc.spill_cap * T2L_CAP_REGULAR * sizeof(uint4))
+                        : nullptr;
 }
 
 static void ensure_t2_huge(Ctx &c) {
