@@ -169,6 +169,8 @@ struct Scratch {
     Buf spill;      // IC: the levels an LDS-tier set had completed when it outgrew the tier,
                     // one slot per entry of the extra-large pass's list (records, then headers)
     uint32_t spill_cap = 0;
+    Buf spill2;     // the same for the extra-large pass's overflow (ids, then headers)
+    uint32_t spill2_cap = 0;
 };
 
 // control word indices

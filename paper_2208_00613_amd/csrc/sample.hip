@@ -389,6 +389,13 @@ constexpr int T2_THREADS = 512;
 constexpr int T2_WAVES = T2_THREADS / WAVE;
 constexpr int T2_SORT_CAP = 4096;  // 24 KB of LDS per block: 4 blocks (32 waves) fit a CU
 
+// LDS-tier capacities (members) and hash sizes (log2 slots): the regular tier, the extra-large pass
+constexpr int T2L_CAP = 2048;
+constexpr int T2L_CAP_REGULAR = T2L_CAP;
+constexpr int T2L_HASH_BITS = 13;
+constexpr int T2X_CAP = 8192;
+constexpr int T2X_HASH_BITS = 14;
+
 struct T2Args {
     SampleArgs a;
     uint32_t *bitmap;  // slots * words
@@ -399,6 +406,11 @@ struct T2Args {
     int model;         // HBM_IC or HBM_LT
     uint32_t qcap;     // queue entries per slot (n for the huge-set pass)
     int can_defer;     // a set outgrowing qcap goes to the huge list (else qcap == n)
+    // IC: levels the extra-large pass spilled (or null): for list entry it < rs_cap, ids
+    // rs_ids[it * T2X_CAP, + n) and rs_hdr[it] = (first member of the last completed level, n)
+    const uint32_t *rs_ids;
+    const uint2 *rs_hdr;
+    uint32_t rs_cap;
 };
 
 // Block-wide inclusive scan of one value per thread (wave shuffles + one LDS pass).
@@ -489,14 +501,31 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
         const uint64_t j = (uint64_t)a.j0 + b;
         const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
         const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
-        if (threadIdx.x == 0) {
+        // IC: go on from the levels the extra-large pass completed, when they fit the queue
+        uint32_t r_lo = 0;
+        bool resumed = false;
+        if (t.model == HBM_IC && t.rs_ids && it < t.rs_cap) {
+            const uint2 hd = t.rs_hdr[it];
+            if (hd.y <= t.qcap) {
+                const uint32_t *src = t.rs_ids + (size_t)it * T2X_CAP;
+                for (uint32_t x = threadIdx.x; x < hd.y; x += T2_THREADS) {
+                    const uint32_t v = src[x];
+                    queue[x] = v;
+                    atomicOr(&bm[v >> 5], 1u << (v & 31));
+                }
+                if (threadIdx.x == 0) qn = hd.y;
+                r_lo = hd.x;
+                resumed = true;
+            }
+        }
+        if (!resumed && threadIdx.x == 0) {
             bm[root >> 5] |= 1u << (root & 31);
             queue[0] = root;
             qn = 1;
         }
         __syncthreads();
         if (t.model == HBM_IC) {
-            uint32_t head = 0;
+            uint32_t head = r_lo;
             uint32_t tail = qn;
             while (head < tail && tail <= t.qcap) {
                 for (uint32_t c0 = head; c0 < tail; c0 += T2_THREADS) {
@@ -640,15 +669,10 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
 // NT threads (512 or 1024) per set with its visited set in an LDS hash and its queue in LDS,
 // so a BFS level costs two dependent device loads (offsets, then sources) instead of four.  A set that
 // outgrows the LDS queue clears the hash and moves to the device-bitmap kernel (k_big).
-// Two capacities: the regular tier keeps 2048 members (hash of 8192 slots, 49-57 KB of LDS,
-// two or three workgroups per CU); its overflow goes to an extra-large pass that keeps 8192
-// (hash of 16384 slots, 112 KB, one 1024-thread workgroup per CU), and only sets beyond that
-// reach the device-bitmap tier.  The hash never holds more than CAP + NT keys.
-constexpr int T2L_CAP = 2048;
-constexpr int T2L_CAP_REGULAR = T2L_CAP;
-constexpr int T2L_HASH_BITS = 13;
-constexpr int T2X_CAP = 8192;
-constexpr int T2X_HASH_BITS = 14;
+// Two capacities: the regular tier keeps 2048 members (hash of 8192 slots, 76-78 KB of LDS,
+// two workgroups per CU); its overflow goes to an extra-large pass that keeps 8192 (hash of
+// 16384 slots, 156 KB, one 1024-thread workgroup per CU), and only sets beyond that reach the
+// device-bitmap tier.  The hash never holds more than CAP + NT keys.
 
 struct T2LArgs {
     SampleArgs a;
@@ -664,6 +688,11 @@ struct T2LArgs {
     uint4 *sp_rec;
     uint2 *sp_hdr;
     uint32_t sp_cap;
+    // the extra-large pass's own overflow, spilled the same way for the device-bitmap tier
+    // (ids only: T2X_CAP from xs_ids + d * T2X_CAP, header xs_hdr[d]; see T2Args::rs_ids)
+    uint32_t *xs_ids;
+    uint2 *xs_hdr;
+    uint32_t xs_cap;
 };
 
 // META: the queue keeps each member's in-edge range and WC threshold beside it, taken from the
@@ -911,7 +940,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
                 head = tail;
             }
         } else {
-            uint32_t head = r_lo, tail = r_n;
+            uint32_t head = r_lo, tail = r_n, lh = r_lo;
             while (head < tail && !ovf) {
                 for (uint32_t c0 = head; c0 < tail; c0 += NT) {
                     const uint32_t cn = tail - c0 < (uint32_t)NT ? tail - c0 : (uint32_t)NT;
@@ -960,10 +989,13 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     for (uint32_t x = threadIdx.x; x < nl; x += NT) insert_edge(live[x]);
                     __syncthreads();
                 }
+                lh = head;
                 head = tail;
                 tail = qn < (uint32_t)T2L_CAP ? qn : (uint32_t)T2L_CAP;
                 __syncthreads();
             }
+            sp_lo = lh;  // as in the regular tier: [0, head) are complete levels
+            sp_n = head;
         }
         if (ovf) {
             for (int x = threadIdx.x; x < T2L_HASH; x += NT) h[x] = EMPTY;
@@ -982,6 +1014,14 @@ __device__ void big_lds_body(const T2LArgs &t) {
                     if (threadIdx.x == 0) t.sp_hdr[d] = make_uint2(sp_lo, sp_n);
                 }
                 __syncthreads();  // q and the records are the next set's
+            } else {
+                const uint64_t d = s_at;
+                if (t.xs_ids && d < (uint64_t)t.xs_cap) {
+                    uint32_t *dst = t.xs_ids + (size_t)d * T2L_CAP;
+                    for (uint32_t x = threadIdx.x; x < sp_n; x += NT) dst[x] = q[x];
+                    if (threadIdx.x == 0) t.xs_hdr[d] = make_uint2(sp_lo, sp_n);
+                }
+                __syncthreads();
             }
             continue;
         }
@@ -1315,6 +1355,24 @@ static void set_spill(Ctx &c, T2LArgs &t) {
                         : nullptr;
 }
 
+// The extra-large pass's spill slots for the device-bitmap tier: up to 256 (sets past 8192
+// members are rare), T2X_CAP ids and an 8-byte header each (8 MB at most).
+static uint32_t spill2_want(const Ctx &c) { return std::min<uint32_t>(spill_want(c), 256u); }
+static void ensure_spill2(Ctx &c) {
+    Scratch &sc = c.sc;
+    const uint32_t want = spill2_want(c);
+    if (sc.spill2_cap >= want) return;
+    buf_alloc(c, sc.spill2, (size_t)want * (T2X_CAP * sizeof(uint32_t) + sizeof(uint2)));
+    sc.spill2_cap = want;
+}
+static void spill2_of(Ctx &c, uint32_t *&ids, uint2 *&hdr, uint32_t &cap) {
+    const Scratch &sc = c.sc;
+    cap = std::min(sc.spill2_cap, spill2_want(c));
+    ids = cap ? sc.spill2.as<uint32_t>() : nullptr;
+    hdr = cap ? reinterpret_cast<uint2 *>(sc.spill2.as<char>() + (size_t)sc.spill2_cap * T2X_CAP * sizeof(uint32_t))
+              : nullptr;
+}
+
 static void ensure_t2_huge(Ctx &c) {
     Scratch &sc = c.sc;
     if (sc.t2h_slots) return;
@@ -1545,6 +1603,8 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
             xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
             set_spill(c, xl.back());  // as the regular tier wrote it
+            ensure_spill2(c);
+            spill2_of(c, xl.back().xs_ids, xl.back().xs_hdr, xl.back().xs_cap);
             xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));
         }
         if (!xl.empty()) {
@@ -1591,7 +1651,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                 if (!nd3) continue;
                 ensure_t2(c);
                 root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
-                T2Args t;
+                T2Args t{};
                 t.a = A[i];
                 t.bitmap = c.sc.t2_bitmap.as<uint32_t>();
                 t.queue = c.sc.t2_queue.as<uint32_t>();
@@ -1601,6 +1661,13 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                 t.model = model;
                 t.qcap = t2_qcap(c);
                 t.can_defer = 1;
+                if (model == HBM_IC) {  // as the extra-large pass wrote them
+                    uint32_t *ids = nullptr;
+                    uint2 *hdr = nullptr;
+                    spill2_of(c, ids, hdr, t.rs_cap);
+                    t.rs_ids = ids;
+                    t.rs_hdr = hdr;
+                }
                 t3.push_back(t);
                 t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));
             }
@@ -1626,7 +1693,7 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         if (!nh) continue;
         ensure_t2_huge(c);
         root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
-        T2Args t;
+        T2Args t{};
         t.a = A[i];
         t.bitmap = c.sc.t2h_bitmap.as<uint32_t>();
         t.queue = c.sc.t2h_queue.as<uint32_t>();
