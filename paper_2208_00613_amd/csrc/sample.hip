@@ -17,7 +17,8 @@
 // pass of one 1024-thread workgroup per CU with room for 8192 members, their in-edge records
 // in device memory beside it (k_big_lds<1024, 8192, 14>), which goes on from the BFS levels
 // the 2048-member tier completed and spilled when the set outgrew it; a workgroup per set with a visited
-// bitmap over V and a bounded device queue (k_big); and, for sets past that queue, slots
+// bitmap over V and a bounded device queue (k_big), which goes on in turn from the levels the
+// extra-large pass spilled; and, for sets past that queue, slots
 // with full n-entry queues.  LT: a lane per walk with its path in LDS, refilled from a list
 // dealt to the lanes; a wave per walk with a 2048-step LDS path; then k_big and the slots.
 //

@@ -306,27 +306,31 @@ def test_imm_small(orc, ctx, model, enc):
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == ost["coverage"]
 
 
-@pytest.mark.parametrize("slots", [4096, 3, 0])
-def test_spilled_levels_resume(orc, P, ctx, slots):
+@pytest.mark.parametrize("scale,theta,slots", [(13, 1_500, 4096), (13, 1_500, 3), (13, 1_500, 0),
+                                              (15, 300, 4096), (15, 300, 2)])
+def test_spilled_levels_resume(orc, P, ctx, scale, theta, slots):
     """IC sets that outgrow the LDS tier (constant p = 0.25: most sets hold thousands of
-    vertices) go on in the extra-large pass from the levels the tier spilled, or start over
-    from their root when no spill slot is left (3 slots: most of them; 0: all); the sets are
-    the oracle's either way."""
-    _say("spilled levels resume: slots", slots)
+    vertices) go on in the extra-large pass from the levels the tier spilled, and sets past
+    8192 members go on in the device-bitmap tier from the levels that pass spilled; or they
+    start over from their root when no spill slot is left (few slots: most of them; 0: all).
+    The sets are the oracle's either way."""
+    _say("spilled levels resume: scale", scale, "slots", slots)
     for bad in (-1, 4097):
         assert P.lib().hbm_set_tuning(ctx.h, P.TUNE["SPILL_SLOTS"], bad) == P.HBM_EINVAL
-    g = G.rmat(13, seed=13)
+    g = G.rmat(scale, seed=scale)
     g = G.with_weights(g, np.full(g.m, 0.25, dtype=np.float32))
     ctx.load_synth(g, "IC", "EDGE")
     ctx.hbm_set_encoding("NONE")
     ctx.hbm_set_tuning("SPILL_SLOTS", slots)
-    theta = 1_500
     ctx.hbm_sample_rr(theta, 42)
     og = _ograph(orc, g, "IC", "EDGE")
     st = orc.sample_store(og, 42, theta)
     off, _ = st.arrays()
     sizes = np.diff(off)
-    assert ((sizes > 2048) & (sizes <= 8192)).sum() > 100  # the extra-large pass has work
+    if scale == 13:
+        assert ((sizes > 2048) & (sizes <= 8192)).sum() > 100  # the extra-large pass ends them
+    else:
+        assert (sizes > 8192).sum() > 50  # they pass through it to the device-bitmap tier
     _check_sets(ctx, st, theta)
 
 
