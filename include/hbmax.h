@@ -395,7 +395,12 @@ typedef enum hbm_tune_key {
                                      (32 KB of device memory each, allocated on first use) so the
                                      extra-large pass goes on from there; the rest start over from
                                      their root */
-    HBM_TUNE_COUNT = 11
+    HBM_TUNE_LDS_SMALL = 11,      /* IC: 1 puts an LDS tier of 1024 members (256 threads, four
+                                     workgroups per CU) in front of the 2048-member one, which goes
+                                     on from the levels it spilled (up to twice SPILL_SLOTS sets per
+                                     block, 16 KB each); 0 does not; 2 (default) = 1 on graphs of at
+                                     least 2^22 vertices, else 0 */
+    HBM_TUNE_COUNT = 12
 } hbm_tune_key;
 
 hbm_status hbm_set_tuning(hbm_ctx *ctx, hbm_tune_key key, int64_t value);

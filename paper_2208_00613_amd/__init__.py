@@ -35,8 +35,9 @@ EXPORTED = ["hbm_create", "hbm_destroy", "hbm_last_error", "hbm_set_budget", "hb
             "hbm_get_memory", "hbm_bench_philox", "hbm_set_spill", "hbm_set_implicit_roots",
             "hbm_set_row_containers"]
 TUNE = {"IC_TIER1": 0, "IC_T1_BUDGET": 1, "BLOCK_SETS": 2, "LT_PATH": 3, "T2_QUEUE": 4, "T2_SLOTS": 5,
-        "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8, "SELECT_GRAPH": 9, "SPILL_SLOTS": 10}
-TUNE_COUNT = 11
+        "LDS_THREADS": 6, "LDS_PER_CU": 7, "SPARSE_COUNTS": 8, "SELECT_GRAPH": 9, "SPILL_SLOTS": 10,
+        "LDS_SMALL": 11}
+TUNE_COUNT = 12
 
 
 class HbmError(RuntimeError):

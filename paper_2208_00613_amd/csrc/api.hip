@@ -542,6 +542,10 @@ void set_tuning(Ctx &c, hbm_tune_key key, int64_t value) {
             HBM_REQUIRE(value >= 0 && value <= 4096, HBM_EINVAL, "SPILL_SLOTS must be in [0, 4096]");
             c.spill_slots = value;
             break;
+        case HBM_TUNE_LDS_SMALL:
+            HBM_REQUIRE(value >= 0 && value <= 2, HBM_EINVAL, "LDS_SMALL must be 0, 1 or 2");
+            c.lds_small = (int)value;
+            break;
         default:
             throw Error{HBM_EINVAL, "unknown tuning key"};
     }
@@ -560,6 +564,7 @@ int64_t get_tuning(const Ctx &c, hbm_tune_key key) {
         case HBM_TUNE_SPARSE_COUNTS: return c.sparse_counts;
         case HBM_TUNE_SELECT_GRAPH: return c.select_graph;
         case HBM_TUNE_SPILL_SLOTS: return c.spill_slots;
+        case HBM_TUNE_LDS_SMALL: return c.lds_small;
         default: return -1;
     }
 }

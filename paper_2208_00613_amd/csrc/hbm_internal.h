@@ -171,6 +171,8 @@ struct Scratch {
     uint32_t spill_cap = 0;
     Buf spill2;     // the same for the extra-large pass's overflow (ids, then headers)
     uint32_t spill2_cap = 0;
+    Buf spill0;     // the same for the 1024-member tier's overflow (records, then headers)
+    uint32_t spill0_cap = 0;
 };
 
 // control word indices
@@ -183,7 +185,8 @@ enum : int {
     CW_SUM = 5,        // generic accumulator
     CW_NHUGE = 6,      // sets that outgrew a big-set slot's queue
     CW_NDEFER2 = 7,    // IC sets that outgrew the LDS tier (-> device-bitmap tier)
-    CW_COUNT = 8
+    CW_NDEFER3 = 8,    // IC, three LDS capacities: sets that outgrew the middle one
+    CW_COUNT = 9
 };
 constexpr uint32_t POS_DEFER = 0xFFFFFFFFu;
 constexpr uint32_t POS_OVF = 0xFFFFFFFEu;
@@ -249,6 +252,7 @@ struct Ctx {
     int sparse_counts = 2;               // selection counts: 0 dense, 1 sparse slots, 2 by size
     int select_graph = 0;                // greedy launches replayed from a captured HIP graph
     int64_t spill_slots = 4096;          // LDS-tier spill slots per sampling block
+    int lds_small = 2;                   // IC: a 1024-member LDS tier in front (0 no, 1 yes, 2 by n)
     hipStream_t cap_stream = nullptr;    // the stream the greedy is captured on
     // instantiated greedy graphs by launch shape (most recently used last), and the selection
     // descriptors they read: a device buffer at a fixed address with a pinned host mirror

@@ -396,6 +396,8 @@ constexpr int T2L_CAP_REGULAR = T2L_CAP;
 constexpr int T2L_HASH_BITS = 13;
 constexpr int T2X_CAP = 8192;
 constexpr int T2X_HASH_BITS = 14;
+constexpr int T2S_CAP = 1024;  // the small tier in front (large graphs): 256 threads, four per CU
+constexpr int T2S_HASH_BITS = 12;
 
 struct T2Args {
     SampleArgs a;
@@ -682,13 +684,19 @@ struct T2LArgs {
     uint32_t *ovf_list;  // where sets that outgrow the LDS queue go
     int ovf_cw;          // control word counting them
     uint4 *xmeta;        // extra-large pass: CAP member records per workgroup of the launch
-    // spilled levels (or null): the regular tier writes, for entry d < sp_cap of its overflow
-    // list, the members of the BFS levels it had completed with their in-edge records
-    // (T2L_CAP_REGULAR records from sp_rec + d * T2L_CAP_REGULAR) and sp_hdr[d] = (first
-    // member of the last completed level, members); the extra-large pass resumes entry d there
+    // spilled levels (or null): a tier of LDS-resident records writes, for entry d < sp_cap of
+    // its overflow list, the members of the BFS levels it had completed with their in-edge
+    // records (CAP records from sp_rec + d * CAP) and sp_hdr[d] = (first member of the last
+    // completed level, members); the next pass resumes entry d there
     uint4 *sp_rec;
     uint2 *sp_hdr;
     uint32_t sp_cap;
+    // this pass's input spill (or null): list entry it < rin_cap resumes from the previous
+    // pass's slot it (records from rin + it * rin_stride, header rin_hdr[it])
+    const uint4 *rin;
+    const uint2 *rin_hdr;
+    uint32_t rin_cap;
+    uint32_t rin_stride;
     // the extra-large pass's own overflow, spilled the same way for the device-bitmap tier
     // (ids only: T2X_CAP from xs_ids + d * T2X_CAP, header xs_hdr[d]; see T2Args::rs_ids)
     uint32_t *xs_ids;
@@ -708,7 +716,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
     constexpr int T2L_HASH = 1 << HBITS;
     constexpr int T2L_HASH_BITS = HBITS;
     constexpr int T2L_CAP = CAP;
-    constexpr bool META = CAP == T2L_CAP_REGULAR;
+    constexpr bool META = CAP != T2X_CAP;  // the member records fit in LDS
     const SampleArgs &a = t.a;
     __shared__ uint32_t h[T2L_HASH];
     __shared__ uint32_t q[T2L_CAP];
@@ -721,7 +729,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
     __shared__ uint32_t sE0[META ? 1 : NT];
     __shared__ uint32_t sE1[META ? 1 : NT];
     __shared__ uint32_t sT[META ? 1 : NT];
-    __shared__ uint32_t wsum[META ? 1 : NT / WAVE];
+    __shared__ uint32_t wsum[NT / WAVE];
     constexpr uint32_t LIVE_CAP = META ? NT : 2 * NT;
     __shared__ uint32_t live[LIVE_CAP];
     __shared__ uint32_t nlive[2];  // by level parity: one is cleared while the other is read
@@ -846,31 +854,54 @@ __device__ void big_lds_body(const T2LArgs &t) {
         const uint64_t j = (uint64_t)a.j0 + b;
         const uint32_t jlo = (uint32_t)j, jhi = (uint32_t)(j >> 32);
         const uint32_t root = rr_root(a.seed, j, (uint32_t)a.n);
-        // the extra-large pass resumes a set whose completed levels the regular tier spilled:
-        // members [0, r_n) with their records, level [r_lo, r_n) to expand next
+        // a set whose completed levels the previous pass spilled resumes there: members
+        // [0, r_n) with their records, level [r_lo, r_n) to expand next
         uint32_t r_lo = 0, r_n = 1;
         bool resumed = false;
-        if constexpr (!META) {
-            if (t.sp_rec && it < t.sp_cap) {
-                const uint2 hd = t.sp_hdr[it];
-                r_lo = hd.x;
-                r_n = hd.y;
-                resumed = true;
-            }
+        if (t.rin && it < t.rin_cap) {
+            const uint2 hd = t.rin_hdr[it];
+            r_lo = hd.x;
+            r_n = hd.y;
+            resumed = true;
         }
         if (resumed) {
-            const uint4 *src = t.sp_rec + (size_t)it * T2L_CAP_REGULAR;
+            const uint4 *src = t.rin + (size_t)it * t.rin_stride;
             for (uint32_t x = threadIdx.x; x < r_n; x += NT) {
                 const uint4 r = src[x];
                 q[x] = r.x;
-                xm[x] = r;
+                if constexpr (META) {
+                    qe0[x] = r.y;
+                    qe1[x] = r.z;
+                    qt[x] = r.w;
+                } else {
+                    xm[x] = r;
+                }
                 uint32_t hs = hash32(r.x, T2L_HASH_BITS);
                 while (atomicCAS(&h[hs], EMPTY, r.x) != EMPTY) hs = (hs + 1) & (T2L_HASH - 1);  // ids are distinct
             }
             if (threadIdx.x == 0) {
-                qn = r_n;
+                if constexpr (!META) qn = r_n;
                 nlive[0] = nlive[1] = 0;
                 ovf = 0;
+            }
+            if constexpr (META) {
+                // first Philox groups of the level to expand and of everything after it: only
+                // members from r_lo on are expanded again
+                __syncthreads();
+                uint32_t carry = 0;
+                for (uint32_t c0 = r_lo; c0 < r_n; c0 += NT) {
+                    const uint32_t x = c0 + threadIdx.x;
+                    uint32_t ng = 0;
+                    if (x < r_n) {
+                        const uint32_t e0 = qe0[x], e1 = qe1[x];
+                        ng = e1 > e0 ? ((e1 - 1) >> 2) - (e0 >> 2) + 1 : 0u;
+                    }
+                    const uint32_t P = block_incl_scan(ng, wsum);
+                    if (x < r_n) qg[x] = carry + P - ng;
+                    for (int w = 0; w < NT / WAVE; w++) carry += wsum[w];
+                    __syncthreads();  // wsum is the next chunk's
+                }
+                if (threadIdx.x == 0) qpack = ((unsigned long long)r_n << 32) | carry;
             }
         } else if (threadIdx.x == 0) {
             h[hash32(root, T2L_HASH_BITS)] = root;
@@ -895,7 +926,7 @@ __device__ void big_lds_body(const T2LArgs &t) {
         if constexpr (META) {
             // level [head, tail): its groups are [qg[head], the group total), every member's
             // group found by a search of qg only when a thread's group leaves its member
-            uint32_t head = 0, lh = 0;
+            uint32_t head = r_lo, lh = r_lo;
             for (uint32_t lev = 0;; lev ^= 1) {
                 const unsigned long long pk = qpack;  // the previous level's inserts are done
                 const uint32_t m = (uint32_t)(pk >> 32);
@@ -1347,13 +1378,54 @@ static void ensure_spill(Ctx &c) {
     buf_alloc(c, sc.spill, (size_t)want * (T2L_CAP_REGULAR * sizeof(uint4) + sizeof(uint2)));
     sc.spill_cap = want;
 }
-static void set_spill(Ctx &c, T2LArgs &t) {
+// output spill of the 2048-member tier, or input of the extra-large pass (set_in)
+static void set_spill(Ctx &c, T2LArgs &t, bool set_in) {
     const Scratch &sc = c.sc;
-    t.sp_cap = std::min(sc.spill_cap, spill_want(c));
-    t.sp_rec = t.sp_cap ? sc.spill.as<uint4>() : nullptr;
-    t.sp_hdr = t.sp_cap ? reinterpret_cast<uint2 *>(sc.spill.as<char>() +
-                                                    (size_t)sc.spill_cap * T2L_CAP_REGULAR * sizeof(uint4))
-                        : nullptr;
+    const uint32_t cap = std::min(sc.spill_cap, spill_want(c));
+    uint4 *rec = cap ? sc.spill.as<uint4>() : nullptr;
+    uint2 *hdr = cap ? reinterpret_cast<uint2 *>(sc.spill.as<char>() +
+                                                 (size_t)sc.spill_cap * T2L_CAP_REGULAR * sizeof(uint4))
+                     : nullptr;
+    if (set_in) {
+        t.rin = rec;
+        t.rin_hdr = hdr;
+        t.rin_cap = cap;
+        t.rin_stride = T2L_CAP_REGULAR;
+    } else {
+        t.sp_rec = rec;
+        t.sp_hdr = hdr;
+        t.sp_cap = cap;
+    }
+}
+
+// The 1024-member tier's spill slots for the 2048-member one: up to twice SPILL_SLOTS (most
+// sets that reach the LDS tiers outgrow 1024 members less often than they fit), 1024 records
+// of 16 bytes and an 8-byte header each (134 MB at most).
+static uint32_t spill0_want(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.sc.bcap, 2 * c.spill_slots); }
+static void ensure_spill0(Ctx &c) {
+    Scratch &sc = c.sc;
+    const uint32_t want = spill0_want(c);
+    if (sc.spill0_cap >= want) return;
+    buf_alloc(c, sc.spill0, (size_t)want * (T2S_CAP * sizeof(uint4) + sizeof(uint2)));
+    sc.spill0_cap = want;
+}
+// output spill of the 1024-member tier, or input of the 2048-member one (set_in)
+static void set_spill0(Ctx &c, T2LArgs &t, bool set_in) {
+    const Scratch &sc = c.sc;
+    const uint32_t cap = std::min(sc.spill0_cap, spill0_want(c));
+    uint4 *rec = cap ? sc.spill0.as<uint4>() : nullptr;
+    uint2 *hdr = cap ? reinterpret_cast<uint2 *>(sc.spill0.as<char>() + (size_t)sc.spill0_cap * T2S_CAP * sizeof(uint4))
+                     : nullptr;
+    if (set_in) {
+        t.rin = rec;
+        t.rin_hdr = hdr;
+        t.rin_cap = cap;
+        t.rin_stride = T2S_CAP;
+    } else {
+        t.sp_rec = rec;
+        t.sp_hdr = hdr;
+        t.sp_cap = cap;
+    }
 }
 
 // The extra-large pass's spill slots for the device-bitmap tier: up to 256 (sets past 8192
@@ -1535,6 +1607,40 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     const bool small_g = gmax < (1 << 22);
     const int lds_threads = root.lds_threads ? root.lds_threads : (small_g ? 1024 : 512);
     const int lds_per_cu = root.lds_per_cu ? root.lds_per_cu : (small_g ? 2 : 3);
+    // IC on large graphs: a 1024-member tier first (four 256-thread workgroups per CU where the
+    // 2048-member one fits two), whose overflow list `defer2` the 2048-member tier takes, with
+    // the levels it spilled; that tier's overflow then goes to `defer3` for the extra-large pass
+    const bool chain = root.lds_small == 1 || (root.lds_small == 2 && !small_g);
+    if (chain) {
+        std::vector<T2LArgs> sm;
+        std::vector<uint32_t> smb;
+        for (size_t i = 0; i < N; i++) {
+            Ctx &c = *J[i];
+            const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
+            if (!nd || c.g.model != HBM_IC) continue;
+            ensure_spill0(c);
+            sm.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
+            set_spill0(c, sm.back(), false);
+            smb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 4));
+        }
+        if (!sm.empty()) {
+            int s1 = prof_begin(root, "ic_sample_block_s");
+            glaunch(root, sm, smb, 0,
+                    [&](const T2LArgs &t, unsigned g) {
+                        k_big_lds<256, T2S_CAP, T2S_HASH_BITS><<<g, 256, 0, st>>>(t);
+                    },
+                    [&](const T2LArgs *d, const uint32_t *b, uint32_t cnt, uint32_t g, int x) {
+                        k_big_lds_g<256, T2S_CAP, T2S_HASH_BITS><<<g, 256, 0, st>>>(GroupArgs<T2LArgs>{d, b, cnt, x});
+                    });
+            HBM_HIP(hipGetLastError());
+            prof_end(root, s1);
+            ctrl_pull(root);
+            if (s1 >= 0) prof_sampler(root, s1, true, J);
+            for (size_t i = 0; i < N; i++)
+                if (J[i]->g.model == HBM_IC) root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
+            ctrl_push(root);
+        }
+    }
     std::vector<T2LArgs> lds;
     std::vector<uint32_t> ldsb;
     std::vector<Lt2Args> ltw;
@@ -1542,12 +1648,18 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     bool lt_deferred = false;
     for (size_t i = 0; i < N; i++) {
         Ctx &c = *J[i];
-        const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
+        const bool ic_chain = chain && c.g.model == HBM_IC;
+        const uint64_t nd = root.ctrl_host[i * CW_COUNT + (ic_chain ? CW_NDEFER2 : CW_NDEFER)];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
             ensure_spill(c);
-            lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
-            set_spill(c, lds.back());
+            if (ic_chain) {
+                lds.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd, A[i].defer3, CW_NDEFER3, nullptr});
+                set_spill0(c, lds.back(), true);
+            } else {
+                lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
+            }
+            set_spill(c, lds.back(), false);
             ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
@@ -1599,11 +1711,11 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             if (c.g.model != HBM_IC) continue;
             // CW_NDEFER still counts the LDS tier's input: from here on it counts tier 3's
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;
-            const uint64_t nd2 = root.ctrl_host[i * CW_COUNT + CW_NDEFER2];
+            const uint64_t nd2 = root.ctrl_host[i * CW_COUNT + (chain ? CW_NDEFER3 : CW_NDEFER2)];
             if (!nd2) continue;
             root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
-            xl.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
-            set_spill(c, xl.back());  // as the regular tier wrote it
+            xl.push_back(T2LArgs{A[i], chain ? A[i].defer3 : A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
+            set_spill(c, xl.back(), true);  // as the 2048-member tier wrote it
             ensure_spill2(c);
             spill2_of(c, xl.back().xs_ids, xl.back().xs_hdr, xl.back().xs_cap);
             xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));

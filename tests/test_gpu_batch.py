@@ -53,13 +53,14 @@ def _small_mix(count, smin, smax, seed):
     return insts
 
 
-@pytest.mark.parametrize("block", [1 << 21, 1024])
-def test_batch_equals_alone_and_oracle(orc, P, block):
+@pytest.mark.parametrize("block,small", [(1 << 21, 0), (1024, 0), (1 << 21, 1)])
+def test_batch_equals_alone_and_oracle(orc, P, block, small):
     insts = _small_mix(10, 8, 11, seed=11)
-    _say("batch of", len(insts), "scales", [i["scale"] for i in insts], "block", block)
+    _say("batch of", len(insts), "scales", [i["scale"] for i in insts], "block", block, "small tier", small)
     ctxs, graphs = _contexts(P, insts)
     try:
         ctxs[0].hbm_set_tuning("BLOCK_SETS", block)
+        ctxs[0].hbm_set_tuning("LDS_SMALL", small)  # the driving context's shape serves the batch
         out = P.imm_batch(ctxs, [(i["k"], i["eps"], i["l"], i["seed"]) for i in insts])
         for inst, c, g, (seeds, gains, st) in zip(insts, ctxs, graphs, out):
             _say("instance", inst["index"], inst["model"], "scale", inst["scale"], "k", inst["k"], "eps", inst["eps"])

@@ -306,22 +306,27 @@ def test_imm_small(orc, ctx, model, enc):
     assert np.array_equal(seeds, os_) and np.array_equal(gains, og_) and st["coverage"] == ost["coverage"]
 
 
-@pytest.mark.parametrize("scale,theta,slots", [(13, 1_500, 4096), (13, 1_500, 3), (13, 1_500, 0),
-                                              (15, 300, 4096), (15, 300, 2)])
-def test_spilled_levels_resume(orc, P, ctx, scale, theta, slots):
-    """IC sets that outgrow the LDS tier (constant p = 0.25: most sets hold thousands of
-    vertices) go on in the extra-large pass from the levels the tier spilled, and sets past
-    8192 members go on in the device-bitmap tier from the levels that pass spilled; or they
-    start over from their root when no spill slot is left (few slots: most of them; 0: all).
-    The sets are the oracle's either way."""
-    _say("spilled levels resume: scale", scale, "slots", slots)
+@pytest.mark.parametrize("scale,theta,slots,small", [(13, 1_500, 4096, 0), (13, 1_500, 3, 0), (13, 1_500, 0, 0),
+                                                    (13, 1_500, 4096, 1), (13, 1_500, 3, 1), (13, 1_500, 0, 1),
+                                                    (15, 300, 4096, 1), (15, 300, 2, 0)])
+def test_spilled_levels_resume(orc, P, ctx, scale, theta, slots, small):
+    """IC sets that outgrow an LDS tier (constant p = 0.25: most sets hold thousands of
+    vertices) go on in the next one from the levels it spilled: from the 1024-member tier
+    (LDS_SMALL = 1) to the 2048-member one, from there to the extra-large pass, and from that
+    pass, past 8192 members, to the device-bitmap tier; or they start over from their root
+    when no spill slot is left (few slots: most of them; 0: all).  The sets are the oracle's
+    either way."""
+    _say("spilled levels resume: scale", scale, "slots", slots, "small tier", small)
     for bad in (-1, 4097):
         assert P.lib().hbm_set_tuning(ctx.h, P.TUNE["SPILL_SLOTS"], bad) == P.HBM_EINVAL
+    for bad in (-1, 3):
+        assert P.lib().hbm_set_tuning(ctx.h, P.TUNE["LDS_SMALL"], bad) == P.HBM_EINVAL
     g = G.rmat(scale, seed=scale)
     g = G.with_weights(g, np.full(g.m, 0.25, dtype=np.float32))
     ctx.load_synth(g, "IC", "EDGE")
     ctx.hbm_set_encoding("NONE")
     ctx.hbm_set_tuning("SPILL_SLOTS", slots)
+    ctx.hbm_set_tuning("LDS_SMALL", small)
     ctx.hbm_sample_rr(theta, 42)
     og = _ograph(orc, g, "IC", "EDGE")
     st = orc.sample_store(og, 42, theta)
@@ -341,7 +346,9 @@ def test_spilled_levels_resume(orc, P, ctx, scale, theta, slots):
                                                           (1, 4096, 3000, 1 << 20, (512, 1)),
                                                           (1, 64, 1 << 21, 64, (1024, 2)),
                                                           (1, 128, 1 << 21, 1 << 20, (512, 4)),
-                                                          (0, 0, 5000, 100, (1024, 4))])
+                                                          (0, 0, 5000, 100, (1024, 4)),
+                                                          (1, 64, 3000, 1 << 20, (512, 3, 1)),
+                                                          (0, 0, 1 << 21, 100, (1024, 2, 1))])
 def test_tuning_invariance(orc, ctx, tier1, budget, block, queue, lds):
     """Tier choice, tier-1 work budget, block size, big-set queue size (small queues
     send sets to the huge-set pass) and the LDS tier's workgroup shape change speed
@@ -355,6 +362,7 @@ def test_tuning_invariance(orc, ctx, tier1, budget, block, queue, lds):
     ctx.hbm_set_tuning("T2_QUEUE", queue)
     ctx.hbm_set_tuning("LDS_THREADS", lds[0])
     ctx.hbm_set_tuning("LDS_PER_CU", lds[1])
+    ctx.hbm_set_tuning("LDS_SMALL", lds[2] if len(lds) > 2 else 0)  # the 1024-member tier in front
     ctx.hbm_set_encoding("HOT_BITMAP", 0.1, 0.01)
     theta = 20_000
     ctx.hbm_sample_rr(theta, 42)
