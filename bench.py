@@ -135,7 +135,8 @@ def csrc_digest():
 # their template arguments)
 PROFILE_KERNELS = {
     "ic_sample_wave": r"k_ic_t1(_g)?\b", "ic_sample_block": r"k_big_lds(_g)?<\d+, 2048,",
-    "ic_sample_block_xl": r"k_big_lds(_g)?<\d+, 8192,", "ic_sample_bitmap": r"k_big(_g)?\b",
+    "ic_sample_block_xl": r"k_big_lds(_g)?<\d+, 8192,", "ic_sample_block_s": r"k_big_lds(_g)?<\d+, 1024,",
+    "ic_sample_bitmap": r"k_big(_g)?\b",
     "lt_sample_lane": r"k_lt_t1(_g)?\b", "lt_sample_wave": r"k_lt_wave(_g)?\b", "lt_sample_block": r"k_big(_g)?\b",
     "sample_huge": r"k_big(_g)?\b",
 }

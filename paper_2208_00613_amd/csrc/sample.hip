@@ -13,7 +13,8 @@
 // visited set in an LDS hash and its queue in LDS, a frontier batch flattened into groups of
 // four in-edges (one Philox call each) over the lanes, up to a group budget (k_ic_t1); a
 // workgroup per set with an LDS hash and a 2048-member queue that keeps each member's
-// in-edge range, threshold and first Philox group (k_big_lds<., 2048, .>); an extra-large
+// in-edge range, threshold and first Philox group (k_big_lds<., 2048, .>; on large graphs a
+// 1024-member one with four workgroups per CU in front, whose spilled levels it resumes); an extra-large
 // pass of one 1024-thread workgroup per CU with room for 8192 members, their in-edge records
 // in device memory beside it (k_big_lds<1024, 8192, 14>), which goes on from the BFS levels
 // the 2048-member tier completed and spilled when the set outgrew it; a workgroup per set with a visited
