@@ -676,12 +676,14 @@ __device__ void apply_words(const SelArgs &A, const Tabs &tb, DecCache &C, uint3
 // come first and ascending; a coded u* is matched by its canonical code and the scan ends
 // at the first larger code).  A set holding u* is marked covered; its members are
 // decremented at once by the lane when its string is short and staged, else, after the
-// word's search, by the whole wave (wave_dec_string, 32 slot intervals at a time).  The word's strings are contiguous:
-// they are copied to LDS with coalesced loads first (when they fit).  Each wave loads the
-// next word's covered mask and bit offsets before decoding the current one, and the grid is
-// sized to stay resident.  The search is bound by decode latency, so residency matters more
-// than staging: with a stage of 256 words a block needs about 21 KB of LDS and seven blocks
-// (the register limit) fit a CU.
+// word's search, by the whole wave (wave_dec_string, 32 slot intervals at a time).  The
+// word's strings are contiguous: they are copied to LDS with coalesced loads first (when they
+// fit).  Each wave loads the next word's covered mask and bit offsets before decoding the
+// current one.  The search is bound by decode latency, so residency matters more than
+// staging: with a stage of 256 words a block needs about 21 KB of LDS, and its registers let
+// five blocks stay resident per CU (the grid asks for seven, which measured the same).  In a
+// store without array rows (A.fused) the kernel also does k_apply's work: it records u* and,
+// for a u* with a bitmap row, covers the row's sets and decrements their members.
 constexpr int FH_NI = 32;                                  // slot intervals per pass of a long string
 constexpr int STAGE_WORDS = (FH_NI * CK_SLOT) / 32 + 4;    // 260: also holds FH_NI intervals
 
@@ -1103,7 +1105,7 @@ SelJob plan_job(Ctx &root, Ctx &c, int32_t k, unsigned long long *keys, const Se
     J.huff = huff;
     J.g_arg = g_arg;
     if (T == 0) J.g_find = 0;
-    else if (huff) J.g_find = gfix ? (uint32_t)root.num_cus * 7 : grid_for(words, 4, (int64_t)root.num_cus * 7);  // resident: 7 blocks per CU
+    else if (huff) J.g_find = gfix ? (uint32_t)root.num_cus * 7 : grid_for(words, 4, (int64_t)root.num_cus * 7);  // seven per CU (five stay resident)
     else J.g_find = (A.nraw > 0 || A.implicit || A.nar) ? (gfix ? (uint32_t)root.num_cus * 4 : grid_for((A.nraw + 3) / 4 + 1, 256, (int64_t)root.num_cus * 4)) : 0;
     J.g_apply = gfix ? (uint32_t)root.num_cus * 2 : grid_for(std::max<int64_t>(words, 1), 4, 1 << 20);
     // hot counts: segments past the words in use find no word to read
