@@ -390,11 +390,12 @@ typedef enum hbm_tune_key {
                                      of that shape (up to 16 shapes kept per driving context).
                                      0 (default): launched kernel by kernel.  Not used while
                                      profiling */
-    HBM_TUNE_SPILL_SLOTS = 10,    /* IC sets that outgrow the LDS tier: how many per sampling block
-                                     (0..4096, default 4096) keep the BFS levels the tier completed
-                                     (32 KB of device memory each, allocated on first use) so the
-                                     extra-large pass goes on from there; the rest start over from
-                                     their root */
+    HBM_TUNE_SPILL_SLOTS = 10,    /* IC sets that outgrow an LDS tier: how many per sampling launch
+                                     (0..4096, default 4096; set on the driving context, shared
+                                     among a batch's instances in proportion to their lists) keep
+                                     the BFS levels the tier completed (32 KB of device memory each,
+                                     held by the driving context) so the next tier goes on from
+                                     there; the rest start over from their root */
     HBM_TUNE_LDS_SMALL = 11,      /* IC: 1 puts an LDS tier of 1024 members (256 threads, four
                                      workgroups per CU) in front of the 2048-member one, which goes
                                      on from the levels it spilled (up to twice SPILL_SLOTS sets per

@@ -73,7 +73,8 @@ void hbm_destroy(hbm_ctx *ctx) {
         hbm::store_free(ctx->c);
         hbm::graph_free(ctx->c);
         for (hbm::Buf *b : {&ctx->c.scan_tmp, &ctx->c.ctrl_arena, &ctx->c.tails, &ctx->c.bkeys,
-                            &ctx->c.dctr, &ctx->c.xmeta, &ctx->c.pfind})
+                            &ctx->c.dctr, &ctx->c.xmeta, &ctx->c.pfind, &ctx->c.spill0, &ctx->c.spill,
+                            &ctx->c.spill2})
             hbm::buf_free(ctx->c, *b);
         hbm::stage_free(ctx->c);
     } catch (...) {

@@ -166,13 +166,6 @@ struct Scratch {
     int t2h_slots = 0;
     Buf aux;        // uint64 per set (+1): bit lengths
     Buf cnt;        // uint32 per set (+1): plain-id counts
-    Buf spill;      // IC: the levels an LDS-tier set had completed when it outgrew the tier,
-                    // one slot per entry of the extra-large pass's list (records, then headers)
-    uint32_t spill_cap = 0;
-    Buf spill2;     // the same for the extra-large pass's overflow (ids, then headers)
-    uint32_t spill2_cap = 0;
-    Buf spill0;     // the same for the 1024-member tier's overflow (records, then headers)
-    uint32_t spill0_cap = 0;
 };
 
 // control word indices
@@ -278,6 +271,12 @@ struct Ctx {
     Buf tails;                             // uint64 per job: gathered totals
     Buf bkeys;                             // uint64 selection keys of every job
     Buf xmeta;                             // extra-large LDS pass: member records (uint4)
+    // IC spill slots of one sampling launch, every job's after the previous job's: the levels a
+    // set had completed when it outgrew an LDS tier (records, or ids for the device-bitmap
+    // tier), for the next tier to resume; headers after the slots
+    Buf spill0;                            // 1024-member tier -> 2048-member tier
+    Buf spill;                             // 2048-member tier -> extra-large pass
+    Buf spill2;                            // extra-large pass -> device-bitmap tier
     Buf pfind;                             // profiling: find_huff's algorithmic bytes (partial sums)
     Prof prof;
     Buf dctr;      // uint64[DC_COUNT] sampler counters (used while profiling)

@@ -1368,83 +1368,60 @@ static void ensure_t2(Ctx &c) {
     sc.t2_slots = slots;
 }
 
-// Spill slots of the regular LDS tier (one per entry of the extra-large pass's list, up to the
-// context's SPILL_SLOTS setting, at most 4096; entries past them start over from the root):
-// T2L_CAP_REGULAR 16-byte records each, then an 8-byte header each (128 MB at most).
-static uint32_t spill_want(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.sc.bcap, c.spill_slots); }
-static void ensure_spill(Ctx &c) {
-    Scratch &sc = c.sc;
-    const uint32_t want = spill_want(c);
-    if (sc.spill_cap >= want) return;
-    buf_alloc(c, sc.spill, (size_t)want * (T2L_CAP_REGULAR * sizeof(uint4) + sizeof(uint2)));
-    sc.spill_cap = want;
-}
-// output spill of the 2048-member tier, or input of the extra-large pass (set_in)
-static void set_spill(Ctx &c, T2LArgs &t, bool set_in) {
-    const Scratch &sc = c.sc;
-    const uint32_t cap = std::min(sc.spill_cap, spill_want(c));
-    uint4 *rec = cap ? sc.spill.as<uint4>() : nullptr;
-    uint2 *hdr = cap ? reinterpret_cast<uint2 *>(sc.spill.as<char>() +
-                                                 (size_t)sc.spill_cap * T2L_CAP_REGULAR * sizeof(uint4))
-                     : nullptr;
-    if (set_in) {
-        t.rin = rec;
-        t.rin_hdr = hdr;
-        t.rin_cap = cap;
-        t.rin_stride = T2L_CAP_REGULAR;
-    } else {
-        t.sp_rec = rec;
-        t.sp_hdr = hdr;
-        t.sp_cap = cap;
+// Spill slots of one sampling launch, in a buffer of the driving context: job i gets cap[i]
+// slots (at most its list's length, as a slot is indexed by the next pass's list entry), after
+// the previous jobs' slots; each slot holds `slot` bytes of records (or ids), and the 8-byte
+// headers follow all slots.  Entries past a job's slots start over from the root.
+struct SpillPlan {
+    std::vector<uint32_t> cap;
+    std::vector<uint64_t> base;
+    size_t slot = 0;
+    uint64_t total = 0;
+    char *p = nullptr;
+    template <class T>
+    T *rec(size_t i) const { return cap[i] ? reinterpret_cast<T *>(p + base[i] * slot) : nullptr; }
+    uint2 *hdr(size_t i) const {
+        return cap[i] ? reinterpret_cast<uint2 *>(p + total * slot + base[i] * sizeof(uint2)) : nullptr;
     }
-}
-
-// The 1024-member tier's spill slots for the 2048-member one: up to twice SPILL_SLOTS (most
-// sets that reach the LDS tiers outgrow 1024 members less often than they fit), 1024 records
-// of 16 bytes and an 8-byte header each (134 MB at most).
-static uint32_t spill0_want(const Ctx &c) { return (uint32_t)std::min<int64_t>(c.sc.bcap, 2 * c.spill_slots); }
-static void ensure_spill0(Ctx &c) {
-    Scratch &sc = c.sc;
-    const uint32_t want = spill0_want(c);
-    if (sc.spill0_cap >= want) return;
-    buf_alloc(c, sc.spill0, (size_t)want * (T2S_CAP * sizeof(uint4) + sizeof(uint2)));
-    sc.spill0_cap = want;
-}
-// output spill of the 1024-member tier, or input of the 2048-member one (set_in)
-static void set_spill0(Ctx &c, T2LArgs &t, bool set_in) {
-    const Scratch &sc = c.sc;
-    const uint32_t cap = std::min(sc.spill0_cap, spill0_want(c));
-    uint4 *rec = cap ? sc.spill0.as<uint4>() : nullptr;
-    uint2 *hdr = cap ? reinterpret_cast<uint2 *>(sc.spill0.as<char>() + (size_t)sc.spill0_cap * T2S_CAP * sizeof(uint4))
-                     : nullptr;
-    if (set_in) {
-        t.rin = rec;
-        t.rin_hdr = hdr;
-        t.rin_cap = cap;
-        t.rin_stride = T2S_CAP;
-    } else {
-        t.sp_rec = rec;
-        t.sp_hdr = hdr;
-        t.sp_cap = cap;
+};
+static void spill_plan(Ctx &root, Buf &buf, size_t slot, const std::vector<uint32_t> &cap, SpillPlan &P) {
+    P.cap = cap;
+    P.slot = slot;
+    P.base.assign(cap.size(), 0);
+    uint64_t t = 0;
+    for (size_t i = 0; i < cap.size(); i++) {
+        P.base[i] = t;
+        t += cap[i];
     }
+    P.total = t;
+    if (t) buf_grow(root, buf, (size_t)t * (slot + sizeof(uint2)), false);
+    P.p = t ? buf.as<char>() : nullptr;
 }
-
-// The extra-large pass's spill slots for the device-bitmap tier: up to 256 (sets past 8192
-// members are rare), T2X_CAP ids and an 8-byte header each (8 MB at most).
-static uint32_t spill2_want(const Ctx &c) { return std::min<uint32_t>(spill_want(c), 256u); }
-static void ensure_spill2(Ctx &c) {
-    Scratch &sc = c.sc;
-    const uint32_t want = spill2_want(c);
-    if (sc.spill2_cap >= want) return;
-    buf_alloc(c, sc.spill2, (size_t)want * (T2X_CAP * sizeof(uint32_t) + sizeof(uint2)));
-    sc.spill2_cap = want;
+// Slots per job: a launch's budget (the driving context's SPILL_SLOTS for the 2048-member tier,
+// twice that for the 1024-member one, whose overflow is the larger, and at most 256 for the
+// extra-large pass: sets past 8192 members are rare) shared among its IC jobs in proportion to
+// their lists (at least 16 each), and never more than a job's list
+static std::vector<uint32_t> spill_caps(const std::vector<uint64_t> &listed, int64_t budget) {
+    uint64_t sum = 0;
+    for (uint64_t n : listed) sum += n;
+    std::vector<uint32_t> cap(listed.size(), 0);
+    for (size_t i = 0; i < listed.size(); i++) {
+        if (!listed[i] || budget <= 0) continue;
+        const uint64_t share = std::max<uint64_t>(16, (uint64_t)((double)budget * (double)listed[i] / (double)sum));
+        cap[i] = (uint32_t)std::min<uint64_t>({listed[i], share, (uint64_t)budget});
+    }
+    return cap;
 }
-static void spill2_of(Ctx &c, uint32_t *&ids, uint2 *&hdr, uint32_t &cap) {
-    const Scratch &sc = c.sc;
-    cap = std::min(sc.spill2_cap, spill2_want(c));
-    ids = cap ? sc.spill2.as<uint32_t>() : nullptr;
-    hdr = cap ? reinterpret_cast<uint2 *>(sc.spill2.as<char>() + (size_t)sc.spill2_cap * T2X_CAP * sizeof(uint32_t))
-              : nullptr;
+static void spill_out(const SpillPlan &P, size_t i, T2LArgs &t) {
+    t.sp_rec = P.rec<uint4>(i);
+    t.sp_hdr = P.hdr(i);
+    t.sp_cap = P.cap[i];
+}
+static void spill_in(const SpillPlan &P, size_t i, T2LArgs &t, uint32_t stride) {
+    t.rin = P.rec<uint4>(i);
+    t.rin_hdr = P.hdr(i);
+    t.rin_cap = P.cap[i];
+    t.rin_stride = stride;
 }
 
 static void ensure_t2_huge(Ctx &c) {
@@ -1612,16 +1589,20 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     // 2048-member one fits two), whose overflow list `defer2` the 2048-member tier takes, with
     // the levels it spilled; that tier's overflow then goes to `defer3` for the extra-large pass
     const bool chain = root.lds_small == 1 || (root.lds_small == 2 && !small_g);
+    SpillPlan sp0, sp1, sp2;  // 1024 -> 2048 members, 2048 -> extra-large, extra-large -> bitmap tier
     if (chain) {
+        std::vector<uint64_t> listed(N, 0);
+        for (size_t i = 0; i < N; i++)
+            if (J[i]->g.model == HBM_IC) listed[i] = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
+        spill_plan(root, root.spill0, T2S_CAP * sizeof(uint4), spill_caps(listed, 2 * root.spill_slots), sp0);
         std::vector<T2LArgs> sm;
         std::vector<uint32_t> smb;
         for (size_t i = 0; i < N; i++) {
             Ctx &c = *J[i];
             const uint64_t nd = root.ctrl_host[i * CW_COUNT + CW_NDEFER];
             if (!nd || c.g.model != HBM_IC) continue;
-            ensure_spill0(c);
             sm.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
-            set_spill0(c, sm.back(), false);
+            spill_out(sp0, i, sm.back());
             smb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * 4));
         }
         if (!sm.empty()) {
@@ -1647,20 +1628,25 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
     std::vector<Lt2Args> ltw;
     std::vector<uint32_t> ltwb;
     bool lt_deferred = false;
+    {
+        std::vector<uint64_t> listed(N, 0);
+        for (size_t i = 0; i < N; i++)
+            if (J[i]->g.model == HBM_IC) listed[i] = root.ctrl_host[i * CW_COUNT + (chain ? CW_NDEFER2 : CW_NDEFER)];
+        spill_plan(root, root.spill, T2L_CAP_REGULAR * sizeof(uint4), spill_caps(listed, root.spill_slots), sp1);
+    }
     for (size_t i = 0; i < N; i++) {
         Ctx &c = *J[i];
         const bool ic_chain = chain && c.g.model == HBM_IC;
         const uint64_t nd = root.ctrl_host[i * CW_COUNT + (ic_chain ? CW_NDEFER2 : CW_NDEFER)];
         if (!nd) continue;
         if (c.g.model == HBM_IC) {
-            ensure_spill(c);
             if (ic_chain) {
                 lds.push_back(T2LArgs{A[i], A[i].defer2, (uint32_t)nd, A[i].defer3, CW_NDEFER3, nullptr});
-                set_spill0(c, lds.back(), true);
+                spill_in(sp0, i, lds.back(), T2S_CAP);
             } else {
                 lds.push_back(T2LArgs{A[i], A[i].defer, (uint32_t)nd, A[i].defer2, CW_NDEFER2, nullptr});
             }
-            set_spill(c, lds.back(), false);
+            spill_out(sp1, i, lds.back());
             ldsb.push_back((uint32_t)std::min<uint64_t>(nd, (uint64_t)root.num_cus * lds_per_cu));
         } else {
             root.ctrl_host[i * CW_COUNT + CW_NDEFER] = 0;  // reused as the tier-3 list length
@@ -1707,6 +1693,14 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
         // entries the LDS tier has consumed)
         std::vector<T2LArgs> xl;
         std::vector<uint32_t> xlb;
+        {
+            std::vector<uint64_t> listed(N, 0);
+            for (size_t i = 0; i < N; i++)
+                if (J[i]->g.model == HBM_IC)
+                    listed[i] = root.ctrl_host[i * CW_COUNT + (chain ? CW_NDEFER3 : CW_NDEFER2)];
+            spill_plan(root, root.spill2, T2X_CAP * sizeof(uint32_t),
+                       spill_caps(listed, std::min<int64_t>(root.spill_slots, 256)), sp2);
+        }
         for (size_t i = 0; i < N; i++) {
             Ctx &c = *J[i];
             if (c.g.model != HBM_IC) continue;
@@ -1716,9 +1710,10 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
             if (!nd2) continue;
             root.ctrl_host[i * CW_COUNT + CW_NEXT2] = 0;
             xl.push_back(T2LArgs{A[i], chain ? A[i].defer3 : A[i].defer2, (uint32_t)nd2, A[i].defer, CW_NDEFER, nullptr});
-            set_spill(c, xl.back(), true);  // as the 2048-member tier wrote it
-            ensure_spill2(c);
-            spill2_of(c, xl.back().xs_ids, xl.back().xs_hdr, xl.back().xs_cap);
+            spill_in(sp1, i, xl.back(), T2L_CAP_REGULAR);  // as the 2048-member tier wrote it
+            xl.back().xs_ids = sp2.rec<uint32_t>(i);
+            xl.back().xs_hdr = sp2.hdr(i);
+            xl.back().xs_cap = sp2.cap[i];
             xlb.push_back((uint32_t)std::min<uint64_t>(nd2, (uint64_t)root.num_cus));
         }
         if (!xl.empty()) {
@@ -1775,12 +1770,10 @@ void sample_blocks(Ctx &root, const std::vector<Ctx *> &J, const std::vector<int
                 t.model = model;
                 t.qcap = t2_qcap(c);
                 t.can_defer = 1;
-                if (model == HBM_IC) {  // as the extra-large pass wrote them
-                    uint32_t *ids = nullptr;
-                    uint2 *hdr = nullptr;
-                    spill2_of(c, ids, hdr, t.rs_cap);
-                    t.rs_ids = ids;
-                    t.rs_hdr = hdr;
+                if (model == HBM_IC && !sp2.cap.empty()) {  // as the extra-large pass wrote them
+                    t.rs_ids = sp2.rec<uint32_t>(i);
+                    t.rs_hdr = sp2.hdr(i);
+                    t.rs_cap = sp2.cap[i];
                 }
                 t3.push_back(t);
                 t3b.push_back((uint32_t)std::min<uint64_t>(nd3, (uint64_t)c.sc.t2_slots));

@@ -522,7 +522,8 @@ void hbm_server_destroy(hbm_server *s) {
         try {
             hbm::select_free(c);
             hbm::store_free(c);
-            for (hbm::Buf *b : {&c.scan_tmp, &c.ctrl_arena, &c.tails, &c.bkeys, &c.dctr, &c.xmeta, &c.pfind})
+            for (hbm::Buf *b : {&c.scan_tmp, &c.ctrl_arena, &c.tails, &c.bkeys, &c.dctr, &c.xmeta, &c.pfind,
+                                &c.spill0, &c.spill, &c.spill2})
                 hbm::buf_free(c, *b);
             hbm::stage_free(c);
         } catch (...) {
@@ -532,11 +533,13 @@ void hbm_server_destroy(hbm_server *s) {
         hbm::select_free(s->root);
         hbm::select_free(s->rootL);
         for (hbm::Buf *b : {&s->root.scan_tmp, &s->root.ctrl_arena, &s->root.tails, &s->root.bkeys,
-                            &s->root.dctr, &s->root.xmeta, &s->root.pfind})
+                            &s->root.dctr, &s->root.xmeta, &s->root.pfind, &s->root.spill0, &s->root.spill,
+                            &s->root.spill2})
             hbm::buf_free(s->root, *b);
         hbm::stage_free(s->root);
         for (hbm::Buf *b : {&s->rootL.scan_tmp, &s->rootL.ctrl_arena, &s->rootL.tails, &s->rootL.bkeys, &s->rootL.dctr,
-                            &s->rootL.xmeta, &s->rootL.pfind})
+                            &s->rootL.xmeta, &s->rootL.pfind, &s->rootL.spill0, &s->rootL.spill,
+                            &s->rootL.spill2})
             hbm::buf_free(s->rootL, *b);
         hbm::stage_free(s->rootL);
     } catch (...) {

@@ -524,13 +524,10 @@ void store_free(Ctx &c) {
         buf_free(c, *b);
     Scratch &sc = c.sc;
     for (Buf *b : {&sc.mem, &sc.pos, &sc.size, &sc.ctrl, &sc.defer, &sc.t2_bitmap, &sc.t2_queue, &sc.t2h_bitmap,
-                   &sc.t2h_queue, &sc.aux, &sc.cnt, &sc.spill, &sc.spill2, &sc.spill0})
+                   &sc.t2h_queue, &sc.aux, &sc.cnt})
         buf_free(c, *b);
     sc.cap = 0;
     sc.bcap = 0;
-    sc.spill_cap = 0;
-    sc.spill2_cap = 0;
-    sc.spill0_cap = 0;
     sc.t2_slots = 0;
     sc.t2h_slots = 0;
 }
