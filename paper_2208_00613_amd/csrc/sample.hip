@@ -670,13 +670,14 @@ __device__ void big_body(const T2Args &t, uint32_t bid) {
 }
 
 // IC sets with few members but heavy expansions (hubs of large in-degree): one workgroup of
-// NT threads (512 or 1024) per set with its visited set in an LDS hash and its queue in LDS,
-// so a BFS level costs two dependent device loads (offsets, then sources) instead of four.  A set that
-// outgrows the LDS queue clears the hash and moves to the device-bitmap kernel (k_big).
-// Two capacities: the regular tier keeps 2048 members (hash of 8192 slots, 76-78 KB of LDS,
-// two workgroups per CU); its overflow goes to an extra-large pass that keeps 8192 (hash of
-// 16384 slots, 156 KB, one 1024-thread workgroup per CU), and only sets beyond that reach the
-// device-bitmap tier.  The hash never holds more than CAP + NT keys.
+// NT threads (256, 512 or 1024) per set with its visited set in an LDS hash and its queue in
+// LDS, so a BFS level costs two dependent device loads (offsets, then sources) instead of four.
+// A set that outgrows a tier's queue clears the hash, spills the levels it completed and
+// moves on to the next capacity: on large graphs a 1024-member tier first (hash of 4096 slots,
+// 38 KB, four 256-thread workgroups per CU); the regular tier of 2048 members (hash of 8192
+// slots, 76-78 KB, two workgroups per CU); an extra-large pass of 8192 (hash of 16384 slots,
+// 156 KB, one 1024-thread workgroup per CU); and only sets beyond that reach the
+// device-bitmap tier (k_big).  The hash never holds more than CAP + NT keys.
 
 struct T2LArgs {
     SampleArgs a;
