@@ -131,8 +131,8 @@ def csrc_digest():
 
 
 # hbm_profile names -> the HIP kernels behind them (regular expressions over the symbol after
-# "hbm::", matching the plain and grouped forms; the LDS tier's two capacities are told apart by
-# their template arguments)
+# "hbm::", matching the plain and grouped forms; the LDS tiers' three capacities are told apart
+# by their template arguments)
 PROFILE_KERNELS = {
     "ic_sample_wave": r"k_ic_t1(_g)?\b", "ic_sample_block": r"k_big_lds(_g)?<\d+, 2048,",
     "ic_sample_block_xl": r"k_big_lds(_g)?<\d+, 8192,", "ic_sample_block_s": r"k_big_lds(_g)?<\d+, 1024,",

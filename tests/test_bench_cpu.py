@@ -67,6 +67,7 @@ def test_traffic_calibrated_by_the_copy(bench, tmp_path, capsys):
         ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 100.0),
         ("void hbm::k_big_lds<1024, 2048, 13>(hbm::T2LArgs)", 300.0),
         ("void hbm::k_big_lds<1024, 8192, 14>(hbm::T2LArgs)", 7.0),
+        ("void hbm::k_big_lds_g<256, 1024, 12>(hbm::GroupArgs<hbm::T2LArgs>)", 5.0),
         ("void hbm::k_argmax(hbm::SelArgs, int)", 10.0),
         (copy, gib_kib / 2 + 3), (copy, gib_kib / 2), (copy, gib_kib / 2 - 3)])
     _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [
@@ -85,9 +86,10 @@ def test_traffic_calibrated_by_the_copy(bench, tmp_path, capsys):
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     k = t["traffic"]
     # mean of the two regular LDS-tier dispatches, fetched x2, plus written; the extra-large
-    # pass is told apart by its template arguments
+    # pass and the 1024-member tier are told apart by their template arguments
     assert k["ic_sample_block"] == pytest.approx(200.0 * 1024 * 2 + 4.0 * 1024)
     assert k["ic_sample_block_xl"] == pytest.approx(7.0 * 1024 * 2)
+    assert k["ic_sample_block_s"] == pytest.approx(5.0 * 1024 * 2)  # the 1024-member tier, grouped form
     assert k["argmax"] == pytest.approx(10.0 * 1024 * 2)
     assert t["l2_hit"] == {"argmax": pytest.approx(80.0 / 100.0)}
     assert t["workload_key"] == "c2" and t["csrc_digest"] == bench.csrc_digest()
